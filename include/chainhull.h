@@ -1,0 +1,155 @@
+/*
+ * chainhull: the data-parallel hot path of the CudaChain planar convex hull
+ * method (G. Mei, "CudaChain: A Practical GPU-accelerated 2D Convex Hull
+ * Algorithm", arXiv 1508.05488) on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Section 2.1, steps 1-7): find the four extreme points; discard
+ * the points inside their quadrilateral and distribute the rest into four
+ * corner regions (Section 2.1.1); sort each region (Table 1); discard again
+ * with the Sorting-based Preprocessing Approach, SPA (Figure 2); join the
+ * per-region chains into a simple polygon; finish with Melkman's convex hull
+ * of a simple polygon (Section 2.1.3).
+ *
+ * Domain.  Points are interleaved float32 (x, y) pairs whose values are
+ * integers in [0, 2^23); -0.0 counts as 0.  Every predicate is exact.  Any
+ * other value (NaN, +-Inf, a fraction, a negative value, >= 2^23) is rejected
+ * with CH_EDOMAIN.
+ *
+ * Output convention.  The hull is the list of its strict vertices (collinear
+ * boundary points are excluded), each reported by the smallest index among
+ * its exact duplicates, counter-clockwise (y axis up), starting at the vertex
+ * with the smallest y and, among those, the smallest x.  One distinct point
+ * gives [its smallest index]; an all-collinear set gives its two end points,
+ * the lowest-then-leftmost first; n == 0 gives an empty hull.
+ *
+ * Ownership.  Every pointer is owned by the caller; the library never frees
+ * or keeps one past the call.  The library owns a workspace per (device,
+ * stream) that grows on demand and is freed by chainhull_release().
+ * Concurrency.  Calls on different streams may run concurrently; calls on
+ * one stream must not overlap (the caller serialises them).
+ * Errors.  Every entry point returns a ch_status.  On failure the hull count
+ * is 0 and the output indices are unspecified.  HIP failures return CH_EHIP
+ * and leave the stream usable.
+ */
+#ifndef CHAINHULL_H
+#define CHAINHULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CH_OK = 0,
+    CH_EINVAL = -1,  /* bad argument: n out of range, null pointer, bad offsets */
+    CH_EDOMAIN = -2, /* a coordinate is not an integer in [0, 2^23) */
+    CH_ENOMEM = -3,  /* device or pinned host allocation failed */
+    CH_EHIP = -4,    /* a HIP runtime call failed */
+    CH_EADMIT = -5   /* reserved for admission control in a serving loop */
+} ch_status;
+
+/* Counts and timings of the most recent call on the calling thread. */
+typedef struct {
+    int64_t n;            /* input points */
+    int32_t ext_idx[4];   /* P_minx, P_miny, P_maxx, P_maxy (Section 2.1 step 1) */
+    int32_t ext_xy[8];    /* their (x, y) */
+    int64_t s1[4];        /* round-1 survivors in R1..R4 (Section 2.1.1) */
+    int64_t candidates;   /* records the tile filter passes to the region sort */
+    int64_t s2[4];        /* SPA survivors in R1..R4 (Figure 2) */
+    int64_t polygon;      /* vertices of the simple polygon before de-duplication */
+    int64_t hull;         /* hull vertices */
+    /* Milliseconds per stage when timing is on (chainhull_set_timing), from
+     * HIP events on the call's stream: 0 extreme points, 1 extreme-point
+     * reduction, 2 classify + tile filter, 3 region sort, 4 SPA, 5 chain
+     * concatenation, 6 device-to-host copy, 7 host finish (wall clock). */
+    float ms[8];
+} ch_stats;
+
+/*
+ * hull2d: exact convex hull of one point set (Section 2.1, steps 1-7).
+ *   points     device memory, n interleaved float32 (x, y) pairs, 8-byte
+ *              aligned, values integers in [0, 2^23).
+ *   n          0 <= n <= 2^31 - 1.
+ *   out_idx    device memory, room for n int32 (a hull never has more
+ *              vertices than points); receives the hull vertex indices.
+ *   out_count  device memory, one int32; receives the number of vertices.
+ *   stream     a hipStream_t (NULL for the default stream); all device work
+ *              is ordered on it.
+ * Blocking: returns after out_idx and out_count are written.
+ * Returns CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM or CH_EHIP.
+ */
+int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
+
+/*
+ * hull2d_batched: num_sets independent hulls (Section 2.1 applied per set).
+ *   points      device memory, the sets' points concatenated as in hull2d.
+ *   offsets     host memory, num_sets + 1 non-decreasing int64 with
+ *               offsets[0] == 0; set s is points[offsets[s] .. offsets[s+1]).
+ *   num_sets    >= 0.
+ *   out_idx     device memory, room for offsets[num_sets] int32; set s
+ *               writes its hull at out_idx + offsets[s], with indices local
+ *               to the set.
+ *   out_counts  device memory, num_sets int32: the hull size of each set, or
+ *               that set's negative ch_status if it failed.
+ *   stream      as in hull2d.
+ * Returns CH_OK if every set succeeded, else the first failing status.
+ */
+int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets,
+                   int32_t* out_idx, int32_t* out_counts, void* stream);
+
+/*
+ * chainhull_polygon: steps 1-6 only (Section 2.1): the simple polygon
+ * [P_minx, R1 chain, P_miny, R2 chain, P_maxx, R3 chain, P_maxy, R4 chain]
+ * (Table 1 order; consecutive coincident extreme points are dropped) that
+ * step 7 takes as input.
+ *   points, n, stream  as in hull2d.
+ *   poly_idx    host memory, room for n + 4 int32; receives the vertices'
+ *               point indices.
+ *   poly_count  host memory; receives the number of polygon vertices.
+ *   stats       host memory or NULL; receives the call's counts.
+ * Blocking.  Returns as hull2d.
+ */
+int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t* poly_count,
+                      ch_stats* stats, void* stream);
+
+/*
+ * chainhull_finish_host: step 7 alone (Section 2.1.3), Melkman's convex hull
+ * of a simple polygon, on the host.  Needs no GPU.
+ *   poly_xy     host memory, m interleaved int32 (x, y) vertices of a simple
+ *               polygon in counter-clockwise order, coordinates in [0, 2^23).
+ *   poly_idx    host memory, m int32: the point index of each vertex.
+ *   m           number of vertices, >= 0.
+ *   out_idx     host memory, room for m int32; receives the hull in the
+ *               output convention above.
+ *   out_count   host memory; receives the hull size.
+ * Returns CH_OK or CH_EINVAL (null pointer, m < 0, coordinate out of range,
+ * or a polygon that is not simple enough for the deque to stay valid).
+ */
+int chainhull_finish_host(const int32_t* poly_xy, const int32_t* poly_idx, int64_t m,
+                          int32_t* out_idx, int64_t* out_count);
+
+/* Copy the counts of the calling thread's last hull2d or chainhull_polygon
+ * call into *out.  Returns CH_OK, or CH_EINVAL for a null pointer. */
+int chainhull_last_stats(ch_stats* out);
+
+/* Turn per-stage HIP event timing on (nonzero) or off (0) for later calls.
+ * Timing adds event records to the stream; it does not change results. */
+void chainhull_set_timing(int enable);
+
+/* A static description of a ch_status value. */
+const char* chainhull_strerror(int status);
+
+/* Free every cached workspace (device and pinned host memory).  Must not be
+ * called while another call is running. */
+void chainhull_release(void);
+
+/* Upper bound on the device workspace bytes a call with n points needs. */
+size_t chainhull_workspace_bytes(int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHAINHULL_H */

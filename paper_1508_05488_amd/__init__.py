@@ -1,0 +1,204 @@
+"""chainhull: the CudaChain convex hull hot path on MI355X (gfx950).
+
+A thin ctypes binding over ``libchainhull.so`` (built in-tree by
+``paper_1508_05488_amd.build``).  Each function marshals arguments to the C
+ABI declared in ``include/chainhull.h`` and nothing more: every step of the
+method runs in the library's HIP kernels and its host finish.  PyTorch only
+provides device memory and the current HIP stream.  There is no fallback:
+when the library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libchainhull.so")
+
+CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4, -5
+
+# C entry points declared in include/chainhull.h
+EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_host",
+           "chainhull_last_stats", "chainhull_set_timing", "chainhull_strerror",
+           "chainhull_release", "chainhull_workspace_bytes")
+
+STAGES = ("extremes", "extremes_final", "classify", "sort", "spa", "chain", "copy_out", "finish")
+
+
+class ChainHullError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = f"{what}: " if what else ""
+        super().__init__(f"{msg}{strerror(status)} (status {status})")
+
+
+class ChStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("ext_idx", ctypes.c_int32 * 4),
+        ("ext_xy", ctypes.c_int32 * 8),
+        ("s1", ctypes.c_int64 * 4),
+        ("candidates", ctypes.c_int64),
+        ("s2", ctypes.c_int64 * 4),
+        ("polygon", ctypes.c_int64),
+        ("hull", ctypes.c_int64),
+        ("ms", ctypes.c_float * 8),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "n": self.n,
+            "ext_idx": list(self.ext_idx),
+            "ext_xy": list(self.ext_xy),
+            "s1": list(self.s1),
+            "candidates": self.candidates,
+            "s2": list(self.s2),
+            "polygon": self.polygon,
+            "hull": self.hull,
+            "ms": dict(zip(STAGES, list(self.ms))),
+        }
+
+
+_lib = None
+
+
+def lib():
+    """Load libchainhull.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1508_05488_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.hull2d.argtypes = [vp, i64, vp, vp, vp]
+    L.hull2d.restype = ctypes.c_int
+    L.hull2d_batched.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.hull2d_batched.restype = ctypes.c_int
+    L.chainhull_polygon.argtypes = [vp, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(ChStats), vp]
+    L.chainhull_polygon.restype = ctypes.c_int
+    L.chainhull_finish_host.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i64)]
+    L.chainhull_finish_host.restype = ctypes.c_int
+    L.chainhull_last_stats.argtypes = [ctypes.POINTER(ChStats)]
+    L.chainhull_last_stats.restype = ctypes.c_int
+    L.chainhull_set_timing.argtypes = [ctypes.c_int]
+    L.chainhull_set_timing.restype = None
+    L.chainhull_strerror.argtypes = [ctypes.c_int]
+    L.chainhull_strerror.restype = ctypes.c_char_p
+    L.chainhull_release.argtypes = []
+    L.chainhull_release.restype = None
+    L.chainhull_workspace_bytes.argtypes = [i64]
+    L.chainhull_workspace_bytes.restype = ctypes.c_size_t
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().chainhull_strerror(int(status)).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != CH_OK:
+        raise ChainHullError(rc, what)
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _device_points(points):
+    import torch
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch.Tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2:
+        raise TypeError("points must be float32 with shape [n, 2]")
+    if not points.is_contiguous():
+        raise TypeError("points must be contiguous")
+    return points
+
+
+def hull2d(points, stream=None):
+    """Hull vertex indices (int32 tensor on the points' device)."""
+    import torch
+    pts = _device_points(points)
+    n = pts.shape[0]
+    with torch.cuda.device(pts.device):
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+        cnt = torch.empty(1, dtype=torch.int32, device=pts.device)
+        rc = lib().hull2d(pts.data_ptr(), n, out.data_ptr(), cnt.data_ptr(), _stream_ptr(stream))
+        _check(rc, "hull2d")
+        h = int(cnt.item())
+    return out[:h]
+
+
+def hull2d_into(points, out_idx, out_count, stream=None) -> int:
+    """hull2d writing into caller-provided device tensors; returns the status."""
+    return lib().hull2d(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
+                        _stream_ptr(stream))
+
+
+def hull2d_batched(points, offsets, stream=None):
+    """Hulls of concatenated sets.  Returns (list of int32 tensors, counts tensor)."""
+    import torch
+    pts = _device_points(points)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    num = offs.shape[0] - 1
+    with torch.cuda.device(pts.device):
+        out = torch.empty(max(int(offs[-1]) if num >= 0 else 0, 1), dtype=torch.int32, device=pts.device)
+        cnt = torch.zeros(max(num, 1), dtype=torch.int32, device=pts.device)
+        rc = lib().hull2d_batched(pts.data_ptr(), offs.ctypes.data, num, out.data_ptr(), cnt.data_ptr(),
+                                  _stream_ptr(stream))
+        _check(rc, "hull2d_batched")
+        counts = cnt[:num].cpu().numpy()
+    return [out[int(offs[s]): int(offs[s]) + int(counts[s])] for s in range(num)], cnt[:num]
+
+
+def polygon(points, stream=None):
+    """Steps 1-6: the simple polygon (numpy int32 indices) and the call's counts."""
+    import torch
+    pts = _device_points(points)
+    n = pts.shape[0]
+    poly = np.empty(n + 4, dtype=np.int32)
+    m = ctypes.c_int64(0)
+    st = ChStats()
+    with torch.cuda.device(pts.device):
+        rc = lib().chainhull_polygon(pts.data_ptr(), n, poly.ctypes.data, ctypes.byref(m), ctypes.byref(st),
+                                     _stream_ptr(stream))
+    _check(rc, "chainhull_polygon")
+    return poly[: m.value].copy(), st.as_dict()
+
+
+def finish_host(poly_xy, poly_idx) -> np.ndarray:
+    """Step 7 on the host: Melkman's hull of a simple polygon (no GPU needed)."""
+    xy = np.ascontiguousarray(np.asarray(poly_xy, dtype=np.int32).reshape(-1, 2))
+    idx = np.ascontiguousarray(np.asarray(poly_idx, dtype=np.int32).reshape(-1))
+    if xy.shape[0] != idx.shape[0]:
+        raise ValueError("poly_xy and poly_idx differ in length")
+    m = idx.shape[0]
+    out = np.empty(max(m, 1), dtype=np.int32)
+    h = ctypes.c_int64(0)
+    rc = lib().chainhull_finish_host(xy.ctypes.data, idx.ctypes.data, m, out.ctypes.data, ctypes.byref(h))
+    _check(rc, "chainhull_finish_host")
+    return out[: h.value].copy()
+
+
+def last_stats() -> dict:
+    st = ChStats()
+    _check(lib().chainhull_last_stats(ctypes.byref(st)), "chainhull_last_stats")
+    return st.as_dict()
+
+
+def set_timing(enable: bool) -> None:
+    lib().chainhull_set_timing(1 if enable else 0)
+
+
+def release() -> None:
+    lib().chainhull_release()
+
+
+def workspace_bytes(n: int) -> int:
+    return int(lib().chainhull_workspace_bytes(int(n)))

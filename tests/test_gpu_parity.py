@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Hull indices must match the oracle bit for bit.  Stage outputs (extreme
+points, round-1 survivor counts, SPA survivor counts and the simple polygon)
+must match the step-by-step model exactly.  Each case prints its name before
+its GPU call.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1508_05488_amd as ch  # noqa: E402
+from oracle import hull as oracle  # noqa: E402
+from oracle import steps  # noqa: E402
+from paper_1508_05488_amd import workloads as wl  # noqa: E402
+from hullcheck import polygon_with_extras  # noqa: E402
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gpu_hull(pts, name=""):
+    say(f"  hull2d {name} n={pts.shape[0]}")
+    return ch.hull2d(torch.from_numpy(np.ascontiguousarray(pts)).cuda()).cpu().numpy()
+
+
+def assert_parity(pts, name=""):
+    got = gpu_hull(pts, name)
+    want = oracle.hull(pts)
+    assert np.array_equal(got, want), f"{name}: got {got[:10]}.. ({got.size}) want {want[:10]}.. ({want.size})"
+
+
+def test_every_subset_of_3x3_lattice():
+    rng = wl.rng_for(61)
+    lattice = np.array([(x, y) for x in range(3) for y in range(3)], np.float32)
+    for mask in range(1, 1 << 9):
+        base = lattice[[i for i in range(9) if mask >> i & 1]]
+        extra = base[rng.integers(0, base.shape[0], size=int(rng.integers(0, 4)))]
+        pts = np.concatenate([base, extra])
+        assert_parity(pts[rng.permutation(pts.shape[0])], f"3x3 mask={mask}")
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 9, 33, 1000, 1 << 23])
+def test_random_small_sets(k):
+    rng = wl.rng_for(62 + k % 83)
+    for t in range(150):
+        n = int(rng.integers(1, 300))
+        assert_parity(wl.small_lattice(n, k, rng), f"lattice k={k} t={t}")
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 8191, 8193, 12345, 65537, 100_000, 262_145])
+@pytest.mark.parametrize("dist", ["square", "disk", "gaussian", "adversarial"])
+def test_tiles_and_ragged_tails(dist, n):
+    assert_parity(wl.generate(dist, n, seed=63 + n % 7), f"{dist}")
+
+
+@pytest.mark.parametrize("dist", ["square", "adversarial"])
+def test_misaligned_input(dist):
+    # a view starting one point in is 8-byte but not 16-byte aligned
+    pts = wl.generate(dist, 50_001, seed=64)
+    t = torch.from_numpy(pts).cuda()
+    view = t[1:]
+    assert view.data_ptr() % 16 == 8
+    say(f"  hull2d misaligned {dist}")
+    got = ch.hull2d(view).cpu().numpy()
+    assert np.array_equal(got, oracle.hull(pts[1:]))
+
+
+def test_degenerate_inputs():
+    cases = {
+        "one": np.array([[7, 9]], np.float32),
+        "two": np.array([[9, 9], [1, 2]], np.float32),
+        "same": np.full((10_000, 2), 12345, np.float32),
+        "horizontal": np.stack([np.arange(5000) % 977, np.full(5000, 3)], 1).astype(np.float32),
+        "vertical": np.stack([np.full(5000, 3), np.arange(5000) % 977], 1).astype(np.float32),
+        "diagonal": np.stack([np.arange(5000) % 977, np.arange(5000) % 977], 1).astype(np.float32),
+        "antidiagonal": np.stack([np.arange(5000) % 977, 977 - np.arange(5000) % 977], 1).astype(np.float32),
+        "corners_max": np.array([[0, 0], [wl.M, 0], [wl.M, wl.M], [0, wl.M], [5, 5]], np.float32),
+        "grid": np.array([(x, y) for y in range(60) for x in range(60)], np.float32),
+    }
+    for name, pts in cases.items():
+        assert_parity(pts, name)
+
+
+def test_constructed_polygons_known_hull():
+    rng = wl.rng_for(65)
+    for t in range(10):
+        pts, want = polygon_with_extras(int(rng.integers(0, 20_000)), int(rng.integers(0, 500)),
+                                        int(rng.integers(0, 500)), rng, scale=int(rng.integers(2, 40000)),
+                                        base=(int(rng.integers(0, 1000)), int(rng.integers(0, 1000))))
+        got = gpu_hull(pts, f"polygon t={t}")
+        assert np.array_equal(got, want)
+
+
+def test_empty_input():
+    say("  hull2d n=0")
+    out = ch.hull2d(torch.zeros((0, 2), dtype=torch.float32, device="cuda"))
+    assert out.numel() == 0
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf, 0.5, -1.0, 2.0 ** 23, 3e9])
+def test_domain_errors(bad):
+    pts = wl.generate("square", 10_000, seed=66)
+    pts[1234, 0] = bad
+    say(f"  hull2d bad value {bad}")
+    with pytest.raises(ch.ChainHullError) as e:
+        ch.hull2d(torch.from_numpy(pts).cuda())
+    assert e.value.status == ch.CH_EDOMAIN
+    # the stream stays usable
+    assert_parity(wl.generate("square", 1000, seed=67), "after error")
+
+
+def test_negative_zero_is_zero():
+    pts = wl.generate("square", 5000, seed=68)
+    pts[:100] = -0.0
+    assert_parity(pts, "negative zero")
+
+
+def test_invalid_arguments_through_c_abi():
+    L = ch.lib()
+    t = torch.zeros((10, 2), dtype=torch.float32, device="cuda")
+    out = torch.zeros(10, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    say("  hull2d invalid arguments")
+    assert L.hull2d(t.data_ptr(), -1, out.data_ptr(), cnt.data_ptr(), s) == ch.CH_EINVAL
+    assert L.hull2d(None, 5, out.data_ptr(), cnt.data_ptr(), s) == ch.CH_EINVAL
+    assert L.hull2d(t.data_ptr(), 5, out.data_ptr(), None, s) == ch.CH_EINVAL
+    assert L.hull2d(t.data_ptr() + 4, 5, out.data_ptr(), cnt.data_ptr(), s) == ch.CH_EINVAL
+    assert L.hull2d(t.data_ptr(), 1 << 31, out.data_ptr(), cnt.data_ptr(), s) == ch.CH_EINVAL
+
+
+def stage_parity(pts, name):
+    say(f"  polygon {name} n={pts.shape[0]}")
+    poly, st = ch.polygon(torch.from_numpy(pts).cuda())
+    ref = steps.cudachain(pts)
+    e = ref["ext"]
+    assert st["ext_idx"] == [e["minx"], e["miny"], e["maxx"], e["maxy"]], name
+    assert st["s1"] == [ref["s1"][r] for r in steps.REGIONS], name
+    assert st["s2"] == [ref["s2"][r] for r in steps.REGIONS], name
+    assert poly.tolist() == ref["polygon"].tolist(), name
+    assert st["candidates"] <= sum(st["s1"])
+    assert st["candidates"] >= sum(st["s2"])
+
+
+@pytest.mark.parametrize("dist", wl.DISTRIBUTIONS)
+@pytest.mark.parametrize("n", [1000, 100_000, 1_000_000])
+def test_stage_parity(dist, n):
+    stage_parity(wl.generate(dist, n, seed=69), f"{dist}")
+
+
+def test_stage_parity_small_lattices():
+    rng = wl.rng_for(70)
+    for t in range(200):
+        k = int(rng.choice([2, 3, 4, 7, 20, 1 << 23]))
+        stage_parity(wl.small_lattice(int(rng.integers(1, 200)), k, rng), f"lattice k={k} t={t}")
+
+
+def test_repeat_calls_are_deterministic():
+    pts = torch.from_numpy(wl.generate("adversarial", 300_000, seed=71)).cuda()
+    say("  hull2d repeat x3")
+    a = ch.hull2d(pts).cpu().numpy()
+    b = ch.hull2d(pts).cpu().numpy()
+    c = ch.hull2d(pts).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(b, c)
+
+
+def test_batched_matches_single():
+    pts, offs, dists = wl.batched_sets(24, 1, 50_000, seed=72)
+    say(f"  hull2d_batched sets={len(dists)} total={offs[-1]}")
+    hulls, counts = ch.hull2d_batched(torch.from_numpy(pts).cuda(), offs)
+    for s in range(len(dists)):
+        want = oracle.hull(pts[offs[s]:offs[s + 1]])
+        assert np.array_equal(hulls[s].cpu().numpy(), want), s
+
+
+def test_timing_stats():
+    pts = torch.from_numpy(wl.generate("square", 200_000, seed=73)).cuda()
+    ch.set_timing(True)
+    try:
+        say("  hull2d timing")
+        ch.hull2d(pts)
+        st = ch.last_stats()
+    finally:
+        ch.set_timing(False)
+    assert st["n"] == 200_000 and st["hull"] > 2
+    assert all(v >= 0 for v in st["ms"].values())
+    assert st["ms"]["classify"] > 0

@@ -1,0 +1,82 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and its host finish (step 7, Melkman) agrees with the oracle when fed
+the oracle's own simple polygons.  No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1508_05488_amd as ch
+from oracle import hull as oracle
+from oracle import steps
+from paper_1508_05488_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "chainhull.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert set(names) == set(ch.EXPORTS), names
+    L = ctypes.CDLL(ch.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_workspace_bound():
+    for code in (ch.CH_OK, ch.CH_EINVAL, ch.CH_EDOMAIN, ch.CH_ENOMEM, ch.CH_EHIP, ch.CH_EADMIT):
+        assert ch.strerror(code)
+    assert ch.strerror(123) == "unknown status"
+    assert ch.workspace_bytes(20_000_000) >= 20_000_000 * 24
+    assert ch.workspace_bytes(10) > 0
+
+
+def _finish_via_library(pts):
+    res = steps.cudachain(pts)
+    X, Y = steps.to_int(pts)
+    poly = res["polygon"]
+    xy = np.stack([X[poly], Y[poly]], axis=1).astype(np.int32)
+    return ch.finish_host(xy, poly.astype(np.int32))
+
+
+def test_host_finish_on_every_3x3_subset():
+    rng = wl.rng_for(51)
+    lattice = np.array([(x, y) for x in range(3) for y in range(3)], np.float32)
+    for mask in range(1, 1 << 9):
+        base = lattice[[i for i in range(9) if mask >> i & 1]]
+        extra = base[rng.integers(0, base.shape[0], size=int(rng.integers(0, 4)))]
+        pts = np.concatenate([base, extra])
+        pts = pts[rng.permutation(pts.shape[0])]
+        assert _finish_via_library(pts).tolist() == oracle.hull(pts).tolist()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 8, 16, 100, 1 << 23])
+def test_host_finish_on_random_small_sets(k):
+    rng = wl.rng_for(52 + k % 89)
+    for _ in range(400):
+        pts = wl.small_lattice(int(rng.integers(1, 40)), k, rng)
+        assert _finish_via_library(pts).tolist() == oracle.hull(pts).tolist()
+
+
+@pytest.mark.parametrize("dist", wl.DISTRIBUTIONS)
+def test_host_finish_on_distributions(dist):
+    pts = wl.generate(dist, 200_000, seed=53)
+    assert _finish_via_library(pts).tolist() == oracle.hull(pts).tolist()
+
+
+def test_host_finish_degenerate_inputs():
+    assert ch.finish_host(np.zeros((0, 2)), np.zeros(0)).tolist() == []
+    assert ch.finish_host([[3, 4]], [7]).tolist() == [7]
+    # coincident vertices collapse; two distinct points start at the lowest
+    assert ch.finish_host([[3, 4], [3, 4], [1, 9], [3, 4]], [5, 6, 2, 8]).tolist() == [5, 2]
+    # collinear polygon: the two far ends
+    assert ch.finish_host([[0, 0], [1, 1], [2, 2], [3, 3], [2, 2]], [0, 1, 2, 3, 4]).tolist() == [0, 3]
+    with pytest.raises(ch.ChainHullError):
+        ch.finish_host([[0, 0], [1 << 23, 0], [0, 1]], [0, 1, 2])
