@@ -24,7 +24,7 @@ EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_ho
            "chainhull_last_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_workspace_bytes")
 
-STAGES = ("extremes", "extremes_final", "classify", "sort", "spa", "chain", "copy_out", "finish")
+STAGES = ("extremes", "unused1", "classify", "sort", "spa", "unused5", "copy_out", "finish")
 
 
 class ChainHullError(RuntimeError):

@@ -1,18 +1,28 @@
 // chainhull: the CudaChain preprocessing path (Section 2.1, steps 1-6) as
 // hand-written gfx950 kernels, the pipeline around them and the C ABI.
 //
+// Kernels of one hull (all on the caller's stream):
+//   k_extremes      step 1: extreme points + validation; the last workgroup
+//                   reduces the partials and derives edges and frames
+//   k_classify      step 2: exact region test (first discard) fused with a
+//                   tile-level use of the SPA dominance rule; writes the
+//                   tile's possible chain points
+//   k_sort_prep     digit counts of the region sort; clears the look-back
+//   k_sort_pass x3  steps 3-4: stable LSD radix passes over (region, k1)
+//   k_spa_chain     steps 5-6: SPA as a segmented prefix minimum, ordered
+//                   compaction of the chains straight into host memory
+// then one device-to-host copy of the header, Melkman on the host (step 7),
+// and the result copied into the caller's device buffers.
+//
 // Data layout in HBM (one workspace per device and stream):
-//   points           caller's n x float32[2], read twice (steps 1 and 2)
-//   ExtPartial[G1]   per-workgroup lexicographic extreme keys (step 1)
-//   DevHeader        extreme points, quadrilateral edges, region frames and
-//                    every counter of the call
-//   key[2][cap]      u32 sort key  q << 23 | k1       (double buffer)
-//   val[2][cap]      u64 payload   k2 << 32 | index   (double buffer)
-//   hist[512 * G]    per-chunk digit counts of the region sort
-//   spa_part/cnt[4G] per-chunk SPA minima and survivor counts
-//   poly[cap + 4]    the simple polygon as (index, x, y) int32 triples
-// After the sort the data sits in buffer 1; the SPA survivors are written,
-// chunk-local, into buffer 0.
+//   points           caller's n x float32[2], read twice (k_extremes, k_classify)
+//   ExtPartial[G1]   per-workgroup extreme keys
+//   DevHeader        extreme points, quadrilateral edges, frames, counters
+//   ghist[1024]      digit counts of the three sort passes (256, 256, 512)
+//   key[2][cap]      u32 sort key  q << 23 | k1      (double buffer)
+//   val[2][cap]      u64 payload   k2 << 32 | index  (double buffer)
+//   look[...]        u64 look-back words of the sort passes and of SPA
+//   chain[cap]       SPA survivors that do not fit the pinned host buffer
 //
 // Regions follow the paper (R1 lower left, R2 lower right, R3 upper right,
 // R4 upper left); q = r - 1 is the region code in the sort key, so ascending
@@ -27,9 +37,10 @@
 //   R2: k1 = y,     k2 = M - x    first point P_miny
 //   R3: k1 = M - x, k2 = M - y    first point P_maxx
 //   R4: k1 = M - y, k2 = x        first point P_maxy
-// with M = 2^23 - 1.
+// with M = 2^23 - 1 (so M - v == v ^ M for 0 <= v <= M).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdint>
 #include <cstring>
@@ -43,42 +54,56 @@
 
 namespace chainhull {
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+typedef long long i64;
+
 constexpr uint32_t kM = (1u << 23) - 1;
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kExtBlocks = 2048;   // workgroups of the extreme-point pass
+constexpr int kExtBlocks = 1024;   // workgroups of the extreme-point pass
 constexpr int kExtUnroll = 4;      // float4 loads in flight per thread
 constexpr int kTilePts = 4096;     // points per classify workgroup
 constexpr int kPtsPerThread = kTilePts / kBlock;  // 16
 constexpr int kSlotBits = 9;
 constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region and tile
-constexpr int kSortBlocks = 512;   // chunks of the region sort and of SPA
-constexpr int kSortIpt = 8;        // records per thread per sort sub-tile
-constexpr int kSortTile = kBlock * kSortIpt;
-constexpr int kMaxBins = 512;
+constexpr int kSortIpt = 8;                       // records per thread per sort tile
+constexpr int kSortTile = kBlock * kSortIpt;      // 2048
+constexpr int kSortGrid = 512;                    // persistent workgroups per pass
+constexpr int kPassBins = 256 + 256 + 512;        // digits of the three passes
 constexpr int kSpaIpt = 4;
-constexpr int kSpaTile = kBlock * kSpaIpt;
+constexpr int kSpaTile = kBlock * kSpaIpt;        // 1024
+constexpr int kSpaGrid = 512;
+constexpr uint32_t kSpinMax = 1u << 22;           // bound on any look-back wait
 
-typedef float v2f __attribute__((ext_vector_type(2)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef unsigned long long u64;
+// Look-back words: flag in bits 63..62 (0 empty, 1 tile aggregate,
+// 2 inclusive prefix), value in bits 61..0.
+constexpr u64 kFlagAgg = 1ull << 62;
+constexpr u64 kFlagInc = 2ull << 62;
+constexpr u64 kValMask = (1ull << 62) - 1;
+
+constexpr uint32_t kErrDomain = 1;   // a coordinate is outside the domain
+constexpr uint32_t kErrSpin = 2;     // a look-back wait exceeded its bound
 
 struct DevHeader {
     double ec[4];        // ex*E_q.y - ey*E_q.x for the edge E_q -> E_{q+1}
     int32_t ex[4], ey[4];
     uint32_t ext_x[4], ext_y[4], ext_idx[4];  // P_minx, P_miny, P_maxx, P_maxy
-    uint32_t k1lo[4], k1shift[4], sigma[4];   // per-region frame data
-    uint32_t err;        // nonzero: a coordinate is outside the domain
+    uint32_t sigma[4];   // k2 of each region's first point
+    uint32_t err;
     uint32_t s1[4];      // round-1 survivors per region
     uint32_t cand;       // records written by the tile filter
     uint32_t s2[4];      // SPA survivors per region
-    uint32_t poly;       // polygon vertices, the four extreme points included
-    uint32_t pad[7];
+    uint32_t chain;      // SPA survivors in all
+    uint32_t ext_ticket; // workgroups of k_extremes done
+    uint32_t ticket[4];  // tile tickets: three sort passes and SPA
+    uint32_t pad[3];
 };
 
 struct ExtPartial {
-    u64 key[4];
-    uint32_t idx[4];
+    i64 kmin[2], kmax[2];      // key 0 = (x, M - y), key 1 = (y, x)
+    uint32_t imin[2], imax[2];
     uint32_t err;
     uint32_t pad[3];
 };
@@ -87,22 +112,21 @@ struct PolyRec {
     int32_t idx, x, y;
 };
 
+// Look-back areas of one call.  Their sizes follow the capacity; the tiles a
+// call uses are a prefix of each.
+struct LookAreas {
+    u64* pass[3];
+    u64* spa_min;
+    u64* spa_cnt;
+};
+
 // ---------------------------------------------------------------------------
 // Wave and workgroup helpers (wave64)
 // ---------------------------------------------------------------------------
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
-__device__ inline uint32_t sel4(uint32_t q, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3)
-{
-    return q == 0 ? a0 : q == 1 ? a1 : q == 2 ? a2 : a3;
-}
-
-// Region frame: (k1, k2) of integer point (X, Y) in region q.
-__device__ inline uint32_t frame_k1(uint32_t q, uint32_t X, uint32_t Y) { return sel4(q, X, Y, kM - X, kM - Y); }
-__device__ inline uint32_t frame_k2(uint32_t q, uint32_t X, uint32_t Y) { return sel4(q, Y, kM - X, kM - Y, X); }
-
-__device__ inline void lexmin_pair(u64& k, uint32_t& i, u64 ok, uint32_t oi)
+__device__ inline void take_min(i64& k, uint32_t& i, i64 ok, uint32_t oi)
 {
     if (ok < k || (ok == k && oi < i)) {
         k = ok;
@@ -110,13 +134,11 @@ __device__ inline void lexmin_pair(u64& k, uint32_t& i, u64 ok, uint32_t oi)
     }
 }
 
-__device__ inline void wave_lexmin(u64& k, uint32_t& i)
+__device__ inline void take_max(i64& k, uint32_t& i, i64 ok, uint32_t oi)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const u64 ok = __shfl_xor(k, off);
-        const uint32_t oi = __shfl_xor(i, off);
-        lexmin_pair(k, i, ok, oi);
+    if (ok > k || (ok == k && oi < i)) {
+        k = ok;
+        i = oi;
     }
 }
 
@@ -124,13 +146,6 @@ __device__ inline uint32_t wave_sum(uint32_t v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-__device__ inline uint32_t wave_min(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off));
     return v;
 }
 
@@ -196,89 +211,140 @@ __device__ inline uint32_t block_excl_min(uint32_t v, uint32_t* scratch, uint32_
     return min(before, excl);
 }
 
-__device__ inline void chunk_range(uint32_t count, uint32_t b, uint32_t nb, uint32_t& lo, uint32_t& hi)
+__device__ inline u64 look_load(const u64* p)
 {
-    const uint32_t per = (count + nb - 1) / nb;
-    lo = min(count, b * per);
-    hi = min(count, lo + per);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void look_store(u64* p, u64 v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back: combine the values published by tiles t-1, t-2, ...
+// until an inclusive prefix is found.  Every earlier tile holds its ticket
+// in a running workgroup and publishes its aggregate before it waits on
+// anything, so the wait ends; the bound only guards against a broken
+// invariant (it then flags kErrSpin instead of hanging).
+template <bool kMin>
+__device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, uint32_t* err)
+{
+    u64 acc = kMin ? kValMask : 0ull;
+    uint32_t spins = 0;
+    int64_t j = (int64_t)t - 1;
+    while (j >= 0) {
+        const u64 w = look_load(words + (u64)j * stride);
+        const u64 f = w & ~kValMask;
+        if (f == 0) {
+            if (++spins > kSpinMax) {
+                atomicOr(err, kErrSpin);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        const u64 v = w & kValMask;
+        acc = kMin ? (v < acc ? v : acc) : acc + v;
+        if (f == kFlagInc) break;
+        --j;
+    }
+    return acc;
 }
 
 // ---------------------------------------------------------------------------
 // Step 1 (Section 2.1 step 1; Section 2.2.1): the four extreme points by a
-// parallel reduction, fused with domain validation.  Each extreme minimises
-// a 46-bit lexicographic key, then the point index:
-//   P_minx  (x, M - y)      P_miny  (y, x)
-//   P_maxx  (M - x, y)      P_maxy  (M - y, M - x)
+// parallel reduction, fused with domain validation.  Two lexicographic keys
+// serve all four: K0 = (x, M - y) has its minimum at P_minx (min x, then max
+// y) and its maximum at P_maxx (max x, then min y); K1 = (y, x) has its
+// minimum at P_miny and its maximum at P_maxy.  Ties go to the smallest index.
 // ---------------------------------------------------------------------------
 
-__device__ inline bool coord_ok(float v) { return v >= 0.0f && v < 8388608.0f && truncf(v) == v; }
-
 struct ExtAcc {
-    u64 k[4];
-    uint32_t i[4];
-    uint32_t bad;
+    i64 kmin[2], kmax[2];
+    uint32_t imin[2], imax[2];
+    uint32_t bad, hi;
 };
 
 __device__ inline void ext_init(ExtAcc& a)
 {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        a.k[e] = ~0ull;
-        a.i[e] = ~0u;
+    for (int e = 0; e < 2; ++e) {
+        a.kmin[e] = (i64)kValMask;
+        a.kmax[e] = -1;
+        a.imin[e] = ~0u;
+        a.imax[e] = ~0u;
     }
     a.bad = 0;
+    a.hi = 0;
 }
 
-// A thread visits its points in increasing index order, so on equal keys the
-// first point seen (the smallest index) stays.
+// Integer value of a coordinate clamped to [0, 2^24]; NaN gives 0.
+__device__ inline uint32_t coord_u32(float v) { return (uint32_t)fminf(fmaxf(v, 0.0f), 16777216.0f); }
+
+// A thread visits its points in increasing index order, so strict
+// comparisons keep the smallest index among equal keys.
 __device__ inline void ext_visit(ExtAcc& a, float fx, float fy, uint32_t idx)
 {
-    const bool ok = coord_ok(fx) && coord_ok(fy);
-    a.bad |= ok ? 0u : 1u;
-    const uint32_t X = ok ? (uint32_t)fx : 0u;
-    const uint32_t Y = ok ? (uint32_t)fy : 0u;
-    const u64 k0 = ((u64)X << 23) | (kM - Y);
-    const u64 k1 = ((u64)Y << 23) | X;
-    const u64 k2 = ((u64)(kM - X) << 23) | Y;
-    const u64 k3 = ((u64)(kM - Y) << 23) | (kM - X);
-    if (k0 < a.k[0]) { a.k[0] = k0; a.i[0] = idx; }
-    if (k1 < a.k[1]) { a.k[1] = k1; a.i[1] = idx; }
-    if (k2 < a.k[2]) { a.k[2] = k2; a.i[2] = idx; }
-    if (k3 < a.k[3]) { a.k[3] = k3; a.i[3] = idx; }
+    const uint32_t X = coord_u32(fx), Y = coord_u32(fy);
+    // integer-valued and finite; the range is checked on the maximum
+    a.bad |= ((float)X != fx) | ((float)Y != fy);
+    a.hi = max(a.hi, max(X, Y));
+    const i64 k0 = ((i64)X << 23) | (i64)(Y ^ kM);
+    const i64 k1 = ((i64)Y << 23) | (i64)X;
+    if (k0 < a.kmin[0]) { a.kmin[0] = k0; a.imin[0] = idx; }
+    if (k0 > a.kmax[0]) { a.kmax[0] = k0; a.imax[0] = idx; }
+    if (k1 < a.kmin[1]) { a.kmin[1] = k1; a.imin[1] = idx; }
+    if (k1 > a.kmax[1]) { a.kmax[1] = k1; a.imax[1] = idx; }
 }
 
-__device__ inline void ext_block_reduce(ExtAcc& a, u64 (*sk)[4], uint32_t (*si)[4], uint32_t* sbad)
+__device__ inline void ext_combine(ExtAcc& a, const ExtAcc& b)
 {
-    const uint32_t wave = threadIdx.x / 64;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) wave_lexmin(a.k[e], a.i[e]);
-    const uint32_t bad = __ballot(a.bad) != 0ull ? 1u : 0u;
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sk[wave][e] = a.k[e];
-            si[wave][e] = a.i[e];
-        }
-        sbad[wave] = bad;
+    for (int e = 0; e < 2; ++e) {
+        take_min(a.kmin[e], a.imin[e], b.kmin[e], b.imin[e]);
+        take_max(a.kmax[e], a.imax[e], b.kmax[e], b.imax[e]);
     }
+    a.bad |= b.bad;
+    a.hi = max(a.hi, b.hi);
+}
+
+__device__ inline void ext_wave_reduce(ExtAcc& a)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ExtAcc b;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            b.kmin[e] = __shfl_xor(a.kmin[e], off);
+            b.kmax[e] = __shfl_xor(a.kmax[e], off);
+            b.imin[e] = __shfl_xor(a.imin[e], off);
+            b.imax[e] = __shfl_xor(a.imax[e], off);
+        }
+        b.bad = __shfl_xor(a.bad, off);
+        b.hi = __shfl_xor(a.hi, off);
+        ext_combine(a, b);
+    }
+}
+
+// Reduce over the workgroup; thread 0 gets the result.
+__device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
+{
+    ext_wave_reduce(a);
+    if (lane_id() == 0) sh[threadIdx.x / 64] = a;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int e = 0; e < 4; ++e) {
-            for (int w = 1; w < kWaves; ++w) lexmin_pair(sk[0][e], si[0][e], sk[w][e], si[w][e]);
-        }
-        for (int w = 1; w < kWaves; ++w) sbad[0] |= sbad[w];
+        for (int w = 1; w < kWaves; ++w) ext_combine(a, sh[w]);
     }
-    __syncthreads();
 }
 
 // `head` leading points (0 or 1) are visited singly so that the rest of the
 // array is 16-byte aligned for float4 loads; an odd last point likewise.
 __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ pts, uint32_t n, uint32_t head,
-                                                     ExtPartial* __restrict__ part)
+                                                     ExtPartial* __restrict__ part, DevHeader* __restrict__ hdr,
+                                                     uint32_t* __restrict__ ghist)
 {
-    __shared__ u64 sk[kWaves][4];
-    __shared__ uint32_t si[kWaves][4];
-    __shared__ uint32_t sbad[kWaves];
+    __shared__ ExtAcc sh[kWaves];
+    __shared__ uint32_t s_last;
     ExtAcc a;
     ext_init(a);
     const uint32_t tid = threadIdx.x;
@@ -307,72 +373,82 @@ __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ p
     }
     if (blockIdx.x == 0 && tid == 1 && ((n - head) & 1u)) ext_visit(a, pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1);
 
-    ext_block_reduce(a, sk, si, sbad);
-    if (tid < 4) {
-        part[blockIdx.x].key[tid] = sk[0][tid];
-        part[blockIdx.x].idx[tid] = si[0][tid];
+    ext_block_reduce(a, sh);
+    if (tid == 0) {
+        ExtPartial p;
+        for (int e = 0; e < 2; ++e) {
+            p.kmin[e] = a.kmin[e];
+            p.kmax[e] = a.kmax[e];
+            p.imin[e] = a.imin[e];
+            p.imax[e] = a.imax[e];
+        }
+        p.err = (a.bad || a.hi > kM) ? 1u : 0u;
+        part[blockIdx.x] = p;
+        // publish the partial, then take a ticket; the last workgroup reduces
+        __threadfence();
+        s_last = atomicAdd(&hdr->ext_ticket, 1u) == gridDim.x - 1;
     }
-    if (tid == 0) part[blockIdx.x].err = sbad[0];
-}
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
 
-// One workgroup: reduce the partials, derive the quadrilateral's edges and the
-// region frames, and zero the call's counters.
-__global__ __launch_bounds__(kBlock) void k_extremes_final(const ExtPartial* __restrict__ part, int nparts,
-                                                           DevHeader* __restrict__ hdr)
-{
-    __shared__ u64 sk[kWaves][4];
-    __shared__ uint32_t si[kWaves][4];
-    __shared__ uint32_t sbad[kWaves];
-    ExtAcc a;
-    ext_init(a);
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) lexmin_pair(a.k[e], a.i[e], part[b].key[e], part[b].idx[e]);
-        a.bad |= part[b].err;
+    ExtAcc r;
+    ext_init(r);
+    for (uint32_t b = tid; b < gridDim.x; b += kBlock) {
+        const ExtPartial p = part[b];
+        ExtAcc o;
+        for (int e = 0; e < 2; ++e) {
+            o.kmin[e] = p.kmin[e];
+            o.kmax[e] = p.kmax[e];
+            o.imin[e] = p.imin[e];
+            o.imax[e] = p.imax[e];
+        }
+        o.bad = p.err;
+        o.hi = 0;
+        ext_combine(r, o);
     }
-    ext_block_reduce(a, sk, si, sbad);
-    if (threadIdx.x != 0) return;
+    // zero the sort's digit counts for this call
+    for (uint32_t d = tid; d < kPassBins; d += kBlock) ghist[d] = 0;
+    __syncthreads();
+    ext_block_reduce(r, sh);
+    if (tid != 0) return;
 
+    // P_minx, P_miny, P_maxx, P_maxy
+    const i64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
+    const uint32_t idx[4] = {r.imin[0], r.imin[1], r.imax[0], r.imax[1]};
     uint32_t X[4], Y[4];
-    const u64* k = sk[0];
-    X[0] = (uint32_t)(k[0] >> 23);      Y[0] = kM - (uint32_t)(k[0] & kM);  // P_minx
-    Y[1] = (uint32_t)(k[1] >> 23);      X[1] = (uint32_t)(k[1] & kM);       // P_miny
-    X[2] = kM - (uint32_t)(k[2] >> 23); Y[2] = (uint32_t)(k[2] & kM);       // P_maxx
-    Y[3] = kM - (uint32_t)(k[3] >> 23); X[3] = kM - (uint32_t)(k[3] & kM);  // P_maxy
+    X[0] = (uint32_t)(key[0] >> 23); Y[0] = (uint32_t)(key[0] & kM) ^ kM;
+    Y[1] = (uint32_t)(key[1] >> 23); X[1] = (uint32_t)(key[1] & kM);
+    X[2] = (uint32_t)(key[2] >> 23); Y[2] = (uint32_t)(key[2] & kM) ^ kM;
+    Y[3] = (uint32_t)(key[3] >> 23); X[3] = (uint32_t)(key[3] & kM);
     for (int e = 0; e < 4; ++e) {
         hdr->ext_x[e] = X[e];
         hdr->ext_y[e] = Y[e];
-        hdr->ext_idx[e] = si[0][e];
+        hdr->ext_idx[e] = idx[e];
     }
     // Edge q runs from E_q to E_{q+1}, E = (P_minx, P_miny, P_maxx, P_maxy);
     // region q is strictly right of it: ex*(y - E_q.y) - ey*(x - E_q.x) < 0.
     for (int q = 0; q < 4; ++q) {
-        const int r = (q + 1) & 3;
-        const int32_t ex = (int32_t)X[r] - (int32_t)X[q];
-        const int32_t ey = (int32_t)Y[r] - (int32_t)Y[q];
+        const int s = (q + 1) & 3;
+        const int32_t ex = (int32_t)X[s] - (int32_t)X[q];
+        const int32_t ey = (int32_t)Y[s] - (int32_t)Y[q];
         hdr->ex[q] = ex;
         hdr->ey[q] = ey;
         hdr->ec[q] = (double)ex * (double)Y[q] - (double)ey * (double)X[q];
     }
-    // Frames: the k1 range of each region and its first point's k2 (sigma).
-    uint32_t lo[4], hi[4], sig[4];
-    lo[0] = X[0];      hi[0] = X[1];      sig[0] = Y[0];       // R1: P_minx .. P_miny
-    lo[1] = Y[1];      hi[1] = Y[2];      sig[1] = kM - X[1];  // R2: P_miny .. P_maxx
-    lo[2] = kM - X[2]; hi[2] = kM - X[3]; sig[2] = kM - Y[2];  // R3: P_maxx .. P_maxy
-    lo[3] = kM - Y[3]; hi[3] = kM - Y[0]; sig[3] = X[3];       // R4: P_maxy .. P_minx
+    hdr->sigma[0] = Y[0];        // R1 starts at P_minx
+    hdr->sigma[1] = X[1] ^ kM;   // R2 starts at P_miny
+    hdr->sigma[2] = Y[2] ^ kM;   // R3 starts at P_maxx
+    hdr->sigma[3] = X[3];        // R4 starts at P_maxy
     for (int q = 0; q < 4; ++q) {
-        const uint32_t span = hi[q] >= lo[q] ? hi[q] - lo[q] : 0u;
-        uint32_t sh = 0;
-        while ((span >> sh) >= (uint32_t)kSlots) ++sh;
-        hdr->k1lo[q] = lo[q];
-        hdr->k1shift[q] = sh;
-        hdr->sigma[q] = sig[q];
         hdr->s1[q] = 0;
         hdr->s2[q] = 0;
+        hdr->ticket[q] = 0;
     }
     hdr->cand = 0;
-    hdr->poly = 0;
-    hdr->err = sbad[0];
+    hdr->chain = 0;
+    hdr->err = r.bad ? kErrDomain : 0u;
+    hdr->ext_ticket = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(const ExtPartial* __r
 // whole set, so dropping tile-dominated points leaves the result of the
 // region sort and SPA unchanged.
 //
-// Per tile and region, k1 is cut into kSlots slots.  A point is dropped when
+// Per tile and region, k1 is cut into kSlots slots of 2^14 values.  A point
+// is dropped when
 //   * the region's first point or a point of an earlier slot has k2 <= its k2,
 //   * the slot's smallest-(k2, k1) point precedes it with k1 <= its k1, or
 //   * it repeats that point's coordinates with a larger index.
@@ -398,9 +475,9 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
                                                      DevHeader* __restrict__ hdr, uint32_t* __restrict__ out_key,
                                                      u64* __restrict__ out_val)
 {
-    __shared__ u64 smin[4][kSlots];
-    __shared__ uint32_t sidx[4][kSlots];
-    __shared__ uint32_t sexc[4][kSlots];
+    __shared__ u64 smin[4 * kSlots];
+    __shared__ uint32_t sidx[4 * kSlots];
+    __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
     __shared__ uint32_t s1cnt[kWaves][4];
     __shared__ uint32_t sbase;
@@ -413,16 +490,10 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
     const double ec0 = hdr->ec[0], ec1 = hdr->ec[1], ec2 = hdr->ec[2], ec3 = hdr->ec[3];
     const double ex0 = hdr->ex[0], ex1 = hdr->ex[1], ex2 = hdr->ex[2], ex3 = hdr->ex[3];
     const double ey0 = hdr->ey[0], ey1 = hdr->ey[1], ey2 = hdr->ey[2], ey3 = hdr->ey[3];
-    const uint32_t lo0 = hdr->k1lo[0], lo1 = hdr->k1lo[1], lo2 = hdr->k1lo[2], lo3 = hdr->k1lo[3];
-    const uint32_t sh0 = hdr->k1shift[0], sh1 = hdr->k1shift[1], sh2 = hdr->k1shift[2], sh3 = hdr->k1shift[3];
-    auto slot_of = [&](uint32_t q, uint32_t k1) -> uint32_t {
-        const uint32_t d = (k1 - sel4(q, lo0, lo1, lo2, lo3)) >> sel4(q, sh0, sh1, sh2, sh3);
-        return min(d, (uint32_t)(kSlots - 1));
-    };
 
     for (int s = tid; s < 4 * kSlots; s += kBlock) {
-        (&smin[0][0])[s] = ~0ull;
-        (&sidx[0][0])[s] = ~0u;
+        smin[s] = ~0ull;
+        sidx[s] = ~0u;
     }
 
     // Point j of this thread: with float4 loads it is tile + 2*(k*256+tid) + h
@@ -463,33 +534,39 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
 
     __syncthreads();
 
-    // Phase 1: region of every point and the per-slot minimum of (k2, k1).
-    u64 reg = 0;  // 3 bits per point: region code, 4 = interior
-    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    // Phase 1: region of every point, its frame, and the per-slot minimum of
+    // (k2, k1).  me = k2 << 23 | k1; addr = q * kSlots + slot, or ~0u.
+    u64 me[kPtsPerThread];
+    uint32_t addr[kPtsPerThread];
+    uint32_t counts = 0;  // 8-bit count per region
+    const bool full_tile = tile + kTilePts <= n;
 #pragma unroll
     for (int j = 0; j < kPtsPerThread; ++j) {
-        uint32_t q = 4;
-        if (index_of(j) < n) {
-            const double fx = (double)px[j], fy = (double)py[j];
-            // exact: every product is below 2^46 and every sum below 2^47
-            if (fma(ex3, fy, -(ey3 * fx)) < ec3) q = 3;
-            if (fma(ex2, fy, -(ey2 * fx)) < ec2) q = 2;
-            if (fma(ex1, fy, -(ey1 * fx)) < ec1) q = 1;
-            if (fma(ex0, fy, -(ey0 * fx)) < ec0) q = 0;
-        }
-        reg |= (u64)q << (3 * j);
-        c0 += q == 0;
-        c1 += q == 1;
-        c2 += q == 2;
-        c3 += q == 3;
-        if (q < 4) {
+        const double fx = (double)px[j], fy = (double)py[j];
+        // exact: every product is below 2^46 and every sum below 2^47
+        const bool t0 = fma(ex0, fy, -(ey0 * fx)) < ec0;
+        const bool t1 = fma(ex1, fy, -(ey1 * fx)) < ec1;
+        const bool t2 = fma(ex2, fy, -(ey2 * fx)) < ec2;
+        const bool t3 = fma(ex3, fy, -(ey3 * fx)) < ec3;
+        uint32_t q = t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
+        if (!full_tile && index_of(j) >= n) q = 4u;
+        me[j] = 0;
+        addr[j] = ~0u;
+        if (q < 4) {  // a wave with no survivor skips this
             const uint32_t X = (uint32_t)px[j], Y = (uint32_t)py[j];
-            const uint32_t k1 = frame_k1(q, X, Y), k2 = frame_k2(q, X, Y);
-            atomicMin(&smin[q][slot_of(q, k1)], ((u64)k2 << 23) | k1);
+            const uint32_t a = (q & 1u) ? Y : X;
+            const uint32_t b = (q & 1u) ? X : Y;
+            const uint32_t k1 = (q & 2u) ? a ^ kM : a;
+            const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+            me[j] = ((u64)(k2 >> 9) << 32) | ((k2 << 23) | k1);
+            addr[j] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
+            counts += 1u << (8 * q);
+            atomicMin(&smin[addr[j]], me[j]);
         }
     }
     {
-        const uint32_t w0 = wave_sum(c0), w1 = wave_sum(c1), w2 = wave_sum(c2), w3 = wave_sum(c3);
+        const uint32_t w0 = wave_sum(counts & 0xff), w1 = wave_sum((counts >> 8) & 0xff);
+        const uint32_t w2 = wave_sum((counts >> 16) & 0xff), w3 = wave_sum(counts >> 24);
         if (lane_id() == 0) {
             s1cnt[wave][0] = w0;
             s1cnt[wave][1] = w1;
@@ -499,8 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
     }
     __syncthreads();
 
-    // Phase 2: wave w scans region w's slots; sexc[w][s] becomes the smallest
-    // k2 over earlier slots and the region's first point.
+    // Phase 2: wave w scans region w's slots; sexc becomes the smallest k2
+    // over earlier slots and the region's first point.
     {
         const uint32_t q = wave;
         const uint32_t sigma = hdr->sigma[q];
@@ -509,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
         uint32_t run = ~0u;
 #pragma unroll
         for (int s = 0; s < per; ++s) {
-            const u64 m = smin[q][lane_id() * per + s];
+            const u64 m = smin[(q << kSlotBits) + lane_id() * per + s];
             v[s] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
             run = min(run, v[s]);
         }
@@ -519,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
         before = min(before, sigma);
 #pragma unroll
         for (int s = 0; s < per; ++s) {
-            sexc[q][lane_id() * per + s] = before;
+            sexc[(q << kSlotBits) + lane_id() * per + s] = before;
             before = min(before, v[s]);
         }
     }
@@ -534,17 +611,13 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
     uint32_t keep = 0, dupc = 0;
 #pragma unroll
     for (int j = 0; j < kPtsPerThread; ++j) {
-        const uint32_t q = (uint32_t)(reg >> (3 * j)) & 7u;
-        if (q < 4) {
-            const uint32_t X = (uint32_t)px[j], Y = (uint32_t)py[j];
-            const uint32_t k1 = frame_k1(q, X, Y), k2 = frame_k2(q, X, Y);
-            const uint32_t slot = slot_of(q, k1);
-            const u64 me = ((u64)k2 << 23) | k1;
-            const u64 best = smin[q][slot];
-            bool k = k2 < sexc[q][slot];
-            if (k && best < me && (uint32_t)(best & kM) <= k1) k = false;
-            if (k && best == me) {
-                atomicMin(&sidx[q][slot], index_of(j));
+        if (addr[j] != ~0u) {
+            const u64 best = smin[addr[j]];
+            const uint32_t k1 = (uint32_t)me[j] & kM, k2 = (uint32_t)(me[j] >> 23);
+            bool k = k2 < sexc[addr[j]];
+            k = k && !(best < me[j] && (uint32_t)(best & kM) <= k1);
+            if (k && best == me[j]) {
+                atomicMin(&sidx[addr[j]], index_of(j));
                 dupc |= 1u << j;
             }
             keep |= (k ? 1u : 0u) << j;
@@ -553,11 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kPtsPerThread; ++j) {
-        if ((dupc >> j) & 1u) {
-            const uint32_t q = (uint32_t)(reg >> (3 * j)) & 7u;
-            const uint32_t X = (uint32_t)px[j], Y = (uint32_t)py[j];
-            if (sidx[q][slot_of(q, frame_k1(q, X, Y))] != index_of(j)) keep &= ~(1u << j);
-        }
+        if (((dupc >> j) & 1u) && sidx[addr[j]] != index_of(j)) keep &= ~(1u << j);
     }
 
     // Phase 4: compact the tile's kept records (one global atomic per tile).
@@ -569,95 +638,124 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
 #pragma unroll
     for (int j = 0; j < kPtsPerThread; ++j) {
         if ((keep >> j) & 1u) {
-            const uint32_t q = (uint32_t)(reg >> (3 * j)) & 7u;
-            const uint32_t X = (uint32_t)px[j], Y = (uint32_t)py[j];
-            out_key[pos] = (q << 23) | frame_k1(q, X, Y);
-            out_val[pos] = ((u64)frame_k2(q, X, Y) << 32) | index_of(j);
+            const uint32_t q = addr[j] >> kSlotBits;
+            out_key[pos] = (q << 23) | ((uint32_t)me[j] & kM);
+            out_val[pos] = ((me[j] >> 23) << 32) | index_of(j);
             ++pos;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Steps 3-4 (Section 2.1; Table 1): sort the surviving records of all four
-// regions at once by the 25-bit key q << 23 | k1, least significant digit
-// first (8, 8, 9 bits), stably, so each region lands contiguously and in
-// Table 1's order.  A pass = per-chunk digit counts, one scan over all
-// counts, then a stable scatter whose in-wave ranks come from ballot
-// matching.  The record count lives in device memory; kSortBlocks chunks
-// split it.
+// Steps 3-4 (Section 2.1; Table 1): sort the records of all four regions at
+// once by the 25-bit key q << 23 | k1, least significant digit first
+// (8, 8, 9 bits), stably, so each region lands contiguously in Table 1's
+// order.  k_sort_prep counts the digits of all passes at once; each pass is
+// one kernel whose tiles (taken in ticket order) rank their records in
+// registers by ballot matching and find their output offsets by decoupled
+// look-back over the tiles before them.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint32_t* __restrict__ key,
-                                                      const DevHeader* __restrict__ hdr, int shift, int bits,
-                                                      uint32_t* __restrict__ hist)
-{
-    __shared__ uint32_t h[kMaxBins];
-    const uint32_t bins = 1u << bits, mask = bins - 1;
-    for (uint32_t d = threadIdx.x; d < bins; d += kBlock) h[d] = 0;
-    __syncthreads();
-    uint32_t lo, hi;
-    chunk_range(hdr->err ? 0u : hdr->cand, blockIdx.x, gridDim.x, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&h[(key[i] >> shift) & mask], 1u);
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < bins; d += kBlock) hist[d * gridDim.x + blockIdx.x] = h[d];
-}
+__device__ inline uint32_t sort_tiles(uint32_t count) { return (count + kSortTile - 1) / kSortTile; }
+__device__ inline uint32_t spa_tiles(uint32_t count) { return (count + kSpaTile - 1) / kSpaTile; }
 
-// One workgroup of 1024 threads: exclusive prefix sum of `len` counts in
-// place (digit-major, so the result is each chunk's first slot per digit).
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, uint32_t len)
+__global__ __launch_bounds__(kBlock) void k_sort_prep(const uint32_t* __restrict__ key,
+                                                      const DevHeader* __restrict__ hdr, uint32_t* __restrict__ ghist,
+                                                      LookAreas look)
 {
-    __shared__ uint32_t wsum[16];
-    const uint32_t tid = threadIdx.x, per = (len + 1023) / 1024;
-    const uint32_t lo = min(len, tid * per), hi = min(len, lo + per);
-    uint32_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i) s += hist[i];
-    const uint32_t incl = wave_incl_sum(s);
-    if (lane_id() == 63) wsum[tid / 64] = incl;
+    __shared__ uint32_t h[kPassBins];
+    for (int d = threadIdx.x; d < kPassBins; d += kBlock) h[d] = 0;
     __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t w = 0; w < tid / 64; ++w) before += wsum[w];
-    uint32_t run = before + incl - s;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t c = hist[i];
-        hist[i] = run;
-        run += c;
+    const uint32_t count = hdr->err ? 0u : hdr->cand;
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t first = blockIdx.x * kBlock + threadIdx.x;
+    for (uint32_t i = first; i < count; i += stride) {
+        const uint32_t k = key[i];
+        atomicAdd(&h[k & 255u], 1u);
+        atomicAdd(&h[256 + ((k >> 8) & 255u)], 1u);
+        atomicAdd(&h[512 + ((k >> 16) & 511u)], 1u);
+    }
+    // clear the look-back words this call will use
+    const uint32_t st = sort_tiles(count), sp = spa_tiles(count);
+    for (uint32_t w = first; w < st * 256; w += stride) {
+        look.pass[0][w] = 0;
+        look.pass[1][w] = 0;
+    }
+    for (uint32_t w = first; w < st * 512; w += stride) look.pass[2][w] = 0;
+    for (uint32_t w = first; w < sp; w += stride) {
+        look.spa_min[w] = 0;
+        look.spa_cnt[w] = 0;
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kPassBins; d += kBlock) {
+        if (h[d]) atomicAdd(&ghist[d], h[d]);
     }
 }
 
 template <int kBits>
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t* __restrict__ key_in,
-                                                         const u64* __restrict__ val_in,
-                                                         uint32_t* __restrict__ key_out, u64* __restrict__ val_out,
-                                                         const DevHeader* __restrict__ hdr, int shift,
-                                                         const uint32_t* __restrict__ offs)
+__global__ __launch_bounds__(kBlock) void k_sort_pass(const uint32_t* __restrict__ key_in,
+                                                      const u64* __restrict__ val_in, uint32_t* __restrict__ key_out,
+                                                      u64* __restrict__ val_out, DevHeader* __restrict__ hdr,
+                                                      int shift, const uint32_t* __restrict__ ghist_pass,
+                                                      u64* __restrict__ look_pass, uint32_t* __restrict__ ticket)
 {
     constexpr uint32_t kBins = 1u << kBits, kMask = kBins - 1;
-    __shared__ uint32_t cursor[kBins];
+    constexpr uint32_t kPer = kBins / kBlock;  // digits per thread (1 or 2)
+    __shared__ uint32_t base[kBins];
     __shared__ uint32_t wcnt[kWaves][kBins];
+    __shared__ uint32_t excl[kBins];
+    __shared__ uint32_t scratch[kWaves];
+    __shared__ uint32_t s_tile;
+
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    for (uint32_t d = tid; d < kBins; d += kBlock) {
-        cursor[d] = offs[d * gridDim.x + blockIdx.x];
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
-    }
-    __syncthreads();
     const uint32_t count = hdr->err ? 0u : hdr->cand;
-    uint32_t lo, hi;
-    chunk_range(count, blockIdx.x, gridDim.x, lo, hi);
+    const uint32_t ntiles = sort_tiles(count);
+    if (ntiles == 0) return;
+
+    // base[d]: records with a smaller digit, over the whole array
+    {
+        uint32_t c[kPer], s = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kPer; ++p) {
+            c[p] = ghist_pass[tid * kPer + p];
+            s += c[p];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_sum(s, scratch, total);
+#pragma unroll
+        for (uint32_t p = 0; p < kPer; ++p) {
+            base[tid * kPer + p] = run;
+            run += c[p];
+        }
+    }
     const u64 lt = (1ull << lane) - 1ull;
-    for (uint32_t base = lo; base < hi; base += kSortTile) {
-        // Wave w owns records [base + w*64*IPT, +64*IPT); record j of lane l
-        // sits at +j*64 + l, so (j, l) is the order of the wave's records.
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+#pragma unroll
+        for (uint32_t p = 0; p < kPer; ++p) {
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) wcnt[w][tid * kPer + p] = 0;
+        }
+        __syncthreads();
+        const uint32_t t = s_tile;
+        if (t >= ntiles) break;
+
+        // Wave w holds records [t*TILE + w*64*IPT, +64*IPT); record j of lane
+        // l sits at +j*64 + l, so (w, j, l) is the records' order.
+        const uint32_t wbase = t * kSortTile + wave * 64 * kSortIpt;
         uint32_t k[kSortIpt], d[kSortIpt], r[kSortIpt];
         u64 v[kSortIpt];
-        const uint32_t wbase = base + wave * 64 * kSortIpt;
 #pragma unroll
         for (int j = 0; j < kSortIpt; ++j) {
             const uint32_t i = wbase + j * 64 + lane;
-            const bool ok = i < hi;
+            const bool ok = i < count;
             k[j] = ok ? key_in[i] : 0u;
             v[j] = ok ? val_in[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kSortIpt; ++j) {
+            const uint32_t i = wbase + j * 64 + lane;
+            const bool ok = i < count;
             d[j] = (k[j] >> shift) & kMask;
             u64 peers = __ballot(ok);
 #pragma unroll
@@ -671,245 +769,186 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t* __restr
             if (ok && below == 0) wcnt[wave][d[j]] = cur + (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        // wcnt[w][d] becomes the output slot of wave w's first digit-d record.
-        for (uint32_t dd = tid; dd < kBins; dd += kBlock) {
-            uint32_t run = cursor[dd];
+        // per digit: the tile's count, each wave's offset inside the tile, and
+        // the records of this digit in earlier tiles (decoupled look-back)
+        // (every aggregate of this thread is published before it waits)
+        uint32_t tcount[kPer];
+#pragma unroll
+        for (uint32_t p = 0; p < kPer; ++p) {
+            const uint32_t dd = tid * kPer + p;
+            uint32_t run = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
                 const uint32_t c = wcnt[w][dd];
                 wcnt[w][dd] = run;
                 run += c;
             }
-            cursor[dd] = run;
+            tcount[p] = run;
+            look_store(look_pass + (u64)t * kBins + dd, (t == 0 ? kFlagInc : kFlagAgg) | run);
+        }
+#pragma unroll
+        for (uint32_t p = 0; p < kPer; ++p) {
+            const uint32_t dd = tid * kPer + p;
+            if (t == 0) {
+                excl[dd] = 0;
+            } else {
+                const u64 before = look_back<false>(look_pass + dd, t, kBins, &hdr->err);
+                look_store(look_pass + (u64)t * kBins + dd, kFlagInc | (before + tcount[p]));
+                excl[dd] = (uint32_t)before;
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kSortIpt; ++j) {
             const uint32_t i = wbase + j * 64 + lane;
-            const uint32_t dst = wcnt[wave][d[j]] + r[j];
-            if (i < hi && dst < count) {
-                key_out[dst] = k[j];
-                val_out[dst] = v[j];
+            if (i < count) {
+                const uint32_t dst = base[d[j]] + excl[d[j]] + wcnt[wave][d[j]] + r[j];
+                if (dst < count) {
+                    key_out[dst] = k[j];
+                    val_out[dst] = v[j];
+                }
             }
         }
         __syncthreads();
-        for (uint32_t dd = tid; dd < kBins; dd += kBlock) {
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) wcnt[w][dd] = 0;
-        }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step 5 (Figure 2): SPA over the sorted records as a segmented exclusive
-// prefix minimum.  In each region a record is kept iff its k2 is below the
-// region's first point's k2 and below every earlier record's k2; Figure 2's
-// threshold t is exactly that running minimum, since a discarded record
-// never lowers it.  Records with equal key (q, k1) form a group; only the
-// group's smallest (k2, index) can survive, and it does so iff its k2 is
-// below the minimum over the records before the group.
+// Steps 5-6 (Figure 2; Section 2.2.2): SPA over the sorted records as a
+// segmented exclusive prefix minimum, and the chains written in order.
+//
+// In each region a record is kept iff its k2 is below the region's first
+// point's k2 and below every earlier record's k2: Figure 2's threshold t is
+// exactly that running minimum, since a discarded record never lowers it.
+// Records with equal (q, k1) form a group; only the group's smallest
+// (k2, index) can survive, and it does iff its k2 is below the minimum over
+// the records before the group.
 //
 // The prefix minimum runs over tagged values ((3 - q) << 23 | k2): records of
-// earlier regions carry larger tags, so a prefix minimum with this region's
-// tag is this region's running minimum.  Chunks get their seed from the
-// per-chunk minima of the chunks before them.
+// earlier regions carry larger tags, so a prefix minimum carrying this
+// region's tag is this region's running minimum.  Tiles find the minimum and
+// the survivor count of all earlier tiles by decoupled look-back.  Survivors
+// are written as (index, x, y) at their rank in the chain order: into the
+// pinned host buffer while the rank fits it, into device memory beyond.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_spa_part(const uint32_t* __restrict__ key, const u64* __restrict__ val,
-                                                     const DevHeader* __restrict__ hdr, uint32_t* __restrict__ part)
+__global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict__ key, const u64* __restrict__ val,
+                                                      DevHeader* __restrict__ hdr, u64* __restrict__ look_min,
+                                                      u64* __restrict__ look_cnt, uint32_t* __restrict__ ticket,
+                                                      PolyRec* __restrict__ host_chain, uint32_t host_cap,
+                                                      PolyRec* __restrict__ dev_chain)
 {
-    __shared__ uint32_t sm[kWaves][4];
-    uint32_t lo, hi;
-    chunk_range(hdr->err ? 0u : hdr->cand, blockIdx.x, gridDim.x, lo, hi);
-    uint32_t m0 = ~0u, m1 = ~0u, m2 = ~0u, m3 = ~0u;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const uint32_t q = key[i] >> 23, k2 = (uint32_t)(val[i] >> 32);
-        if (q == 0) m0 = min(m0, k2);
-        if (q == 1) m1 = min(m1, k2);
-        if (q == 2) m2 = min(m2, k2);
-        if (q == 3) m3 = min(m3, k2);
-    }
-    m0 = wave_min(m0);
-    m1 = wave_min(m1);
-    m2 = wave_min(m2);
-    m3 = wave_min(m3);
-    const uint32_t wave = threadIdx.x / 64;
-    if (lane_id() == 0) {
-        sm[wave][0] = m0;
-        sm[wave][1] = m1;
-        sm[wave][2] = m2;
-        sm[wave][3] = m3;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        uint32_t m = ~0u;
-        for (int w = 0; w < kWaves; ++w) m = min(m, sm[w][threadIdx.x]);
-        part[blockIdx.x * 4 + threadIdx.x] = m;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_spa_keep(const uint32_t* __restrict__ key, const u64* __restrict__ val,
-                                                     const DevHeader* __restrict__ hdr,
-                                                     const uint32_t* __restrict__ part, uint32_t* __restrict__ kept_key,
-                                                     u64* __restrict__ kept_val, uint32_t* __restrict__ cnt)
-{
-    __shared__ uint32_t seed[4];
-    __shared__ uint32_t red[kWaves][4];
     __shared__ uint32_t scratch[kWaves];
+    __shared__ uint32_t s_tile, s_min_before, s_cnt_before;
     __shared__ uint32_t kcnt[4];
-    const uint32_t tid = threadIdx.x, wave = tid / 64, b = blockIdx.x;
-    const uint32_t count = hdr->err ? 0u : hdr->cand;
+    __shared__ uint32_t sigma[4];
 
-    // Seed per region: the first point's k2 and the minima of earlier chunks.
-    {
-        uint32_t m[4] = {~0u, ~0u, ~0u, ~0u};
-        for (uint32_t c = tid; c < b; c += kBlock) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) m[q] = min(m[q], part[c * 4 + q]);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            m[q] = wave_min(m[q]);
-            if (lane_id() == 0) red[wave][q] = m[q];
-        }
+    const uint32_t tid = threadIdx.x;
+    const uint32_t count = hdr->err ? 0u : hdr->cand;
+    const uint32_t ntiles = spa_tiles(count);
+    if (ntiles == 0) return;
+    if (tid < 4) sigma[tid] = hdr->sigma[tid];
+
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(ticket, 1u);
         if (tid < 4) kcnt[tid] = 0;
         __syncthreads();
-        if (tid < 4) {
-            uint32_t s = hdr->sigma[tid];
-            for (int w = 0; w < kWaves; ++w) s = min(s, red[w][tid]);
-            seed[tid] = s;
-        }
-        __syncthreads();
-    }
+        const uint32_t t = s_tile;
+        if (t >= ntiles) break;
 
-    uint32_t lo, hi;
-    chunk_range(count, b, gridDim.x, lo, hi);
-    uint32_t carry = ~0u;   // tagged minimum over this chunk's earlier sub-tiles
-    uint32_t written = 0;   // survivors written so far by this chunk
-    for (uint32_t base = lo; base < hi; base += kSpaTile) {
-        // Thread t holds records base + t*IPT + j (consecutive per thread).
-        uint32_t kk[kSpaIpt], tag[kSpaIpt], pre[kSpaIpt];
+        // Thread tid holds records base + j (consecutive).
+        const uint32_t base = t * kSpaTile + tid * kSpaIpt;
+        uint32_t kk[kSpaIpt], pre[kSpaIpt];
         u64 vv[kSpaIpt];
         uint32_t run = ~0u;
 #pragma unroll
         for (int j = 0; j < kSpaIpt; ++j) {
-            const uint32_t i = base + tid * kSpaIpt + j;
-            const bool ok = i < hi;
+            const uint32_t i = base + j;
+            const bool ok = i < count;
             kk[j] = ok ? key[i] : 0u;
             vv[j] = ok ? val[i] : 0ull;
-            tag[j] = ok ? ((3u - (kk[j] >> 23)) << 23) | (uint32_t)(vv[j] >> 32) : ~0u;
+            const uint32_t tag = ok ? ((3u - (kk[j] >> 23)) << 23) | (uint32_t)(vv[j] >> 32) : ~0u;
             pre[j] = run;
-            run = min(run, tag[j]);
+            run = min(run, tag);
         }
         uint32_t tile_min;
-        const uint32_t before = min(carry, block_excl_min(run, scratch, tile_min));
+        const uint32_t before_in_tile = block_excl_min(run, scratch, tile_min);
+        if (tid == 0) {
+            u64* w = look_min + t;
+            if (t == 0) {
+                look_store(w, kFlagInc | tile_min);
+                s_min_before = ~0u;
+            } else {
+                look_store(w, kFlagAgg | tile_min);
+                const u64 b = look_back<true>(look_min, t, 1, &hdr->err);
+                const uint32_t bm = b >= 0xffffffffull ? ~0u : (uint32_t)b;
+                look_store(w, kFlagInc | min(bm, tile_min));
+                s_min_before = bm;
+            }
+        }
+        __syncthreads();
+        const uint32_t before = min(s_min_before, before_in_tile);
+
         uint32_t keep = 0;
         u64 gmin[kSpaIpt];
 #pragma unroll
         for (int j = 0; j < kSpaIpt; ++j) {
-            const uint32_t i = base + tid * kSpaIpt + j;
+            const uint32_t i = base + j;
             gmin[j] = vv[j];
-            if (i < hi) {
+            if (i < count) {
                 const uint32_t q = kk[j] >> 23;
                 const uint32_t pm = min(before, pre[j]);
-                uint32_t thr = seed[q];
+                uint32_t thr = sigma[q];
                 if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
-                const bool head = (i == 0) || key[i - 1] != kk[j];
-                if (head) {
+                const uint32_t prev = j > 0 ? kk[j > 0 ? j - 1 : 0] : (i > 0 ? key[i - 1] : ~0u);
+                if (prev != kk[j]) {
+                    // group head: the group's smallest (k2, index)
                     u64 g = vv[j];
-                    for (uint32_t m = i + 1; m < count && key[m] == kk[j]; ++m) g = min(g, val[m]);
+                    for (uint32_t m = i + 1; m < count && key[m] == kk[j]; ++m) {
+                        const u64 vm = val[m];
+                        g = vm < g ? vm : g;
+                    }
                     gmin[j] = g;
                     if ((uint32_t)(g >> 32) < thr) keep |= 1u << j;
                 }
             }
         }
-        uint32_t total;
-        uint32_t pos = block_excl_sum(__popc(keep), scratch, total);
+        uint32_t tile_kept;
+        uint32_t pos = block_excl_sum(__popc(keep), scratch, tile_kept);
+        if (tid == 0) {
+            u64* w = look_cnt + t;
+            if (t == 0) {
+                look_store(w, kFlagInc | tile_kept);
+                s_cnt_before = 0;
+            } else {
+                look_store(w, kFlagAgg | tile_kept);
+                const u64 b = look_back<false>(look_cnt, t, 1, &hdr->err);
+                look_store(w, kFlagInc | (b + tile_kept));
+                s_cnt_before = (uint32_t)b;
+            }
+            if (tile_kept) atomicAdd(&hdr->chain, tile_kept);
+        }
+        __syncthreads();
+        pos += s_cnt_before;
 #pragma unroll
         for (int j = 0; j < kSpaIpt; ++j) {
             if ((keep >> j) & 1u) {
-                kept_key[lo + written + pos] = kk[j];
-                kept_val[lo + written + pos] = gmin[j];
-                atomicAdd(&kcnt[kk[j] >> 23], 1u);
+                const uint32_t q = kk[j] >> 23, k1 = kk[j] & kM, k2 = (uint32_t)(gmin[j] >> 32);
+                // invert the frame: x = (k1, M-k2, M-k1, k2), y = (k2, k1, M-k2, M-k1)
+                const uint32_t a = (q & 1u) ? k2 : k1;
+                const uint32_t b = (q & 1u) ? k1 : k2;
+                const uint32_t X = ((q ^ (q >> 1)) & 1u) ? a ^ kM : a;
+                const uint32_t Y = (q & 2u) ? b ^ kM : b;
+                const PolyRec rec{(int32_t)(uint32_t)gmin[j], (int32_t)X, (int32_t)Y};
+                if (pos < host_cap) host_chain[pos] = rec;
+                else dev_chain[pos - host_cap] = rec;
+                atomicAdd(&kcnt[q], 1u);
                 ++pos;
             }
         }
-        written += total;
-        carry = min(carry, tile_min);
-    }
-    __syncthreads();
-    if (tid < 4) cnt[b * 4 + tid] = kcnt[tid];
-}
-
-// ---------------------------------------------------------------------------
-// Step 6 (Section 2.1; Section 2.2.2): join the chains into the simple polygon
-// [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] with coordinates rebuilt
-// from the frames.
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_chain(const uint32_t* __restrict__ kept_key,
-                                                  const u64* __restrict__ kept_val, const uint32_t* __restrict__ cnt,
-                                                  DevHeader* __restrict__ hdr, PolyRec* __restrict__ poly)
-{
-    __shared__ uint32_t tot[kWaves][4], pre[kWaves][4];
-    __shared__ uint32_t T[4], P[4], mine[4];
-    const uint32_t tid = threadIdx.x, wave = tid / 64, b = blockIdx.x, nb = gridDim.x;
-    {
-        uint32_t t[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0};
-        for (uint32_t c = tid; c < nb; c += kBlock) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t v = cnt[c * 4 + q];
-                t[q] += v;
-                p[q] += c < b ? v : 0u;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            t[q] = wave_sum(t[q]);
-            p[q] = wave_sum(p[q]);
-            if (lane_id() == 0) {
-                tot[wave][q] = t[q];
-                pre[wave][q] = p[q];
-            }
-        }
         __syncthreads();
-        if (tid < 4) {
-            uint32_t a = 0, c = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                a += tot[w][tid];
-                c += pre[w][tid];
-            }
-            T[tid] = a;
-            P[tid] = c;
-            mine[tid] = cnt[b * 4 + tid];
-        }
+        if (tid < 4 && kcnt[tid]) atomicAdd(&hdr->s2[tid], kcnt[tid]);
         __syncthreads();
-    }
-    const uint32_t count = hdr->err ? 0u : hdr->cand;
-    if (b == 0 && tid < 4) {
-        uint32_t at = tid;
-        for (uint32_t q = 0; q < tid; ++q) at += T[q];
-        poly[at] = PolyRec{(int32_t)hdr->ext_idx[tid], (int32_t)hdr->ext_x[tid], (int32_t)hdr->ext_y[tid]};
-        hdr->s2[tid] = T[tid];
-        if (tid == 0) hdr->poly = 4 + T[0] + T[1] + T[2] + T[3];
-    }
-    uint32_t lo, hi;
-    chunk_range(count, b, nb, lo, hi);
-    const uint32_t n_here = mine[0] + mine[1] + mine[2] + mine[3];
-    for (uint32_t k = tid; k < n_here; k += kBlock) {
-        const uint32_t kk = kept_key[lo + k];
-        const u64 vv = kept_val[lo + k];
-        const uint32_t q = kk >> 23, k1 = kk & kM, k2 = (uint32_t)(vv >> 32);
-        uint32_t start = q + 1, rank = k;
-        for (uint32_t r = 0; r < q; ++r) {
-            start += T[r];
-            rank -= mine[r];
-        }
-        const uint32_t X = sel4(q, k1, kM - k2, kM - k1, k2);
-        const uint32_t Y = sel4(q, k2, k1, kM - k2, kM - k1);
-        poly[start + P[q] + rank] = PolyRec{(int32_t)(uint32_t)vv, (int32_t)X, (int32_t)Y};
     }
 }
 
@@ -921,6 +960,8 @@ namespace {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+constexpr size_t kHostChainDefault = 1u << 20;  // pinned chain records
+
 struct Workspace {
     std::mutex mu;
     int device = 0;
@@ -929,32 +970,38 @@ struct Workspace {
     char* dbuf = nullptr;
     DevHeader* hdr = nullptr;
     ExtPartial* part = nullptr;
+    uint32_t* ghist = nullptr;
     uint32_t* key[2] = {nullptr, nullptr};
     u64* val[2] = {nullptr, nullptr};
-    uint32_t* hist = nullptr;
-    uint32_t* spa_part = nullptr;
-    uint32_t* spa_cnt = nullptr;
-    PolyRec* poly = nullptr;
+    LookAreas look = {};
+    PolyRec* dev_chain = nullptr;
     DevHeader* h_hdr = nullptr;     // pinned
-    PolyRec* h_poly = nullptr;      // pinned
-    size_t h_poly_cap = 0;
+    PolyRec* h_chain = nullptr;     // pinned, device-visible
+    PolyRec* h_chain_dev = nullptr; // its device address
+    size_t h_chain_cap = 0;
     int32_t* h_out = nullptr;       // pinned: count, then indices
     size_t h_out_cap = 0;
     std::vector<int32_t> xy, idx;   // finish input
+    std::vector<PolyRec> spill;     // chain records beyond the pinned buffer
     hipEvent_t ev[8] = {};
     bool events = false;
 };
+
+size_t sort_tile_cap(size_t cap) { return (cap + kSortTile - 1) / kSortTile; }
+size_t spa_tile_cap(size_t cap) { return (cap + kSpaTile - 1) / kSpaTile; }
 
 size_t device_bytes(size_t cap)
 {
     size_t b = 0;
     b += align_up(sizeof(DevHeader), 256);
     b += align_up(sizeof(ExtPartial) * kExtBlocks, 256);
+    b += align_up(sizeof(uint32_t) * kPassBins, 256);
     b += 2 * align_up(sizeof(uint32_t) * cap, 256);
     b += 2 * align_up(sizeof(u64) * cap, 256);
-    b += align_up(sizeof(uint32_t) * kMaxBins * kSortBlocks, 256);
-    b += 2 * align_up(sizeof(uint32_t) * 4 * kSortBlocks, 256);
-    b += align_up(sizeof(PolyRec) * (cap + 4), 256);
+    b += 2 * align_up(sizeof(u64) * sort_tile_cap(cap) * 256, 256);
+    b += align_up(sizeof(u64) * sort_tile_cap(cap) * 512, 256);
+    b += 2 * align_up(sizeof(u64) * spa_tile_cap(cap), 256);
+    b += align_up(sizeof(PolyRec) * cap, 256);
     return b;
 }
 
@@ -976,6 +1023,13 @@ inline int hip_status(int rc) { return rc; }  // already a ch_status
     do {                                  \
         const int rc_ = hip_status(expr); \
         if (rc_ != CH_OK) return rc_;     \
+    } while (0)
+
+#define CH_LAUNCH(...)                                 \
+    do {                                               \
+        __VA_ARGS__;                                   \
+        const int rc_ = hip_status(hipGetLastError()); \
+        if (rc_ != CH_OK) return rc_;                  \
     } while (0)
 
 int ensure_device(Workspace& w, size_t n)
@@ -1001,24 +1055,29 @@ int ensure_device(Workspace& w, size_t n)
     };
     w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kExtBlocks));
+    w.ghist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kPassBins));
     for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * cap));
     for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * cap));
-    w.hist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kMaxBins * kSortBlocks));
-    w.spa_part = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kSortBlocks));
-    w.spa_cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kSortBlocks));
-    w.poly = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * (cap + 4)));
+    const size_t st = sort_tile_cap(cap), sp = spa_tile_cap(cap);
+    w.look.pass[0] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
+    w.look.pass[1] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
+    w.look.pass[2] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 512));
+    w.look.spa_min = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
+    w.look.spa_cnt = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
+    w.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    // the extreme-point ticket must start at zero
+    CH_TRY(hipMemsetAsync(w.hdr, 0, sizeof(DevHeader), w.stream));
     return CH_OK;
 }
 
-int ensure_host(Workspace& w, size_t poly, size_t out)
+int ensure_host(Workspace& w, size_t out)
 {
     if (!w.h_hdr) CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_hdr), sizeof(DevHeader), hipHostMallocDefault));
-    if (w.h_poly_cap < poly) {
-        if (w.h_poly) CH_TRY(hipHostFree(w.h_poly));
-        w.h_poly = nullptr;
-        const size_t cap = std::max<size_t>(poly, 4096);
-        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_poly), sizeof(PolyRec) * cap, hipHostMallocDefault));
-        w.h_poly_cap = cap;
+    if (!w.h_chain) {
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_chain), sizeof(PolyRec) * kHostChainDefault,
+                             hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_chain_dev), w.h_chain, 0));
+        w.h_chain_cap = kHostChainDefault;
     }
     if (w.h_out_cap < out + 1) {
         if (w.h_out) CH_TRY(hipHostFree(w.h_out));
@@ -1051,9 +1110,10 @@ void free_workspace(Workspace* w)
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(w->device);
+    (void)hipStreamSynchronize(w->stream);
     if (w->dbuf) (void)hipFree(w->dbuf);
     if (w->h_hdr) (void)hipHostFree(w->h_hdr);
-    if (w->h_poly) (void)hipHostFree(w->h_poly);
+    if (w->h_chain) (void)hipHostFree(w->h_chain);
     if (w->h_out) (void)hipHostFree(w->h_out);
     if (w->events) {
         for (auto& e : w->ev) (void)hipEventDestroy(e);
@@ -1072,27 +1132,19 @@ int record(Workspace& w, int k)
     return hip_status(hipEventRecord(w.ev[k], w.stream));
 }
 
-#define CH_LAUNCH(...)                                   \
-    do {                                                 \
-        __VA_ARGS__;                                     \
-        const int rc_ = hip_status(hipGetLastError());   \
-        if (rc_ != CH_OK) return rc_;                    \
-    } while (0)
-
-// Steps 1-6 on the device; leaves the polygon in w.poly and the counts in
-// w.hdr, then copies both to pinned host memory and waits.
+// Steps 1-6 on the device; the chains end in w.h_chain (and w.spill), the
+// counts in w.h_hdr.  Timing events: 0 | k_extremes | 1 | k_classify | 2 |
+// sort | 3 | SPA + chains | 4 | copy-out | 5.
 int run_preprocess(Workspace& w, const float* pts, uint32_t n)
 {
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
     const uint32_t n4 = (n - head) / 2;
-    const int gext = (int)std::max<uint32_t>(1u, std::min<uint32_t>(kExtBlocks, (n4 + kBlock * kExtUnroll - 1) /
-                                                                                   (kBlock * kExtUnroll)));
-    CH_LAUNCH(hipLaunchKernelGGL(k_extremes, dim3(gext), dim3(kBlock), 0, s, pts, n, head, w.part));
+    const uint32_t gext = std::max<uint32_t>(
+        1u, std::min<uint32_t>(kExtBlocks, (n4 + kBlock * kExtUnroll - 1) / (kBlock * kExtUnroll)));
+    CH_LAUNCH(hipLaunchKernelGGL(k_extremes, dim3(gext), dim3(kBlock), 0, s, pts, n, head, w.part, w.hdr, w.ghist));
     CH_TRY(record(w, 1));
-    CH_LAUNCH(hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(kBlock), 0, s, w.part, gext, w.hdr));
-    CH_TRY(record(w, 2));
     const uint32_t tiles = (n + kTilePts - 1) / kTilePts;
     if (head == 0) {
         CH_LAUNCH(hipLaunchKernelGGL(k_classify<true>, dim3(tiles), dim3(kBlock), 0, s, pts, n, w.hdr, w.key[0],
@@ -1101,41 +1153,67 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n)
         CH_LAUNCH(hipLaunchKernelGGL(k_classify<false>, dim3(tiles), dim3(kBlock), 0, s, pts, n, w.hdr, w.key[0],
                                      w.val[0]));
     }
+    CH_TRY(record(w, 2));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(256), dim3(kBlock), 0, s, w.key[0], w.hdr, w.ghist, w.look));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
+                                 w.val[1], w.hdr, 0, w.ghist, w.look.pass[0], &w.hdr->ticket[0]));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.key[0],
+                                 w.val[0], w.hdr, 8, w.ghist + 256, w.look.pass[1], &w.hdr->ticket[1]));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<9>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
+                                 w.val[1], w.hdr, 16, w.ghist + 512, w.look.pass[2], &w.hdr->ticket[2]));
     CH_TRY(record(w, 3));
-    // region sort: digits [0,8), [8,16), [16,25)
-    const int shifts[3] = {0, 8, 16}, bits[3] = {8, 8, 9};
-    for (int p = 0; p < 3; ++p) {
-        const int src = p & 1, dst = src ^ 1;
-        CH_LAUNCH(hipLaunchKernelGGL(k_sort_hist, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[src], w.hdr, shifts[p],
-                                     bits[p], w.hist));
-        CH_LAUNCH(hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, w.hist,
-                                     (uint32_t)((1u << bits[p]) * kSortBlocks)));
-        if (bits[p] == 8) {
-            CH_LAUNCH(hipLaunchKernelGGL(k_sort_scatter<8>, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[src],
-                                         w.val[src], w.key[dst], w.val[dst], w.hdr, shifts[p], w.hist));
-        } else {
-            CH_LAUNCH(hipLaunchKernelGGL(k_sort_scatter<9>, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[src],
-                                         w.val[src], w.key[dst], w.val[dst], w.hdr, shifts[p], w.hist));
+    CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
+                                 w.look.spa_min, w.look.spa_cnt, &w.hdr->ticket[3], w.h_chain_dev,
+                                 (uint32_t)w.h_chain_cap, w.dev_chain));
+    CH_TRY(record(w, 4));
+    CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
+    CH_TRY(record(w, 5));
+    CH_TRY(hipStreamSynchronize(s));
+    if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
+    if (w.h_hdr->err) return CH_EHIP;
+    const size_t m = w.h_hdr->chain;
+    w.spill.clear();
+    if (m > w.h_chain_cap) {
+        w.spill.resize(m - w.h_chain_cap);
+        CH_TRY(hipMemcpy(w.spill.data(), w.dev_chain, sizeof(PolyRec) * w.spill.size(), hipMemcpyDeviceToHost));
+    }
+    return CH_OK;
+}
+
+inline const PolyRec& chain_at(const Workspace& w, size_t i)
+{
+    return i < w.h_chain_cap ? w.h_chain[i] : w.spill[i - w.h_chain_cap];
+}
+
+// The simple polygon [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] with
+// consecutive coincident vertices dropped (cyclically), into w.xy / w.idx.
+void build_polygon(Workspace& w)
+{
+    const DevHeader& h = *w.h_hdr;
+    w.xy.clear();
+    w.idx.clear();
+    w.xy.reserve(2 * ((size_t)h.chain + 4));
+    w.idx.reserve((size_t)h.chain + 4);
+    auto push = [&](int32_t idx, int32_t x, int32_t y) {
+        const size_t k = w.idx.size();
+        if (k && w.xy[2 * k - 2] == x && w.xy[2 * k - 1] == y) return;
+        w.idx.push_back(idx);
+        w.xy.push_back(x);
+        w.xy.push_back(y);
+    };
+    size_t at = 0;
+    for (int q = 0; q < 4; ++q) {
+        push((int32_t)h.ext_idx[q], (int32_t)h.ext_x[q], (int32_t)h.ext_y[q]);
+        for (uint32_t k = 0; k < h.s2[q]; ++k, ++at) {
+            const PolyRec& r = chain_at(w, at);
+            push(r.idx, r.x, r.y);
         }
     }
-    CH_TRY(record(w, 4));
-    CH_LAUNCH(hipLaunchKernelGGL(k_spa_part, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
-                                 w.spa_part));
-    CH_LAUNCH(hipLaunchKernelGGL(k_spa_keep, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
-                                 w.spa_part, w.key[0], w.val[0], w.spa_cnt));
-    CH_TRY(record(w, 5));
-    CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kSortBlocks), dim3(kBlock), 0, s, w.key[0], w.val[0], w.spa_cnt, w.hdr,
-                                 w.poly));
-    CH_TRY(record(w, 6));
-    CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
-    CH_TRY(hipStreamSynchronize(s));
-    if (w.h_hdr->err) return CH_EDOMAIN;
-    const size_t m = w.h_hdr->poly;
-    CH_TRY(ensure_host(w, m, 0));
-    if (m) CH_TRY(hipMemcpyAsync(w.h_poly, w.poly, sizeof(PolyRec) * m, hipMemcpyDeviceToHost, s));
-    CH_TRY(record(w, 7));
-    CH_TRY(hipStreamSynchronize(s));
-    return CH_OK;
+    while (w.idx.size() > 1 && w.xy[2 * w.idx.size() - 2] == w.xy[0] && w.xy[2 * w.idx.size() - 1] == w.xy[1]) {
+        w.idx.pop_back();
+        w.xy.pop_back();
+        w.xy.pop_back();
+    }
 }
 
 void fill_stats(const Workspace& w, int64_t n, ch_stats* st)
@@ -1152,27 +1230,16 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st)
         st->s2[e] = h.s2[e];
     }
     st->candidates = h.cand;
-    st->polygon = h.poly;
+    st->polygon = (int64_t)h.chain + 4;
     if (g_timing && w.events) {
-        for (int k = 0; k < 7; ++k) {
+        // stage slots: 0 k_extremes (with its final reduction), 1 unused,
+        // 2 k_classify, 3 sort, 4 SPA + chains, 5 unused, 6 copy-out
+        const int slot[5] = {0, 2, 3, 4, 6};
+        for (int k = 0; k < 5; ++k) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
+            if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[slot[k]] = ms;
         }
     }
-}
-
-// Finish on the host: Melkman on the polygon copied out by run_preprocess.
-int finish(Workspace& w, int32_t* out, int64_t* h)
-{
-    const size_t m = w.h_hdr->poly;
-    w.xy.resize(2 * m);
-    w.idx.resize(m);
-    for (size_t i = 0; i < m; ++i) {
-        w.idx[i] = w.h_poly[i].idx;
-        w.xy[2 * i] = w.h_poly[i].x;
-        w.xy[2 * i + 1] = w.h_poly[i].y;
-    }
-    return melkman_finish(w.xy.data(), w.idx.data(), (int64_t)m, out, h) == 0 ? CH_OK : CH_EHIP;
 }
 
 int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, hipStream_t stream)
@@ -1186,7 +1253,7 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     Workspace* w = workspace_for(stream, &rc);
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
-    CH_TRY(ensure_host(*w, 0, 0));
+    CH_TRY(ensure_host(*w, 0));
     if (n == 0) {
         w->h_out[0] = 0;
         CH_TRY(hipMemcpyAsync(out_count, w->h_out, sizeof(int32_t), hipMemcpyHostToDevice, stream));
@@ -1195,14 +1262,17 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     }
     CH_TRY(ensure_device(*w, (size_t)n));
     rc = run_preprocess(*w, points, (uint32_t)n);
-    if (rc == CH_OK) {
-        fill_stats(*w, n, &st);
-        rc = ensure_host(*w, 0, (size_t)w->h_hdr->poly);
-    }
     int64_t h = 0;
     if (rc == CH_OK) {
+        fill_stats(*w, n, &st);
         const auto t0 = std::chrono::steady_clock::now();
-        rc = finish(*w, w->h_out + 1, &h);
+        build_polygon(*w);
+        rc = ensure_host(*w, w->idx.size());
+        if (rc == CH_OK) {
+            rc = melkman_finish(w->xy.data(), w->idx.data(), (int64_t)w->idx.size(), w->h_out + 1, &h) == 0
+                     ? CH_OK
+                     : CH_EHIP;
+        }
         const auto t1 = std::chrono::steady_clock::now();
         st.ms[7] = std::chrono::duration<float, std::milli>(t1 - t0).count();
         st.hull = h;
@@ -1268,38 +1338,14 @@ int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t
     Workspace* w = workspace_for(reinterpret_cast<hipStream_t>(stream), &rc);
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
-    CH_TRY(ensure_host(*w, 0, 0));
+    CH_TRY(ensure_host(*w, 0));
     CH_TRY(ensure_device(*w, (size_t)n));
     rc = run_preprocess(*w, points, (uint32_t)n);
     if (rc != CH_OK) return rc;
     fill_stats(*w, n, &st);
-    // drop consecutive coincident vertices (cyclically), as the finish does
-    const size_t m = w->h_hdr->poly;
-    int64_t k = 0;
-    int32_t lx = -1, ly = -1;
-    for (size_t i = 0; i < m; ++i) {
-        const PolyRec& r = w->h_poly[i];
-        if (k > 0 && r.x == lx && r.y == ly) continue;
-        poly_idx[k++] = r.idx;
-        lx = r.x;
-        ly = r.y;
-    }
-    if (m) {
-        const int32_t fx = w->h_poly[0].x, fy = w->h_poly[0].y;
-        // the first vertex is kept; trailing copies of it close the cycle
-        while (k > 1 && lx == fx && ly == fy) {
-            --k;
-            // coordinates of the new last kept vertex
-            for (size_t i = m; i-- > 0;) {
-                if (w->h_poly[i].idx == poly_idx[k - 1]) {
-                    lx = w->h_poly[i].x;
-                    ly = w->h_poly[i].y;
-                    break;
-                }
-            }
-        }
-    }
-    *poly_count = k;
+    build_polygon(*w);
+    for (size_t i = 0; i < w->idx.size(); ++i) poly_idx[i] = w->idx[i];
+    *poly_count = (int64_t)w->idx.size();
     if (stats) *stats = st;
     return CH_OK;
 }

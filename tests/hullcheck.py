@@ -154,27 +154,51 @@ def convex_lattice_polygon(scale: int = 3, base=(1000, 1000)):
     return verts, steps
 
 
+def _inner_rectangle(V):
+    """An axis-aligned rectangle strictly inside the convex polygon V: all
+    four corners are strictly inside, hence (convexity) the whole of it."""
+    ex = np.roll(V, -1, axis=0) - V
+    c = V.mean(axis=0)
+    half = (V.max(axis=0) - V.min(axis=0)) / 2.0
+    for a in np.linspace(0.7, 0.05, 14):
+        lo = np.floor(c - a * half).astype(np.int64)
+        hi = np.ceil(c + a * half).astype(np.int64)
+        corners = np.array([[lo[0], lo[1]], [hi[0], lo[1]], [hi[0], hi[1]], [lo[0], hi[1]]])
+        cr = ex[:, None, 0] * (corners[None, :, 1] - V[:, None, 1]) - ex[:, None, 1] * (corners[None, :, 0] - V[:, None, 0])
+        if (cr > 0).all():
+            return lo, hi
+    return None
+
+
 def polygon_with_extras(n_interior: int, n_edge: int, n_dup: int, rng, scale: int = 3,
-                        base=(1000, 1000)):
+                        base=(1000, 1000), core: float = 0.0):
     """Points whose exact hull is known: polygon vertices plus extras.
 
     Returns ``(points f32 [n,2], expected hull indices)``.  Vertices are
-    placed at random positions; interior points (strictly inside, by
-    rejection), points on edges and duplicates of vertices are placed so that
-    every duplicate has a larger index than the vertex copy that must be
-    reported.
+    placed at random positions; interior points are strictly inside (a
+    fraction ``core`` of them uniform in a rectangle that is strictly inside,
+    the rest by rejection over the bounding box), points lie strictly inside
+    edges, and duplicates of vertices come after every vertex copy that must
+    be reported.
     """
     verts, steps = convex_lattice_polygon(scale, base)
     V = np.array(verts, dtype=np.int64)
     h = V.shape[0]
-    # strictly interior lattice points
-    lo, hi = V.min(axis=0), V.max(axis=0)
-    inner = []
-    need = n_interior
     ex = np.roll(V, -1, axis=0) - V
+    inner = []
+    n_core = int(n_interior * core)
+    if n_core:
+        rect = _inner_rectangle(V)
+        assert rect is not None
+        lo, hi = rect
+        inner.append(np.stack([rng.integers(lo[0], hi[0] + 1, size=n_core),
+                               rng.integers(lo[1], hi[1] + 1, size=n_core)], axis=1))
+    lo, hi = V.min(axis=0), V.max(axis=0)
+    need = n_interior - n_core
     while need > 0:
-        cand = np.stack([rng.integers(lo[0], hi[0] + 1, size=4 * need + 16),
-                         rng.integers(lo[1], hi[1] + 1, size=4 * need + 16)], axis=1)
+        batch = min(2 * need + 16, 1 << 23)
+        cand = np.stack([rng.integers(lo[0], hi[0] + 1, size=batch),
+                         rng.integers(lo[1], hi[1] + 1, size=batch)], axis=1)
         ok = np.ones(cand.shape[0], dtype=bool)
         for k in range(h):
             cr = ex[k, 0] * (cand[:, 1] - V[k, 1]) - ex[k, 1] * (cand[:, 0] - V[k, 0])
@@ -184,12 +208,10 @@ def polygon_with_extras(n_interior: int, n_edge: int, n_dup: int, rng, scale: in
         need -= got.shape[0]
     inner = np.concatenate(inner) if inner else np.zeros((0, 2), np.int64)
     # points strictly inside edges
-    on_edge = []
-    for _ in range(n_edge):
-        k = int(rng.integers(0, h))
-        j = int(rng.integers(1, scale))
-        on_edge.append(V[k] + j * np.array(steps[k]))
-    on_edge = np.array(on_edge, dtype=np.int64).reshape(-1, 2)
+    S = np.array(steps, dtype=np.int64)
+    ke = rng.integers(0, h, size=n_edge)
+    je = rng.integers(1, scale, size=n_edge) if scale > 1 else np.zeros(n_edge, np.int64)
+    on_edge = V[ke] + je[:, None] * S[ke]
     extras = np.concatenate([inner, on_edge])
     extras = extras[rng.permutation(extras.shape[0])]
     n_extra = extras.shape[0]
