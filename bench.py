@@ -135,6 +135,13 @@ def main():
             "finish_ms": float(np.mean([x["ms"]["finish"] for x in stats[d]])),
         }
 
+    # counts of the discard rounds (the stats mode of the library counts the
+    # round-1 survivors; outside the timed regions)
+    for d, _ in DISTS:
+        _, pst = ch.polygon(inputs[d])
+        per_dist[d].update({"s1": int(sum(pst["s1"])), "s2": int(sum(pst["s2"]))})
+    torch.cuda.synchronize()
+
     # roofline of the dominant single kernel (extreme-point pass or classify)
     cand_mean = float(np.mean([s["candidates"] for d, _ in DISTS for s in stats[d]]))
     kernels = {
@@ -150,10 +157,7 @@ def main():
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms}
 
     # whole-preprocessing accounting with B_alg = 16n + 24*s1 + 12*s2
-    b_alg = []
-    for d, _ in DISTS:
-        s = stats[d][-1]
-        b_alg.append(16.0 * n + 24.0 * sum(s["s1"]) + 12.0 * sum(s["s2"]))
+    b_alg = [16.0 * n + 24.0 * per_dist[d]["s1"] + 12.0 * per_dist[d]["s2"] for d, _ in DISTS]
     t_pre = sum(stage_ms[k] for k in ("extremes", "classify", "sort", "spa"))
     pre_frac = float(np.mean(b_alg)) / (t_pre * 1e-3) / (HBM_PEAK_GBS * 1e9) if t_pre > 0 else 0.0
 

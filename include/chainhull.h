@@ -55,15 +55,18 @@ typedef struct {
     int64_t n;            /* input points */
     int32_t ext_idx[4];   /* P_minx, P_miny, P_maxx, P_maxy (Section 2.1 step 1) */
     int32_t ext_xy[8];    /* their (x, y) */
-    int64_t s1[4];        /* round-1 survivors in R1..R4 (Section 2.1.1) */
-    int64_t candidates;   /* records the tile filter passes to the region sort */
+    int64_t s1[4];        /* round-1 survivors in R1..R4 (Section 2.1.1); counted
+                             by chainhull_polygon only, -1 after hull2d */
+    int64_t candidates;   /* records the dominance filters pass to the region sort */
     int64_t s2[4];        /* SPA survivors in R1..R4 (Figure 2) */
-    int64_t polygon;      /* vertices of the simple polygon before de-duplication */
+    int64_t polygon;      /* vertices of the polygon handed to the finish, the
+                             four extreme points included, before de-duplication */
     int64_t hull;         /* hull vertices */
     /* Milliseconds per stage when timing is on (chainhull_set_timing), from
-     * HIP events on the call's stream: 0 extreme points, 1 extreme-point
-     * reduction, 2 classify + tile filter, 3 region sort, 4 SPA, 5 chain
-     * concatenation, 6 device-to-host copy, 7 host finish (wall clock). */
+     * HIP events on the call's stream: 0 extreme points (partial and final
+     * reduction), 2 quadrilateral discard + region distribution + dominance
+     * filters, 3 region sort, 4 SPA + chain concatenation, 6 copy of the
+     * counts to the host, 7 host finish (wall clock); 1 and 5 are unused. */
     float ms[8];
 } ch_stats;
 
@@ -77,7 +80,10 @@ typedef struct {
  *   out_count  device memory, one int32; receives the number of vertices.
  *   stream     a hipStream_t (NULL for the default stream); all device work
  *              is ordered on it.
- * Blocking: returns after out_idx and out_count are written.
+ * Synchrony: returns after the hull is known on the host; the copies into
+ * out_idx and out_count are queued on `stream`, so later work on that
+ * stream sees them (synchronise the stream before reading them on the host).
+ * On failure out_count is set to 0 the same way.
  * Returns CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM or CH_EHIP.
  */
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);

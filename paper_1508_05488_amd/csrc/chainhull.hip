@@ -62,10 +62,8 @@ typedef long long i64;
 constexpr uint32_t kM = (1u << 23) - 1;
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kExtBlocks = 1024;   // workgroups of the extreme-point pass
+constexpr int kExtBlocks = 2048;   // workgroups of the extreme-point pass
 constexpr int kExtUnroll = 4;      // float4 loads in flight per thread
-constexpr int kTilePts = 4096;     // points per classify workgroup
-constexpr int kPtsPerThread = kTilePts / kBlock;  // 16
 constexpr int kSlotBits = 9;
 constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region and tile
 constexpr int kSortIpt = 8;                       // records per thread per sort tile
@@ -95,10 +93,10 @@ struct DevHeader {
     uint32_t s1[4];      // round-1 survivors per region
     uint32_t cand;       // records written by the tile filter
     uint32_t s2[4];      // SPA survivors per region
-    uint32_t chain;      // SPA survivors in all
-    uint32_t ext_ticket; // workgroups of k_extremes done
+    uint32_t w2[4];      // chain records written per region (after the pre-hull)
+    uint32_t chain;      // chain records written in all
     uint32_t ticket[4];  // tile tickets: three sort passes and SPA
-    uint32_t pad[3];
+    uint32_t pad[8];
 };
 
 struct ExtPartial {
@@ -337,17 +335,44 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
     }
 }
 
+// Sampled staircases.  The first kSampleBlocks workgroups also take a strided
+// sample of kSamplePts points spread over the whole array and record, in
+// each region's frame, the smallest k2 per k1-slot of 2^14 values (for any
+// point, not only the region's: see k_classify).  k_extremes_final turns
+// them into exclusive prefix minima over the slots.
+constexpr int kSampleBlocks = 64;
+constexpr int kSamplePerThread = 8;
+constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
+constexpr int kStairBits = 9;
+constexpr int kStairSlots = 1 << kStairBits;
+constexpr int kStairShift = 23 - kStairBits;
+
 // `head` leading points (0 or 1) are visited singly so that the rest of the
 // array is 16-byte aligned for float4 loads; an odd last point likewise.
 __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ pts, uint32_t n, uint32_t head,
-                                                     ExtPartial* __restrict__ part, DevHeader* __restrict__ hdr,
-                                                     uint32_t* __restrict__ ghist)
+                                                     ExtPartial* __restrict__ part, uint32_t* __restrict__ samp)
 {
     __shared__ ExtAcc sh[kWaves];
-    __shared__ uint32_t s_last;
+    __shared__ uint32_t st[4 * kStairSlots];
     ExtAcc a;
     ext_init(a);
     const uint32_t tid = threadIdx.x;
+    const bool sampler = blockIdx.x < (uint32_t)kSampleBlocks;
+    if (sampler) {
+        for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSamplePerThread; ++k) {
+            const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
+            const uint32_t i = (uint32_t)(((u64)sidx * n) / kSamplePts);
+            const uint32_t X = coord_u32(pts[2 * i]) & kM, Y = coord_u32(pts[2 * i + 1]) & kM;
+            const uint32_t xm = X ^ kM, ym = Y ^ kM;
+            atomicMin(&st[0 * kStairSlots + (X >> kStairShift)], Y);   // R1: (x, y)
+            atomicMin(&st[1 * kStairSlots + (Y >> kStairShift)], xm);  // R2: (y, M-x)
+            atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym); // R3: (M-x, M-y)
+            atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X);  // R4: (M-y, x)
+        }
+    }
     if (blockIdx.x == 0 && tid == 0 && head) ext_visit(a, pts[0], pts[1], 0);
 
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
@@ -384,17 +409,29 @@ __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ p
         }
         p.err = (a.bad || a.hi > kM) ? 1u : 0u;
         part[blockIdx.x] = p;
-        // publish the partial, then take a ticket; the last workgroup reduces
-        __threadfence();
-        s_last = atomicAdd(&hdr->ext_ticket, 1u) == gridDim.x - 1;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    if (sampler) {
+        for (int e = tid; e < 4 * kStairSlots; e += kBlock) samp[blockIdx.x * 4 * kStairSlots + e] = st[e];
+    }
+}
 
+// One workgroup of kFinal threads: reduce the partials; derive the
+// quadrilateral's edges, the region frames and the sampled staircases'
+// prefix minima; zero the call's counters.
+constexpr int kFinal = 1024;
+
+__global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __restrict__ part, int nparts,
+                                                           const uint32_t* __restrict__ samp,
+                                                           DevHeader* __restrict__ hdr, uint32_t* __restrict__ stair,
+                                                           uint32_t* __restrict__ ghist)
+{
+    constexpr int kW = kFinal / 64;
+    __shared__ ExtAcc sh[kW];
+    __shared__ uint32_t wmin[kW];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     ExtAcc r;
     ext_init(r);
-    for (uint32_t b = tid; b < gridDim.x; b += kBlock) {
+    for (int b = tid; b < nparts; b += kFinal) {
         const ExtPartial p = part[b];
         ExtAcc o;
         for (int e = 0; e < 2; ++e) {
@@ -407,11 +444,31 @@ __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ p
         o.hi = 0;
         ext_combine(r, o);
     }
-    // zero the sort's digit counts for this call
-    for (uint32_t d = tid; d < kPassBins; d += kBlock) ghist[d] = 0;
+    ext_wave_reduce(r);
+    if (lane == 0) sh[wave] = r;
+    for (uint32_t d = tid; d < kPassBins; d += kFinal) ghist[d] = 0;
+
+    // Staircases: thread t owns slot t of each region's frame (needs
+    // kFinal >= kStairSlots); exclusive prefix minimum over the slots.
+    for (int q = 0; q < 4; ++q) {
+        uint32_t v = ~0u;
+        if (tid < (uint32_t)kStairSlots) {
+#pragma unroll 16
+            for (int b = 0; b < kSampleBlocks; ++b) v = min(v, samp[b * 4 * kStairSlots + q * kStairSlots + tid]);
+        }
+        const uint32_t incl = wave_incl_min(v);
+        uint32_t excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = ~0u;
+        __syncthreads();
+        if (lane == 63) wmin[wave] = incl;
+        __syncthreads();
+        uint32_t before = ~0u;
+        for (uint32_t w = 0; w < wave; ++w) before = min(before, wmin[w]);
+        if (tid < (uint32_t)kStairSlots) stair[q * kStairSlots + tid] = min(before, excl);
+    }
     __syncthreads();
-    ext_block_reduce(r, sh);
     if (tid != 0) return;
+    for (int w = 1; w < kW; ++w) ext_combine(r, sh[w]);
 
     // P_minx, P_miny, P_maxx, P_maxy
     const i64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
@@ -443,141 +500,201 @@ __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ p
     for (int q = 0; q < 4; ++q) {
         hdr->s1[q] = 0;
         hdr->s2[q] = 0;
+        hdr->w2[q] = 0;
         hdr->ticket[q] = 0;
     }
     hdr->cand = 0;
     hdr->chain = 0;
     hdr->err = r.bad ? kErrDomain : 0u;
-    hdr->ext_ticket = 0;
 }
 
 // ---------------------------------------------------------------------------
 // Step 2 (Section 2.1.1): exact region test against the quadrilateral (the
-// first discard), fused with a tile-level use of the SPA dominance rule, so
-// that only the tile's possible chain points reach HBM.
+// first discard), fused with two uses of the SPA dominance rule, so that only
+// possible chain points reach HBM.
 //
 // A point p of region q is dominated by another point p' of the region when
 // k1' <= k1 and k2' <= k2 and p' precedes p in (k1, k2, index) order; then p
 // lies in the triangle (first point, p', last point) and is not a hull vertex
-// (the argument of Figure 3).  Domination inside a tile is domination in the
-// whole set, so dropping tile-dominated points leaves the result of the
-// region sort and SPA unchanged.
+// (the argument of Figure 3).  Dropping dominated points leaves the result of
+// the region sort and SPA unchanged, so any filter that only drops dominated
+// points may run before them.
 //
-// Per tile and region, k1 is cut into kSlots slots of 2^14 values.  A point
-// is dropped when
-//   * the region's first point or a point of an earlier slot has k2 <= its k2,
-//   * the slot's smallest-(k2, k1) point precedes it with k1 <= its k1, or
-//   * it repeats that point's coordinates with a larger index.
+// 1. Sampled staircases: in each region frame, the smallest k2 of the sample
+//    points in earlier k1-slots.  A sample point p' with smaller k1 and
+//    k2 <= k2 of p, in the frame of p's region, lies in that region as well
+//    (moving towards the corner never re-enters the quadrilateral), so it
+//    dominates p there.  A point dominated in all four frames is dominated in
+//    its own region and is dropped before the region test; one dominated in
+//    its own region's frame is dropped after it.
+// 2. Workgroup staircases: each persistent workgroup streams a grid-strided
+//    share of the points; the survivors of step 1 that lie in a region go to
+//    an LDS list and update, per region and k1-slot of 2^14 values, the
+//    smallest (k2, k1).  A listed point is then dropped when the region's
+//    first point or a point of an earlier slot has k2 <= its k2, or when its
+//    slot's smallest point precedes it with k1 <= its k1.  The rest is written
+//    out.  Points that do not fit the list are written out unfiltered.
+//
+// With kStats the sample test is skipped and every point's region is counted
+// (the round-1 survivors).
 // ---------------------------------------------------------------------------
 
-template <bool kVec4>
-__global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ pts, uint32_t n,
-                                                     DevHeader* __restrict__ hdr, uint32_t* __restrict__ out_key,
-                                                     u64* __restrict__ out_val)
+constexpr int kClsGrid = 1024;      // persistent workgroups of k_classify
+constexpr int kClsUnroll = 4;       // float4 loads in flight per thread
+constexpr int kCandCap = 1024;      // listed points per workgroup
+
+struct ClsParams {
+    double ec[4], ex[4], ey[4];
+};
+
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ pts, uint32_t n, uint32_t head,
+                                                     DevHeader* __restrict__ hdr, const uint32_t* __restrict__ stair,
+                                                     uint32_t* __restrict__ out_key, u64* __restrict__ out_val)
 {
+    static_assert(kSlots == kStairSlots, "the staircase copy and the slot prefixes share storage");
     __shared__ u64 smin[4 * kSlots];
-    __shared__ uint32_t sidx[4 * kSlots];
-    __shared__ uint32_t sexc[4 * kSlots];
+    __shared__ uint32_t swork[4 * kSlots];  // sampled staircases, then slot prefixes
+    uint32_t* const sst = swork;
+    uint32_t* const sexc = swork;
+    __shared__ uint32_t cl_idx[kCandCap], cl_addr[kCandCap];
     __shared__ uint32_t scratch[kWaves];
+    __shared__ uint32_t s_count, sbase;
     __shared__ uint32_t s1cnt[kWaves][4];
-    __shared__ uint32_t sbase;
 
     if (hdr->err) return;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t wave = tid / 64;
-    const uint32_t tile = blockIdx.x * kTilePts;
-
-    const double ec0 = hdr->ec[0], ec1 = hdr->ec[1], ec2 = hdr->ec[2], ec3 = hdr->ec[3];
-    const double ex0 = hdr->ex[0], ex1 = hdr->ex[1], ex2 = hdr->ex[2], ex3 = hdr->ex[3];
-    const double ey0 = hdr->ey[0], ey1 = hdr->ey[1], ey2 = hdr->ey[2], ey3 = hdr->ey[3];
-
-    for (int s = tid; s < 4 * kSlots; s += kBlock) {
-        smin[s] = ~0ull;
-        sidx[s] = ~0u;
-    }
-
-    // Point j of this thread: with float4 loads it is tile + 2*(k*256+tid) + h
-    // for j = 2k + h; otherwise tile + j*256 + tid.
-    float px[kPtsPerThread], py[kPtsPerThread];
-    if (kVec4) {
-        const v4f* p4 = reinterpret_cast<const v4f*>(pts) + tile / 2;
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
+    const u64 lt = (1ull << lane) - 1ull;
+    ClsParams P;
 #pragma unroll
-        for (int k = 0; k < kPtsPerThread / 2; ++k) {
-            const uint32_t i = tile + 2 * (k * kBlock + tid);
-            v4f v = {0.f, 0.f, 0.f, 0.f};
-            if (i + 1 < n) {
-                v = __builtin_nontemporal_load(p4 + k * kBlock + tid);
-            } else if (i < n) {
-                v.x = pts[2 * i];
-                v.y = pts[2 * i + 1];
+    for (int q = 0; q < 4; ++q) {
+        P.ec[q] = hdr->ec[q];
+        P.ex[q] = (double)hdr->ex[q];
+        P.ey[q] = (double)hdr->ey[q];
+    }
+    for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
+    if (!kStats) {
+        for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
+    }
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;  // region counts (kStats)
+    // One point: sample test, region test, workgroup staircase, list.  Every
+    // lane of the wave calls it together (the list append is wave-wide).
+    auto visit = [&](float fx, float fy, uint32_t idx, bool valid) {
+        const uint32_t X = (uint32_t)fx, Y = (uint32_t)fy;
+        uint32_t open = valid ? 0xfu : 0u;
+        if (!kStats && valid) {
+            const uint32_t xm = X ^ kM, ym = Y ^ kM;
+            open = (Y < sst[0 * kStairSlots + (X >> kStairShift)] ? 1u : 0u) |
+                   (xm < sst[1 * kStairSlots + (Y >> kStairShift)] ? 2u : 0u) |
+                   (ym < sst[2 * kStairSlots + (xm >> kStairShift)] ? 4u : 0u) |
+                   (X < sst[3 * kStairSlots + (ym >> kStairShift)] ? 8u : 0u);
+        }
+        uint32_t addr = ~0u;
+        if (open) {
+            const double dx = (double)fx, dy = (double)fy;
+            // exact: every product is below 2^46 and every sum below 2^47
+            const bool t0 = fma(P.ex[0], dy, -(P.ey[0] * dx)) < P.ec[0];
+            const bool t1 = fma(P.ex[1], dy, -(P.ey[1] * dx)) < P.ec[1];
+            const bool t2 = fma(P.ex[2], dy, -(P.ey[2] * dx)) < P.ec[2];
+            const bool t3 = fma(P.ex[3], dy, -(P.ey[3] * dx)) < P.ec[3];
+            const uint32_t q = t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
+            if (kStats) {
+                c0 += q == 0;
+                c1 += q == 1;
+                c2 += q == 2;
+                c3 += q == 3;
             }
-            px[2 * k] = v.x;
-            py[2 * k] = v.y;
-            px[2 * k + 1] = v.z;
-            py[2 * k + 1] = v.w;
+            if (q < 4 && ((open >> q) & 1u)) {
+                const uint32_t a = (q & 1u) ? Y : X;
+                const uint32_t b = (q & 1u) ? X : Y;
+                const uint32_t k1 = (q & 2u) ? a ^ kM : a;
+                const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+                addr = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
+                atomicMin(&smin[addr], ((u64)k2 << 23) | k1);
+            }
         }
-    } else {
-        const v2f* p2 = reinterpret_cast<const v2f*>(pts);
-#pragma unroll
-        for (int k = 0; k < kPtsPerThread; ++k) {
-            const uint32_t i = tile + k * kBlock + tid;
-            v2f v = {0.f, 0.f};
-            if (i < n) v = __builtin_nontemporal_load(p2 + i);
-            px[k] = v.x;
-            py[k] = v.y;
+        const u64 want = __ballot(addr != ~0u);
+        if (want) {
+            uint32_t first = 0;
+            if (lane == (uint32_t)__ffsll((long long)want) - 1) first = atomicAdd(&s_count, (uint32_t)__popcll(want));
+            first = __shfl(first, __ffsll((long long)want) - 1);
+            if (addr != ~0u) {
+                const uint32_t slot = first + (uint32_t)__popcll(want & lt);
+                if (slot < (uint32_t)kCandCap) {
+                    cl_idx[slot] = idx;
+                    cl_addr[slot] = addr;
+                } else {
+                    // list full: write the point unfiltered
+                    const uint32_t q = addr >> kSlotBits;
+                    const uint32_t a = (q & 1u) ? Y : X;
+                    const uint32_t b = (q & 1u) ? X : Y;
+                    const uint32_t k1 = (q & 2u) ? a ^ kM : a;
+                    const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+                    const uint32_t pos = atomicAdd(&hdr->cand, 1u);
+                    out_key[pos] = (q << 23) | k1;
+                    out_val[pos] = ((u64)k2 << 32) | idx;
+                }
+            }
         }
-    }
-    auto index_of = [&](int j) -> uint32_t {
-        return kVec4 ? tile + 2 * ((uint32_t)(j >> 1) * kBlock + tid) + (uint32_t)(j & 1)
-                     : tile + (uint32_t)j * kBlock + tid;
     };
 
-    __syncthreads();
-
-    // Phase 1: region of every point, its frame, and the per-slot minimum of
-    // (k2, k1).  me = k2 << 23 | k1; addr = q * kSlots + slot, or ~0u.
-    u64 me[kPtsPerThread];
-    uint32_t addr[kPtsPerThread];
-    uint32_t counts = 0;  // 8-bit count per region
-    const bool full_tile = tile + kTilePts <= n;
+    // head point, float4 body, odd last point (as in k_extremes)
+    if (blockIdx.x == 0 && wave == 0) {
+        const bool h = head && lane == 0;
+        visit(h ? pts[0] : 0.f, h ? pts[1] : 0.f, 0, h);
+    }
+    const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
+    const uint32_t n4 = (n - head) / 2;
+    const uint32_t stride = gridDim.x * kBlock;
+    // every lane runs the same number of iterations (the list append is
+    // wave-wide); lanes past the end visit invalid points
+    const uint32_t rounds = (n4 + stride * kClsUnroll - 1) / (stride * kClsUnroll);
+    uint32_t f = blockIdx.x * kBlock + tid;
+    for (uint32_t it = 0; it < rounds; ++it, f += kClsUnroll * stride) {
+        v4f v[kClsUnroll];
 #pragma unroll
-    for (int j = 0; j < kPtsPerThread; ++j) {
-        const double fx = (double)px[j], fy = (double)py[j];
-        // exact: every product is below 2^46 and every sum below 2^47
-        const bool t0 = fma(ex0, fy, -(ey0 * fx)) < ec0;
-        const bool t1 = fma(ex1, fy, -(ey1 * fx)) < ec1;
-        const bool t2 = fma(ex2, fy, -(ey2 * fx)) < ec2;
-        const bool t3 = fma(ex3, fy, -(ey3 * fx)) < ec3;
-        uint32_t q = t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
-        if (!full_tile && index_of(j) >= n) q = 4u;
-        me[j] = 0;
-        addr[j] = ~0u;
-        if (q < 4) {  // a wave with no survivor skips this
-            const uint32_t X = (uint32_t)px[j], Y = (uint32_t)py[j];
-            const uint32_t a = (q & 1u) ? Y : X;
-            const uint32_t b = (q & 1u) ? X : Y;
-            const uint32_t k1 = (q & 2u) ? a ^ kM : a;
-            const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-            me[j] = ((u64)(k2 >> 9) << 32) | ((k2 << 23) | k1);
-            addr[j] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
-            counts += 1u << (8 * q);
-            atomicMin(&smin[addr[j]], me[j]);
+        for (int u = 0; u < kClsUnroll; ++u) {
+            const uint32_t g = f + u * stride;
+            v[u] = g < n4 ? __builtin_nontemporal_load(p4 + g) : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < kClsUnroll; ++u) {
+            const uint32_t g = f + u * stride;
+            const uint32_t i = head + 2 * g;
+            visit(v[u].x, v[u].y, i, g < n4);
+            visit(v[u].z, v[u].w, i + 1, g < n4);
         }
     }
-    {
-        const uint32_t w0 = wave_sum(counts & 0xff), w1 = wave_sum((counts >> 8) & 0xff);
-        const uint32_t w2 = wave_sum((counts >> 16) & 0xff), w3 = wave_sum(counts >> 24);
-        if (lane_id() == 0) {
-            s1cnt[wave][0] = w0;
-            s1cnt[wave][1] = w1;
-            s1cnt[wave][2] = w2;
-            s1cnt[wave][3] = w3;
+    if (blockIdx.x == 0 && wave == 0) {
+        const bool t = ((n - head) & 1u) && lane == 0;
+        visit(t ? pts[2 * (n - 1)] : 0.f, t ? pts[2 * (n - 1) + 1] : 0.f, n - 1, t);
+    }
+    if (kStats) {
+        c0 = wave_sum(c0);
+        c1 = wave_sum(c1);
+        c2 = wave_sum(c2);
+        c3 = wave_sum(c3);
+        if (lane == 0) {
+            s1cnt[wave][0] = c0;
+            s1cnt[wave][1] = c1;
+            s1cnt[wave][2] = c2;
+            s1cnt[wave][3] = c3;
         }
     }
     __syncthreads();
+    if (kStats && tid < 4) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s1cnt[w][tid];
+        if (tot) atomicAdd(&hdr->s1[tid], tot);
+    }
+    const uint32_t listed = min(s_count, (uint32_t)kCandCap);
+    if (listed == 0) return;
 
-    // Phase 2: wave w scans region w's slots; sexc becomes the smallest k2
-    // over earlier slots and the region's first point.
+    // Wave w scans region w's slots: sexc becomes the smallest k2 over earlier
+    // slots and the region's first point.
     {
         const uint32_t q = wave;
         const uint32_t sigma = hdr->sigma[q];
@@ -585,62 +702,59 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
         uint32_t v[per];
         uint32_t run = ~0u;
 #pragma unroll
-        for (int s = 0; s < per; ++s) {
-            const u64 m = smin[(q << kSlotBits) + lane_id() * per + s];
-            v[s] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
-            run = min(run, v[s]);
+        for (int k = 0; k < per; ++k) {
+            const u64 m = smin[(q << kSlotBits) + lane * per + k];
+            v[k] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
+            run = min(run, v[k]);
         }
         const uint32_t incl = wave_incl_min(run);
         uint32_t before = __shfl_up(incl, 1);
-        if (lane_id() == 0) before = ~0u;
+        if (lane == 0) before = ~0u;
         before = min(before, sigma);
 #pragma unroll
-        for (int s = 0; s < per; ++s) {
-            sexc[(q << kSlotBits) + lane_id() * per + s] = before;
-            before = min(before, v[s]);
+        for (int k = 0; k < per; ++k) {
+            sexc[(q << kSlotBits) + lane * per + k] = before;
+            before = min(before, v[k]);
         }
-    }
-    if (tid < 4) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += s1cnt[w][tid];
-        if (tot) atomicAdd(&hdr->s1[tid], tot);
     }
     __syncthreads();
 
-    // Phase 3: dominance tests.
-    uint32_t keep = 0, dupc = 0;
+    // Dominance tests on the list, then one compaction.
+    constexpr int kPer = kCandCap / kBlock;
+    uint32_t keep = 0, rk[kPer], rv[kPer], ri[kPer];
 #pragma unroll
-    for (int j = 0; j < kPtsPerThread; ++j) {
-        if (addr[j] != ~0u) {
-            const u64 best = smin[addr[j]];
-            const uint32_t k1 = (uint32_t)me[j] & kM, k2 = (uint32_t)(me[j] >> 23);
-            bool k = k2 < sexc[addr[j]];
-            k = k && !(best < me[j] && (uint32_t)(best & kM) <= k1);
-            if (k && best == me[j]) {
-                atomicMin(&sidx[addr[j]], index_of(j));
-                dupc |= 1u << j;
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t e = k * kBlock + tid;
+        rk[k] = rv[k] = ri[k] = 0;
+        if (e < listed) {
+            const uint32_t idx = cl_idx[e], addr = cl_addr[e], q = addr >> kSlotBits;
+            const uint32_t X = (uint32_t)pts[2 * idx], Y = (uint32_t)pts[2 * idx + 1];
+            const uint32_t a = (q & 1u) ? Y : X;
+            const uint32_t b = (q & 1u) ? X : Y;
+            const uint32_t k1 = (q & 2u) ? a ^ kM : a;
+            const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+            const u64 me = ((u64)k2 << 23) | k1;
+            const u64 best = smin[addr];
+            bool ok = k2 < sexc[addr];
+            ok = ok && !(best < me && (uint32_t)(best & kM) <= k1);
+            if (ok) {
+                keep |= 1u << k;
+                rk[k] = (q << 23) | k1;
+                rv[k] = k2;
+                ri[k] = idx;
             }
-            keep |= (k ? 1u : 0u) << j;
         }
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPtsPerThread; ++j) {
-        if (((dupc >> j) & 1u) && sidx[addr[j]] != index_of(j)) keep &= ~(1u << j);
-    }
-
-    // Phase 4: compact the tile's kept records (one global atomic per tile).
     uint32_t total;
-    const uint32_t off = block_excl_sum(__popc(keep), scratch, total);
+    uint32_t pos = block_excl_sum(__popc(keep), scratch, total);
     if (tid == 0) sbase = total ? atomicAdd(&hdr->cand, total) : 0u;
     __syncthreads();
-    uint32_t pos = sbase + off;
+    pos += sbase;
 #pragma unroll
-    for (int j = 0; j < kPtsPerThread; ++j) {
-        if ((keep >> j) & 1u) {
-            const uint32_t q = addr[j] >> kSlotBits;
-            out_key[pos] = (q << 23) | ((uint32_t)me[j] & kM);
-            out_val[pos] = ((me[j] >> 23) << 32) | index_of(j);
+    for (int k = 0; k < kPer; ++k) {
+        if ((keep >> k) & 1u) {
+            out_key[pos] = rk[k];
+            out_val[pos] = ((u64)rv[k] << 32) | ri[k];
             ++pos;
         }
     }
@@ -822,7 +936,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint32_t* __restrict
 // exactly that running minimum, since a discarded record never lowers it.
 // Records with equal (q, k1) form a group; only the group's smallest
 // (k2, index) can survive, and it does iff its k2 is below the minimum over
-// the records before the group.
+// the records before the group.  Group minima come from a segmented suffix
+// minimum over the tile; a group that runs past the tile's end is finished
+// by its head's workgroup reading forward together, 256 records at a time.
 //
 // The prefix minimum runs over tagged values ((3 - q) << 23 | k2): records of
 // earlier regions carry larger tags, so a prefix minimum carrying this
@@ -830,18 +946,44 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint32_t* __restrict
 // the survivor count of all earlier tiles by decoupled look-back.  Survivors
 // are written as (index, x, y) at their rank in the chain order: into the
 // pinned host buffer while the rank fits it, into device memory beyond.
+//
+// With `prehull`, a tile also drops the survivors that are not on the lower
+// convex chain (in the region's frame, which is a rotation) of the tile's
+// survivors of the same region.  Such a point lies on or above the segment
+// joining two survivors on either side of it, so its support value never
+// strictly exceeds theirs for any outward direction of that corner: it is
+// not a strict hull vertex.  This shortens the polygon the finish scans
+// without changing its hull.
 // ---------------------------------------------------------------------------
+
+// Frame cross product (o, a, b): > 0 for a left turn.
+__device__ inline i64 frame_turn(uint32_t o1, uint32_t o2, uint32_t a1, uint32_t a2, uint32_t b1, uint32_t b2)
+{
+    return (i64)((int32_t)a1 - (int32_t)o1) * (i64)((int32_t)b2 - (int32_t)o2) -
+           (i64)((int32_t)a2 - (int32_t)o2) * (i64)((int32_t)b1 - (int32_t)o1);
+}
 
 __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict__ key, const u64* __restrict__ val,
                                                       DevHeader* __restrict__ hdr, u64* __restrict__ look_min,
                                                       u64* __restrict__ look_cnt, uint32_t* __restrict__ ticket,
                                                       PolyRec* __restrict__ host_chain, uint32_t host_cap,
-                                                      PolyRec* __restrict__ dev_chain)
+                                                      PolyRec* __restrict__ dev_chain, int prehull)
 {
     __shared__ uint32_t scratch[kWaves];
     __shared__ uint32_t s_tile, s_min_before, s_cnt_before;
-    __shared__ uint32_t kcnt[4];
+    __shared__ uint32_t kcnt[4], kspa[4];
     __shared__ uint32_t sigma[4];
+    __shared__ uint32_t shb[kBlock];     // head bits of each thread's records
+    __shared__ u64 sseg[kBlock];         // suffix minima per thread (segment carry)
+    __shared__ uint32_t sflag[kBlock];
+    __shared__ u64 wtot[kWaves];
+    __shared__ uint32_t wflag[kWaves];
+    __shared__ uint32_t s_last_head, s_cont;
+    __shared__ u64 s_ext;
+    __shared__ u64 sk[kSpaTile];         // survivors' frame coordinates k1 | k2 << 32
+    __shared__ uint8_t sq[kSpaTile];     // and region
+    __shared__ uint8_t alive[kSpaTile];
+    __shared__ uint16_t stk[kSpaTile];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t count = hdr->err ? 0u : hdr->cand;
@@ -851,7 +993,10 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
 
     for (;;) {
         if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-        if (tid < 4) kcnt[tid] = 0;
+        if (tid < 4) {
+            kcnt[tid] = 0;
+            kspa[tid] = 0;
+        }
         __syncthreads();
         const uint32_t t = s_tile;
         if (t >= ntiles) break;
@@ -889,27 +1034,161 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
         __syncthreads();
         const uint32_t before = min(s_min_before, before_in_tile);
 
-        uint32_t keep = 0;
-        u64 gmin[kSpaIpt];
+        // --- group minima: segmented suffix minimum over the tile ---
+        // head bit j: record base+j starts a group (records past the end
+        // count as heads so that they close every segment)
+        uint32_t hb = 0;
+        if (tid == 0) s_last_head = 0;
 #pragma unroll
         for (int j = 0; j < kSpaIpt; ++j) {
             const uint32_t i = base + j;
-            gmin[j] = vv[j];
-            if (i < count) {
+            const uint32_t prev = j > 0 ? kk[j > 0 ? j - 1 : 0] : (i > 0 && i < count ? key[i - 1] : ~0u);
+            if (i >= count || prev != kk[j]) hb |= 1u << j;
+        }
+        shb[tid] = hb;
+        __syncthreads();
+        // brk bit j: the segment of record j ends at j (record j+1 is a head,
+        // or j is the tile's last record)
+        const uint32_t next0 = tid + 1 < (uint32_t)kBlock ? (shb[tid + 1] & 1u) : 1u;
+        const uint32_t brk = (hb >> 1) | (next0 << (kSpaIpt - 1));
+        // thread aggregate: minimum from item 0 to the first break, and
+        // whether a break occurs
+        u64 agg = ~0ull;
+        uint32_t fl = 0;
+#pragma unroll
+        for (int j = 0; j < kSpaIpt; ++j) {
+            if (!fl) {
+                agg = vv[j] < agg ? vv[j] : agg;
+                fl = (brk >> j) & 1u;
+            }
+        }
+        // reverse inclusive scan of (fl, agg) under (fL,aL)+(fR,aR) =
+        // fL ? (1,aL) : (fR, min(aL,aR)); wave level, then across waves
+        {
+            const uint32_t lane = lane_id(), wave = tid / 64;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const u64 oa = __shfl_down(agg, off);
+                const uint32_t of = __shfl_down(fl, off);
+                if (lane + off < 64 && !fl) {
+                    agg = oa < agg ? oa : agg;
+                    fl = of;
+                }
+            }
+            if (lane == 0) {
+                wtot[wave] = agg;
+                wflag[wave] = fl;
+            }
+            __syncthreads();
+            if (!fl) {
+                for (int w = wave + 1; w < kWaves; ++w) {
+                    agg = wtot[w] < agg ? wtot[w] : agg;
+                    if (wflag[w]) break;
+                }
+            }
+            sseg[tid] = agg;
+            __syncthreads();
+        }
+        // per-record suffix minimum of its segment inside the tile
+        u64 gmin[kSpaIpt];
+        {
+            u64 run = tid + 1 < (uint32_t)kBlock ? sseg[tid + 1] : ~0ull;
+#pragma unroll
+            for (int j = kSpaIpt - 1; j >= 0; --j) {
+                if ((brk >> j) & 1u) run = vv[j];
+                else run = vv[j] < run ? vv[j] : run;
+                gmin[j] = run;
+            }
+        }
+        // the tile's last group may continue into later tiles
+#pragma unroll
+        for (int j = 0; j < kSpaIpt; ++j) {
+            if (((hb >> j) & 1u) && base + j < count) atomicMax(&s_last_head, base + j + 1);
+        }
+        __syncthreads();
+        const uint32_t tile_end = min(count, (t + 1) * kSpaTile);
+        if (tid == 0) {
+            s_cont = (s_last_head != 0 && tile_end < count && key[tile_end] == key[tile_end - 1]) ? 1u : 0u;
+            s_ext = ~0ull;
+        }
+        __syncthreads();
+        if (s_cont) {
+            const uint32_t gkey = key[tile_end - 1];
+            u64 m = ~0ull;
+            for (uint32_t at = tile_end;; at += kBlock) {
+                const uint32_t i = at + tid;
+                const bool in = i < count && key[i] == gkey;
+                if (in) m = val[i] < m ? val[i] : m;
+                if (!__syncthreads_or(!in)) continue;
+                break;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const u64 o = __shfl_xor(m, off);
+                m = o < m ? o : m;
+            }
+            if (lane_id() == 0) atomicMin(&s_ext, m);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kSpaIpt; ++j) {
+                if (base + j + 1 == s_last_head) gmin[j] = s_ext < gmin[j] ? s_ext : gmin[j];
+            }
+        }
+
+        uint32_t keep = 0;
+#pragma unroll
+        for (int j = 0; j < kSpaIpt; ++j) {
+            const uint32_t i = base + j;
+            if (i < count && ((hb >> j) & 1u)) {
                 const uint32_t q = kk[j] >> 23;
                 const uint32_t pm = min(before, pre[j]);
                 uint32_t thr = sigma[q];
                 if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
-                const uint32_t prev = j > 0 ? kk[j > 0 ? j - 1 : 0] : (i > 0 ? key[i - 1] : ~0u);
-                if (prev != kk[j]) {
-                    // group head: the group's smallest (k2, index)
-                    u64 g = vv[j];
-                    for (uint32_t m = i + 1; m < count && key[m] == kk[j]; ++m) {
-                        const u64 vm = val[m];
-                        g = vm < g ? vm : g;
+                if ((uint32_t)(gmin[j] >> 32) < thr) {
+                    keep |= 1u << j;
+                    atomicAdd(&kspa[q], 1u);
+                }
+            }
+        }
+        if (prehull) {
+            // stage the tile's survivors in chain order, scan each region's
+            // run for its lower convex chain (one thread), drop the rest
+            uint32_t n_tile;
+            const uint32_t first = block_excl_sum(__popc(keep), scratch, n_tile);
+            uint32_t at = first;
+#pragma unroll
+            for (int j = 0; j < kSpaIpt; ++j) {
+                if ((keep >> j) & 1u) {
+                    sk[at] = (u64)(kk[j] & kM) | ((gmin[j] >> 32) << 32);
+                    sq[at] = (uint8_t)(kk[j] >> 23);
+                    ++at;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t top = 0;
+                for (uint32_t i = 0; i < n_tile; ++i) {
+                    const u64 p = sk[i];
+                    const uint32_t p1 = (uint32_t)p, p2 = (uint32_t)(p >> 32);
+                    if (i > 0 && sq[i] != sq[i - 1]) top = 0;  // a new region starts
+                    while (top >= 2) {
+                        const u64 o = sk[stk[top - 2]], a = sk[stk[top - 1]];
+                        if (frame_turn((uint32_t)o, (uint32_t)(o >> 32), (uint32_t)a, (uint32_t)(a >> 32), p1, p2) > 0)
+                            break;
+                        alive[stk[top - 1]] = 0;
+                        --top;
                     }
-                    gmin[j] = g;
-                    if ((uint32_t)(g >> 32) < thr) keep |= 1u << j;
+                    stk[top++] = (uint16_t)i;
+                    alive[i] = 1;
+                }
+            }
+            __syncthreads();
+            at = first;
+#pragma unroll
+            for (int j = 0; j < kSpaIpt; ++j) {
+                if ((keep >> j) & 1u) {
+                    if (!alive[at]) keep &= ~(1u << j);
+                    ++at;
                 }
             }
         }
@@ -947,7 +1226,10 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
             }
         }
         __syncthreads();
-        if (tid < 4 && kcnt[tid]) atomicAdd(&hdr->s2[tid], kcnt[tid]);
+        if (tid < 4) {
+            if (kcnt[tid]) atomicAdd(&hdr->w2[tid], kcnt[tid]);
+            if (kspa[tid]) atomicAdd(&hdr->s2[tid], kspa[tid]);
+        }
         __syncthreads();
     }
 }
@@ -971,6 +1253,8 @@ struct Workspace {
     DevHeader* hdr = nullptr;
     ExtPartial* part = nullptr;
     uint32_t* ghist = nullptr;
+    uint32_t* samp = nullptr;
+    uint32_t* stair = nullptr;
     uint32_t* key[2] = {nullptr, nullptr};
     u64* val[2] = {nullptr, nullptr};
     LookAreas look = {};
@@ -996,6 +1280,8 @@ size_t device_bytes(size_t cap)
     b += align_up(sizeof(DevHeader), 256);
     b += align_up(sizeof(ExtPartial) * kExtBlocks, 256);
     b += align_up(sizeof(uint32_t) * kPassBins, 256);
+    b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
+    b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
     b += 2 * align_up(sizeof(uint32_t) * cap, 256);
     b += 2 * align_up(sizeof(u64) * cap, 256);
     b += 2 * align_up(sizeof(u64) * sort_tile_cap(cap) * 256, 256);
@@ -1056,6 +1342,8 @@ int ensure_device(Workspace& w, size_t n)
     w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kExtBlocks));
     w.ghist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kPassBins));
+    w.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
+    w.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
     for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * cap));
     for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * cap));
     const size_t st = sort_tile_cap(cap), sp = spa_tile_cap(cap);
@@ -1065,8 +1353,6 @@ int ensure_device(Workspace& w, size_t n)
     w.look.spa_min = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
     w.look.spa_cnt = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
     w.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
-    // the extreme-point ticket must start at zero
-    CH_TRY(hipMemsetAsync(w.hdr, 0, sizeof(DevHeader), w.stream));
     return CH_OK;
 }
 
@@ -1135,24 +1421,22 @@ int record(Workspace& w, int k)
 // Steps 1-6 on the device; the chains end in w.h_chain (and w.spill), the
 // counts in w.h_hdr.  Timing events: 0 | k_extremes | 1 | k_classify | 2 |
 // sort | 3 | SPA + chains | 4 | copy-out | 5.
-int run_preprocess(Workspace& w, const float* pts, uint32_t n)
+int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
 {
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
     const uint32_t n4 = (n - head) / 2;
     const uint32_t gext = std::max<uint32_t>(
-        1u, std::min<uint32_t>(kExtBlocks, (n4 + kBlock * kExtUnroll - 1) / (kBlock * kExtUnroll)));
-    CH_LAUNCH(hipLaunchKernelGGL(k_extremes, dim3(gext), dim3(kBlock), 0, s, pts, n, head, w.part, w.hdr, w.ghist));
+        kSampleBlocks, std::min<uint32_t>(kExtBlocks, (n4 + kBlock * kExtUnroll - 1) / (kBlock * kExtUnroll)));
+    CH_LAUNCH(hipLaunchKernelGGL(k_extremes, dim3(gext), dim3(kBlock), 0, s, pts, n, head, w.part, w.samp));
+    CH_LAUNCH(hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(kFinal), 0, s, w.part, (int)gext, w.samp, w.hdr,
+                                 w.stair, w.ghist));
     CH_TRY(record(w, 1));
-    const uint32_t tiles = (n + kTilePts - 1) / kTilePts;
-    if (head == 0) {
-        CH_LAUNCH(hipLaunchKernelGGL(k_classify<true>, dim3(tiles), dim3(kBlock), 0, s, pts, n, w.hdr, w.key[0],
-                                     w.val[0]));
-    } else {
-        CH_LAUNCH(hipLaunchKernelGGL(k_classify<false>, dim3(tiles), dim3(kBlock), 0, s, pts, n, w.hdr, w.key[0],
-                                     w.val[0]));
-    }
+    const uint32_t gcls = std::max<uint32_t>(1u, std::min<uint32_t>(kClsGrid, (n4 + kBlock - 1) / kBlock));
+    auto classify = stats ? k_classify<true> : k_classify<false>;
+    CH_LAUNCH(hipLaunchKernelGGL(classify, dim3(gcls), dim3(kBlock), 0, s, pts, n, head, w.hdr, w.stair, w.key[0],
+                                 w.val[0]));
     CH_TRY(record(w, 2));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(256), dim3(kBlock), 0, s, w.key[0], w.hdr, w.ghist, w.look));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
@@ -1164,7 +1448,7 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n)
     CH_TRY(record(w, 3));
     CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
                                  w.look.spa_min, w.look.spa_cnt, &w.hdr->ticket[3], w.h_chain_dev,
-                                 (uint32_t)w.h_chain_cap, w.dev_chain));
+                                 (uint32_t)w.h_chain_cap, w.dev_chain, stats ? 0 : 1));
     CH_TRY(record(w, 4));
     CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
     CH_TRY(record(w, 5));
@@ -1204,7 +1488,7 @@ void build_polygon(Workspace& w)
     size_t at = 0;
     for (int q = 0; q < 4; ++q) {
         push((int32_t)h.ext_idx[q], (int32_t)h.ext_x[q], (int32_t)h.ext_y[q]);
-        for (uint32_t k = 0; k < h.s2[q]; ++k, ++at) {
+        for (uint32_t k = 0; k < h.w2[q]; ++k, ++at) {
             const PolyRec& r = chain_at(w, at);
             push(r.idx, r.x, r.y);
         }
@@ -1216,7 +1500,7 @@ void build_polygon(Workspace& w)
     }
 }
 
-void fill_stats(const Workspace& w, int64_t n, ch_stats* st)
+void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
 {
     std::memset(st, 0, sizeof(*st));
     st->n = n;
@@ -1226,7 +1510,7 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st)
         st->ext_idx[e] = (int32_t)h.ext_idx[e];
         st->ext_xy[2 * e] = (int32_t)h.ext_x[e];
         st->ext_xy[2 * e + 1] = (int32_t)h.ext_y[e];
-        st->s1[e] = h.s1[e];
+        st->s1[e] = stats ? (int64_t)h.s1[e] : -1;
         st->s2[e] = h.s2[e];
     }
     st->candidates = h.cand;
@@ -1253,18 +1537,17 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     Workspace* w = workspace_for(stream, &rc);
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
-    CH_TRY(ensure_host(*w, 0));
     if (n == 0) {
-        w->h_out[0] = 0;
-        CH_TRY(hipMemcpyAsync(out_count, w->h_out, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        CH_TRY(hipStreamSynchronize(stream));
+        // no host buffer: a copy from an earlier call may still read it
+        CH_TRY(hipMemsetAsync(out_count, 0, sizeof(int32_t), stream));
         return CH_OK;
     }
+    CH_TRY(ensure_host(*w, 0));
     CH_TRY(ensure_device(*w, (size_t)n));
-    rc = run_preprocess(*w, points, (uint32_t)n);
+    rc = run_preprocess(*w, points, (uint32_t)n, false);
     int64_t h = 0;
     if (rc == CH_OK) {
-        fill_stats(*w, n, &st);
+        fill_stats(*w, n, &st, false);
         const auto t0 = std::chrono::steady_clock::now();
         build_polygon(*w);
         rc = ensure_host(*w, w->idx.size());
@@ -1277,12 +1560,18 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
         st.ms[7] = std::chrono::duration<float, std::milli>(t1 - t0).count();
         st.hull = h;
     }
-    if (rc != CH_OK) h = 0;
+    if (rc != CH_OK) {
+        // the call may have failed before its mid-call synchronisation
+        (void)hipStreamSynchronize(stream);
+        (void)hipMemsetAsync(out_count, 0, sizeof(int32_t), stream);
+        return rc;
+    }
+    // Stream-ordered results: the pinned buffer is rewritten only after the
+    // next call's synchronisation on this stream, which follows these copies.
     w->h_out[0] = (int32_t)h;
     CH_TRY(hipMemcpyAsync(out_count, w->h_out, sizeof(int32_t), hipMemcpyHostToDevice, stream));
     if (h) CH_TRY(hipMemcpyAsync(out_idx, w->h_out + 1, sizeof(int32_t) * (size_t)h, hipMemcpyHostToDevice, stream));
-    CH_TRY(hipStreamSynchronize(stream));
-    return rc;
+    return CH_OK;
 }
 
 }  // namespace
@@ -1340,9 +1629,9 @@ int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t
     std::lock_guard<std::mutex> lk(w->mu);
     CH_TRY(ensure_host(*w, 0));
     CH_TRY(ensure_device(*w, (size_t)n));
-    rc = run_preprocess(*w, points, (uint32_t)n);
+    rc = run_preprocess(*w, points, (uint32_t)n, true);
     if (rc != CH_OK) return rc;
-    fill_stats(*w, n, &st);
+    fill_stats(*w, n, &st, true);
     build_polygon(*w);
     for (size_t i = 0; i < w->idx.size(); ++i) poly_idx[i] = w->idx[i];
     *poly_count = (int64_t)w->idx.size();

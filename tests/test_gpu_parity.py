@@ -193,3 +193,24 @@ def test_timing_stats():
     assert st["n"] == 200_000 and st["hull"] > 2
     assert all(v >= 0 for v in st["ms"].values())
     assert st["ms"]["classify"] > 0
+
+
+@pytest.mark.parametrize("seed", [74, 75])
+def test_long_groups_across_tiles(seed):
+    """Many points share a region's k1 (box sides, a column inside a region,
+    repeated vertices), so equal-key groups span several sort and SPA tiles."""
+    rng = wl.rng_for(seed)
+    m = 60_000
+    side = rng.integers(0, 1 << 23, size=m)
+    parts = [
+        np.stack([np.zeros(m), side], 1),                       # x = 0
+        np.stack([side, np.zeros(m)], 1),                       # y = 0
+        np.stack([np.full(m, wl.M), rng.integers(0, 1 << 23, m)], 1),   # x = M
+        np.stack([np.full(m, 123), rng.integers(0, 4_000_000, m)], 1),  # a column in R1
+        np.tile(np.array([[0, 5_000_000]]), (m, 1)),            # a repeated vertex
+        rng.integers(1_000_000, 7_000_000, size=(4 * m, 2)),
+    ]
+    pts = np.concatenate(parts).astype(np.float32)
+    pts = pts[rng.permutation(pts.shape[0])]
+    assert_parity(pts, f"long groups seed={seed}")
+    stage_parity(pts, f"long groups seed={seed}")
