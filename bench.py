@@ -51,16 +51,25 @@ def src_hash() -> str:
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source."""
-    path = os.path.join(PROFILE_DIR, f"{kernel}_traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    ``kernel`` (``profiles/<kernel>_traffic_20m.md``), if its counters were
+    taken on the current kernel source.  The summary holds ``key: value``
+    lines, among them ``source_sha256_16`` and ``bytes_per_launch``."""
+    path = os.path.join(PROFILE_DIR, f"{kernel}_traffic_20m.md")
     if not os.path.exists(path):
         return None
+    rec = {}
     with open(path) as f:
-        rec = json.load(f)
+        for line in f:
+            k, sep, v = line.strip().lstrip("-* ").partition(":")
+            if sep:
+                rec[k.strip().strip("`")] = v.strip().strip("`")
     if rec.get("source_sha256_16") != src_hash():
         return None
-    return rec.get("bytes_per_launch")
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():

@@ -99,8 +99,10 @@ struct DevHeader {
     uint32_t pad[8];
 };
 
+// Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
+// P_maxx are the minimum and maximum of key 0, P_miny and P_maxy of key 1.
 struct ExtPartial {
-    i64 kmin[2], kmax[2];      // key 0 = (x, M - y), key 1 = (y, x)
+    u64 kmin[2], kmax[2];
     uint32_t imin[2], imax[2];
     uint32_t err;
     uint32_t pad[3];
@@ -124,7 +126,7 @@ struct LookAreas {
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
-__device__ inline void take_min(i64& k, uint32_t& i, i64 ok, uint32_t oi)
+__device__ inline void take_min(u64& k, uint32_t& i, u64 ok, uint32_t oi)
 {
     if (ok < k || (ok == k && oi < i)) {
         k = ok;
@@ -132,7 +134,7 @@ __device__ inline void take_min(i64& k, uint32_t& i, i64 ok, uint32_t oi)
     }
 }
 
-__device__ inline void take_max(i64& k, uint32_t& i, i64 ok, uint32_t oi)
+__device__ inline void take_max(u64& k, uint32_t& i, u64 ok, uint32_t oi)
 {
     if (ok > k || (ok == k && oi < i)) {
         k = ok;
@@ -224,6 +226,10 @@ __device__ inline void look_store(u64* p, u64 v)
 // in a running workgroup and publishes its aggregate before it waits on
 // anything, so the wait ends; the bound only guards against a broken
 // invariant (it then flags kErrSpin instead of hanging).
+// The words of up to kLookBatch earlier tiles are loaded at once, so a
+// walk past many tiles that only published aggregates costs few round trips.
+constexpr int kLookBatch = 16;
+
 template <bool kMin>
 __device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, uint32_t* err)
 {
@@ -231,20 +237,28 @@ __device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, u
     uint32_t spins = 0;
     int64_t j = (int64_t)t - 1;
     while (j >= 0) {
-        const u64 w = look_load(words + (u64)j * stride);
-        const u64 f = w & ~kValMask;
-        if (f == 0) {
-            if (++spins > kSpinMax) {
-                atomicOr(err, kErrSpin);
-                break;
+        u64 w[kLookBatch];
+#pragma unroll
+        for (int b = 0; b < kLookBatch; ++b) w[b] = j - b >= 0 ? look_load(words + (u64)(j - b) * stride) : kFlagInc;
+        bool done = false;
+#pragma unroll
+        for (int b = 0; b < kLookBatch; ++b) {
+            if (done || j < 0) continue;
+            u64 v = w[b];
+            while ((v & ~kValMask) == 0) {  // not published yet: wait for it
+                if (++spins > kSpinMax) {
+                    atomicOr(err, kErrSpin);
+                    return acc;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                v = look_load(words + (u64)j * stride);
             }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
+            const u64 x = v & kValMask;
+            acc = kMin ? (x < acc ? x : acc) : acc + x;
+            if ((v & ~kValMask) == kFlagInc) done = true;
+            else --j;
         }
-        const u64 v = w & kValMask;
-        acc = kMin ? (v < acc ? v : acc) : acc + v;
-        if (f == kFlagInc) break;
-        --j;
+        if (done) break;
     }
     return acc;
 }
@@ -257,38 +271,51 @@ __device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, u
 // minimum at P_miny and its maximum at P_maxy.  Ties go to the smallest index.
 // ---------------------------------------------------------------------------
 
+// A maximum still at its initial (0, ~0u) after the reduction means that
+// every key is 0; the minimum's index is then the answer (k_extremes_final).
 struct ExtAcc {
-    i64 kmin[2], kmax[2];
+    u64 kmin[2], kmax[2];
     uint32_t imin[2], imax[2];
-    uint32_t bad, hi;
+    uint32_t hi;
+    bool bad;
 };
 
 __device__ inline void ext_init(ExtAcc& a)
 {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        a.kmin[e] = (i64)kValMask;
-        a.kmax[e] = -1;
+        a.kmin[e] = ~0ull;
+        a.kmax[e] = 0;
         a.imin[e] = ~0u;
         a.imax[e] = ~0u;
     }
-    a.bad = 0;
+    a.bad = false;
     a.hi = 0;
 }
 
 // Integer value of a coordinate clamped to [0, 2^24]; NaN gives 0.
 __device__ inline uint32_t coord_u32(float v) { return (uint32_t)fminf(fmaxf(v, 0.0f), 16777216.0f); }
 
+// The hardware conversion: truncates, saturates to [0, 2^32 - 1], NaN gives 0.
+__device__ inline uint32_t cvt_u32_sat(float v)
+{
+    uint32_t r;
+    asm("v_cvt_u32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 // A thread visits its points in increasing index order, so strict
-// comparisons keep the smallest index among equal keys.
+// comparisons keep the smallest index among equal keys.  A coordinate is in
+// the domain iff its conversion converts back to it exactly (so it is an
+// integer, not NaN, not negative apart from -0) and the maximum over all
+// coordinates is at most M.
 __device__ inline void ext_visit(ExtAcc& a, float fx, float fy, uint32_t idx)
 {
-    const uint32_t X = coord_u32(fx), Y = coord_u32(fy);
-    // integer-valued and finite; the range is checked on the maximum
-    a.bad |= ((float)X != fx) | ((float)Y != fy);
+    const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
+    a.bad = a.bad | ((float)X != fx) | ((float)Y != fy);
     a.hi = max(a.hi, max(X, Y));
-    const i64 k0 = ((i64)X << 23) | (i64)(Y ^ kM);
-    const i64 k1 = ((i64)Y << 23) | (i64)X;
+    const u64 k0 = ((u64)X << 32) | (Y ^ kM);
+    const u64 k1 = ((u64)Y << 32) | X;
     if (k0 < a.kmin[0]) { a.kmin[0] = k0; a.imin[0] = idx; }
     if (k0 > a.kmax[0]) { a.kmax[0] = k0; a.imax[0] = idx; }
     if (k1 < a.kmin[1]) { a.kmin[1] = k1; a.imin[1] = idx; }
@@ -340,8 +367,8 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // each region's frame, the smallest k2 per k1-slot of 2^14 values (for any
 // point, not only the region's: see k_classify).  k_extremes_final turns
 // them into exclusive prefix minima over the slots.
-constexpr int kSampleBlocks = 64;
-constexpr int kSamplePerThread = 8;
+constexpr int kSampleBlocks = 16;
+constexpr int kSamplePerThread = 32;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
 constexpr int kStairBits = 9;
 constexpr int kStairSlots = 1 << kStairBits;
@@ -440,7 +467,7 @@ __global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __r
             o.imin[e] = p.imin[e];
             o.imax[e] = p.imax[e];
         }
-        o.bad = p.err;
+        o.bad = p.err != 0;
         o.hi = 0;
         ext_combine(r, o);
     }
@@ -449,13 +476,22 @@ __global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __r
     for (uint32_t d = tid; d < kPassBins; d += kFinal) ghist[d] = 0;
 
     // Staircases: thread t owns slot t of each region's frame (needs
-    // kFinal >= kStairSlots); exclusive prefix minimum over the slots.
+    // kFinal >= kStairSlots); exclusive prefix minimum over the slots.  All
+    // sample minima are loaded before the first is used.
+    uint32_t vq[4] = {~0u, ~0u, ~0u, ~0u};
+    if (tid < (uint32_t)kStairSlots) {
+        uint32_t t[4][kSampleBlocks];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < kSampleBlocks; ++b) t[q][b] = samp[b * 4 * kStairSlots + q * kStairSlots + tid];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < kSampleBlocks; ++b) vq[q] = min(vq[q], t[q][b]);
+    }
     for (int q = 0; q < 4; ++q) {
-        uint32_t v = ~0u;
-        if (tid < (uint32_t)kStairSlots) {
-#pragma unroll 16
-            for (int b = 0; b < kSampleBlocks; ++b) v = min(v, samp[b * 4 * kStairSlots + q * kStairSlots + tid]);
-        }
+        const uint32_t v = vq[q];
         const uint32_t incl = wave_incl_min(v);
         uint32_t excl = __shfl_up(incl, 1);
         if (lane == 0) excl = ~0u;
@@ -470,14 +506,21 @@ __global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __r
     if (tid != 0) return;
     for (int w = 1; w < kW; ++w) ext_combine(r, sh[w]);
 
-    // P_minx, P_miny, P_maxx, P_maxy
-    const i64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
+    for (int e = 0; e < 2; ++e) {
+        if (r.imax[e] == ~0u) {
+            r.kmax[e] = r.kmin[e];
+            r.imax[e] = r.imin[e];
+        }
+    }
+    // P_minx, P_miny, P_maxx, P_maxy (masked so that a rejected input still
+    // gives in-range values)
+    const u64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
     const uint32_t idx[4] = {r.imin[0], r.imin[1], r.imax[0], r.imax[1]};
     uint32_t X[4], Y[4];
-    X[0] = (uint32_t)(key[0] >> 23); Y[0] = (uint32_t)(key[0] & kM) ^ kM;
-    Y[1] = (uint32_t)(key[1] >> 23); X[1] = (uint32_t)(key[1] & kM);
-    X[2] = (uint32_t)(key[2] >> 23); Y[2] = (uint32_t)(key[2] & kM) ^ kM;
-    Y[3] = (uint32_t)(key[3] >> 23); X[3] = (uint32_t)(key[3] & kM);
+    X[0] = (uint32_t)(key[0] >> 32) & kM; Y[0] = ((uint32_t)key[0] & kM) ^ kM;
+    Y[1] = (uint32_t)(key[1] >> 32) & kM; X[1] = (uint32_t)key[1] & kM;
+    X[2] = (uint32_t)(key[2] >> 32) & kM; Y[2] = ((uint32_t)key[2] & kM) ^ kM;
+    Y[3] = (uint32_t)(key[3] >> 32) & kM; X[3] = (uint32_t)key[3] & kM;
     for (int e = 0; e < 4; ++e) {
         hdr->ext_x[e] = X[e];
         hdr->ext_y[e] = Y[e];
@@ -535,8 +578,8 @@ __global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __r
 //    slot's smallest point precedes it with k1 <= its k1.  The rest is written
 //    out.  Points that do not fit the list are written out unfiltered.
 //
-// With kStats the sample test is skipped and every point's region is counted
-// (the round-1 survivors).
+// With kStats every point also takes the region test so that the round-1
+// survivors are counted; the filters are the same.
 // ---------------------------------------------------------------------------
 
 constexpr int kClsGrid = 1024;      // persistent workgroups of k_classify
@@ -573,9 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
         P.ey[q] = (double)hdr->ey[q];
     }
     for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
-    if (!kStats) {
-        for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
-    }
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
     if (tid == 0) s_count = 0;
     __syncthreads();
 
@@ -584,8 +625,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
     // lane of the wave calls it together (the list append is wave-wide).
     auto visit = [&](float fx, float fy, uint32_t idx, bool valid) {
         const uint32_t X = (uint32_t)fx, Y = (uint32_t)fy;
-        uint32_t open = valid ? 0xfu : 0u;
-        if (!kStats && valid) {
+        uint32_t open = 0;
+        if (valid) {
             const uint32_t xm = X ^ kM, ym = Y ^ kM;
             open = (Y < sst[0 * kStairSlots + (X >> kStairShift)] ? 1u : 0u) |
                    (xm < sst[1 * kStairSlots + (Y >> kStairShift)] ? 2u : 0u) |
@@ -593,7 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
                    (X < sst[3 * kStairSlots + (ym >> kStairShift)] ? 8u : 0u);
         }
         uint32_t addr = ~0u;
-        if (open) {
+        // kStats: every point's region is counted; only the sample test's
+        // survivors are listed either way
+        if (kStats ? valid : open != 0) {
             const double dx = (double)fx, dy = (double)fy;
             // exact: every product is below 2^46 and every sum below 2^47
             const bool t0 = fma(P.ex[0], dy, -(P.ey[0] * dx)) < P.ec[0];
@@ -618,22 +661,29 @@ __global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ p
         }
         const u64 want = __ballot(addr != ~0u);
         if (want) {
+            const int lead = __ffsll((long long)want) - 1;
             uint32_t first = 0;
-            if (lane == (uint32_t)__ffsll((long long)want) - 1) first = atomicAdd(&s_count, (uint32_t)__popcll(want));
-            first = __shfl(first, __ffsll((long long)want) - 1);
-            if (addr != ~0u) {
-                const uint32_t slot = first + (uint32_t)__popcll(want & lt);
-                if (slot < (uint32_t)kCandCap) {
-                    cl_idx[slot] = idx;
-                    cl_addr[slot] = addr;
-                } else {
-                    // list full: write the point unfiltered
+            if (lane == (uint32_t)lead) first = atomicAdd(&s_count, (uint32_t)__popcll(want));
+            first = __shfl(first, lead);
+            const uint32_t slot = addr != ~0u ? first + (uint32_t)__popcll(want & lt) : 0u;
+            if (addr != ~0u && slot < (uint32_t)kCandCap) {
+                cl_idx[slot] = idx;
+                cl_addr[slot] = addr;
+            }
+            // list full: such points are written unfiltered, one atomic a wave
+            const u64 over = __ballot(addr != ~0u && slot >= (uint32_t)kCandCap);
+            if (over) {
+                const int olead = __ffsll((long long)over) - 1;
+                uint32_t obase = 0;
+                if (lane == (uint32_t)olead) obase = atomicAdd(&hdr->cand, (uint32_t)__popcll(over));
+                obase = __shfl(obase, olead);
+                if (addr != ~0u && slot >= (uint32_t)kCandCap) {
                     const uint32_t q = addr >> kSlotBits;
                     const uint32_t a = (q & 1u) ? Y : X;
                     const uint32_t b = (q & 1u) ? X : Y;
                     const uint32_t k1 = (q & 2u) ? a ^ kM : a;
                     const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-                    const uint32_t pos = atomicAdd(&hdr->cand, 1u);
+                    const uint32_t pos = obase + (uint32_t)__popcll(over & lt);
                     out_key[pos] = (q << 23) | k1;
                     out_val[pos] = ((u64)k2 << 32) | idx;
                 }
@@ -1234,6 +1284,17 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
     }
 }
 
+// The finished hull, from pinned host memory into the caller's buffers.  The
+// host rewrites that memory between calls, so it is read with system-scope
+// loads, which no stale cache line can serve.
+__global__ __launch_bounds__(kBlock) void k_put_result(const int32_t* host_hull, int32_t h,
+                                                       int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count)
+{
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < h) out_idx[i] = __hip_atomic_load(host_hull + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (i == 0) *out_count = h;
+}
+
 // ---------------------------------------------------------------------------
 // Host side: workspaces, the pipeline and the C ABI
 // ---------------------------------------------------------------------------
@@ -1263,7 +1324,8 @@ struct Workspace {
     PolyRec* h_chain = nullptr;     // pinned, device-visible
     PolyRec* h_chain_dev = nullptr; // its device address
     size_t h_chain_cap = 0;
-    int32_t* h_out = nullptr;       // pinned: count, then indices
+    int32_t* h_out = nullptr;       // pinned, device-visible: count, then indices
+    int32_t* h_out_dev = nullptr;   // its device address
     size_t h_out_cap = 0;
     std::vector<int32_t> xy, idx;   // finish input
     std::vector<PolyRec> spill;     // chain records beyond the pinned buffer
@@ -1369,7 +1431,8 @@ int ensure_host(Workspace& w, size_t out)
         if (w.h_out) CH_TRY(hipHostFree(w.h_out));
         w.h_out = nullptr;
         const size_t cap = std::max<size_t>(out + 1, 4096);
-        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_out), sizeof(int32_t) * cap, hipHostMallocDefault));
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_out), sizeof(int32_t) * cap, hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_out_dev), w.h_out, 0));
         w.h_out_cap = cap;
     }
     return CH_OK;
@@ -1569,8 +1632,9 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     // Stream-ordered results: the pinned buffer is rewritten only after the
     // next call's synchronisation on this stream, which follows these copies.
     w->h_out[0] = (int32_t)h;
-    CH_TRY(hipMemcpyAsync(out_count, w->h_out, sizeof(int32_t), hipMemcpyHostToDevice, stream));
-    if (h) CH_TRY(hipMemcpyAsync(out_idx, w->h_out + 1, sizeof(int32_t) * (size_t)h, hipMemcpyHostToDevice, stream));
+    const uint32_t g = (uint32_t)std::max<int64_t>(1, (h + kBlock - 1) / kBlock);
+    CH_LAUNCH(hipLaunchKernelGGL(k_put_result, dim3(g), dim3(kBlock), 0, stream, w->h_out_dev + 1, (int32_t)h,
+                                 out_idx, out_count));
     return CH_OK;
 }
 
