@@ -136,13 +136,11 @@ def main():
     for d, _ in DISTS:
         s = stats[d][-1]
         per_dist[d] = {
-            "hull": s["hull"], "s1": int(sum(s["s1"])), "candidates": s["candidates"], "s2": int(sum(s["s2"])),
-            "classify_ms": float(np.mean([x["ms"]["classify"] for x in stats[d]])),
-            "extremes_ms": float(np.mean([x["ms"]["extremes"] for x in stats[d]])),
-            "sort_ms": float(np.mean([x["ms"]["sort"] for x in stats[d]])),
-            "spa_ms": float(np.mean([x["ms"]["spa"] for x in stats[d]])),
-            "finish_ms": float(np.mean([x["ms"]["finish"] for x in stats[d]])),
+            "hull": s["hull"], "s1": int(sum(s["s1"])), "open": s["open"], "candidates": s["candidates"],
+            "s2": int(sum(s["s2"])),
         }
+        for key in ("sample", "stream", "cand", "sort", "spa", "finish"):
+            per_dist[d][key + "_ms"] = float(np.mean([x["ms"][key] for x in stats[d]]))
 
     # counts of the discard rounds (the stats mode of the library counts the
     # round-1 survivors; outside the timed regions)
@@ -151,14 +149,12 @@ def main():
         per_dist[d].update({"s1": int(sum(pst["s1"])), "s2": int(sum(pst["s2"]))})
     torch.cuda.synchronize()
 
-    # roofline of the dominant single kernel (extreme-point pass or classify)
-    cand_mean = float(np.mean([s["candidates"] for d, _ in DISTS for s in stats[d]]))
-    kernels = {
-        "k_classify": (stage_ms["classify"], 8.0 * n + 12.0 * cand_mean),
-        "k_extremes": (stage_ms["extremes"], 8.0 * n),
-    }
-    dom = max(kernels, key=lambda k: kernels[k][0])
-    dom_ms, dom_bytes = kernels[dom]
+    # roofline of the dominant kernel, the one pass over the points: it reads
+    # 8 bytes per point and writes 12 bytes per listed (open) point; its
+    # duration is the event pair that brackets its launch alone
+    open_mean = float(np.mean([s["open"] for d, _ in DISTS for s in stats[d]]))
+    dom = "k_stream"
+    dom_ms, dom_bytes = stage_ms["stream"], 8.0 * n + 12.0 * open_mean
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     traffic = load_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -167,7 +163,7 @@ def main():
 
     # whole-preprocessing accounting with B_alg = 16n + 24*s1 + 12*s2
     b_alg = [16.0 * n + 24.0 * per_dist[d]["s1"] + 12.0 * per_dist[d]["s2"] for d, _ in DISTS]
-    t_pre = sum(stage_ms[k] for k in ("extremes", "classify", "sort", "spa"))
+    t_pre = sum(stage_ms[k] for k in ("sample", "stream", "cand", "sort", "spa"))
     pre_frac = float(np.mean(b_alg)) / (t_pre * 1e-3) / (HBM_PEAK_GBS * 1e9) if t_pre > 0 else 0.0
 
     cpu = None
@@ -206,7 +202,7 @@ def main():
                    "n_points": n, "inputs_per_step": len(DISTS), "seeds": [s for _, s in DISTS]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "stages_ms": {k: round(v, 4) for k in ("extremes", "classify", "sort", "spa", "copy_out", "finish")
+        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "copy_out", "finish")
                       for v in [stage_ms[k]]},
         "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
         "preprocess_b_alg_frac": round(pre_frac, 4),

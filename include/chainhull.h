@@ -57,16 +57,20 @@ typedef struct {
     int32_t ext_xy[8];    /* their (x, y) */
     int64_t s1[4];        /* round-1 survivors in R1..R4 (Section 2.1.1); counted
                              by chainhull_polygon only, -1 after hull2d */
+    int64_t open;         /* points that pass the sampled-staircase dominance test
+                             in the single pass over the input */
     int64_t candidates;   /* records the dominance filters pass to the region sort */
     int64_t s2[4];        /* SPA survivors in R1..R4 (Figure 2) */
     int64_t polygon;      /* vertices of the polygon handed to the finish, the
                              four extreme points included, before de-duplication */
     int64_t hull;         /* hull vertices */
     /* Milliseconds per stage when timing is on (chainhull_set_timing), from
-     * HIP events on the call's stream: 0 extreme points (partial and final
-     * reduction), 2 quadrilateral discard + region distribution + dominance
-     * filters, 3 region sort, 4 SPA + chain concatenation, 6 copy of the
-     * counts to the host, 7 host finish (wall clock); 1 and 5 are unused. */
+     * HIP events on the call's stream: 0 sampled staircases, 1 the pass over
+     * the points (extreme-point keys, validation, staircase test), 2 extreme
+     * points reduced, quadrilateral discard + region distribution + second
+     * dominance filter (and, in chainhull_polygon, the round-1 counts),
+     * 3 region sort, 4 SPA + chain concatenation, 5 copy of the counts to
+     * the host, 7 host finish (wall clock); 6 is unused. */
     float ms[8];
 } ch_stats;
 

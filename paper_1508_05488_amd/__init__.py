@@ -24,7 +24,7 @@ EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_ho
            "chainhull_last_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_workspace_bytes")
 
-STAGES = ("extremes", "unused1", "classify", "sort", "spa", "unused5", "copy_out", "finish")
+STAGES = ("sample", "stream", "cand", "sort", "spa", "copy_out", "unused6", "finish")
 
 
 class ChainHullError(RuntimeError):
@@ -40,6 +40,7 @@ class ChStats(ctypes.Structure):
         ("ext_idx", ctypes.c_int32 * 4),
         ("ext_xy", ctypes.c_int32 * 8),
         ("s1", ctypes.c_int64 * 4),
+        ("open", ctypes.c_int64),
         ("candidates", ctypes.c_int64),
         ("s2", ctypes.c_int64 * 4),
         ("polygon", ctypes.c_int64),
@@ -53,6 +54,7 @@ class ChStats(ctypes.Structure):
             "ext_idx": list(self.ext_idx),
             "ext_xy": list(self.ext_xy),
             "s1": list(self.s1),
+            "open": self.open,
             "candidates": self.candidates,
             "s2": list(self.s2),
             "polygon": self.polygon,

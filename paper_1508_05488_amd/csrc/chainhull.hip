@@ -2,11 +2,14 @@
 // hand-written gfx950 kernels, the pipeline around them and the C ABI.
 //
 // Kernels of one hull (all on the caller's stream):
-//   k_extremes      step 1: extreme points + validation; the last workgroup
-//                   reduces the partials and derives edges and frames
-//   k_classify      step 2: exact region test (first discard) fused with a
-//                   tile-level use of the SPA dominance rule; writes the
-//                   tile's possible chain points
+//   k_sample        a strided sample of the points: per-frame slot minima
+//   k_stair         the sampled staircases (prefix minima); clears counters
+//   k_stream        the one full pass over the points: step 1's extreme
+//                   keys and the domain check, and the sampled-staircase
+//                   dominance test; lists the points that pass it
+//   k_cand          reduces the extreme points (quadrilateral), step 2's
+//                   exact region test on the listed points, a second
+//                   dominance filter; writes the sort records
 //   k_sort_prep     digit counts of the region sort; clears the look-back
 //   k_sort_pass x3  steps 3-4: stable LSD radix passes over (region, k1)
 //   k_spa_chain     steps 5-6: SPA as a segmented prefix minimum, ordered
@@ -15,8 +18,11 @@
 // and the result copied into the caller's device buffers.
 //
 // Data layout in HBM (one workspace per device and stream):
-//   points           caller's n x float32[2], read twice (k_extremes, k_classify)
-//   ExtPartial[G1]   per-workgroup extreme keys
+//   points           caller's n x float32[2], read once in full (k_stream)
+//   samp, stair      sampled slot minima, staircases (4 x 1024 u32 each)
+//   ExtPartial[G]    per-workgroup extreme keys
+//   open lists       the points k_stream lists (index; x, y, frame mask),
+//                    held in the second sort buffers
 //   DevHeader        extreme points, quadrilateral edges, frames, counters
 //   ghist[1024]      digit counts of the three sort passes (256, 256, 512)
 //   key[2][cap]      u32 sort key  q << 23 | k1      (double buffer)
@@ -62,8 +68,6 @@ typedef long long i64;
 constexpr uint32_t kM = (1u << 23) - 1;
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kExtBlocks = 2048;   // workgroups of the extreme-point pass
-constexpr int kExtUnroll = 4;      // float4 loads in flight per thread
 constexpr int kSlotBits = 9;
 constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region and tile
 constexpr int kSortIpt = 8;                       // records per thread per sort tile
@@ -96,7 +100,8 @@ struct DevHeader {
     uint32_t w2[4];      // chain records written per region (after the pre-hull)
     uint32_t chain;      // chain records written in all
     uint32_t ticket[4];  // tile tickets: three sort passes and SPA
-    uint32_t pad[8];
+    uint32_t open;       // points listed by k_stream
+    uint32_t pad[7];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -272,7 +277,7 @@ __device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, u
 // ---------------------------------------------------------------------------
 
 // A maximum still at its initial (0, ~0u) after the reduction means that
-// every key is 0; the minimum's index is then the answer (k_extremes_final).
+// every key is 0; the minimum's index is then the answer (make_quad).
 struct ExtAcc {
     u64 kmin[2], kmax[2];
     uint32_t imin[2], imax[2];
@@ -362,68 +367,217 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
     }
 }
 
-// Sampled staircases.  The first kSampleBlocks workgroups also take a strided
-// sample of kSamplePts points spread over the whole array and record, in
-// each region's frame, the smallest k2 per k1-slot of 2^14 values (for any
-// point, not only the region's: see k_classify).  k_extremes_final turns
-// them into exclusive prefix minima over the slots.
+// ---------------------------------------------------------------------------
+// Steps 1-2 (Section 2.1 step 1; Section 2.1.1) in one pass over the points,
+// with the SPA dominance rule used as an early filter.
+//
+// A point p of region q is dominated by another point p' of the region when
+// k1' <= k1 and k2' <= k2 and p' precedes p in (k1, k2, index) order; then p
+// lies in the triangle (first point, p', last point) and is not a hull vertex
+// (the argument of Figure 3).  Dropping dominated points leaves the result of
+// the region sort and SPA unchanged, so any filter that only drops dominated
+// points may run before them.
+//
+// Sampled staircases.  k_sample takes a strided sample of kSamplePts points
+// and records, in each of the four region frames, the smallest k2 per slot of
+// 2^kStairShift k1 values, over all sample points (not only the region's);
+// k_stair turns them into exclusive prefix minima over the slots.  A sample
+// point p' with smaller k1 and k2 <= k2 of p in the frame of p's region lies
+// in that region as well (moving towards the corner never re-enters the
+// quadrilateral), so it dominates p there.  A point whose k2 is not below
+// the staircase in any of the four frames is therefore dominated in its own
+// region, or lies in no region, whatever the extreme points turn out to be:
+// the test needs no extreme point and runs in the same pass that finds them.
+//
+// k_stream reads every point once: the extreme-point keys and the domain
+// check, and the staircase test; the points that pass it ("open" points) go,
+// with their 4-bit frame mask, to a per-wave list in LDS that is flushed to
+// a compact array.  k_cand then reduces the extreme points, runs the exact
+// region test on the open points only (a point counts for its region only if
+// it passed that region's frame), and filters again with a staircase over
+// chunks of 1024 records: per region and k1-slot of 2^14 values the smallest
+// (k2, k1) in LDS; a record is dropped when the region's first point or a
+// record of an earlier slot has k2 <= its k2, or when its slot's smallest
+// record precedes it with k1 <= its k1.  The rest become sort records.
+// ---------------------------------------------------------------------------
+
 constexpr int kSampleBlocks = 16;
 constexpr int kSamplePerThread = 32;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
-constexpr int kStairBits = 9;
+constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
+constexpr int kStreamGrid = 1024;   // persistent workgroups of k_stream
+constexpr int kStreamUnroll = 4;    // float4 loads in flight per thread
+constexpr int kWaveList = 256;      // open points listed per wave before a flush
+constexpr int kCandGrid = 256;      // persistent workgroups of k_cand
+constexpr int kCandChunk = 1024;    // records filtered together
+
+// Open-point record: X | Y << 23 | frame mask << 46.
+__device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
+{
+    return (u64)X | ((u64)Y << 23) | ((u64)mask << 46);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts, uint32_t n,
+                                                   uint32_t* __restrict__ samp)
+{
+    __shared__ uint32_t st[4 * kStairSlots];
+    const uint32_t tid = threadIdx.x;
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
+    __syncthreads();
+    uint32_t X[kSamplePerThread], Y[kSamplePerThread];
+#pragma unroll
+    for (int k = 0; k < kSamplePerThread; ++k) {
+        const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
+        const uint32_t i = (uint32_t)(((u64)sidx * n) / kSamplePts);
+        const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
+        // out-of-domain values only need to stay in range here: such a call
+        // fails with a domain error
+        X[k] = coord_u32(p.x) & kM;
+        Y[k] = coord_u32(p.y) & kM;
+    }
+#pragma unroll
+    for (int k = 0; k < kSamplePerThread; ++k) {
+        const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
+        atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
+        atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
+        atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
+        atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
+    }
+    __syncthreads();
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock) samp[blockIdx.x * 4 * kStairSlots + e] = st[e];
+}
+
+// Workgroup q (of 4, kStairSlots threads each) builds frame q's staircase.
+// Layout: stair[2s], stair[2s+1] = R1 at x-slot s, R3 at its own slot of
+// the same x; stair[2S + 2s], stair[2S + 2s + 1] = R2 at y-slot s, R4 at its
+// own slot of the same y (S = kStairSlots), so that one 64-bit LDS read per
+// coordinate serves two frames.  Workgroup 0 also clears the call's
+// counters.
+__global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restrict__ samp,
+                                                       uint32_t* __restrict__ stair, DevHeader* __restrict__ hdr,
+                                                       uint32_t* __restrict__ ghist)
+{
+    constexpr int kW = kStairSlots / 64;
+    __shared__ uint32_t wmin[kW];
+    const uint32_t q = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = t / 64;
+    uint32_t v[kSampleBlocks];
+#pragma unroll
+    for (int b = 0; b < kSampleBlocks; ++b) v[b] = samp[b * 4 * kStairSlots + q * kStairSlots + t];
+    uint32_t m = ~0u;
+#pragma unroll
+    for (int b = 0; b < kSampleBlocks; ++b) m = min(m, v[b]);
+    const uint32_t incl = wave_incl_min(m);
+    uint32_t excl = __shfl_up(incl, 1);
+    if (lane == 0) excl = ~0u;
+    if (lane == 63) wmin[wave] = incl;
+    __syncthreads();
+    for (uint32_t w = 0; w < wave; ++w) excl = min(excl, wmin[w]);
+    const uint32_t S = kStairSlots;
+    const uint32_t at = q == 0 ? 2 * t : q == 1 ? 2 * S + 2 * t : q == 2 ? 2 * (S - 1 - t) + 1 : 2 * S + 2 * (S - 1 - t) + 1;
+    stair[at] = excl;
+    if (q == 0) {
+        for (uint32_t d = t; d < kPassBins; d += kStairSlots) ghist[d] = 0;
+        if (t < 4) {
+            hdr->s1[t] = 0;
+            hdr->s2[t] = 0;
+            hdr->w2[t] = 0;
+            hdr->ticket[t] = 0;
+        }
+        if (t == 0) {
+            hdr->open = 0;
+            hdr->cand = 0;
+            hdr->chain = 0;
+            hdr->err = 0;
+        }
+    }
+}
 
 // `head` leading points (0 or 1) are visited singly so that the rest of the
 // array is 16-byte aligned for float4 loads; an odd last point likewise.
-__global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ pts, uint32_t n, uint32_t head,
-                                                     ExtPartial* __restrict__ part, uint32_t* __restrict__ samp)
+__global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
+                                                   const uint32_t* __restrict__ stair, ExtPartial* __restrict__ part,
+                                                   uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
+                                                   DevHeader* __restrict__ hdr)
 {
+    __shared__ uint32_t sst[4 * kStairSlots];
+    __shared__ uint32_t lidx[kWaves][kWaveList];
+    __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
-    __shared__ uint32_t st[4 * kStairSlots];
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
+    const u64 lt = (1ull << lane) - 1ull;
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
+    __syncthreads();
+    const u64* const sx64 = reinterpret_cast<const u64*>(sst);
+    const u64* const sy64 = sx64 + kStairSlots;
+
     ExtAcc a;
     ext_init(a);
-    const uint32_t tid = threadIdx.x;
-    const bool sampler = blockIdx.x < (uint32_t)kSampleBlocks;
-    if (sampler) {
-        for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kSamplePerThread; ++k) {
-            const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
-            const uint32_t i = (uint32_t)(((u64)sidx * n) / kSamplePts);
-            const uint32_t X = coord_u32(pts[2 * i]) & kM, Y = coord_u32(pts[2 * i + 1]) & kM;
-            const uint32_t xm = X ^ kM, ym = Y ^ kM;
-            atomicMin(&st[0 * kStairSlots + (X >> kStairShift)], Y);   // R1: (x, y)
-            atomicMin(&st[1 * kStairSlots + (Y >> kStairShift)], xm);  // R2: (y, M-x)
-            atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym); // R3: (M-x, M-y)
-            atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X);  // R4: (M-y, x)
-        }
-    }
-    if (blockIdx.x == 0 && tid == 0 && head) ext_visit(a, pts[0], pts[1], 0);
+    uint32_t wcount = 0;  // the same in every lane of a wave
 
+    auto flush = [&]() {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&hdr->open, wcount);
+        base = __shfl(base, 0);
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t e = lane; e < wcount; e += 64) {
+            open_idx[base + e] = lidx[wave][e];
+            open_xym[base + e] = lxym[wave][e];
+        }
+        __builtin_amdgcn_wave_barrier();
+        wcount = 0;
+    };
+    // Every lane of the wave calls it together (the list append is wave-wide).
+    auto visit = [&](float fx, float fy, uint32_t idx, bool valid) {
+        ext_visit(a, fx, fy, idx);
+        const uint32_t X = cvt_u32_sat(fx) & kM, Y = cvt_u32_sat(fy) & kM;
+        const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
+        const bool o1 = Y < (uint32_t)sxv;                  // R1: k2 = y
+        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);   // R3: k2 = M - y
+        const bool o2 = (X ^ kM) < (uint32_t)syv;           // R2: k2 = M - x
+        const bool o4 = X < (uint32_t)(syv >> 32);          // R4: k2 = x
+        const bool open = valid && (o1 || o2 || o3 || o4);
+        const u64 bal = __ballot(open);
+        if (bal) {
+            if (open) {
+                const uint32_t mask = (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
+                const uint32_t slot = wcount + (uint32_t)__popcll(bal & lt);
+                lidx[wave][slot] = idx;
+                lxym[wave][slot] = open_rec(X, Y, mask);
+            }
+            wcount += (uint32_t)__popcll(bal);
+            if (wcount > (uint32_t)(kWaveList - 64)) flush();
+        }
+    };
+
+    if (blockIdx.x == 0 && wave == 0 && head) visit(pts[0], pts[1], 0, lane == 0);
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
     const uint32_t stride = gridDim.x * kBlock;
+    // every lane runs the same number of rounds (the list append is
+    // wave-wide); lanes past the end revisit the last float4, which leaves
+    // the extremes unchanged and lists nothing
+    const uint32_t rounds = (n4 + stride * kStreamUnroll - 1) / (stride * kStreamUnroll);
     uint32_t f = blockIdx.x * kBlock + tid;
-    for (; f + (kExtUnroll - 1) * stride < n4; f += kExtUnroll * stride) {
-        v4f v[kExtUnroll];
+    for (uint32_t it = 0; it < rounds; ++it, f += kStreamUnroll * stride) {
+        v4f v[kStreamUnroll];
 #pragma unroll
-        for (int u = 0; u < kExtUnroll; ++u) v[u] = p4[f + u * stride];
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint32_t g = min(f + u * stride, n4 - 1);
+            v[u] = __builtin_nontemporal_load(p4 + g);
+        }
 #pragma unroll
-        for (int u = 0; u < kExtUnroll; ++u) {
-            const uint32_t i = head + 2 * (f + u * stride);
-            ext_visit(a, v[u].x, v[u].y, i);
-            ext_visit(a, v[u].z, v[u].w, i + 1);
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            const uint32_t g0 = f + u * stride;
+            const uint32_t g = min(g0, n4 - 1);
+            const uint32_t i = head + 2 * g;
+            visit(v[u].x, v[u].y, i, g0 < n4);
+            visit(v[u].z, v[u].w, i + 1, g0 < n4);
         }
     }
-    for (; f < n4; f += stride) {
-        const v4f v = p4[f];
-        const uint32_t i = head + 2 * f;
-        ext_visit(a, v.x, v.y, i);
-        ext_visit(a, v.z, v.w, i + 1);
-    }
-    if (blockIdx.x == 0 && tid == 1 && ((n - head) & 1u)) ext_visit(a, pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1);
+    if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u)) visit(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
+    if (wcount) flush();
 
     ext_block_reduce(a, sh);
     if (tid == 0) {
@@ -437,28 +591,58 @@ __global__ __launch_bounds__(kBlock) void k_extremes(const float* __restrict__ p
         p.err = (a.bad || a.hi > kM) ? 1u : 0u;
         part[blockIdx.x] = p;
     }
-    if (sampler) {
-        for (int e = tid; e < 4 * kStairSlots; e += kBlock) samp[blockIdx.x * 4 * kStairSlots + e] = st[e];
-    }
 }
 
-// One workgroup of kFinal threads: reduce the partials; derive the
-// quadrilateral's edges, the region frames and the sampled staircases'
-// prefix minima; zero the call's counters.
-constexpr int kFinal = 1024;
+// The quadrilateral: extreme points, edges and frames, from the reduced
+// extreme keys.
+struct Quad {
+    uint32_t X[4], Y[4], idx[4];  // P_minx, P_miny, P_maxx, P_maxy
+    int32_t ex[4], ey[4];         // edge q runs from E_q to E_{q+1}
+    double ec[4];                 // ex*E_q.y - ey*E_q.x
+    uint32_t sigma[4];            // k2 of each region's first point
+    uint32_t err;
+};
 
-__global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __restrict__ part, int nparts,
-                                                           const uint32_t* __restrict__ samp,
-                                                           DevHeader* __restrict__ hdr, uint32_t* __restrict__ stair,
-                                                           uint32_t* __restrict__ ghist)
+__device__ inline void make_quad(ExtAcc r, Quad& Q)
 {
-    constexpr int kW = kFinal / 64;
-    __shared__ ExtAcc sh[kW];
-    __shared__ uint32_t wmin[kW];
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    for (int e = 0; e < 2; ++e) {
+        if (r.imax[e] == ~0u) {  // every key is 0: the minimum is the answer
+            r.kmax[e] = r.kmin[e];
+            r.imax[e] = r.imin[e];
+        }
+    }
+    // masked so that a rejected input still gives in-range values
+    const u64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
+    Q.idx[0] = r.imin[0];
+    Q.idx[1] = r.imin[1];
+    Q.idx[2] = r.imax[0];
+    Q.idx[3] = r.imax[1];
+    Q.X[0] = (uint32_t)(key[0] >> 32) & kM; Q.Y[0] = ((uint32_t)key[0] & kM) ^ kM;
+    Q.Y[1] = (uint32_t)(key[1] >> 32) & kM; Q.X[1] = (uint32_t)key[1] & kM;
+    Q.X[2] = (uint32_t)(key[2] >> 32) & kM; Q.Y[2] = ((uint32_t)key[2] & kM) ^ kM;
+    Q.Y[3] = (uint32_t)(key[3] >> 32) & kM; Q.X[3] = (uint32_t)key[3] & kM;
+    // region q lies strictly right of edge q: ex*(y - E_q.y) - ey*(x - E_q.x) < 0
+    for (int q = 0; q < 4; ++q) {
+        const int s = (q + 1) & 3;
+        Q.ex[q] = (int32_t)Q.X[s] - (int32_t)Q.X[q];
+        Q.ey[q] = (int32_t)Q.Y[s] - (int32_t)Q.Y[q];
+        Q.ec[q] = (double)Q.ex[q] * (double)Q.Y[q] - (double)Q.ey[q] * (double)Q.X[q];
+    }
+    Q.sigma[0] = Q.Y[0];        // R1 starts at P_minx
+    Q.sigma[1] = Q.X[1] ^ kM;   // R2 starts at P_miny
+    Q.sigma[2] = Q.Y[2] ^ kM;   // R3 starts at P_maxx
+    Q.sigma[3] = Q.X[3];        // R4 starts at P_maxy
+    Q.err = r.bad ? kErrDomain : 0u;
+}
+
+// Every workgroup reduces the per-workgroup extreme partials itself (a few
+// tens of KB) and derives the quadrilateral; workgroup 0 publishes it.
+__device__ inline void reduce_quad(const ExtPartial* __restrict__ part, int nparts, DevHeader* __restrict__ hdr,
+                                   Quad& Q, ExtAcc* sh)
+{
     ExtAcc r;
     ext_init(r);
-    for (int b = tid; b < nparts; b += kFinal) {
+    for (int b = threadIdx.x; b < nparts; b += kBlock) {
         const ExtPartial p = part[b];
         ExtAcc o;
         for (int e = 0; e < 2; ++e) {
@@ -471,345 +655,167 @@ __global__ __launch_bounds__(kFinal) void k_extremes_final(const ExtPartial* __r
         o.hi = 0;
         ext_combine(r, o);
     }
-    ext_wave_reduce(r);
-    if (lane == 0) sh[wave] = r;
-    for (uint32_t d = tid; d < kPassBins; d += kFinal) ghist[d] = 0;
-
-    // Staircases: thread t owns slot t of each region's frame (needs
-    // kFinal >= kStairSlots); exclusive prefix minimum over the slots.  All
-    // sample minima are loaded before the first is used.
-    uint32_t vq[4] = {~0u, ~0u, ~0u, ~0u};
-    if (tid < (uint32_t)kStairSlots) {
-        uint32_t t[4][kSampleBlocks];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int b = 0; b < kSampleBlocks; ++b) t[q][b] = samp[b * 4 * kStairSlots + q * kStairSlots + tid];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int b = 0; b < kSampleBlocks; ++b) vq[q] = min(vq[q], t[q][b]);
-    }
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t v = vq[q];
-        const uint32_t incl = wave_incl_min(v);
-        uint32_t excl = __shfl_up(incl, 1);
-        if (lane == 0) excl = ~0u;
-        __syncthreads();
-        if (lane == 63) wmin[wave] = incl;
-        __syncthreads();
-        uint32_t before = ~0u;
-        for (uint32_t w = 0; w < wave; ++w) before = min(before, wmin[w]);
-        if (tid < (uint32_t)kStairSlots) stair[q * kStairSlots + tid] = min(before, excl);
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    for (int w = 1; w < kW; ++w) ext_combine(r, sh[w]);
-
-    for (int e = 0; e < 2; ++e) {
-        if (r.imax[e] == ~0u) {
-            r.kmax[e] = r.kmin[e];
-            r.imax[e] = r.imin[e];
+    ext_block_reduce(r, sh);
+    __shared__ Quad sq;
+    if (threadIdx.x == 0) {
+        make_quad(r, sq);
+        if (blockIdx.x == 0) {
+            for (int e = 0; e < 4; ++e) {
+                hdr->ext_x[e] = sq.X[e];
+                hdr->ext_y[e] = sq.Y[e];
+                hdr->ext_idx[e] = sq.idx[e];
+                hdr->ex[e] = sq.ex[e];
+                hdr->ey[e] = sq.ey[e];
+                hdr->ec[e] = sq.ec[e];
+                hdr->sigma[e] = sq.sigma[e];
+            }
+            if (sq.err) atomicOr(&hdr->err, sq.err);
         }
     }
-    // P_minx, P_miny, P_maxx, P_maxy (masked so that a rejected input still
-    // gives in-range values)
-    const u64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
-    const uint32_t idx[4] = {r.imin[0], r.imin[1], r.imax[0], r.imax[1]};
-    uint32_t X[4], Y[4];
-    X[0] = (uint32_t)(key[0] >> 32) & kM; Y[0] = ((uint32_t)key[0] & kM) ^ kM;
-    Y[1] = (uint32_t)(key[1] >> 32) & kM; X[1] = (uint32_t)key[1] & kM;
-    X[2] = (uint32_t)(key[2] >> 32) & kM; Y[2] = ((uint32_t)key[2] & kM) ^ kM;
-    Y[3] = (uint32_t)(key[3] >> 32) & kM; X[3] = (uint32_t)key[3] & kM;
-    for (int e = 0; e < 4; ++e) {
-        hdr->ext_x[e] = X[e];
-        hdr->ext_y[e] = Y[e];
-        hdr->ext_idx[e] = idx[e];
-    }
-    // Edge q runs from E_q to E_{q+1}, E = (P_minx, P_miny, P_maxx, P_maxy);
-    // region q is strictly right of it: ex*(y - E_q.y) - ey*(x - E_q.x) < 0.
-    for (int q = 0; q < 4; ++q) {
-        const int s = (q + 1) & 3;
-        const int32_t ex = (int32_t)X[s] - (int32_t)X[q];
-        const int32_t ey = (int32_t)Y[s] - (int32_t)Y[q];
-        hdr->ex[q] = ex;
-        hdr->ey[q] = ey;
-        hdr->ec[q] = (double)ex * (double)Y[q] - (double)ey * (double)X[q];
-    }
-    hdr->sigma[0] = Y[0];        // R1 starts at P_minx
-    hdr->sigma[1] = X[1] ^ kM;   // R2 starts at P_miny
-    hdr->sigma[2] = Y[2] ^ kM;   // R3 starts at P_maxx
-    hdr->sigma[3] = X[3];        // R4 starts at P_maxy
-    for (int q = 0; q < 4; ++q) {
-        hdr->s1[q] = 0;
-        hdr->s2[q] = 0;
-        hdr->w2[q] = 0;
-        hdr->ticket[q] = 0;
-    }
-    hdr->cand = 0;
-    hdr->chain = 0;
-    hdr->err = r.bad ? kErrDomain : 0u;
+    __syncthreads();
+    Q = sq;
 }
 
-// ---------------------------------------------------------------------------
-// Step 2 (Section 2.1.1): exact region test against the quadrilateral (the
-// first discard), fused with two uses of the SPA dominance rule, so that only
-// possible chain points reach HBM.
-//
-// A point p of region q is dominated by another point p' of the region when
-// k1' <= k1 and k2' <= k2 and p' precedes p in (k1, k2, index) order; then p
-// lies in the triangle (first point, p', last point) and is not a hull vertex
-// (the argument of Figure 3).  Dropping dominated points leaves the result of
-// the region sort and SPA unchanged, so any filter that only drops dominated
-// points may run before them.
-//
-// 1. Sampled staircases: in each region frame, the smallest k2 of the sample
-//    points in earlier k1-slots.  A sample point p' with smaller k1 and
-//    k2 <= k2 of p, in the frame of p's region, lies in that region as well
-//    (moving towards the corner never re-enters the quadrilateral), so it
-//    dominates p there.  A point dominated in all four frames is dominated in
-//    its own region and is dropped before the region test; one dominated in
-//    its own region's frame is dropped after it.
-// 2. Workgroup staircases: each persistent workgroup streams a grid-strided
-//    share of the points; the survivors of step 1 that lie in a region go to
-//    an LDS list and update, per region and k1-slot of 2^14 values, the
-//    smallest (k2, k1).  A listed point is then dropped when the region's
-//    first point or a point of an earlier slot has k2 <= its k2, or when its
-//    slot's smallest point precedes it with k1 <= its k1.  The rest is written
-//    out.  Points that do not fit the list are written out unfiltered.
-//
-// With kStats every point also takes the region test so that the round-1
-// survivors are counted; the filters are the same.
-// ---------------------------------------------------------------------------
-
-constexpr int kClsGrid = 1024;      // persistent workgroups of k_classify
-constexpr int kClsUnroll = 4;       // float4 loads in flight per thread
-constexpr int kCandCap = 1024;      // listed points per workgroup
-
-struct ClsParams {
-    double ec[4], ex[4], ey[4];
-};
-
-template <bool kStats>
-__global__ __launch_bounds__(kBlock) void k_classify(const float* __restrict__ pts, uint32_t n, uint32_t head,
-                                                     DevHeader* __restrict__ hdr, const uint32_t* __restrict__ stair,
-                                                     uint32_t* __restrict__ out_key, u64* __restrict__ out_val)
+// Region (0..3, or 4 for none) of a point by the exact test: every product is
+// below 2^46 and every sum below 2^47, so fp64 is exact.
+__device__ inline uint32_t region_of(const Quad& Q, uint32_t X, uint32_t Y)
 {
-    static_assert(kSlots == kStairSlots, "the staircase copy and the slot prefixes share storage");
+    const double dx = (double)X, dy = (double)Y;
+    const bool t0 = fma((double)Q.ex[0], dy, -((double)Q.ey[0] * dx)) < Q.ec[0];
+    const bool t1 = fma((double)Q.ex[1], dy, -((double)Q.ey[1] * dx)) < Q.ec[1];
+    const bool t2 = fma((double)Q.ex[2], dy, -((double)Q.ey[2] * dx)) < Q.ec[2];
+    const bool t3 = fma((double)Q.ex[3], dy, -((double)Q.ey[3] * dx)) < Q.ec[3];
+    return t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ part, int nparts,
+                                                 const uint32_t* __restrict__ open_idx,
+                                                 const u64* __restrict__ open_xym, DevHeader* __restrict__ hdr,
+                                                 uint32_t* __restrict__ out_key, u64* __restrict__ out_val)
+{
+    __shared__ ExtAcc sh[kWaves];
     __shared__ u64 smin[4 * kSlots];
-    __shared__ uint32_t swork[4 * kSlots];  // sampled staircases, then slot prefixes
-    uint32_t* const sst = swork;
-    uint32_t* const sexc = swork;
-    __shared__ uint32_t cl_idx[kCandCap], cl_addr[kCandCap];
+    __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_count, sbase;
-    __shared__ uint32_t s1cnt[kWaves][4];
-
-    if (hdr->err) return;
+    __shared__ uint32_t sbase;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    const u64 lt = (1ull << lane) - 1ull;
-    ClsParams P;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        P.ec[q] = hdr->ec[q];
-        P.ex[q] = (double)hdr->ex[q];
-        P.ey[q] = (double)hdr->ey[q];
-    }
-    for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
-    if (tid == 0) s_count = 0;
-    __syncthreads();
+    Quad Q;
+    reduce_quad(part, nparts, hdr, Q, sh);
+    if (Q.err) return;
+    const uint32_t count = hdr->open;
+    constexpr int kPer = kCandChunk / kBlock;
 
-    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;  // region counts (kStats)
-    // One point: sample test, region test, workgroup staircase, list.  Every
-    // lane of the wave calls it together (the list append is wave-wide).
-    auto visit = [&](float fx, float fy, uint32_t idx, bool valid) {
-        const uint32_t X = (uint32_t)fx, Y = (uint32_t)fy;
-        uint32_t open = 0;
-        if (valid) {
-            const uint32_t xm = X ^ kM, ym = Y ^ kM;
-            open = (Y < sst[0 * kStairSlots + (X >> kStairShift)] ? 1u : 0u) |
-                   (xm < sst[1 * kStairSlots + (Y >> kStairShift)] ? 2u : 0u) |
-                   (ym < sst[2 * kStairSlots + (xm >> kStairShift)] ? 4u : 0u) |
-                   (X < sst[3 * kStairSlots + (ym >> kStairShift)] ? 8u : 0u);
-        }
-        uint32_t addr = ~0u;
-        // kStats: every point's region is counted; only the sample test's
-        // survivors are listed either way
-        if (kStats ? valid : open != 0) {
-            const double dx = (double)fx, dy = (double)fy;
-            // exact: every product is below 2^46 and every sum below 2^47
-            const bool t0 = fma(P.ex[0], dy, -(P.ey[0] * dx)) < P.ec[0];
-            const bool t1 = fma(P.ex[1], dy, -(P.ey[1] * dx)) < P.ec[1];
-            const bool t2 = fma(P.ex[2], dy, -(P.ey[2] * dx)) < P.ec[2];
-            const bool t3 = fma(P.ex[3], dy, -(P.ey[3] * dx)) < P.ec[3];
-            const uint32_t q = t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
-            if (kStats) {
-                c0 += q == 0;
-                c1 += q == 1;
-                c2 += q == 2;
-                c3 += q == 3;
-            }
-            if (q < 4 && ((open >> q) & 1u)) {
-                const uint32_t a = (q & 1u) ? Y : X;
-                const uint32_t b = (q & 1u) ? X : Y;
-                const uint32_t k1 = (q & 2u) ? a ^ kM : a;
-                const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-                addr = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
-                atomicMin(&smin[addr], ((u64)k2 << 23) | k1);
-            }
-        }
-        const u64 want = __ballot(addr != ~0u);
-        if (want) {
-            const int lead = __ffsll((long long)want) - 1;
-            uint32_t first = 0;
-            if (lane == (uint32_t)lead) first = atomicAdd(&s_count, (uint32_t)__popcll(want));
-            first = __shfl(first, lead);
-            const uint32_t slot = addr != ~0u ? first + (uint32_t)__popcll(want & lt) : 0u;
-            if (addr != ~0u && slot < (uint32_t)kCandCap) {
-                cl_idx[slot] = idx;
-                cl_addr[slot] = addr;
-            }
-            // list full: such points are written unfiltered, one atomic a wave
-            const u64 over = __ballot(addr != ~0u && slot >= (uint32_t)kCandCap);
-            if (over) {
-                const int olead = __ffsll((long long)over) - 1;
-                uint32_t obase = 0;
-                if (lane == (uint32_t)olead) obase = atomicAdd(&hdr->cand, (uint32_t)__popcll(over));
-                obase = __shfl(obase, olead);
-                if (addr != ~0u && slot >= (uint32_t)kCandCap) {
-                    const uint32_t q = addr >> kSlotBits;
+    for (uint32_t c0 = blockIdx.x * kCandChunk; c0 < count; c0 += gridDim.x * kCandChunk) {
+        for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
+        __syncthreads();
+        uint32_t k1s[kPer], k2s[kPer], idxs[kPer], addrs[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t e = c0 + k * kBlock + tid;
+            addrs[k] = ~0u;
+            if (e < count) {
+                const u64 r = open_xym[e];
+                const uint32_t X = (uint32_t)r & kM, Y = (uint32_t)(r >> 23) & kM, mask = (uint32_t)(r >> 46);
+                const uint32_t q = region_of(Q, X, Y);
+                if (q < 4 && ((mask >> q) & 1u)) {
                     const uint32_t a = (q & 1u) ? Y : X;
                     const uint32_t b = (q & 1u) ? X : Y;
                     const uint32_t k1 = (q & 2u) ? a ^ kM : a;
                     const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-                    const uint32_t pos = obase + (uint32_t)__popcll(over & lt);
-                    out_key[pos] = (q << 23) | k1;
-                    out_val[pos] = ((u64)k2 << 32) | idx;
+                    k1s[k] = k1;
+                    k2s[k] = k2;
+                    idxs[k] = open_idx[e];
+                    addrs[k] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
+                    atomicMin(&smin[addrs[k]], ((u64)k2 << 23) | k1);
                 }
             }
         }
-    };
-
-    // head point, float4 body, odd last point (as in k_extremes)
-    if (blockIdx.x == 0 && wave == 0) {
-        const bool h = head && lane == 0;
-        visit(h ? pts[0] : 0.f, h ? pts[1] : 0.f, 0, h);
-    }
-    const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
-    const uint32_t n4 = (n - head) / 2;
-    const uint32_t stride = gridDim.x * kBlock;
-    // every lane runs the same number of iterations (the list append is
-    // wave-wide); lanes past the end visit invalid points
-    const uint32_t rounds = (n4 + stride * kClsUnroll - 1) / (stride * kClsUnroll);
-    uint32_t f = blockIdx.x * kBlock + tid;
-    for (uint32_t it = 0; it < rounds; ++it, f += kClsUnroll * stride) {
-        v4f v[kClsUnroll];
+        __syncthreads();
+        // Wave w scans region w's slots: sexc becomes the smallest k2 over
+        // earlier slots and the region's first point.
+        {
+            const uint32_t q = wave;
+            constexpr int per = kSlots / 64;
+            uint32_t v[per];
+            uint32_t run = ~0u;
 #pragma unroll
-        for (int u = 0; u < kClsUnroll; ++u) {
-            const uint32_t g = f + u * stride;
-            v[u] = g < n4 ? __builtin_nontemporal_load(p4 + g) : v4f{0.f, 0.f, 0.f, 0.f};
-        }
+            for (int k = 0; k < per; ++k) {
+                const u64 m = smin[(q << kSlotBits) + lane * per + k];
+                v[k] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
+                run = min(run, v[k]);
+            }
+            const uint32_t incl = wave_incl_min(run);
+            uint32_t before = __shfl_up(incl, 1);
+            if (lane == 0) before = ~0u;
+            before = min(before, Q.sigma[q]);
 #pragma unroll
-        for (int u = 0; u < kClsUnroll; ++u) {
-            const uint32_t g = f + u * stride;
-            const uint32_t i = head + 2 * g;
-            visit(v[u].x, v[u].y, i, g < n4);
-            visit(v[u].z, v[u].w, i + 1, g < n4);
-        }
-    }
-    if (blockIdx.x == 0 && wave == 0) {
-        const bool t = ((n - head) & 1u) && lane == 0;
-        visit(t ? pts[2 * (n - 1)] : 0.f, t ? pts[2 * (n - 1) + 1] : 0.f, n - 1, t);
-    }
-    if (kStats) {
-        c0 = wave_sum(c0);
-        c1 = wave_sum(c1);
-        c2 = wave_sum(c2);
-        c3 = wave_sum(c3);
-        if (lane == 0) {
-            s1cnt[wave][0] = c0;
-            s1cnt[wave][1] = c1;
-            s1cnt[wave][2] = c2;
-            s1cnt[wave][3] = c3;
-        }
-    }
-    __syncthreads();
-    if (kStats && tid < 4) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += s1cnt[w][tid];
-        if (tot) atomicAdd(&hdr->s1[tid], tot);
-    }
-    const uint32_t listed = min(s_count, (uint32_t)kCandCap);
-    if (listed == 0) return;
-
-    // Wave w scans region w's slots: sexc becomes the smallest k2 over earlier
-    // slots and the region's first point.
-    {
-        const uint32_t q = wave;
-        const uint32_t sigma = hdr->sigma[q];
-        constexpr int per = kSlots / 64;
-        uint32_t v[per];
-        uint32_t run = ~0u;
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            const u64 m = smin[(q << kSlotBits) + lane * per + k];
-            v[k] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
-            run = min(run, v[k]);
-        }
-        const uint32_t incl = wave_incl_min(run);
-        uint32_t before = __shfl_up(incl, 1);
-        if (lane == 0) before = ~0u;
-        before = min(before, sigma);
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            sexc[(q << kSlotBits) + lane * per + k] = before;
-            before = min(before, v[k]);
-        }
-    }
-    __syncthreads();
-
-    // Dominance tests on the list, then one compaction.
-    constexpr int kPer = kCandCap / kBlock;
-    uint32_t keep = 0, rk[kPer], rv[kPer], ri[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const uint32_t e = k * kBlock + tid;
-        rk[k] = rv[k] = ri[k] = 0;
-        if (e < listed) {
-            const uint32_t idx = cl_idx[e], addr = cl_addr[e], q = addr >> kSlotBits;
-            const uint32_t X = (uint32_t)pts[2 * idx], Y = (uint32_t)pts[2 * idx + 1];
-            const uint32_t a = (q & 1u) ? Y : X;
-            const uint32_t b = (q & 1u) ? X : Y;
-            const uint32_t k1 = (q & 2u) ? a ^ kM : a;
-            const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-            const u64 me = ((u64)k2 << 23) | k1;
-            const u64 best = smin[addr];
-            bool ok = k2 < sexc[addr];
-            ok = ok && !(best < me && (uint32_t)(best & kM) <= k1);
-            if (ok) {
-                keep |= 1u << k;
-                rk[k] = (q << 23) | k1;
-                rv[k] = k2;
-                ri[k] = idx;
+            for (int k = 0; k < per; ++k) {
+                sexc[(q << kSlotBits) + lane * per + k] = before;
+                before = min(before, v[k]);
             }
         }
-    }
-    uint32_t total;
-    uint32_t pos = block_excl_sum(__popc(keep), scratch, total);
-    if (tid == 0) sbase = total ? atomicAdd(&hdr->cand, total) : 0u;
-    __syncthreads();
-    pos += sbase;
+        __syncthreads();
+        uint32_t keep = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        if ((keep >> k) & 1u) {
-            out_key[pos] = rk[k];
-            out_val[pos] = ((u64)rv[k] << 32) | ri[k];
-            ++pos;
+        for (int k = 0; k < kPer; ++k) {
+            if (addrs[k] != ~0u) {
+                const u64 me = ((u64)k2s[k] << 23) | k1s[k];
+                const u64 best = smin[addrs[k]];
+                bool ok = k2s[k] < sexc[addrs[k]];
+                ok = ok && !(best < me && (uint32_t)(best & kM) <= k1s[k]);
+                if (ok) keep |= 1u << k;
+            }
         }
+        uint32_t total;
+        uint32_t pos = block_excl_sum(__popc(keep), scratch, total);
+        if (tid == 0) sbase = total ? atomicAdd(&hdr->cand, total) : 0u;
+        __syncthreads();
+        pos += sbase;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if ((keep >> k) & 1u) {
+                out_key[pos] = ((addrs[k] >> kSlotBits) << 23) | k1s[k];
+                out_val[pos] = ((u64)k2s[k] << 32) | idxs[k];
+                ++pos;
+            }
+        }
+        __syncthreads();
     }
 }
 
+// Round-1 survivor counts per region (Section 2.1.1), for chainhull_polygon:
+// the exact region test on every point.
+__global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restrict__ pts, uint32_t n,
+                                                          DevHeader* __restrict__ hdr)
+{
+    __shared__ uint32_t wc[kWaves][4];
+    if (hdr->err) return;
+    Quad Q;
+    for (int q = 0; q < 4; ++q) {
+        Q.ex[q] = hdr->ex[q];
+        Q.ey[q] = hdr->ey[q];
+        Q.ec[q] = hdr->ec[q];
+    }
+    uint32_t c[4] = {0, 0, 0, 0};
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
+        const uint32_t q = region_of(Q, (uint32_t)p.x, (uint32_t)p.y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] += q == (uint32_t)r;
+    }
+    const uint32_t wave = threadIdx.x / 64;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        c[r] = wave_sum(c[r]);
+        if (lane_id() == 0) wc[wave][r] = c[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wc[w][threadIdx.x];
+        if (tot) atomicAdd(&hdr->s1[threadIdx.x], tot);
+    }
+}
 // ---------------------------------------------------------------------------
 // Steps 3-4 (Section 2.1; Table 1): sort the records of all four regions at
 // once by the 25-bit key q << 23 | k1, least significant digit first
@@ -1025,7 +1031,6 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
     __shared__ uint32_t sigma[4];
     __shared__ uint32_t shb[kBlock];     // head bits of each thread's records
     __shared__ u64 sseg[kBlock];         // suffix minima per thread (segment carry)
-    __shared__ uint32_t sflag[kBlock];
     __shared__ u64 wtot[kWaves];
     __shared__ uint32_t wflag[kWaves];
     __shared__ uint32_t s_last_head, s_cont;
@@ -1340,7 +1345,7 @@ size_t device_bytes(size_t cap)
 {
     size_t b = 0;
     b += align_up(sizeof(DevHeader), 256);
-    b += align_up(sizeof(ExtPartial) * kExtBlocks, 256);
+    b += align_up(sizeof(ExtPartial) * kStreamGrid, 256);
     b += align_up(sizeof(uint32_t) * kPassBins, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
@@ -1402,7 +1407,7 @@ int ensure_device(Workspace& w, size_t n)
         return r;
     };
     w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
-    w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kExtBlocks));
+    w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
     w.ghist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kPassBins));
     w.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
     w.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
@@ -1482,25 +1487,31 @@ int record(Workspace& w, int k)
 }
 
 // Steps 1-6 on the device; the chains end in w.h_chain (and w.spill), the
-// counts in w.h_hdr.  Timing events: 0 | k_extremes | 1 | k_classify | 2 |
-// sort | 3 | SPA + chains | 4 | copy-out | 5.
+// counts in w.h_hdr.  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
+// 2 | k_cand (+ k_count_regions) | 3 | sort | 4 | SPA + chains | 5 |
+// copy-out | 6.
 int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
 {
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.samp));
+    CH_LAUNCH(hipLaunchKernelGGL(k_stair, dim3(4), dim3(kStairSlots), 0, s, w.samp, w.stair, w.hdr, w.ghist));
+    CH_TRY(record(w, 1));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
     const uint32_t n4 = (n - head) / 2;
-    const uint32_t gext = std::max<uint32_t>(
-        kSampleBlocks, std::min<uint32_t>(kExtBlocks, (n4 + kBlock * kExtUnroll - 1) / (kBlock * kExtUnroll)));
-    CH_LAUNCH(hipLaunchKernelGGL(k_extremes, dim3(gext), dim3(kBlock), 0, s, pts, n, head, w.part, w.samp));
-    CH_LAUNCH(hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(kFinal), 0, s, w.part, (int)gext, w.samp, w.hdr,
-                                 w.stair, w.ghist));
-    CH_TRY(record(w, 1));
-    const uint32_t gcls = std::max<uint32_t>(1u, std::min<uint32_t>(kClsGrid, (n4 + kBlock - 1) / kBlock));
-    auto classify = stats ? k_classify<true> : k_classify<false>;
-    CH_LAUNCH(hipLaunchKernelGGL(classify, dim3(gcls), dim3(kBlock), 0, s, pts, n, head, w.hdr, w.stair, w.key[0],
-                                 w.val[0]));
+    const uint32_t gs = std::max<uint32_t>(
+        1u, std::min<uint32_t>(kStreamGrid, (n4 + kBlock * kStreamUnroll - 1) / (kBlock * kStreamUnroll)));
+    // the open lists live in the second sort buffers until k_cand has read them
+    CH_LAUNCH(hipLaunchKernelGGL(k_stream, dim3(gs), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part, w.key[1],
+                                 w.val[1], w.hdr));
     CH_TRY(record(w, 2));
+    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(kCandGrid), dim3(kBlock), 0, s, w.part, (int)gs, w.key[1], w.val[1],
+                                 w.hdr, w.key[0], w.val[0]));
+    if (stats) {
+        const uint32_t gc = std::max<uint32_t>(1u, std::min<uint32_t>(2048u, (n + kBlock * 8 - 1) / (kBlock * 8)));
+        CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gc), dim3(kBlock), 0, s, pts, n, w.hdr));
+    }
+    CH_TRY(record(w, 3));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(256), dim3(kBlock), 0, s, w.key[0], w.hdr, w.ghist, w.look));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
                                  w.val[1], w.hdr, 0, w.ghist, w.look.pass[0], &w.hdr->ticket[0]));
@@ -1508,13 +1519,13 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
                                  w.val[0], w.hdr, 8, w.ghist + 256, w.look.pass[1], &w.hdr->ticket[1]));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<9>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
                                  w.val[1], w.hdr, 16, w.ghist + 512, w.look.pass[2], &w.hdr->ticket[2]));
-    CH_TRY(record(w, 3));
+    CH_TRY(record(w, 4));
     CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
                                  w.look.spa_min, w.look.spa_cnt, &w.hdr->ticket[3], w.h_chain_dev,
                                  (uint32_t)w.h_chain_cap, w.dev_chain, stats ? 0 : 1));
-    CH_TRY(record(w, 4));
-    CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
     CH_TRY(record(w, 5));
+    CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
+    CH_TRY(record(w, 6));
     CH_TRY(hipStreamSynchronize(s));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
@@ -1576,15 +1587,15 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
         st->s1[e] = stats ? (int64_t)h.s1[e] : -1;
         st->s2[e] = h.s2[e];
     }
+    st->open = h.open;
     st->candidates = h.cand;
     st->polygon = (int64_t)h.chain + 4;
     if (g_timing && w.events) {
-        // stage slots: 0 k_extremes (with its final reduction), 1 unused,
-        // 2 k_classify, 3 sort, 4 SPA + chains, 5 unused, 6 copy-out
-        const int slot[5] = {0, 2, 3, 4, 6};
-        for (int k = 0; k < 5; ++k) {
+        // stage slots: 0 sample + staircases, 1 k_stream, 2 k_cand, 3 sort,
+        // 4 SPA + chains, 5 copy-out (6 is unused, 7 the host finish)
+        for (int k = 0; k < 6; ++k) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[slot[k]] = ms;
+            if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
         }
     }
 }

@@ -192,7 +192,7 @@ def test_timing_stats():
         ch.set_timing(False)
     assert st["n"] == 200_000 and st["hull"] > 2
     assert all(v >= 0 for v in st["ms"].values())
-    assert st["ms"]["classify"] > 0
+    assert st["ms"]["stream"] > 0 and st["ms"]["cand"] > 0
 
 
 @pytest.mark.parametrize("seed", [74, 75])
