@@ -401,8 +401,8 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // record precedes it with k1 <= its k1.  The rest become sort records.
 // ---------------------------------------------------------------------------
 
-constexpr int kSampleBlocks = 16;
-constexpr int kSamplePerThread = 32;
+constexpr int kSampleBlocks = 64;
+constexpr int kSamplePerThread = 8;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
 constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
@@ -496,19 +496,26 @@ __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restric
 
 // `head` leading points (0 or 1) are visited singly so that the rest of the
 // array is 16-byte aligned for float4 loads; an odd last point likewise.
+// Workgroup b writes its open points to its own region [b*region, ...) of
+// the open arrays and their number to wgcount[b]: no two workgroups share a
+// counter (same-address atomics from many workgroups serialise).
 __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
                                                    const uint32_t* __restrict__ stair, ExtPartial* __restrict__ part,
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
-                                                   DevHeader* __restrict__ hdr)
+                                                   uint32_t region, uint32_t* __restrict__ wgcount)
 {
     __shared__ uint32_t sst[4 * kStairSlots];
     __shared__ uint32_t lidx[kWaves][kWaveList];
     __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
+    __shared__ uint32_t s_fill;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     const u64 lt = (1ull << lane) - 1ull;
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
+    if (tid == 0) s_fill = 0;
     __syncthreads();
+    uint32_t* const my_idx = open_idx + (size_t)blockIdx.x * region;
+    u64* const my_xym = open_xym + (size_t)blockIdx.x * region;
     const u64* const sx64 = reinterpret_cast<const u64*>(sst);
     const u64* const sy64 = sx64 + kStairSlots;
 
@@ -518,32 +525,34 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
 
     auto flush = [&]() {
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&hdr->open, wcount);
+        if (lane == 0) base = atomicAdd(&s_fill, wcount);
         base = __shfl(base, 0);
         __builtin_amdgcn_wave_barrier();
         for (uint32_t e = lane; e < wcount; e += 64) {
-            open_idx[base + e] = lidx[wave][e];
-            open_xym[base + e] = lxym[wave][e];
+            my_idx[base + e] = lidx[wave][e];
+            my_xym[base + e] = lxym[wave][e];
         }
         __builtin_amdgcn_wave_barrier();
         wcount = 0;
     };
-    // Every lane of the wave calls it together (the list append is wave-wide).
-    auto visit = [&](float fx, float fy, uint32_t idx, bool valid) {
-        ext_visit(a, fx, fy, idx);
-        const uint32_t X = cvt_u32_sat(fx) & kM, Y = cvt_u32_sat(fy) & kM;
-        const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
-        const bool o1 = Y < (uint32_t)sxv;                  // R1: k2 = y
-        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);   // R3: k2 = M - y
-        const bool o2 = (X ^ kM) < (uint32_t)syv;           // R2: k2 = M - x
-        const bool o4 = X < (uint32_t)(syv >> 32);          // R4: k2 = x
-        const bool open = valid && (o1 || o2 || o3 || o4);
-        const u64 bal = __ballot(open);
-        if (bal) {
-            if (open) {
-                const uint32_t mask = (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
+    // The staircase test of one point: bit r-1 set when the point is below
+    // the sampled staircase of frame Rr.
+    auto frames_open = [&](uint32_t X, uint32_t Y, u64 sxv, u64 syv) {
+        return (Y < (uint32_t)sxv ? 1u : 0u) |                  // R1: k2 = y
+               ((X ^ kM) < (uint32_t)syv ? 2u : 0u) |           // R2: k2 = M - x
+               ((Y ^ kM) < (uint32_t)(sxv >> 32) ? 4u : 0u) |   // R3: k2 = M - y
+               (X < (uint32_t)(syv >> 32) ? 8u : 0u);           // R4: k2 = x
+    };
+    // Lists the open points among `cnt` points of this lane; every lane of
+    // the wave calls it together (the list append is wave-wide).
+    auto list_open = [&](const float* fxy, const uint32_t* idx, const bool* valid, int cnt) {
+        for (int p = 0; p < cnt; ++p) {
+            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
+            const uint32_t mask = valid[p] ? frames_open(X, Y, sx64[X >> kStairShift], sy64[Y >> kStairShift]) : 0u;
+            const u64 bal = __ballot(mask != 0);
+            if (mask) {
                 const uint32_t slot = wcount + (uint32_t)__popcll(bal & lt);
-                lidx[wave][slot] = idx;
+                lidx[wave][slot] = idx[p];
                 lxym[wave][slot] = open_rec(X, Y, mask);
             }
             wcount += (uint32_t)__popcll(bal);
@@ -551,7 +560,13 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         }
     };
 
-    if (blockIdx.x == 0 && wave == 0 && head) visit(pts[0], pts[1], 0, lane == 0);
+    if (blockIdx.x == 0 && wave == 0 && head) {
+        const float fxy[2] = {pts[0], pts[1]};
+        const uint32_t i0 = 0;
+        const bool ok = lane == 0;
+        ext_visit(a, fxy[0], fxy[1], 0);
+        list_open(fxy, &i0, &ok, 1);
+    }
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
     const uint32_t stride = gridDim.x * kBlock;
@@ -561,26 +576,55 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     const uint32_t rounds = (n4 + stride * kStreamUnroll - 1) / (stride * kStreamUnroll);
     uint32_t f = blockIdx.x * kBlock + tid;
     for (uint32_t it = 0; it < rounds; ++it, f += kStreamUnroll * stride) {
+        constexpr int kP = 2 * kStreamUnroll;
         v4f v[kStreamUnroll];
 #pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) {
-            const uint32_t g = min(f + u * stride, n4 - 1);
-            v[u] = __builtin_nontemporal_load(p4 + g);
-        }
+        for (int u = 0; u < kStreamUnroll; ++u) v[u] = __builtin_nontemporal_load(p4 + min(f + u * stride, n4 - 1));
+        float fxy[2 * kP];
+        uint32_t idx[kP];
+        bool valid[kP];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
-            const uint32_t g0 = f + u * stride;
-            const uint32_t g = min(g0, n4 - 1);
-            const uint32_t i = head + 2 * g;
-            visit(v[u].x, v[u].y, i, g0 < n4);
-            visit(v[u].z, v[u].w, i + 1, g0 < n4);
+            const uint32_t g0 = f + u * stride, g = min(g0, n4 - 1);
+            fxy[4 * u + 0] = v[u].x;
+            fxy[4 * u + 1] = v[u].y;
+            fxy[4 * u + 2] = v[u].z;
+            fxy[4 * u + 3] = v[u].w;
+            idx[2 * u] = head + 2 * g;
+            idx[2 * u + 1] = head + 2 * g + 1;
+            valid[2 * u] = valid[2 * u + 1] = g0 < n4;
         }
+        // all staircase reads first, then the tests: one wait per round
+        u64 sxv[kP], syv[kP];
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
+            sxv[p] = sx64[X >> kStairShift];
+            syv[p] = sy64[Y >> kStairShift];
+        }
+#pragma unroll
+        for (int p = 0; p < kP; ++p) ext_visit(a, fxy[2 * p], fxy[2 * p + 1], idx[p]);
+        bool any = false;
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
+            any = any | (valid[p] && frames_open(X, Y, sxv[p], syv[p]) != 0);
+        }
+        // rare: some lane of the wave has an open point this round
+        if (__ballot(any)) list_open(fxy, idx, valid, kP);
     }
-    if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u)) visit(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
+    if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u)) {
+        const float fxy[2] = {pts[2 * (n - 1)], pts[2 * (n - 1) + 1]};
+        const uint32_t i0 = n - 1;
+        const bool ok = lane == 0;
+        ext_visit(a, fxy[0], fxy[1], n - 1);
+        list_open(fxy, &i0, &ok, 1);
+    }
     if (wcount) flush();
 
-    ext_block_reduce(a, sh);
+    ext_block_reduce(a, sh);  // ends with a workgroup barrier: s_fill is final
     if (tid == 0) {
+        wgcount[blockIdx.x] = s_fill;
         ExtPartial p;
         for (int e = 0; e < 2; ++e) {
             p.kmin[e] = a.kmin[e];
@@ -688,24 +732,52 @@ __device__ inline uint32_t region_of(const Quad& Q, uint32_t X, uint32_t Y)
     return t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
 }
 
+// Workgroup j takes the open lists of k_stream workgroups 4j .. 4j+3 and
+// writes its records to its own region [j*4*region, ...) of the record
+// arrays, their number to candcount[j].
+constexpr int kListsPerCand = 4;
+
 __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ part, int nparts,
                                                  const uint32_t* __restrict__ open_idx,
-                                                 const u64* __restrict__ open_xym, DevHeader* __restrict__ hdr,
-                                                 uint32_t* __restrict__ out_key, u64* __restrict__ out_val)
+                                                 const u64* __restrict__ open_xym, uint32_t region,
+                                                 const uint32_t* __restrict__ wgcount, DevHeader* __restrict__ hdr,
+                                                 uint32_t* __restrict__ out_key, u64* __restrict__ out_val,
+                                                 uint32_t* __restrict__ candcount)
 {
     __shared__ ExtAcc sh[kWaves];
     __shared__ u64 smin[4 * kSlots];
     __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t sbase;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     Quad Q;
     reduce_quad(part, nparts, hdr, Q, sh);
-    if (Q.err) return;
-    const uint32_t count = hdr->open;
+    if (blockIdx.x == 0) {
+        // the number of open points, for the call's counts
+        uint32_t c = 0;
+        for (int b = tid; b < nparts; b += kBlock) c += wgcount[b];
+        uint32_t total;
+        (void)block_excl_sum(c, scratch, total);
+        if (tid == 0) hdr->open = total;
+    }
+    if (Q.err) {
+        if (tid == 0) candcount[blockIdx.x] = 0;
+        return;
+    }
+    // the workgroup's lists, concatenated
+    uint32_t start[kListsPerCand + 1];
+    start[0] = 0;
+#pragma unroll
+    for (int l = 0; l < kListsPerCand; ++l) {
+        const int b = (int)blockIdx.x * kListsPerCand + l;
+        start[l + 1] = start[l] + (b < nparts ? wgcount[b] : 0u);
+    }
+    const uint32_t count = start[kListsPerCand];
+    uint32_t* const my_key = out_key + (size_t)blockIdx.x * kListsPerCand * region;
+    u64* const my_val = out_val + (size_t)blockIdx.x * kListsPerCand * region;
+    uint32_t written = 0;
     constexpr int kPer = kCandChunk / kBlock;
 
-    for (uint32_t c0 = blockIdx.x * kCandChunk; c0 < count; c0 += gridDim.x * kCandChunk) {
+    for (uint32_t c0 = 0; c0 < count; c0 += kCandChunk) {
         for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
         __syncthreads();
         uint32_t k1s[kPer], k2s[kPer], idxs[kPer], addrs[kPer];
@@ -714,7 +786,16 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
             const uint32_t e = c0 + k * kBlock + tid;
             addrs[k] = ~0u;
             if (e < count) {
-                const u64 r = open_xym[e];
+                uint32_t l = 0, sl = 0;
+#pragma unroll
+                for (int m = 1; m < kListsPerCand; ++m) {
+                    if (e >= start[m]) {
+                        l = m;
+                        sl = start[m];
+                    }
+                }
+                const size_t at = (size_t)(blockIdx.x * kListsPerCand + l) * region + (e - sl);
+                const u64 r = open_xym[at];
                 const uint32_t X = (uint32_t)r & kM, Y = (uint32_t)(r >> 23) & kM, mask = (uint32_t)(r >> 46);
                 const uint32_t q = region_of(Q, X, Y);
                 if (q < 4 && ((mask >> q) & 1u)) {
@@ -724,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
                     const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
                     k1s[k] = k1;
                     k2s[k] = k2;
-                    idxs[k] = open_idx[e];
+                    idxs[k] = open_idx[at];
                     addrs[k] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
                     atomicMin(&smin[addrs[k]], ((u64)k2 << 23) | k1);
                 }
@@ -747,7 +828,8 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
             const uint32_t incl = wave_incl_min(run);
             uint32_t before = __shfl_up(incl, 1);
             if (lane == 0) before = ~0u;
-            before = min(before, Q.sigma[q]);
+            const uint32_t sigma = q == 0 ? Q.sigma[0] : q == 1 ? Q.sigma[1] : q == 2 ? Q.sigma[2] : Q.sigma[3];
+            before = min(before, sigma);
 #pragma unroll
             for (int k = 0; k < per; ++k) {
                 sexc[(q << kSlotBits) + lane * per + k] = before;
@@ -767,20 +849,19 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
             }
         }
         uint32_t total;
-        uint32_t pos = block_excl_sum(__popc(keep), scratch, total);
-        if (tid == 0) sbase = total ? atomicAdd(&hdr->cand, total) : 0u;
-        __syncthreads();
-        pos += sbase;
+        uint32_t pos = written + block_excl_sum(__popc(keep), scratch, total);
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if ((keep >> k) & 1u) {
-                out_key[pos] = ((addrs[k] >> kSlotBits) << 23) | k1s[k];
-                out_val[pos] = ((u64)k2s[k] << 32) | idxs[k];
+                my_key[pos] = ((addrs[k] >> kSlotBits) << 23) | k1s[k];
+                my_val[pos] = ((u64)k2s[k] << 32) | idxs[k];
                 ++pos;
             }
         }
+        written += total;
         __syncthreads();
     }
+    if (tid == 0) candcount[blockIdx.x] = written;
 }
 
 // Round-1 survivor counts per region (Section 2.1.1), for chainhull_polygon:
@@ -827,26 +908,63 @@ __global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restric
 // ---------------------------------------------------------------------------
 
 __device__ inline uint32_t sort_tiles(uint32_t count) { return (count + kSortTile - 1) / kSortTile; }
+
+// Tile order of the look-back kernels: workgroup b takes tile b first, so
+// every tile it waits on belongs to a workgroup dispatched before it; tiles
+// beyond the grid (more tiles than workgroups) are handed out in ticket
+// order to workgroups that have finished their first tile.  Returns the
+// next tile of the calling workgroup (ntiles when there is none).
+__device__ inline uint32_t next_tile(uint32_t ntiles, uint32_t* ticket, uint32_t* s_tile)
+{
+    if (ntiles <= gridDim.x) return ntiles;
+    __syncthreads();
+    if (threadIdx.x == 0) *s_tile = gridDim.x + atomicAdd(ticket, 1u);
+    __syncthreads();
+    return *s_tile;
+}
 __device__ inline uint32_t spa_tiles(uint32_t count) { return (count + kSpaTile - 1) / kSpaTile; }
 
-__global__ __launch_bounds__(kBlock) void k_sort_prep(const uint32_t* __restrict__ key,
-                                                      const DevHeader* __restrict__ hdr, uint32_t* __restrict__ ghist,
+// Workgroup j copies k_cand workgroup j's records to their place in one
+// compact array (offset: the records of the workgroups before it), counts
+// the digits of all three passes, and clears the look-back words the call
+// will use.  Workgroup 0 publishes the record count.
+__global__ __launch_bounds__(kBlock) void k_sort_prep(const uint32_t* __restrict__ in_key,
+                                                      const u64* __restrict__ in_val, uint32_t in_region,
+                                                      const uint32_t* __restrict__ candcount, int nlists,
+                                                      uint32_t* __restrict__ key, u64* __restrict__ val,
+                                                      DevHeader* __restrict__ hdr, uint32_t* __restrict__ ghist,
                                                       LookAreas look)
 {
     __shared__ uint32_t h[kPassBins];
-    for (int d = threadIdx.x; d < kPassBins; d += kBlock) h[d] = 0;
+    __shared__ uint32_t scratch[kWaves];
+    const uint32_t tid = threadIdx.x;
+    for (int d = tid; d < kPassBins; d += kBlock) h[d] = 0;
+    // offset of this workgroup's list and the total (nlists <= kBlock)
+    const uint32_t c = (int)tid < nlists && !hdr->err ? candcount[tid] : 0u;
+    uint32_t count;
+    const uint32_t off = block_excl_sum(c, scratch, count);
+    __shared__ uint32_t s_off, s_len;
+    if (tid == blockIdx.x) {
+        s_off = off;
+        s_len = c;
+    }
+    if (blockIdx.x == 0 && tid == 0) hdr->cand = count;
     __syncthreads();
-    const uint32_t count = hdr->err ? 0u : hdr->cand;
-    const uint32_t stride = gridDim.x * kBlock;
-    const uint32_t first = blockIdx.x * kBlock + threadIdx.x;
-    for (uint32_t i = first; i < count; i += stride) {
-        const uint32_t k = key[i];
+    const uint32_t base = s_off, len = s_len;
+    const uint32_t* const src_k = in_key + (size_t)blockIdx.x * in_region;
+    const u64* const src_v = in_val + (size_t)blockIdx.x * in_region;
+    for (uint32_t i = tid; i < len; i += kBlock) {
+        const uint32_t k = src_k[i];
+        key[base + i] = k;
+        val[base + i] = src_v[i];
         atomicAdd(&h[k & 255u], 1u);
         atomicAdd(&h[256 + ((k >> 8) & 255u)], 1u);
         atomicAdd(&h[512 + ((k >> 16) & 511u)], 1u);
     }
     // clear the look-back words this call will use
     const uint32_t st = sort_tiles(count), sp = spa_tiles(count);
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t first = blockIdx.x * kBlock + tid;
     for (uint32_t w = first; w < st * 256; w += stride) {
         look.pass[0][w] = 0;
         look.pass[1][w] = 0;
@@ -857,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_prep(const uint32_t* __restrict
         look.spa_cnt[w] = 0;
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kPassBins; d += kBlock) {
+    for (int d = tid; d < kPassBins; d += kBlock) {
         if (h[d]) atomicAdd(&ghist[d], h[d]);
     }
 }
@@ -899,16 +1017,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(const uint32_t* __restrict
         }
     }
     const u64 lt = (1ull << lane) - 1ull;
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (uint32_t t = blockIdx.x; t < ntiles; t = next_tile(ntiles, ticket, &s_tile)) {
 #pragma unroll
         for (uint32_t p = 0; p < kPer; ++p) {
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) wcnt[w][tid * kPer + p] = 0;
         }
         __syncthreads();
-        const uint32_t t = s_tile;
-        if (t >= ntiles) break;
 
         // Wave w holds records [t*TILE + w*64*IPT, +64*IPT); record j of lane
         // l sits at +j*64 + l, so (w, j, l) is the records' order.
@@ -1046,15 +1161,12 @@ __global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict
     if (ntiles == 0) return;
     if (tid < 4) sigma[tid] = hdr->sigma[tid];
 
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (uint32_t t = blockIdx.x; t < ntiles; t = next_tile(ntiles, ticket, &s_tile)) {
         if (tid < 4) {
             kcnt[tid] = 0;
             kspa[tid] = 0;
         }
         __syncthreads();
-        const uint32_t t = s_tile;
-        if (t >= ntiles) break;
 
         // Thread tid holds records base + j (consecutive).
         const uint32_t base = t * kSpaTile + tid * kSpaIpt;
@@ -1321,7 +1433,11 @@ struct Workspace {
     uint32_t* ghist = nullptr;
     uint32_t* samp = nullptr;
     uint32_t* stair = nullptr;
-    uint32_t* key[2] = {nullptr, nullptr};
+    uint32_t* open_idx = nullptr;   // k_stream's per-workgroup lists
+    u64* open_xym = nullptr;
+    uint32_t* wgcount = nullptr;
+    uint32_t* candcount = nullptr;
+    uint32_t* key[2] = {nullptr, nullptr};  // k_cand's regions, then the sort
     u64* val[2] = {nullptr, nullptr};
     LookAreas look = {};
     PolyRec* dev_chain = nullptr;
@@ -1341,16 +1457,47 @@ struct Workspace {
 size_t sort_tile_cap(size_t cap) { return (cap + kSortTile - 1) / kSortTile; }
 size_t spa_tile_cap(size_t cap) { return (cap + kSpaTile - 1) / kSpaTile; }
 
+// Launch shape of k_stream for n points whose first `head` (0 or 1) points
+// precede the 16-byte aligned part: grid, and the points one workgroup can
+// visit (its region in the open lists).
+struct StreamShape {
+    uint32_t n4, grid, region;
+};
+
+StreamShape stream_shape(size_t n, uint32_t head)
+{
+    StreamShape sh;
+    sh.n4 = (uint32_t)((n - head) / 2);
+    const size_t per_wg = (size_t)kBlock * kStreamUnroll;
+    sh.grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(kStreamGrid, (sh.n4 + per_wg - 1) / per_wg));
+    const size_t per_round = (size_t)sh.grid * per_wg;
+    const size_t rounds = std::max<size_t>(1, (sh.n4 + per_round - 1) / per_round);
+    sh.region = (uint32_t)(2 * per_wg * rounds + 2);
+    return sh;
+}
+
+// Records the per-workgroup regions need for any call with up to cap points
+// (k_cand's regions, 4 lists each, fit in the same room since kStreamGrid
+// is a multiple of 4).
+size_t region_cap(size_t cap)
+{
+    static_assert(kStreamGrid % kListsPerCand == 0, "k_cand regions");
+    return (size_t)kStreamGrid * stream_shape(cap, 0).region;
+}
+
 size_t device_bytes(size_t cap)
 {
+    const size_t rc = region_cap(cap);
     size_t b = 0;
     b += align_up(sizeof(DevHeader), 256);
     b += align_up(sizeof(ExtPartial) * kStreamGrid, 256);
     b += align_up(sizeof(uint32_t) * kPassBins, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
-    b += 2 * align_up(sizeof(uint32_t) * cap, 256);
-    b += 2 * align_up(sizeof(u64) * cap, 256);
+    b += 2 * align_up(sizeof(uint32_t) * kStreamGrid, 256);
+    b += align_up(sizeof(uint32_t) * rc, 256) + align_up(sizeof(u64) * rc, 256);
+    b += 2 * align_up(sizeof(uint32_t) * rc, 256);
+    b += 2 * align_up(sizeof(u64) * rc, 256);
     b += 2 * align_up(sizeof(u64) * sort_tile_cap(cap) * 256, 256);
     b += align_up(sizeof(u64) * sort_tile_cap(cap) * 512, 256);
     b += 2 * align_up(sizeof(u64) * spa_tile_cap(cap), 256);
@@ -1411,8 +1558,13 @@ int ensure_device(Workspace& w, size_t n)
     w.ghist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kPassBins));
     w.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
     w.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
-    for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * cap));
-    for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * cap));
+    const size_t rc = region_cap(cap);
+    w.wgcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
+    w.candcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
+    w.open_idx = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
+    w.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
+    for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
+    for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
     const size_t st = sort_tile_cap(cap), sp = spa_tile_cap(cap);
     w.look.pass[0] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
     w.look.pass[1] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
@@ -1498,29 +1650,30 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
     CH_LAUNCH(hipLaunchKernelGGL(k_stair, dim3(4), dim3(kStairSlots), 0, s, w.samp, w.stair, w.hdr, w.ghist));
     CH_TRY(record(w, 1));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
-    const uint32_t n4 = (n - head) / 2;
-    const uint32_t gs = std::max<uint32_t>(
-        1u, std::min<uint32_t>(kStreamGrid, (n4 + kBlock * kStreamUnroll - 1) / (kBlock * kStreamUnroll)));
-    // the open lists live in the second sort buffers until k_cand has read them
-    CH_LAUNCH(hipLaunchKernelGGL(k_stream, dim3(gs), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part, w.key[1],
-                                 w.val[1], w.hdr));
+    const StreamShape sh = stream_shape(n, head);
+    CH_LAUNCH(hipLaunchKernelGGL(k_stream, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
+                                 w.open_idx, w.open_xym, sh.region, w.wgcount));
     CH_TRY(record(w, 2));
-    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(kCandGrid), dim3(kBlock), 0, s, w.part, (int)gs, w.key[1], w.val[1],
-                                 w.hdr, w.key[0], w.val[0]));
+    const uint32_t gc = (sh.grid + kListsPerCand - 1) / kListsPerCand;
+    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kBlock), 0, s, w.part, (int)sh.grid, w.open_idx, w.open_xym,
+                                 sh.region, w.wgcount, w.hdr, w.key[0], w.val[0], w.candcount));
     if (stats) {
-        const uint32_t gc = std::max<uint32_t>(1u, std::min<uint32_t>(2048u, (n + kBlock * 8 - 1) / (kBlock * 8)));
-        CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gc), dim3(kBlock), 0, s, pts, n, w.hdr));
+        const uint32_t gr = std::max<uint32_t>(1u, std::min<uint32_t>(256u, (n + kBlock * 8 - 1) / (kBlock * 8)));
+        CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gr), dim3(kBlock), 0, s, pts, n, w.hdr));
     }
     CH_TRY(record(w, 3));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(256), dim3(kBlock), 0, s, w.key[0], w.hdr, w.ghist, w.look));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
-                                 w.val[1], w.hdr, 0, w.ghist, w.look.pass[0], &w.hdr->ticket[0]));
+    // k_cand's regions (key[0]) -> compact (key[1]) -> passes 1, 2, 3 -> key[0]
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(gc), dim3(kBlock), 0, s, w.key[0], w.val[0],
+                                 kListsPerCand * sh.region, w.candcount, (int)gc, w.key[1], w.val[1], w.hdr, w.ghist,
+                                 w.look));
     CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.key[0],
-                                 w.val[0], w.hdr, 8, w.ghist + 256, w.look.pass[1], &w.hdr->ticket[1]));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<9>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
-                                 w.val[1], w.hdr, 16, w.ghist + 512, w.look.pass[2], &w.hdr->ticket[2]));
+                                 w.val[0], w.hdr, 0, w.ghist, w.look.pass[0], &w.hdr->ticket[0]));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
+                                 w.val[1], w.hdr, 8, w.ghist + 256, w.look.pass[1], &w.hdr->ticket[1]));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<9>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.key[0],
+                                 w.val[0], w.hdr, 16, w.ghist + 512, w.look.pass[2], &w.hdr->ticket[2]));
     CH_TRY(record(w, 4));
-    CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.hdr,
+    CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.hdr,
                                  w.look.spa_min, w.look.spa_cnt, &w.hdr->ticket[3], w.h_chain_dev,
                                  (uint32_t)w.h_chain_cap, w.dev_chain, stats ? 0 : 1));
     CH_TRY(record(w, 5));
