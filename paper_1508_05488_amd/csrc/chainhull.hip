@@ -276,8 +276,10 @@ __device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, u
 // minimum at P_miny and its maximum at P_maxy.  Ties go to the smallest index.
 // ---------------------------------------------------------------------------
 
-// A maximum still at its initial (0, ~0u) after the reduction means that
-// every key is 0; the minimum's index is then the answer (make_quad).
+// Per-lane extreme keys (with indices), the domain flag and the largest
+// coordinate.  A maximum still at its initial (0, ~0u) after the reduction
+// means that every key is 0; the minimum's index is then the answer
+// (make_quad).
 struct ExtAcc {
     u64 kmin[2], kmax[2];
     uint32_t imin[2], imax[2];
@@ -309,22 +311,26 @@ __device__ inline uint32_t cvt_u32_sat(float v)
     return r;
 }
 
-// A thread visits its points in increasing index order, so strict
-// comparisons keep the smallest index among equal keys.  A coordinate is in
+// Domain check of one point, X and Y its conversions: a coordinate is in
 // the domain iff its conversion converts back to it exactly (so it is an
 // integer, not NaN, not negative apart from -0) and the maximum over all
 // coordinates is at most M.
-__device__ inline void ext_visit(ExtAcc& a, float fx, float fy, uint32_t idx)
+__device__ inline void ext_check(ExtAcc& a, float fx, float fy, uint32_t X, uint32_t Y)
 {
-    const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
     a.bad = a.bad | ((float)X != fx) | ((float)Y != fy);
     a.hi = max(a.hi, max(X, Y));
+}
+
+// One candidate for the extreme points, in any order: ties of a key go to
+// the smaller index.
+__device__ inline void ext_take(ExtAcc& a, uint32_t X, uint32_t Y, uint32_t idx)
+{
     const u64 k0 = ((u64)X << 32) | (Y ^ kM);
     const u64 k1 = ((u64)Y << 32) | X;
-    if (k0 < a.kmin[0]) { a.kmin[0] = k0; a.imin[0] = idx; }
-    if (k0 > a.kmax[0]) { a.kmax[0] = k0; a.imax[0] = idx; }
-    if (k1 < a.kmin[1]) { a.kmin[1] = k1; a.imin[1] = idx; }
-    if (k1 > a.kmax[1]) { a.kmax[1] = k1; a.imax[1] = idx; }
+    take_min(a.kmin[0], a.imin[0], k0, idx);
+    take_max(a.kmax[0], a.imax[0], k0, idx);
+    take_min(a.kmin[1], a.imin[1], k1, idx);
+    take_max(a.kmax[1], a.imax[1], k1, idx);
 }
 
 __device__ inline void ext_combine(ExtAcc& a, const ExtAcc& b)
@@ -389,10 +395,15 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // region, or lies in no region, whatever the extreme points turn out to be:
 // the test needs no extreme point and runs in the same pass that finds them.
 //
-// k_stream reads every point once: the extreme-point keys and the domain
-// check, and the staircase test; the points that pass it ("open" points) go,
-// with their 4-bit frame mask, to a per-wave list in LDS that is flushed to
-// a compact array.  k_cand then reduces the extreme points, runs the exact
+// k_stream reads every point once: the domain check and the staircase test;
+// the points that pass it ("open" points) go, with their 4-bit frame mask,
+// to a per-wave list in LDS that is flushed to the workgroup's region.  The
+// extreme points are found among the open points only: every point with the
+// smallest x is open in frame R1 (no sample has a smaller x, so the
+// staircase is empty up to its slot), and likewise every point with the
+// smallest y (R2), the largest x (R3) and the largest y (R4); so the
+// lexicographic extremes of the open points, ties to the smallest index,
+// are those of all points.  k_cand then reduces the extreme points, runs the exact
 // region test on the open points only (a point counts for its region only if
 // it passed that region's frame), and filters again with a staircase over
 // chunks of 1024 records: per region and k1-slot of 2^14 values the smallest
@@ -529,44 +540,46 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         base = __shfl(base, 0);
         __builtin_amdgcn_wave_barrier();
         for (uint32_t e = lane; e < wcount; e += 64) {
-            my_idx[base + e] = lidx[wave][e];
-            my_xym[base + e] = lxym[wave][e];
+            const uint32_t i = lidx[wave][e];
+            const u64 r = lxym[wave][e];
+            ext_take(a, (uint32_t)r & kM, (uint32_t)(r >> 23) & kM, i);
+            my_idx[base + e] = i;
+            my_xym[base + e] = r;
         }
         __builtin_amdgcn_wave_barrier();
         wcount = 0;
     };
-    // The staircase test of one point: bit r-1 set when the point is below
-    // the sampled staircase of frame Rr.
-    auto frames_open = [&](uint32_t X, uint32_t Y, u64 sxv, u64 syv) {
-        return (Y < (uint32_t)sxv ? 1u : 0u) |                  // R1: k2 = y
-               ((X ^ kM) < (uint32_t)syv ? 2u : 0u) |           // R2: k2 = M - x
-               ((Y ^ kM) < (uint32_t)(sxv >> 32) ? 4u : 0u) |   // R3: k2 = M - y
-               (X < (uint32_t)(syv >> 32) ? 8u : 0u);           // R4: k2 = x
-    };
-    // Lists the open points among `cnt` points of this lane; every lane of
-    // the wave calls it together (the list append is wave-wide).
-    auto list_open = [&](const float* fxy, const uint32_t* idx, const bool* valid, int cnt) {
-        for (int p = 0; p < cnt; ++p) {
-            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
-            const uint32_t mask = valid[p] ? frames_open(X, Y, sx64[X >> kStairShift], sy64[Y >> kStairShift]) : 0u;
-            const u64 bal = __ballot(mask != 0);
-            if (mask) {
+    // One point of every lane: list it if it is open.  Every lane of the
+    // wave calls it together (the list append is wave-wide); the branch is
+    // taken when some lane of the wave has an open point.
+    auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
+        const bool o1 = Y < (uint32_t)sxv;                  // R1: k2 = y
+        const bool o2 = (X ^ kM) < (uint32_t)syv;           // R2: k2 = M - x
+        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);   // R3: k2 = M - y
+        const bool o4 = X < (uint32_t)(syv >> 32);          // R4: k2 = x
+        const bool open = valid && (o1 || o2 || o3 || o4);
+        const u64 bal = __ballot(open);
+        if (bal) {
+            if (open) {
+                const uint32_t mask = (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
                 const uint32_t slot = wcount + (uint32_t)__popcll(bal & lt);
-                lidx[wave][slot] = idx[p];
-                lxym[wave][slot] = open_rec(X, Y, mask);
+                lidx[wave][slot] = idx;
+                lxym[wave][slot] = open_rec(X & kM, Y & kM, mask);
             }
             wcount += (uint32_t)__popcll(bal);
             if (wcount > (uint32_t)(kWaveList - 64)) flush();
         }
     };
+    // (out-of-domain coordinates only need to index the staircase in range:
+    // such a call fails with a domain error)
+    auto slot_of = [](uint32_t v) { return (v >> kStairShift) & (kStairSlots - 1); };
+    auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
+        const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
+        ext_check(a, fx, fy, X, Y);
+        list_point(X, Y, idx, valid, sx64[slot_of(X)], sy64[slot_of(Y)]);
+    };
 
-    if (blockIdx.x == 0 && wave == 0 && head) {
-        const float fxy[2] = {pts[0], pts[1]};
-        const uint32_t i0 = 0;
-        const bool ok = lane == 0;
-        ext_visit(a, fxy[0], fxy[1], 0);
-        list_open(fxy, &i0, &ok, 1);
-    }
+    if (blockIdx.x == 0 && wave == 0 && head) visit_one(pts[0], pts[1], 0, lane == 0);
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
     const uint32_t stride = gridDim.x * kBlock;
@@ -595,31 +608,22 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             valid[2 * u] = valid[2 * u + 1] = g0 < n4;
         }
         // all staircase reads first, then the tests: one wait per round
+        uint32_t X[kP], Y[kP];
         u64 sxv[kP], syv[kP];
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
-            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
-            sxv[p] = sx64[X >> kStairShift];
-            syv[p] = sy64[Y >> kStairShift];
+            X[p] = cvt_u32_sat(fxy[2 * p]);
+            Y[p] = cvt_u32_sat(fxy[2 * p + 1]);
+            sxv[p] = sx64[slot_of(X[p])];
+            syv[p] = sy64[slot_of(Y[p])];
         }
 #pragma unroll
-        for (int p = 0; p < kP; ++p) ext_visit(a, fxy[2 * p], fxy[2 * p + 1], idx[p]);
-        bool any = false;
+        for (int p = 0; p < kP; ++p) ext_check(a, fxy[2 * p], fxy[2 * p + 1], X[p], Y[p]);
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
-            const uint32_t X = cvt_u32_sat(fxy[2 * p]) & kM, Y = cvt_u32_sat(fxy[2 * p + 1]) & kM;
-            any = any | (valid[p] && frames_open(X, Y, sxv[p], syv[p]) != 0);
-        }
-        // rare: some lane of the wave has an open point this round
-        if (__ballot(any)) list_open(fxy, idx, valid, kP);
+        for (int p = 0; p < kP; ++p) list_point(X[p], Y[p], idx[p], valid[p], sxv[p], syv[p]);
     }
-    if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u)) {
-        const float fxy[2] = {pts[2 * (n - 1)], pts[2 * (n - 1) + 1]};
-        const uint32_t i0 = n - 1;
-        const bool ok = lane == 0;
-        ext_visit(a, fxy[0], fxy[1], n - 1);
-        list_open(fxy, &i0, &ok, 1);
-    }
+    if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u))
+        visit_one(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
     if (wcount) flush();
 
     ext_block_reduce(a, sh);  // ends with a workgroup barrier: s_fill is final
