@@ -69,24 +69,15 @@ constexpr uint32_t kM = (1u << 23) - 1;
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kSlotBits = 9;
-constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region and tile
-constexpr int kSortIpt = 8;                       // records per thread per sort tile
-constexpr int kSortTile = kBlock * kSortIpt;      // 2048
-constexpr int kSortGrid = 512;                    // persistent workgroups per pass
-constexpr int kPassBins = 256 + 256 + 512;        // digits of the three passes
-constexpr int kSpaIpt = 4;
-constexpr int kSpaTile = kBlock * kSpaIpt;        // 1024
-constexpr int kSpaGrid = 512;
-constexpr uint32_t kSpinMax = 1u << 22;           // bound on any look-back wait
-
-// Look-back words: flag in bits 63..62 (0 empty, 1 tile aggregate,
-// 2 inclusive prefix), value in bits 61..0.
-constexpr u64 kFlagAgg = 1ull << 62;
-constexpr u64 kFlagInc = 2ull << 62;
-constexpr u64 kValMask = (1ull << 62) - 1;
+constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region (chunk filter)
+// Buckets of the region sort: region q and the top kBucketBits bits of k1;
+// inside a bucket, k1's low kLowBits bits address an LDS table directly.
+constexpr int kBucketBits = 11;
+constexpr int kLowBits = 23 - kBucketBits;
+constexpr int kBuckets = 4 << kBucketBits;        // 8192
+constexpr int kLowSize = 1 << kLowBits;           // 4096
 
 constexpr uint32_t kErrDomain = 1;   // a coordinate is outside the domain
-constexpr uint32_t kErrSpin = 2;     // a look-back wait exceeded its bound
 
 struct DevHeader {
     double ec[4];        // ex*E_q.y - ey*E_q.x for the edge E_q -> E_{q+1}
@@ -94,14 +85,12 @@ struct DevHeader {
     uint32_t ext_x[4], ext_y[4], ext_idx[4];  // P_minx, P_miny, P_maxx, P_maxy
     uint32_t sigma[4];   // k2 of each region's first point
     uint32_t err;
-    uint32_t s1[4];      // round-1 survivors per region
-    uint32_t cand;       // records written by the tile filter
-    uint32_t s2[4];      // SPA survivors per region
-    uint32_t w2[4];      // chain records written per region (after the pre-hull)
-    uint32_t chain;      // chain records written in all
-    uint32_t ticket[4];  // tile tickets: three sort passes and SPA
+    uint32_t s1[4];      // round-1 survivors per region (chainhull_polygon)
+    uint32_t cand;       // sort records (after the dominance filters)
     uint32_t open;       // points listed by k_stream
-    uint32_t pad[7];
+    uint32_t s2[4];      // SPA survivors per region
+    uint32_t chain;      // SPA survivors in all (chain points before the pre-hull)
+    uint32_t pad[15];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -117,12 +106,14 @@ struct PolyRec {
     int32_t idx, x, y;
 };
 
-// Look-back areas of one call.  Their sizes follow the capacity; the tiles a
-// call uses are a prefix of each.
-struct LookAreas {
-    u64* pass[3];
-    u64* spa_min;
-    u64* spa_cnt;
+// Per-bucket arrays of one call (device memory unless noted).
+struct Buckets {
+    uint32_t* cnt;    // records per bucket (k_cand)
+    uint32_t* kmin;   // smallest k2 per bucket (k_cand)
+    uint32_t* cur;    // fill cursors (k_bucket)
+    uint32_t* off;    // first record of each bucket (k_bucket)
+    uint32_t* thr;    // smallest k2 over the region's earlier buckets and first point
+    uint32_t* surv;   // SPA survivors per bucket (k_bucket_spa)
 };
 
 // ---------------------------------------------------------------------------
@@ -214,58 +205,6 @@ __device__ inline uint32_t block_excl_min(uint32_t v, uint32_t* scratch, uint32_
     __syncthreads();
     total = all;
     return min(before, excl);
-}
-
-__device__ inline u64 look_load(const u64* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline void look_store(u64* p, u64 v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Decoupled look-back: combine the values published by tiles t-1, t-2, ...
-// until an inclusive prefix is found.  Every earlier tile holds its ticket
-// in a running workgroup and publishes its aggregate before it waits on
-// anything, so the wait ends; the bound only guards against a broken
-// invariant (it then flags kErrSpin instead of hanging).
-// The words of up to kLookBatch earlier tiles are loaded at once, so a
-// walk past many tiles that only published aggregates costs few round trips.
-constexpr int kLookBatch = 16;
-
-template <bool kMin>
-__device__ inline u64 look_back(const u64* words, uint32_t t, uint32_t stride, uint32_t* err)
-{
-    u64 acc = kMin ? kValMask : 0ull;
-    uint32_t spins = 0;
-    int64_t j = (int64_t)t - 1;
-    while (j >= 0) {
-        u64 w[kLookBatch];
-#pragma unroll
-        for (int b = 0; b < kLookBatch; ++b) w[b] = j - b >= 0 ? look_load(words + (u64)(j - b) * stride) : kFlagInc;
-        bool done = false;
-#pragma unroll
-        for (int b = 0; b < kLookBatch; ++b) {
-            if (done || j < 0) continue;
-            u64 v = w[b];
-            while ((v & ~kValMask) == 0) {  // not published yet: wait for it
-                if (++spins > kSpinMax) {
-                    atomicOr(err, kErrSpin);
-                    return acc;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                v = look_load(words + (u64)j * stride);
-            }
-            const u64 x = v & kValMask;
-            acc = kMin ? (x < acc ? x : acc) : acc + x;
-            if ((v & ~kValMask) == kFlagInc) done = true;
-            else --j;
-        }
-        if (done) break;
-    }
-    return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -464,11 +403,11 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
 // Layout: stair[2s], stair[2s+1] = R1 at x-slot s, R3 at its own slot of
 // the same x; stair[2S + 2s], stair[2S + 2s + 1] = R2 at y-slot s, R4 at its
 // own slot of the same y (S = kStairSlots), so that one 64-bit LDS read per
-// coordinate serves two frames.  Workgroup 0 also clears the call's
-// counters.
+// coordinate serves two frames.  The workgroups also clear the call's
+// counters and bucket arrays.
 __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restrict__ samp,
                                                        uint32_t* __restrict__ stair, DevHeader* __restrict__ hdr,
-                                                       uint32_t* __restrict__ ghist)
+                                                       Buckets bk)
 {
     constexpr int kW = kStairSlots / 64;
     __shared__ uint32_t wmin[kW];
@@ -488,18 +427,16 @@ __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restric
     const uint32_t S = kStairSlots;
     const uint32_t at = q == 0 ? 2 * t : q == 1 ? 2 * S + 2 * t : q == 2 ? 2 * (S - 1 - t) + 1 : 2 * S + 2 * (S - 1 - t) + 1;
     stair[at] = excl;
+    for (uint32_t b = q * kStairSlots + t; b < (uint32_t)kBuckets; b += 4 * kStairSlots) {
+        bk.cnt[b] = 0;
+        bk.kmin[b] = ~0u;
+        bk.cur[b] = 0;
+    }
     if (q == 0) {
-        for (uint32_t d = t; d < kPassBins; d += kStairSlots) ghist[d] = 0;
-        if (t < 4) {
-            hdr->s1[t] = 0;
-            hdr->s2[t] = 0;
-            hdr->w2[t] = 0;
-            hdr->ticket[t] = 0;
-        }
+        if (t < 4) hdr->s1[t] = 0;
         if (t == 0) {
             hdr->open = 0;
             hdr->cand = 0;
-            hdr->chain = 0;
             hdr->err = 0;
         }
     }
@@ -509,11 +446,12 @@ __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restric
 // array is 16-byte aligned for float4 loads; an odd last point likewise.
 // Workgroup b writes its open points to its own region [b*region, ...) of
 // the open arrays and their number to wgcount[b]: no two workgroups share a
-// counter (same-address atomics from many workgroups serialise).
+// counter (same-address atomics from many workgroups serialise).  `per`
+// float4s per workgroup, a multiple of kBlock*kStreamUnroll.
 __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
                                                    const uint32_t* __restrict__ stair, ExtPartial* __restrict__ part,
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
-                                                   uint32_t region, uint32_t* __restrict__ wgcount)
+                                                   uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount)
 {
     __shared__ uint32_t sst[4 * kStairSlots];
     __shared__ uint32_t lidx[kWaves][kWaveList];
@@ -580,32 +518,36 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     };
 
     if (blockIdx.x == 0 && wave == 0 && head) visit_one(pts[0], pts[1], 0, lane == 0);
+    // Workgroup b streams float4s [b*per, (b+1)*per) of the aligned part, a
+    // round of kBlock*kStreamUnroll at a time, the next round's loads in
+    // flight while this round is tested.  Every lane runs the same number of
+    // rounds (the list append is wave-wide); lanes past the range reread the
+    // last float4, which changes nothing and lists nothing.
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
-    const uint32_t stride = gridDim.x * kBlock;
-    // every lane runs the same number of rounds (the list append is
-    // wave-wide); lanes past the end revisit the last float4, which leaves
-    // the extremes unchanged and lists nothing
-    const uint32_t rounds = (n4 + stride * kStreamUnroll - 1) / (stride * kStreamUnroll);
-    uint32_t f = blockIdx.x * kBlock + tid;
-    for (uint32_t it = 0; it < rounds; ++it, f += kStreamUnroll * stride) {
-        constexpr int kP = 2 * kStreamUnroll;
-        v4f v[kStreamUnroll];
+    constexpr uint32_t kRound = kBlock * kStreamUnroll;
+    const uint32_t lo = min(n4, blockIdx.x * per), hi = min(n4, lo + per);
+    const uint32_t rounds = (hi - lo + kRound - 1) / kRound;
+    auto load_round = [&](uint32_t r, v4f* v) {
 #pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) v[u] = __builtin_nontemporal_load(p4 + min(f + u * stride, n4 - 1));
+        for (int u = 0; u < kStreamUnroll; ++u)
+            v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
+    };
+    auto test_round = [&](uint32_t r, const v4f* v) {
+        constexpr int kP = 2 * kStreamUnroll;
         float fxy[2 * kP];
         uint32_t idx[kP];
         bool valid[kP];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
-            const uint32_t g0 = f + u * stride, g = min(g0, n4 - 1);
+            const uint32_t g0 = lo + r * kRound + u * kBlock + tid, g = min(g0, n4 - 1);
             fxy[4 * u + 0] = v[u].x;
             fxy[4 * u + 1] = v[u].y;
             fxy[4 * u + 2] = v[u].z;
             fxy[4 * u + 3] = v[u].w;
             idx[2 * u] = head + 2 * g;
             idx[2 * u + 1] = head + 2 * g + 1;
-            valid[2 * u] = valid[2 * u + 1] = g0 < n4;
+            valid[2 * u] = valid[2 * u + 1] = g0 < hi;
         }
         // all staircase reads first, then the tests: one wait per round
         uint32_t X[kP], Y[kP];
@@ -621,6 +563,15 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         for (int p = 0; p < kP; ++p) ext_check(a, fxy[2 * p], fxy[2 * p + 1], X[p], Y[p]);
 #pragma unroll
         for (int p = 0; p < kP; ++p) list_point(X[p], Y[p], idx[p], valid[p], sxv[p], syv[p]);
+    };
+    v4f va[kStreamUnroll], vb[kStreamUnroll];
+    if (rounds) load_round(0, va);
+    for (uint32_t r = 0; r < rounds; r += 2) {
+        if (r + 1 < rounds) load_round(r + 1, vb);
+        test_round(r, va);
+        if (r + 1 >= rounds) break;
+        if (r + 2 < rounds) load_round(r + 2, va);
+        test_round(r + 1, vb);
     }
     if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u))
         visit_one(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
@@ -738,7 +689,8 @@ __device__ inline uint32_t region_of(const Quad& Q, uint32_t X, uint32_t Y)
 
 // Workgroup j takes the open lists of k_stream workgroups 4j .. 4j+3 and
 // writes its records to its own region [j*4*region, ...) of the record
-// arrays, their number to candcount[j].
+// arrays, their number to candcount[j], and adds its records' number and
+// smallest k2 per sort bucket to the global bucket arrays.
 constexpr int kListsPerCand = 4;
 
 __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ part, int nparts,
@@ -746,12 +698,17 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
                                                  const u64* __restrict__ open_xym, uint32_t region,
                                                  const uint32_t* __restrict__ wgcount, DevHeader* __restrict__ hdr,
                                                  uint32_t* __restrict__ out_key, u64* __restrict__ out_val,
-                                                 uint32_t* __restrict__ candcount)
+                                                 uint32_t* __restrict__ candcount, Buckets bk)
 {
     __shared__ ExtAcc sh[kWaves];
     __shared__ u64 smin[4 * kSlots];
     __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
+    __shared__ uint32_t lcnt[kBuckets], lmin[kBuckets];  // per sort bucket, this chunk
+    for (int b = threadIdx.x; b < kBuckets; b += kBlock) {
+        lcnt[b] = 0;
+        lmin[b] = ~0u;
+    }
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     Quad Q;
     reduce_quad(part, nparts, hdr, Q, sh);
@@ -854,15 +811,32 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
         }
         uint32_t total;
         uint32_t pos = written + block_excl_sum(__popc(keep), scratch, total);
+        uint32_t own = 0;  // records whose bucket this thread publishes
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if ((keep >> k) & 1u) {
-                my_key[pos] = ((addrs[k] >> kSlotBits) << 23) | k1s[k];
+                const uint32_t q = addrs[k] >> kSlotBits;
+                my_key[pos] = (q << 23) | k1s[k];
                 my_val[pos] = ((u64)k2s[k] << 32) | idxs[k];
                 ++pos;
+                const uint32_t b = (q << kBucketBits) | (k1s[k] >> kLowBits);
+                if (atomicAdd(&lcnt[b], 1u) == 0) own |= 1u << k;
+                atomicMin(&lmin[b], k2s[k]);
             }
         }
         written += total;
+        __syncthreads();
+        // the chunk's records and smallest k2 per bucket, one atomic each
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if ((own >> k) & 1u) {
+                const uint32_t b = ((addrs[k] >> kSlotBits) << kBucketBits) | (k1s[k] >> kLowBits);
+                atomicAdd(&bk.cnt[b], lcnt[b]);
+                atomicMin(&bk.kmin[b], lmin[b]);
+                lcnt[b] = 0;
+                lmin[b] = ~0u;
+            }
+        }
         __syncthreads();
     }
     if (tid == 0) candcount[blockIdx.x] = written;
@@ -902,234 +876,242 @@ __global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restric
     }
 }
 // ---------------------------------------------------------------------------
-// Steps 3-4 (Section 2.1; Table 1): sort the records of all four regions at
-// once by the 25-bit key q << 23 | k1, least significant digit first
-// (8, 8, 9 bits), stably, so each region lands contiguously in Table 1's
-// order.  k_sort_prep counts the digits of all passes at once; each pass is
-// one kernel whose tiles (taken in ticket order) rank their records in
-// registers by ballot matching and find their output offsets by decoupled
-// look-back over the tiles before them.
+// Steps 3-6 (Section 2.1; Table 1; Figure 2): the region sort, SPA and the
+// chain order, as a two-level sort fused with SPA.
+//
+// Level 1 (k_bucket): the records are placed by bucket, the region code and
+// the top kBucketBits bits of k1 (a counting sort: k_cand counted the
+// buckets).  Buckets in ascending order list the regions in Table 1's order
+// and each region by ascending k1.
+//
+// Level 2 (k_bucket_spa, one workgroup per bucket): inside a bucket the low
+// kLowBits bits of k1 address an LDS table directly, and a 64-bit atomic
+// minimum of (k2 << 32 | index) per entry leaves each group of equal k1 with
+// its smallest (k2, index): the order Table 1 asks for, restricted to what
+// SPA can keep.  SPA keeps a record iff its k2 is below the k2 of every
+// earlier record of its region and of the region's first point (Figure 2's
+// threshold t is exactly that running minimum, since a discarded record
+// never lowers it); within an equal-k1 group only the group's smallest
+// (k2, index) can qualify.  The running minimum entering a bucket is the
+// minimum over the region's earlier buckets (their smallest k2, counted by
+// k_cand) and the region's first point; inside the bucket it is an
+// exclusive prefix minimum over the table.  Survivors are written, in k1
+// order, as (index, x, y) at the bucket's first record position of the
+// chain buffer (pinned host memory while it fits); the number per bucket
+// goes to host memory, and the host concatenates the buckets.
 // ---------------------------------------------------------------------------
 
-__device__ inline uint32_t sort_tiles(uint32_t count) { return (count + kSortTile - 1) / kSortTile; }
+// Exclusive prefix sum (counts) and, per region, exclusive prefix minimum
+// seeded with the region's first point (thresholds) over all buckets; every
+// thread owns kBuckets / kBlock consecutive buckets.  Returns the total.
+constexpr int kPerThreadBuckets = kBuckets / kBlock;  // 32
 
-// Tile order of the look-back kernels: workgroup b takes tile b first, so
-// every tile it waits on belongs to a workgroup dispatched before it; tiles
-// beyond the grid (more tiles than workgroups) are handed out in ticket
-// order to workgroups that have finished their first tile.  Returns the
-// next tile of the calling workgroup (ntiles when there is none).
-__device__ inline uint32_t next_tile(uint32_t ntiles, uint32_t* ticket, uint32_t* s_tile)
+__global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ in_key,
+                                                   const u64* __restrict__ in_val, uint32_t in_region,
+                                                   const uint32_t* __restrict__ candcount, int nlists,
+                                                   uint32_t* __restrict__ key, u64* __restrict__ val,
+                                                   DevHeader* __restrict__ hdr, Buckets bk)
 {
-    if (ntiles <= gridDim.x) return ntiles;
-    __syncthreads();
-    if (threadIdx.x == 0) *s_tile = gridDim.x + atomicAdd(ticket, 1u);
-    __syncthreads();
-    return *s_tile;
-}
-__device__ inline uint32_t spa_tiles(uint32_t count) { return (count + kSpaTile - 1) / kSpaTile; }
-
-// Workgroup j copies k_cand workgroup j's records to their place in one
-// compact array (offset: the records of the workgroups before it), counts
-// the digits of all three passes, and clears the look-back words the call
-// will use.  Workgroup 0 publishes the record count.
-__global__ __launch_bounds__(kBlock) void k_sort_prep(const uint32_t* __restrict__ in_key,
-                                                      const u64* __restrict__ in_val, uint32_t in_region,
-                                                      const uint32_t* __restrict__ candcount, int nlists,
-                                                      uint32_t* __restrict__ key, u64* __restrict__ val,
-                                                      DevHeader* __restrict__ hdr, uint32_t* __restrict__ ghist,
-                                                      LookAreas look)
-{
-    __shared__ uint32_t h[kPassBins];
+    static_assert(kBuckets % kBlock == 0 && (kBuckets / 4) % kPerThreadBuckets == 0, "bucket ownership");
+    __shared__ uint32_t soff[kBuckets];   // first position of each bucket
+    __shared__ uint32_t lcnt[kBuckets];   // this chunk's records per bucket, then their base
     __shared__ uint32_t scratch[kWaves];
     const uint32_t tid = threadIdx.x;
-    for (int d = tid; d < kPassBins; d += kBlock) h[d] = 0;
-    // offset of this workgroup's list and the total (nlists <= kBlock)
-    const uint32_t c = (int)tid < nlists && !hdr->err ? candcount[tid] : 0u;
-    uint32_t count;
-    const uint32_t off = block_excl_sum(c, scratch, count);
-    __shared__ uint32_t s_off, s_len;
-    if (tid == blockIdx.x) {
-        s_off = off;
-        s_len = c;
-    }
-    if (blockIdx.x == 0 && tid == 0) hdr->cand = count;
-    __syncthreads();
-    const uint32_t base = s_off, len = s_len;
-    const uint32_t* const src_k = in_key + (size_t)blockIdx.x * in_region;
-    const u64* const src_v = in_val + (size_t)blockIdx.x * in_region;
-    for (uint32_t i = tid; i < len; i += kBlock) {
-        const uint32_t k = src_k[i];
-        key[base + i] = k;
-        val[base + i] = src_v[i];
-        atomicAdd(&h[k & 255u], 1u);
-        atomicAdd(&h[256 + ((k >> 8) & 255u)], 1u);
-        atomicAdd(&h[512 + ((k >> 16) & 511u)], 1u);
-    }
-    // clear the look-back words this call will use
-    const uint32_t st = sort_tiles(count), sp = spa_tiles(count);
-    const uint32_t stride = gridDim.x * kBlock;
-    const uint32_t first = blockIdx.x * kBlock + tid;
-    for (uint32_t w = first; w < st * 256; w += stride) {
-        look.pass[0][w] = 0;
-        look.pass[1][w] = 0;
-    }
-    for (uint32_t w = first; w < st * 512; w += stride) look.pass[2][w] = 0;
-    for (uint32_t w = first; w < sp; w += stride) {
-        look.spa_min[w] = 0;
-        look.spa_cnt[w] = 0;
-    }
-    __syncthreads();
-    for (int d = tid; d < kPassBins; d += kBlock) {
-        if (h[d]) atomicAdd(&ghist[d], h[d]);
-    }
-}
+    if (hdr->err) return;
 
-template <int kBits>
-__global__ __launch_bounds__(kBlock) void k_sort_pass(const uint32_t* __restrict__ key_in,
-                                                      const u64* __restrict__ val_in, uint32_t* __restrict__ key_out,
-                                                      u64* __restrict__ val_out, DevHeader* __restrict__ hdr,
-                                                      int shift, const uint32_t* __restrict__ ghist_pass,
-                                                      u64* __restrict__ look_pass, uint32_t* __restrict__ ticket)
-{
-    constexpr uint32_t kBins = 1u << kBits, kMask = kBins - 1;
-    constexpr uint32_t kPer = kBins / kBlock;  // digits per thread (1 or 2)
-    __shared__ uint32_t base[kBins];
-    __shared__ uint32_t wcnt[kWaves][kBins];
-    __shared__ uint32_t excl[kBins];
-    __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_tile;
-
-    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    const uint32_t count = hdr->err ? 0u : hdr->cand;
-    const uint32_t ntiles = sort_tiles(count);
-    if (ntiles == 0) return;
-
-    // base[d]: records with a smaller digit, over the whole array
+    // bucket offsets (every workgroup); totals and thresholds (workgroup 0)
     {
-        uint32_t c[kPer], s = 0;
+        uint32_t c[kPerThreadBuckets], sum = 0;
 #pragma unroll
-        for (uint32_t p = 0; p < kPer; ++p) {
-            c[p] = ghist_pass[tid * kPer + p];
-            s += c[p];
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            c[k] = bk.cnt[tid * kPerThreadBuckets + k];
+            sum += c[k];
         }
         uint32_t total;
-        uint32_t run = block_excl_sum(s, scratch, total);
+        uint32_t run = block_excl_sum(sum, scratch, total);
 #pragma unroll
-        for (uint32_t p = 0; p < kPer; ++p) {
-            base[tid * kPer + p] = run;
-            run += c[p];
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            soff[tid * kPerThreadBuckets + k] = run;
+            lcnt[tid * kPerThreadBuckets + k] = 0;
+            run += c[k];
+        }
+        if (blockIdx.x == 0) {
+            // a region's buckets are owned by 64 consecutive threads: one wave
+            const uint32_t q = tid / 64;
+            uint32_t m[kPerThreadBuckets], lo = ~0u;
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) {
+                m[k] = bk.kmin[tid * kPerThreadBuckets + k];
+                lo = min(lo, m[k]);
+            }
+            const uint32_t incl = wave_incl_min(lo);
+            uint32_t before = __shfl_up(incl, 1);
+            if (lane_id() == 0) before = ~0u;
+            before = min(before, hdr->sigma[q]);
+            uint32_t r2 = run - sum;
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) {
+                const uint32_t b = tid * kPerThreadBuckets + k;
+                bk.thr[b] = before;
+                bk.off[b] = r2;
+                before = min(before, m[k]);
+                r2 += c[k];
+            }
+            if (tid == 0) hdr->cand = total;
         }
     }
-    const u64 lt = (1ull << lane) - 1ull;
-    for (uint32_t t = blockIdx.x; t < ntiles; t = next_tile(ntiles, ticket, &s_tile)) {
-#pragma unroll
-        for (uint32_t p = 0; p < kPer; ++p) {
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) wcnt[w][tid * kPer + p] = 0;
-        }
-        __syncthreads();
+    __syncthreads();
 
-        // Wave w holds records [t*TILE + w*64*IPT, +64*IPT); record j of lane
-        // l sits at +j*64 + l, so (w, j, l) is the records' order.
-        const uint32_t wbase = t * kSortTile + wave * 64 * kSortIpt;
-        uint32_t k[kSortIpt], d[kSortIpt], r[kSortIpt];
-        u64 v[kSortIpt];
+    // place this workgroup's records (k_cand workgroup blockIdx.x), a chunk
+    // at a time: local ranks by LDS atomics, one global reservation per
+    // bucket and chunk
+    const uint32_t count = (int)blockIdx.x < nlists ? candcount[blockIdx.x] : 0u;
+    const uint32_t* const src_k = in_key + (size_t)blockIdx.x * in_region;
+    const u64* const src_v = in_val + (size_t)blockIdx.x * in_region;
+    constexpr int kPer = 4;
+    for (uint32_t c0 = 0; c0 < count; c0 += kPer * kBlock) {
+        uint32_t kk[kPer], b[kPer], r[kPer];
+        u64 vv[kPer];
+        uint32_t own = 0;
 #pragma unroll
-        for (int j = 0; j < kSortIpt; ++j) {
-            const uint32_t i = wbase + j * 64 + lane;
-            const bool ok = i < count;
-            k[j] = ok ? key_in[i] : 0u;
-            v[j] = ok ? val_in[i] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < kSortIpt; ++j) {
-            const uint32_t i = wbase + j * 64 + lane;
-            const bool ok = i < count;
-            d[j] = (k[j] >> shift) & kMask;
-            u64 peers = __ballot(ok);
-#pragma unroll
-            for (int b = 0; b < kBits; ++b) {
-                const u64 bal = __ballot((d[j] >> b) & 1u);
-                peers &= ((d[j] >> b) & 1u) ? bal : ~bal;
-            }
-            const uint32_t below = (uint32_t)__popcll(peers & lt);
-            const uint32_t cur = ok ? wcnt[wave][d[j]] : 0u;
-            r[j] = cur + below;
-            if (ok && below == 0) wcnt[wave][d[j]] = cur + (uint32_t)__popcll(peers);
-        }
-        __syncthreads();
-        // per digit: the tile's count, each wave's offset inside the tile, and
-        // the records of this digit in earlier tiles (decoupled look-back)
-        // (every aggregate of this thread is published before it waits)
-        uint32_t tcount[kPer];
-#pragma unroll
-        for (uint32_t p = 0; p < kPer; ++p) {
-            const uint32_t dd = tid * kPer + p;
-            uint32_t run = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = wcnt[w][dd];
-                wcnt[w][dd] = run;
-                run += c;
-            }
-            tcount[p] = run;
-            look_store(look_pass + (u64)t * kBins + dd, (t == 0 ? kFlagInc : kFlagAgg) | run);
-        }
-#pragma unroll
-        for (uint32_t p = 0; p < kPer; ++p) {
-            const uint32_t dd = tid * kPer + p;
-            if (t == 0) {
-                excl[dd] = 0;
-            } else {
-                const u64 before = look_back<false>(look_pass + dd, t, kBins, &hdr->err);
-                look_store(look_pass + (u64)t * kBins + dd, kFlagInc | (before + tcount[p]));
-                excl[dd] = (uint32_t)before;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSortIpt; ++j) {
-            const uint32_t i = wbase + j * 64 + lane;
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = c0 + k * kBlock + tid;
+            b[k] = ~0u;
             if (i < count) {
-                const uint32_t dst = base[d[j]] + excl[d[j]] + wcnt[wave][d[j]] + r[j];
-                if (dst < count) {
-                    key_out[dst] = k[j];
-                    val_out[dst] = v[j];
-                }
+                kk[k] = src_k[i];
+                vv[k] = src_v[i];
+                b[k] = ((kk[k] >> 23) << kBucketBits) | ((kk[k] & kM) >> kLowBits);
+                r[k] = atomicAdd(&lcnt[b[k]], 1u);
+                if (r[k] == 0) own |= 1u << k;
             }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if ((own >> k) & 1u) lcnt[b[k]] = soff[b[k]] + atomicAdd(&bk.cur[b[k]], lcnt[b[k]]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (b[k] != ~0u) {
+                const uint32_t pos = lcnt[b[k]] + r[k];
+                key[pos] = kk[k];
+                val[pos] = vv[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if ((own >> k) & 1u) lcnt[b[k]] = 0;
         }
         __syncthreads();
     }
 }
 
+// kBucketsPerSpa consecutive buckets per workgroup, one after the other.
+// kLowSize table entries, kLowSize / kBlock per thread (consecutive).
+// Survivors go, as (index, x, y), to dev_chain at the bucket's first record
+// position; their number to bk.surv.
+constexpr int kPerThreadLow = kLowSize / kBlock;  // 16
+constexpr int kBucketsPerSpa = 4;
+
+__global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restrict__ key,
+                                                       const u64* __restrict__ val,
+                                                       const DevHeader* __restrict__ hdr, Buckets bk,
+                                                       PolyRec* __restrict__ dev_chain)
+{
+    __shared__ u64 tab[kLowSize];
+    __shared__ uint32_t scratch[kWaves];
+    const uint32_t tid = threadIdx.x;
+    if (hdr->err) return;
+    uint32_t fill[kBucketsPerSpa];
+#pragma unroll
+    for (int k = 0; k < kBucketsPerSpa; ++k) fill[k] = bk.cur[blockIdx.x * kBucketsPerSpa + k];
+    for (int kb = 0; kb < kBucketsPerSpa; ++kb) {
+        const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = fill[kb];
+        if (m == 0) {
+            if (tid == 0) bk.surv[b] = 0;
+            continue;
+        }
+        const uint32_t off = bk.off[b], thr = bk.thr[b];
+        for (int e = tid; e < kLowSize; e += kBlock) tab[e] = ~0ull;
+        __syncthreads();
+        for (uint32_t i = tid; i < m; i += kBlock) {
+            const uint32_t k1 = key[off + i] & kM;
+            const u64 v = val[off + i];  // k2 << 32 | index
+            atomicMin(&tab[k1 & (kLowSize - 1)], v);
+        }
+        __syncthreads();
+        // exclusive prefix minimum of k2 over the table, seeded with the
+        // threshold entering the bucket; survivors in table order
+        u64 e[kPerThreadLow];
+        uint32_t lo = ~0u;
+#pragma unroll
+        for (int k = 0; k < kPerThreadLow; ++k) {
+            e[k] = tab[tid * kPerThreadLow + k];
+            lo = min(lo, (uint32_t)(e[k] >> 32));
+        }
+        uint32_t unused;
+        uint32_t run = min(thr, block_excl_min(lo, scratch, unused));
+        uint32_t keep = 0;
+#pragma unroll
+        for (int k = 0; k < kPerThreadLow; ++k) {
+            const uint32_t k2 = (uint32_t)(e[k] >> 32);
+            if (e[k] != ~0ull && k2 < run) keep |= 1u << k;
+            run = min(run, k2);
+        }
+        uint32_t total;
+        uint32_t pos = off + block_excl_sum(__popc(keep), scratch, total);
+        const uint32_t q = b >> kBucketBits;
+        const uint32_t k1base = (b & ((1u << kBucketBits) - 1)) << kLowBits;
+#pragma unroll
+        for (int k = 0; k < kPerThreadLow; ++k) {
+            if ((keep >> k) & 1u) {
+                const uint32_t k1 = k1base + tid * kPerThreadLow + k, k2 = (uint32_t)(e[k] >> 32);
+                // invert the frame: x = (k1, M-k2, M-k1, k2), y = (k2, k1, M-k2, M-k1)
+                const uint32_t a = (q & 1u) ? k2 : k1;
+                const uint32_t bb = (q & 1u) ? k1 : k2;
+                const uint32_t X = ((q ^ (q >> 1)) & 1u) ? a ^ kM : a;
+                const uint32_t Y = (q & 2u) ? bb ^ kM : bb;
+                dev_chain[pos++] = PolyRec{(int32_t)(uint32_t)e[k], (int32_t)X, (int32_t)Y};
+            }
+        }
+        if (tid == 0) bk.surv[b] = total;
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Steps 5-6 (Figure 2; Section 2.2.2): SPA over the sorted records as a
-// segmented exclusive prefix minimum, and the chains written in order.
+// Step 6 (Section 2.1; Section 2.2.2): the chains concatenated in bucket
+// order, cut into segments of kSeg points, each shortened by a pre-hull and
+// written to pinned host memory.
 //
-// In each region a record is kept iff its k2 is below the region's first
-// point's k2 and below every earlier record's k2: Figure 2's threshold t is
-// exactly that running minimum, since a discarded record never lowers it.
-// Records with equal (q, k1) form a group; only the group's smallest
-// (k2, index) can survive, and it does iff its k2 is below the minimum over
-// the records before the group.  Group minima come from a segmented suffix
-// minimum over the tile; a group that runs past the tile's end is finished
-// by its head's workgroup reading forward together, 256 records at a time.
+// Pre-hull: a chain point whose two neighbours (in the segment, after the
+// removals so far) belong to its region and with which it makes no left
+// turn in the region's frame lies on or above the segment joining two
+// points of the region, so its support value never strictly exceeds theirs
+// for any outward direction of that corner: it is not a strict hull vertex.
+// All such points are removed at once, and again, until none is left (at
+// most kPrehullRounds times).  Only non-vertices go, so the hull of the
+// polygon the finish scans is unchanged; the frames are rotations, so turns
+// keep their sign.
 //
-// The prefix minimum runs over tagged values ((3 - q) << 23 | k2): records of
-// earlier regions carry larger tags, so a prefix minimum carrying this
-// region's tag is this region's running minimum.  Tiles find the minimum and
-// the survivor count of all earlier tiles by decoupled look-back.  Survivors
-// are written as (index, x, y) at their rank in the chain order: into the
-// pinned host buffer while the rank fits it, into device memory beyond.
-//
-// With `prehull`, a tile also drops the survivors that are not on the lower
-// convex chain (in the region's frame, which is a rotation) of the tile's
-// survivors of the same region.  Such a point lies on or above the segment
-// joining two survivors on either side of it, so its support value never
-// strictly exceeds theirs for any outward direction of that corner: it is
-// not a strict hull vertex.  This shortens the polygon the finish scans
-// without changing its hull.
+// Segment s keeps its points at [s*kSeg, ...) of the host chain buffer and
+// writes how many of each region it kept to segcnt[4s .. 4s+3].  Workgroup
+// 0 also publishes the SPA survivor counts per region.
 // ---------------------------------------------------------------------------
+constexpr int kSeg = 4096;
+constexpr int kPerThreadSeg = kSeg / kBlock;  // 16
+constexpr int kChainGrid = 256;
+constexpr int kPrehullRounds = 24;
+
+__device__ inline void to_frame(uint32_t q, uint32_t X, uint32_t Y, uint32_t& k1, uint32_t& k2)
+{
+    const uint32_t a = (q & 1u) ? Y : X;
+    const uint32_t b = (q & 1u) ? X : Y;
+    k1 = (q & 2u) ? a ^ kM : a;
+    k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+}
 
 // Frame cross product (o, a, b): > 0 for a left turn.
 __device__ inline i64 frame_turn(uint32_t o1, uint32_t o2, uint32_t a1, uint32_t a2, uint32_t b1, uint32_t b2)
@@ -1138,269 +1120,114 @@ __device__ inline i64 frame_turn(uint32_t o1, uint32_t o2, uint32_t a1, uint32_t
            (i64)((int32_t)a2 - (int32_t)o2) * (i64)((int32_t)b1 - (int32_t)o1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_spa_chain(const uint32_t* __restrict__ key, const u64* __restrict__ val,
-                                                      DevHeader* __restrict__ hdr, u64* __restrict__ look_min,
-                                                      u64* __restrict__ look_cnt, uint32_t* __restrict__ ticket,
-                                                      PolyRec* __restrict__ host_chain, uint32_t host_cap,
-                                                      PolyRec* __restrict__ dev_chain, int prehull)
+__global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ dev_chain,
+                                                  DevHeader* __restrict__ hdr, Buckets bk,
+                                                  PolyRec* __restrict__ host_chain, uint32_t host_cap,
+                                                  PolyRec* __restrict__ spill, uint32_t* __restrict__ segcnt,
+                                                  int prehull)
 {
+    __shared__ uint32_t pre[kBuckets];  // chain points before each bucket
+    __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
+    __shared__ uint16_t lst[kSeg];
+    __shared__ uint8_t reg[kSeg], alive[kSeg];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_tile, s_min_before, s_cnt_before;
-    __shared__ uint32_t kcnt[4], kspa[4];
-    __shared__ uint32_t sigma[4];
-    __shared__ uint32_t shb[kBlock];     // head bits of each thread's records
-    __shared__ u64 sseg[kBlock];         // suffix minima per thread (segment carry)
-    __shared__ u64 wtot[kWaves];
-    __shared__ uint32_t wflag[kWaves];
-    __shared__ uint32_t s_last_head, s_cont;
-    __shared__ u64 s_ext;
-    __shared__ u64 sk[kSpaTile];         // survivors' frame coordinates k1 | k2 << 32
-    __shared__ uint8_t sq[kSpaTile];     // and region
-    __shared__ uint8_t alive[kSpaTile];
-    __shared__ uint16_t stk[kSpaTile];
-
+    __shared__ uint32_t s_removed, s_cnt[4];
     const uint32_t tid = threadIdx.x;
-    const uint32_t count = hdr->err ? 0u : hdr->cand;
-    const uint32_t ntiles = spa_tiles(count);
-    if (ntiles == 0) return;
-    if (tid < 4) sigma[tid] = hdr->sigma[tid];
+    if (hdr->err) return;
 
-    for (uint32_t t = blockIdx.x; t < ntiles; t = next_tile(ntiles, ticket, &s_tile)) {
-        if (tid < 4) {
-            kcnt[tid] = 0;
-            kspa[tid] = 0;
-        }
-        __syncthreads();
-
-        // Thread tid holds records base + j (consecutive).
-        const uint32_t base = t * kSpaTile + tid * kSpaIpt;
-        uint32_t kk[kSpaIpt], pre[kSpaIpt];
-        u64 vv[kSpaIpt];
-        uint32_t run = ~0u;
+    uint32_t total;
+    {
+        uint32_t c[kPerThreadBuckets], sum = 0;
 #pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            const uint32_t i = base + j;
-            const bool ok = i < count;
-            kk[j] = ok ? key[i] : 0u;
-            vv[j] = ok ? val[i] : 0ull;
-            const uint32_t tag = ok ? ((3u - (kk[j] >> 23)) << 23) | (uint32_t)(vv[j] >> 32) : ~0u;
-            pre[j] = run;
-            run = min(run, tag);
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            c[k] = bk.surv[tid * kPerThreadBuckets + k];
+            sum += c[k];
         }
-        uint32_t tile_min;
-        const uint32_t before_in_tile = block_excl_min(run, scratch, tile_min);
-        if (tid == 0) {
-            u64* w = look_min + t;
-            if (t == 0) {
-                look_store(w, kFlagInc | tile_min);
-                s_min_before = ~0u;
-            } else {
-                look_store(w, kFlagAgg | tile_min);
-                const u64 b = look_back<true>(look_min, t, 1, &hdr->err);
-                const uint32_t bm = b >= 0xffffffffull ? ~0u : (uint32_t)b;
-                look_store(w, kFlagInc | min(bm, tile_min));
-                s_min_before = bm;
+        uint32_t run = block_excl_sum(sum, scratch, total);
+#pragma unroll
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            pre[tid * kPerThreadBuckets + k] = run;
+            run += c[k];
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < 4) {
+        const uint32_t first = pre[tid << kBucketBits];
+        const uint32_t last = tid == 3 ? total : pre[(tid + 1) << kBucketBits];
+        hdr->s2[tid] = last - first;
+        if (tid == 0) hdr->chain = total;
+    }
+    const uint32_t nseg = (total + kSeg - 1) / kSeg;
+    for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const uint32_t base = sg * kSeg, len = min((uint32_t)kSeg, total - base);
+        // every point: its bucket (the last with pre <= position: its range
+        // holds the position), region, place in dev_chain, frame coordinates
+        for (uint32_t i = tid; i < len; i += kBlock) {
+            const uint32_t g = base + i;
+            uint32_t lo = 0, hi = kBuckets - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (pre[mid] <= g) lo = mid;
+                else hi = mid - 1;
             }
+            const uint32_t q = lo >> kBucketBits;
+            const uint32_t a = bk.off[lo] + (g - pre[lo]);
+            const PolyRec r = dev_chain[a];
+            uint32_t k1, k2;
+            to_frame(q, (uint32_t)r.x, (uint32_t)r.y, k1, k2);
+            at[i] = a;
+            reg[i] = (uint8_t)q;
+            ka[i] = k1;
+            kb[i] = k2;
+            alive[i] = 1;
         }
+        if (tid < 4) s_cnt[tid] = 0;
         __syncthreads();
-        const uint32_t before = min(s_min_before, before_in_tile);
-
-        // --- group minima: segmented suffix minimum over the tile ---
-        // head bit j: record base+j starts a group (records past the end
-        // count as heads so that they close every segment)
-        uint32_t hb = 0;
-        if (tid == 0) s_last_head = 0;
+        // alive points in order: thread t owns positions [16t, 16t+16)
+        auto compact = [&]() -> uint32_t {
+            uint32_t mine = 0;
 #pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            const uint32_t i = base + j;
-            const uint32_t prev = j > 0 ? kk[j > 0 ? j - 1 : 0] : (i > 0 && i < count ? key[i - 1] : ~0u);
-            if (i >= count || prev != kk[j]) hb |= 1u << j;
-        }
-        shb[tid] = hb;
-        __syncthreads();
-        // brk bit j: the segment of record j ends at j (record j+1 is a head,
-        // or j is the tile's last record)
-        const uint32_t next0 = tid + 1 < (uint32_t)kBlock ? (shb[tid + 1] & 1u) : 1u;
-        const uint32_t brk = (hb >> 1) | (next0 << (kSpaIpt - 1));
-        // thread aggregate: minimum from item 0 to the first break, and
-        // whether a break occurs
-        u64 agg = ~0ull;
-        uint32_t fl = 0;
-#pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            if (!fl) {
-                agg = vv[j] < agg ? vv[j] : agg;
-                fl = (brk >> j) & 1u;
+            for (int k = 0; k < kPerThreadSeg; ++k) {
+                const uint32_t i = tid * kPerThreadSeg + k;
+                mine += (i < len && alive[i]) ? 1u : 0u;
             }
-        }
-        // reverse inclusive scan of (fl, agg) under (fL,aL)+(fR,aR) =
-        // fL ? (1,aL) : (fR, min(aL,aR)); wave level, then across waves
-        {
-            const uint32_t lane = lane_id(), wave = tid / 64;
+            uint32_t n_alive;
+            uint32_t o = block_excl_sum(mine, scratch, n_alive);
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const u64 oa = __shfl_down(agg, off);
-                const uint32_t of = __shfl_down(fl, off);
-                if (lane + off < 64 && !fl) {
-                    agg = oa < agg ? oa : agg;
-                    fl = of;
-                }
-            }
-            if (lane == 0) {
-                wtot[wave] = agg;
-                wflag[wave] = fl;
+            for (int k = 0; k < kPerThreadSeg; ++k) {
+                const uint32_t i = tid * kPerThreadSeg + k;
+                if (i < len && alive[i]) lst[o++] = (uint16_t)i;
             }
             __syncthreads();
-            if (!fl) {
-                for (int w = wave + 1; w < kWaves; ++w) {
-                    agg = wtot[w] < agg ? wtot[w] : agg;
-                    if (wflag[w]) break;
-                }
-            }
-            sseg[tid] = agg;
+            return n_alive;
+        };
+        uint32_t n_alive = compact();
+        for (int round = 0; prehull && round < kPrehullRounds; ++round) {
+            if (tid == 0) s_removed = 0;
             __syncthreads();
-        }
-        // per-record suffix minimum of its segment inside the tile
-        u64 gmin[kSpaIpt];
-        {
-            u64 run = tid + 1 < (uint32_t)kBlock ? sseg[tid + 1] : ~0ull;
-#pragma unroll
-            for (int j = kSpaIpt - 1; j >= 0; --j) {
-                if ((brk >> j) & 1u) run = vv[j];
-                else run = vv[j] < run ? vv[j] : run;
-                gmin[j] = run;
-            }
-        }
-        // the tile's last group may continue into later tiles
-#pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            if (((hb >> j) & 1u) && base + j < count) atomicMax(&s_last_head, base + j + 1);
-        }
-        __syncthreads();
-        const uint32_t tile_end = min(count, (t + 1) * kSpaTile);
-        if (tid == 0) {
-            s_cont = (s_last_head != 0 && tile_end < count && key[tile_end] == key[tile_end - 1]) ? 1u : 0u;
-            s_ext = ~0ull;
-        }
-        __syncthreads();
-        if (s_cont) {
-            const uint32_t gkey = key[tile_end - 1];
-            u64 m = ~0ull;
-            for (uint32_t at = tile_end;; at += kBlock) {
-                const uint32_t i = at + tid;
-                const bool in = i < count && key[i] == gkey;
-                if (in) m = val[i] < m ? val[i] : m;
-                if (!__syncthreads_or(!in)) continue;
-                break;
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const u64 o = __shfl_xor(m, off);
-                m = o < m ? o : m;
-            }
-            if (lane_id() == 0) atomicMin(&s_ext, m);
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kSpaIpt; ++j) {
-                if (base + j + 1 == s_last_head) gmin[j] = s_ext < gmin[j] ? s_ext : gmin[j];
-            }
-        }
-
-        uint32_t keep = 0;
-#pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            const uint32_t i = base + j;
-            if (i < count && ((hb >> j) & 1u)) {
-                const uint32_t q = kk[j] >> 23;
-                const uint32_t pm = min(before, pre[j]);
-                uint32_t thr = sigma[q];
-                if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
-                if ((uint32_t)(gmin[j] >> 32) < thr) {
-                    keep |= 1u << j;
-                    atomicAdd(&kspa[q], 1u);
-                }
-            }
-        }
-        if (prehull) {
-            // stage the tile's survivors in chain order, scan each region's
-            // run for its lower convex chain (one thread), drop the rest
-            uint32_t n_tile;
-            const uint32_t first = block_excl_sum(__popc(keep), scratch, n_tile);
-            uint32_t at = first;
-#pragma unroll
-            for (int j = 0; j < kSpaIpt; ++j) {
-                if ((keep >> j) & 1u) {
-                    sk[at] = (u64)(kk[j] & kM) | ((gmin[j] >> 32) << 32);
-                    sq[at] = (uint8_t)(kk[j] >> 23);
-                    ++at;
+            for (uint32_t p = tid + 1; p + 1 < n_alive; p += kBlock) {
+                const uint32_t a = lst[p - 1], i = lst[p], c = lst[p + 1];
+                if (reg[a] == reg[i] && reg[c] == reg[i] &&
+                    frame_turn(ka[a], kb[a], ka[i], kb[i], ka[c], kb[c]) <= 0) {
+                    alive[i] = 0;
+                    s_removed = 1;
                 }
             }
             __syncthreads();
-            if (tid == 0) {
-                uint32_t top = 0;
-                for (uint32_t i = 0; i < n_tile; ++i) {
-                    const u64 p = sk[i];
-                    const uint32_t p1 = (uint32_t)p, p2 = (uint32_t)(p >> 32);
-                    if (i > 0 && sq[i] != sq[i - 1]) top = 0;  // a new region starts
-                    while (top >= 2) {
-                        const u64 o = sk[stk[top - 2]], a = sk[stk[top - 1]];
-                        if (frame_turn((uint32_t)o, (uint32_t)(o >> 32), (uint32_t)a, (uint32_t)(a >> 32), p1, p2) > 0)
-                            break;
-                        alive[stk[top - 1]] = 0;
-                        --top;
-                    }
-                    stk[top++] = (uint16_t)i;
-                    alive[i] = 1;
-                }
-            }
-            __syncthreads();
-            at = first;
-#pragma unroll
-            for (int j = 0; j < kSpaIpt; ++j) {
-                if ((keep >> j) & 1u) {
-                    if (!alive[at]) keep &= ~(1u << j);
-                    ++at;
-                }
-            }
+            if (!s_removed) break;
+            n_alive = compact();
         }
-        uint32_t tile_kept;
-        uint32_t pos = block_excl_sum(__popc(keep), scratch, tile_kept);
-        if (tid == 0) {
-            u64* w = look_cnt + t;
-            if (t == 0) {
-                look_store(w, kFlagInc | tile_kept);
-                s_cnt_before = 0;
-            } else {
-                look_store(w, kFlagAgg | tile_kept);
-                const u64 b = look_back<false>(look_cnt, t, 1, &hdr->err);
-                look_store(w, kFlagInc | (b + tile_kept));
-                s_cnt_before = (uint32_t)b;
-            }
-            if (tile_kept) atomicAdd(&hdr->chain, tile_kept);
+        // the kept points, in order, at base + rank
+        for (uint32_t p = tid; p < n_alive; p += kBlock) {
+            const uint32_t i = lst[p];
+            const PolyRec r = dev_chain[at[i]];
+            const uint32_t o = base + p;
+            if (o < host_cap) host_chain[o] = r;
+            else spill[o - host_cap] = r;
+            atomicAdd(&s_cnt[reg[i]], 1u);
         }
         __syncthreads();
-        pos += s_cnt_before;
-#pragma unroll
-        for (int j = 0; j < kSpaIpt; ++j) {
-            if ((keep >> j) & 1u) {
-                const uint32_t q = kk[j] >> 23, k1 = kk[j] & kM, k2 = (uint32_t)(gmin[j] >> 32);
-                // invert the frame: x = (k1, M-k2, M-k1, k2), y = (k2, k1, M-k2, M-k1)
-                const uint32_t a = (q & 1u) ? k2 : k1;
-                const uint32_t b = (q & 1u) ? k1 : k2;
-                const uint32_t X = ((q ^ (q >> 1)) & 1u) ? a ^ kM : a;
-                const uint32_t Y = (q & 2u) ? b ^ kM : b;
-                const PolyRec rec{(int32_t)(uint32_t)gmin[j], (int32_t)X, (int32_t)Y};
-                if (pos < host_cap) host_chain[pos] = rec;
-                else dev_chain[pos - host_cap] = rec;
-                atomicAdd(&kcnt[q], 1u);
-                ++pos;
-            }
-        }
-        __syncthreads();
-        if (tid < 4) {
-            if (kcnt[tid]) atomicAdd(&hdr->w2[tid], kcnt[tid]);
-            if (kspa[tid]) atomicAdd(&hdr->s2[tid], kspa[tid]);
-        }
+        if (tid < 4) segcnt[4 * sg + tid] = s_cnt[tid];
         __syncthreads();
     }
 }
@@ -1434,16 +1261,15 @@ struct Workspace {
     char* dbuf = nullptr;
     DevHeader* hdr = nullptr;
     ExtPartial* part = nullptr;
-    uint32_t* ghist = nullptr;
     uint32_t* samp = nullptr;
     uint32_t* stair = nullptr;
     uint32_t* open_idx = nullptr;   // k_stream's per-workgroup lists
     u64* open_xym = nullptr;
     uint32_t* wgcount = nullptr;
     uint32_t* candcount = nullptr;
-    uint32_t* key[2] = {nullptr, nullptr};  // k_cand's regions, then the sort
+    uint32_t* key[2] = {nullptr, nullptr};  // k_cand's regions; the bucketed records
     u64* val[2] = {nullptr, nullptr};
-    LookAreas look = {};
+    Buckets bk = {};
     PolyRec* dev_chain = nullptr;
     DevHeader* h_hdr = nullptr;     // pinned
     PolyRec* h_chain = nullptr;     // pinned, device-visible
@@ -1454,29 +1280,32 @@ struct Workspace {
     size_t h_out_cap = 0;
     std::vector<int32_t> xy, idx;   // finish input
     std::vector<PolyRec> spill;     // chain records beyond the pinned buffer
+    PolyRec* dev_spill = nullptr;   // device: chain records beyond the pinned buffer
+    uint32_t* h_segcnt = nullptr;   // pinned, device-visible: kept points per segment and region
+    uint32_t* h_segcnt_dev = nullptr;
+    size_t h_segcnt_cap = 0;        // segments
+    int64_t s2[4] = {}, w2[4] = {}, chain = 0;  // counts of the last call
     hipEvent_t ev[8] = {};
     bool events = false;
 };
-
-size_t sort_tile_cap(size_t cap) { return (cap + kSortTile - 1) / kSortTile; }
-size_t spa_tile_cap(size_t cap) { return (cap + kSpaTile - 1) / kSpaTile; }
 
 // Launch shape of k_stream for n points whose first `head` (0 or 1) points
 // precede the 16-byte aligned part: grid, and the points one workgroup can
 // visit (its region in the open lists).
 struct StreamShape {
-    uint32_t n4, grid, region;
+    uint32_t n4, grid, per, region;
 };
 
 StreamShape stream_shape(size_t n, uint32_t head)
 {
     StreamShape sh;
     sh.n4 = (uint32_t)((n - head) / 2);
-    const size_t per_wg = (size_t)kBlock * kStreamUnroll;
-    sh.grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(kStreamGrid, (sh.n4 + per_wg - 1) / per_wg));
-    const size_t per_round = (size_t)sh.grid * per_wg;
-    const size_t rounds = std::max<size_t>(1, (sh.n4 + per_round - 1) / per_round);
-    sh.region = (uint32_t)(2 * per_wg * rounds + 2);
+    const size_t round = (size_t)kBlock * kStreamUnroll;
+    sh.grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(kStreamGrid, (sh.n4 + round - 1) / round));
+    const size_t per = std::max<size_t>(1, (sh.n4 + sh.grid - 1) / sh.grid);
+    sh.per = (uint32_t)((per + round - 1) / round * round);
+    sh.grid = (uint32_t)std::max<size_t>(1, (sh.n4 + sh.per - 1) / sh.per);  // no empty workgroup
+    sh.region = 2 * sh.per + 2;  // points one workgroup can visit (+ head and tail)
     return sh;
 }
 
@@ -1495,17 +1324,14 @@ size_t device_bytes(size_t cap)
     size_t b = 0;
     b += align_up(sizeof(DevHeader), 256);
     b += align_up(sizeof(ExtPartial) * kStreamGrid, 256);
-    b += align_up(sizeof(uint32_t) * kPassBins, 256);
+    b += 6 * align_up(sizeof(uint32_t) * kBuckets, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
     b += 2 * align_up(sizeof(uint32_t) * kStreamGrid, 256);
     b += align_up(sizeof(uint32_t) * rc, 256) + align_up(sizeof(u64) * rc, 256);
     b += 2 * align_up(sizeof(uint32_t) * rc, 256);
     b += 2 * align_up(sizeof(u64) * rc, 256);
-    b += 2 * align_up(sizeof(u64) * sort_tile_cap(cap) * 256, 256);
-    b += align_up(sizeof(u64) * sort_tile_cap(cap) * 512, 256);
-    b += 2 * align_up(sizeof(u64) * spa_tile_cap(cap), 256);
-    b += align_up(sizeof(PolyRec) * cap, 256);
+    b += 2 * align_up(sizeof(PolyRec) * cap, 256);
     return b;
 }
 
@@ -1559,7 +1385,12 @@ int ensure_device(Workspace& w, size_t n)
     };
     w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
-    w.ghist = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kPassBins));
+    w.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.kmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.cur = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.thr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.surv = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     w.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
     w.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
     const size_t rc = region_cap(cap);
@@ -1569,13 +1400,8 @@ int ensure_device(Workspace& w, size_t n)
     w.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
     for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
     for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
-    const size_t st = sort_tile_cap(cap), sp = spa_tile_cap(cap);
-    w.look.pass[0] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
-    w.look.pass[1] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 256));
-    w.look.pass[2] = reinterpret_cast<u64*>(take(sizeof(u64) * st * 512));
-    w.look.spa_min = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
-    w.look.spa_cnt = reinterpret_cast<u64*>(take(sizeof(u64) * sp));
     w.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    w.dev_spill = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
     return CH_OK;
 }
 
@@ -1587,6 +1413,14 @@ int ensure_host(Workspace& w, size_t out)
                              hipHostMallocMapped));
         CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_chain_dev), w.h_chain, 0));
         w.h_chain_cap = kHostChainDefault;
+    }
+    const size_t nseg = w.cap / kSeg + 1;
+    if (w.h_segcnt_cap < nseg) {
+        if (w.h_segcnt) CH_TRY(hipHostFree(w.h_segcnt));
+        w.h_segcnt = nullptr;
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_segcnt), sizeof(uint32_t) * 4 * nseg, hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_segcnt_dev), w.h_segcnt, 0));
+        w.h_segcnt_cap = nseg;
     }
     if (w.h_out_cap < out + 1) {
         if (w.h_out) CH_TRY(hipHostFree(w.h_out));
@@ -1625,6 +1459,7 @@ void free_workspace(Workspace* w)
     if (w->h_hdr) (void)hipHostFree(w->h_hdr);
     if (w->h_chain) (void)hipHostFree(w->h_chain);
     if (w->h_out) (void)hipHostFree(w->h_out);
+    if (w->h_segcnt) (void)hipHostFree(w->h_segcnt);
     if (w->events) {
         for (auto& e : w->ev) (void)hipEventDestroy(e);
     }
@@ -1651,46 +1486,41 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
     CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.samp));
-    CH_LAUNCH(hipLaunchKernelGGL(k_stair, dim3(4), dim3(kStairSlots), 0, s, w.samp, w.stair, w.hdr, w.ghist));
+    CH_LAUNCH(hipLaunchKernelGGL(k_stair, dim3(4), dim3(kStairSlots), 0, s, w.samp, w.stair, w.hdr, w.bk));
     CH_TRY(record(w, 1));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
     const StreamShape sh = stream_shape(n, head);
     CH_LAUNCH(hipLaunchKernelGGL(k_stream, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
-                                 w.open_idx, w.open_xym, sh.region, w.wgcount));
+                                 w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount));
     CH_TRY(record(w, 2));
     const uint32_t gc = (sh.grid + kListsPerCand - 1) / kListsPerCand;
     CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kBlock), 0, s, w.part, (int)sh.grid, w.open_idx, w.open_xym,
-                                 sh.region, w.wgcount, w.hdr, w.key[0], w.val[0], w.candcount));
+                                 sh.region, w.wgcount, w.hdr, w.key[0], w.val[0], w.candcount, w.bk));
     if (stats) {
         const uint32_t gr = std::max<uint32_t>(1u, std::min<uint32_t>(256u, (n + kBlock * 8 - 1) / (kBlock * 8)));
         CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gr), dim3(kBlock), 0, s, pts, n, w.hdr));
     }
     CH_TRY(record(w, 3));
-    // k_cand's regions (key[0]) -> compact (key[1]) -> passes 1, 2, 3 -> key[0]
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_prep, dim3(gc), dim3(kBlock), 0, s, w.key[0], w.val[0],
-                                 kListsPerCand * sh.region, w.candcount, (int)gc, w.key[1], w.val[1], w.hdr, w.ghist,
-                                 w.look));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.key[0],
-                                 w.val[0], w.hdr, 0, w.ghist, w.look.pass[0], &w.hdr->ticket[0]));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<8>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.key[1],
-                                 w.val[1], w.hdr, 8, w.ghist + 256, w.look.pass[1], &w.hdr->ticket[1]));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sort_pass<9>, dim3(kSortGrid), dim3(kBlock), 0, s, w.key[1], w.val[1], w.key[0],
-                                 w.val[0], w.hdr, 16, w.ghist + 512, w.look.pass[2], &w.hdr->ticket[2]));
+    // k_cand's regions (key[0]) -> by bucket (key[1]) -> SPA per bucket
+    CH_LAUNCH(hipLaunchKernelGGL(k_bucket, dim3(gc), dim3(kBlock), 0, s, w.key[0], w.val[0],
+                                 kListsPerCand * sh.region, w.candcount, (int)gc, w.key[1], w.val[1], w.hdr, w.bk));
     CH_TRY(record(w, 4));
-    CH_LAUNCH(hipLaunchKernelGGL(k_spa_chain, dim3(kSpaGrid), dim3(kBlock), 0, s, w.key[0], w.val[0], w.hdr,
-                                 w.look.spa_min, w.look.spa_cnt, &w.hdr->ticket[3], w.h_chain_dev,
-                                 (uint32_t)w.h_chain_cap, w.dev_chain, stats ? 0 : 1));
+    CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1], w.val[1],
+                                 w.hdr, w.bk, w.dev_chain));
+    CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kChainGrid), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
+                                 w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill, w.h_segcnt_dev, stats ? 0 : 1));
     CH_TRY(record(w, 5));
     CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
     CH_TRY(record(w, 6));
     CH_TRY(hipStreamSynchronize(s));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
+    // kept chain points sit below the chain length
     const size_t m = w.h_hdr->chain;
     w.spill.clear();
     if (m > w.h_chain_cap) {
         w.spill.resize(m - w.h_chain_cap);
-        CH_TRY(hipMemcpy(w.spill.data(), w.dev_chain, sizeof(PolyRec) * w.spill.size(), hipMemcpyDeviceToHost));
+        CH_TRY(hipMemcpy(w.spill.data(), w.dev_spill, sizeof(PolyRec) * w.spill.size(), hipMemcpyDeviceToHost));
     }
     return CH_OK;
 }
@@ -1701,14 +1531,13 @@ inline const PolyRec& chain_at(const Workspace& w, size_t i)
 }
 
 // The simple polygon [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] with
-// consecutive coincident vertices dropped (cyclically), into w.xy / w.idx.
+// consecutive coincident vertices dropped (cyclically), into w.xy / w.idx:
+// each region's chain is its buckets' survivors in bucket order.
 void build_polygon(Workspace& w)
 {
     const DevHeader& h = *w.h_hdr;
     w.xy.clear();
     w.idx.clear();
-    w.xy.reserve(2 * ((size_t)h.chain + 4));
-    w.idx.reserve((size_t)h.chain + 4);
     auto push = [&](int32_t idx, int32_t x, int32_t y) {
         const size_t k = w.idx.size();
         if (k && w.xy[2 * k - 2] == x && w.xy[2 * k - 1] == y) return;
@@ -1716,14 +1545,31 @@ void build_polygon(Workspace& w)
         w.xy.push_back(x);
         w.xy.push_back(y);
     };
-    size_t at = 0;
-    for (int q = 0; q < 4; ++q) {
-        push((int32_t)h.ext_idx[q], (int32_t)h.ext_x[q], (int32_t)h.ext_y[q]);
-        for (uint32_t k = 0; k < h.w2[q]; ++k, ++at) {
-            const PolyRec& r = chain_at(w, at);
-            push(r.idx, r.x, r.y);
+    int cur = -1;  // regions whose extreme point is in
+    auto enter = [&](int q) {
+        while (cur < q) {
+            ++cur;
+            push((int32_t)h.ext_idx[cur], (int32_t)h.ext_x[cur], (int32_t)h.ext_y[cur]);
+        }
+    };
+    for (int q = 0; q < 4; ++q) w.w2[q] = 0;
+    const size_t nseg = ((size_t)h.chain + kSeg - 1) / kSeg;
+    for (size_t sg = 0; sg < nseg; ++sg) {
+        size_t at = sg * kSeg;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t c = w.h_segcnt[4 * sg + q];
+            if (!c) continue;
+            enter(q);
+            for (uint32_t r = 0; r < c; ++r, ++at) {
+                const PolyRec& rec = chain_at(w, at);
+                push(rec.idx, rec.x, rec.y);
+            }
+            w.w2[q] += c;
         }
     }
+    enter(3);
+    for (int q = 0; q < 4; ++q) w.s2[q] = h.s2[q];
+    w.chain = h.chain;
     while (w.idx.size() > 1 && w.xy[2 * w.idx.size() - 2] == w.xy[0] && w.xy[2 * w.idx.size() - 1] == w.xy[1]) {
         w.idx.pop_back();
         w.xy.pop_back();
@@ -1742,11 +1588,11 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
         st->ext_xy[2 * e] = (int32_t)h.ext_x[e];
         st->ext_xy[2 * e + 1] = (int32_t)h.ext_y[e];
         st->s1[e] = stats ? (int64_t)h.s1[e] : -1;
-        st->s2[e] = h.s2[e];
+        st->s2[e] = w.s2[e];
     }
     st->open = h.open;
     st->candidates = h.cand;
-    st->polygon = (int64_t)h.chain + 4;
+    st->polygon = w.w2[0] + w.w2[1] + w.w2[2] + w.w2[3] + 4;
     if (g_timing && w.events) {
         // stage slots: 0 sample + staircases, 1 k_stream, 2 k_cand, 3 sort,
         // 4 SPA + chains, 5 copy-out (6 is unused, 7 the host finish)
@@ -1773,14 +1619,14 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
         CH_TRY(hipMemsetAsync(out_count, 0, sizeof(int32_t), stream));
         return CH_OK;
     }
-    CH_TRY(ensure_host(*w, 0));
     CH_TRY(ensure_device(*w, (size_t)n));
+    CH_TRY(ensure_host(*w, 0));  // after the device part: sized by its capacity
     rc = run_preprocess(*w, points, (uint32_t)n, false);
     int64_t h = 0;
     if (rc == CH_OK) {
-        fill_stats(*w, n, &st, false);
         const auto t0 = std::chrono::steady_clock::now();
         build_polygon(*w);
+        fill_stats(*w, n, &st, false);
         rc = ensure_host(*w, w->idx.size());
         if (rc == CH_OK) {
             rc = melkman_finish(w->xy.data(), w->idx.data(), (int64_t)w->idx.size(), w->h_out + 1, &h) == 0
@@ -1859,12 +1705,12 @@ int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t
     Workspace* w = workspace_for(reinterpret_cast<hipStream_t>(stream), &rc);
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
-    CH_TRY(ensure_host(*w, 0));
     CH_TRY(ensure_device(*w, (size_t)n));
+    CH_TRY(ensure_host(*w, 0));  // after the device part: sized by its capacity
     rc = run_preprocess(*w, points, (uint32_t)n, true);
     if (rc != CH_OK) return rc;
-    fill_stats(*w, n, &st, true);
     build_polygon(*w);
+    fill_stats(*w, n, &st, true);
     for (size_t i = 0; i < w->idx.size(); ++i) poly_idx[i] = w->idx[i];
     *poly_count = (int64_t)w->idx.size();
     if (stats) *stats = st;

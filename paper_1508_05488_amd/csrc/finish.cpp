@@ -12,6 +12,7 @@
 //  * the newest vertex, kept at both deque ends, is finally dropped when it
 //    lies on the segment joining its two neighbours;
 //  * the result is rotated to start at the smallest (y, x).
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -36,7 +37,11 @@ inline int64_t turn(const V& a, const V& b, const V& c)
 int melkman_finish(const int32_t* xy, const int32_t* idx, int64_t m, int32_t* out, int64_t* out_count)
 {
     *out_count = 0;
-    std::vector<V> p;
+    // working arrays kept per thread: their memory is reused by later calls
+    // instead of being mapped and faulted in afresh
+    thread_local std::vector<V> p, hull, d;
+    p.clear();
+    hull.clear();
     p.reserve(static_cast<size_t>(m));
     for (int64_t i = 0; i < m; ++i) {
         V v{xy[2 * i], xy[2 * i + 1], idx[i]};
@@ -46,7 +51,6 @@ int melkman_finish(const int32_t* xy, const int32_t* idx, int64_t m, int32_t* ou
     }
     while (p.size() > 1 && p.back().x == p.front().x && p.back().y == p.front().y) p.pop_back();
 
-    std::vector<V> hull;
     const size_t np = p.size();
     if (np <= 2) {
         hull = p;
@@ -69,7 +73,7 @@ int melkman_finish(const int32_t* xy, const int32_t* idx, int64_t m, int32_t* ou
             // Deque in a flat array with room to grow by one slot per vertex
             // at either end: d[bot] .. d[top], with d[bot] == d[top].
             const int64_t cap = 2 * static_cast<int64_t>(np) + 8;
-            std::vector<V> d(static_cast<size_t>(cap));
+            if (d.size() < static_cast<size_t>(cap)) d.resize(static_cast<size_t>(cap));
             int64_t bot = static_cast<int64_t>(np) + 2, top = bot + 3;
             d[bot] = p[k];
             d[top] = p[k];
