@@ -109,7 +109,7 @@ struct PolyRec {
 // Per-bucket arrays of one call (device memory unless noted).
 struct Buckets {
     uint32_t* cnt;    // records per bucket (k_cand)
-    uint32_t* kmin;   // smallest k2 per bucket (k_cand)
+    u64* kmin;        // smallest (k2 << 23 | k1) per bucket (k_cand)
     uint32_t* cur;    // fill cursors (k_bucket)
     uint32_t* off;    // first record of each bucket (k_bucket)
     uint32_t* thr;    // smallest k2 over the region's earlier buckets and first point
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restric
     stair[at] = excl;
     for (uint32_t b = q * kStairSlots + t; b < (uint32_t)kBuckets; b += 4 * kStairSlots) {
         bk.cnt[b] = 0;
-        bk.kmin[b] = ~0u;
+        bk.kmin[b] = ~0ull;
         bk.cur[b] = 0;
     }
     if (q == 0) {
@@ -704,10 +704,11 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
     __shared__ u64 smin[4 * kSlots];
     __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t lcnt[kBuckets], lmin[kBuckets];  // per sort bucket, this chunk
+    __shared__ uint32_t lcnt[kBuckets];  // per sort bucket, this chunk
+    __shared__ u64 lmin[kBuckets];
     for (int b = threadIdx.x; b < kBuckets; b += kBlock) {
         lcnt[b] = 0;
-        lmin[b] = ~0u;
+        lmin[b] = ~0ull;
     }
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     Quad Q;
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
                 ++pos;
                 const uint32_t b = (q << kBucketBits) | (k1s[k] >> kLowBits);
                 if (atomicAdd(&lcnt[b], 1u) == 0) own |= 1u << k;
-                atomicMin(&lmin[b], k2s[k]);
+                atomicMin(&lmin[b], ((u64)k2s[k] << 23) | k1s[k]);
             }
         }
         written += total;
@@ -834,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
                 atomicAdd(&bk.cnt[b], lcnt[b]);
                 atomicMin(&bk.kmin[b], lmin[b]);
                 lcnt[b] = 0;
-                lmin[b] = ~0u;
+                lmin[b] = ~0ull;
             }
         }
         __syncthreads();
@@ -914,65 +915,63 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
 {
     static_assert(kBuckets % kBlock == 0 && (kBuckets / 4) % kPerThreadBuckets == 0, "bucket ownership");
     __shared__ uint32_t soff[kBuckets];   // first position of each bucket
+    __shared__ uint32_t sthr[kBuckets];   // threshold entering each bucket
     __shared__ uint32_t lcnt[kBuckets];   // this chunk's records per bucket, then their base
     __shared__ uint32_t scratch[kWaves];
     const uint32_t tid = threadIdx.x;
     if (hdr->err) return;
 
-    // bucket offsets (every workgroup); totals and thresholds (workgroup 0)
+    // bucket offsets and thresholds: thread t owns kPerThreadBuckets
+    // consecutive buckets, so a region's buckets are one wave's
     {
         uint32_t c[kPerThreadBuckets], sum = 0;
+        u64 mk[kPerThreadBuckets];
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
             c[k] = bk.cnt[tid * kPerThreadBuckets + k];
+            mk[k] = bk.kmin[tid * kPerThreadBuckets + k];
             sum += c[k];
         }
         uint32_t total;
         uint32_t run = block_excl_sum(sum, scratch, total);
+        const uint32_t q = tid / 64;
+        uint32_t lo = ~0u;
+#pragma unroll
+        for (int k = 0; k < kPerThreadBuckets; ++k) lo = min(lo, (uint32_t)(mk[k] >> 23));
+        const uint32_t incl = wave_incl_min(lo);
+        uint32_t before = __shfl_up(incl, 1);
+        if (lane_id() == 0) before = ~0u;
+        before = min(before, hdr->sigma[q]);
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
-            soff[tid * kPerThreadBuckets + k] = run;
-            lcnt[tid * kPerThreadBuckets + k] = 0;
-            run += c[k];
-        }
-        if (blockIdx.x == 0) {
-            // a region's buckets are owned by 64 consecutive threads: one wave
-            const uint32_t q = tid / 64;
-            uint32_t m[kPerThreadBuckets], lo = ~0u;
-#pragma unroll
-            for (int k = 0; k < kPerThreadBuckets; ++k) {
-                m[k] = bk.kmin[tid * kPerThreadBuckets + k];
-                lo = min(lo, m[k]);
-            }
-            const uint32_t incl = wave_incl_min(lo);
-            uint32_t before = __shfl_up(incl, 1);
-            if (lane_id() == 0) before = ~0u;
-            before = min(before, hdr->sigma[q]);
-            uint32_t r2 = run - sum;
-#pragma unroll
-            for (int k = 0; k < kPerThreadBuckets; ++k) {
-                const uint32_t b = tid * kPerThreadBuckets + k;
+            const uint32_t b = tid * kPerThreadBuckets + k;
+            soff[b] = run;
+            sthr[b] = before;
+            lcnt[b] = 0;
+            if (blockIdx.x == 0) {
+                bk.off[b] = run;
                 bk.thr[b] = before;
-                bk.off[b] = r2;
-                before = min(before, m[k]);
-                r2 += c[k];
             }
-            if (tid == 0) hdr->cand = total;
+            run += c[k];
+            before = min(before, (uint32_t)(mk[k] >> 23));
         }
+        if (blockIdx.x == 0 && tid == 0) hdr->cand = total;
     }
     __syncthreads();
 
-    // place this workgroup's records (k_cand workgroup blockIdx.x), a chunk
+    // Place this workgroup's records (k_cand workgroup blockIdx.x), a chunk
     // at a time: local ranks by LDS atomics, one global reservation per
-    // bucket and chunk
+    // bucket and chunk.  A record is dropped first when the threshold
+    // entering its bucket is <= its k2 (a record of an earlier bucket, or the
+    // region's first point, dominates it) or when its bucket's smallest
+    // record precedes it with k1 <= its k1; the sort and SPA would drop it.
     const uint32_t count = (int)blockIdx.x < nlists ? candcount[blockIdx.x] : 0u;
     const uint32_t* const src_k = in_key + (size_t)blockIdx.x * in_region;
     const u64* const src_v = in_val + (size_t)blockIdx.x * in_region;
     constexpr int kPer = 4;
     for (uint32_t c0 = 0; c0 < count; c0 += kPer * kBlock) {
         uint32_t kk[kPer], b[kPer], r[kPer];
-        u64 vv[kPer];
-        uint32_t own = 0;
+        u64 vv[kPer], bm[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = c0 + k * kBlock + tid;
@@ -981,8 +980,22 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
                 kk[k] = src_k[i];
                 vv[k] = src_v[i];
                 b[k] = ((kk[k] >> 23) << kBucketBits) | ((kk[k] & kM) >> kLowBits);
-                r[k] = atomicAdd(&lcnt[b[k]], 1u);
-                if (r[k] == 0) own |= 1u << k;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) bm[k] = b[k] != ~0u ? bk.kmin[b[k]] : ~0ull;
+        uint32_t own = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (b[k] != ~0u) {
+                const uint32_t k1 = kk[k] & kM, k2 = (uint32_t)(vv[k] >> 32);
+                const u64 me = ((u64)k2 << 23) | k1;
+                if (k2 >= sthr[b[k]] || (bm[k] < me && (uint32_t)(bm[k] & kM) <= k1)) {
+                    b[k] = ~0u;
+                } else {
+                    r[k] = atomicAdd(&lcnt[b[k]], 1u);
+                    if (r[k] == 0) own |= 1u << k;
+                }
             }
         }
         __syncthreads();
@@ -1008,12 +1021,27 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
     }
 }
 
-// kBucketsPerSpa consecutive buckets per workgroup, one after the other.
-// kLowSize table entries, kLowSize / kBlock per thread (consecutive).
-// Survivors go, as (index, x, y), to dev_chain at the bucket's first record
-// position; their number to bk.surv.
+// Workgroup g takes buckets 4g .. 4g+3.  A bucket of at most 64 records is
+// resolved by one wave without the table: lane l holds record l, which SPA
+// keeps iff its k2 is below the threshold and no record of the bucket
+// precedes it in (k1, k2, index) order with k2 <= its k2; its rank in the
+// chain is the number of kept records with a smaller k1 (kept records have
+// distinct k1).  Larger buckets use the table, the whole workgroup on one
+// bucket at a time.  Survivors go, as (index, x, y), to dev_chain at the
+// bucket's first record position; their number to bk.surv.
 constexpr int kPerThreadLow = kLowSize / kBlock;  // 16
-constexpr int kBucketsPerSpa = 4;
+constexpr int kBucketsPerSpa = kWaves;
+constexpr uint32_t kWaveBucket = 64;
+
+__device__ inline PolyRec chain_rec(uint32_t q, uint32_t k1, uint32_t k2, uint32_t idx)
+{
+    // invert the frame: x = (k1, M-k2, M-k1, k2), y = (k2, k1, M-k2, M-k1)
+    const uint32_t a = (q & 1u) ? k2 : k1;
+    const uint32_t b = (q & 1u) ? k1 : k2;
+    const uint32_t X = ((q ^ (q >> 1)) & 1u) ? a ^ kM : a;
+    const uint32_t Y = (q & 2u) ? b ^ kM : b;
+    return PolyRec{(int32_t)idx, (int32_t)X, (int32_t)Y};
+}
 
 __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restrict__ key,
                                                        const u64* __restrict__ val,
@@ -1022,24 +1050,59 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
 {
     __shared__ u64 tab[kLowSize];
     __shared__ uint32_t scratch[kWaves];
-    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_fill[kBucketsPerSpa];
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     if (hdr->err) return;
-    uint32_t fill[kBucketsPerSpa];
-#pragma unroll
-    for (int k = 0; k < kBucketsPerSpa; ++k) fill[k] = bk.cur[blockIdx.x * kBucketsPerSpa + k];
-    for (int kb = 0; kb < kBucketsPerSpa; ++kb) {
-        const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = fill[kb];
-        if (m == 0) {
-            if (tid == 0) bk.surv[b] = 0;
-            continue;
+    {
+        // one wave per bucket of at most kWaveBucket records
+        const uint32_t b = blockIdx.x * kBucketsPerSpa + wave;
+        const uint32_t m = bk.cur[b];
+        if (lane == 0) s_fill[wave] = m;
+        if (m <= kWaveBucket) {
+            const uint32_t off = bk.off[b], thr = bk.thr[b];
+            uint32_t k1 = ~0u, k2 = ~0u, idx = ~0u;
+            if (lane < m) {
+                k1 = key[off + lane] & kM;
+                const u64 v = val[off + lane];
+                k2 = (uint32_t)(v >> 32);
+                idx = (uint32_t)v;
+            }
+            bool kept = lane < m && k2 < thr;
+            for (uint32_t j = 0; j < m; ++j) {
+                const uint32_t a1 = __shfl(k1, j), a2 = __shfl(k2, j), ai = __shfl(idx, j);
+                const bool prec = a1 < k1 || (a1 == k1 && (a2 < k2 || (a2 == k2 && ai < idx)));
+                if (prec && a2 <= k2) kept = false;
+            }
+            const u64 kb = __ballot(kept);
+            uint32_t rank = 0;
+            for (uint32_t j = 0; j < m; ++j) {
+                const uint32_t a1 = __shfl(k1, j);
+                if (((kb >> j) & 1ull) && a1 < k1) ++rank;
+            }
+            if (kept) dev_chain[off + rank] = chain_rec(b >> kBucketBits, k1, k2, idx);
+            if (lane == 0) bk.surv[b] = (uint32_t)__popcll(kb);
         }
+    }
+    __syncthreads();
+    for (int kb = 0; kb < kBucketsPerSpa; ++kb) {
+        const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = s_fill[kb];
+        if (m <= kWaveBucket) continue;
         const uint32_t off = bk.off[b], thr = bk.thr[b];
         for (int e = tid; e < kLowSize; e += kBlock) tab[e] = ~0ull;
         __syncthreads();
-        for (uint32_t i = tid; i < m; i += kBlock) {
-            const uint32_t k1 = key[off + i] & kM;
-            const u64 v = val[off + i];  // k2 << 32 | index
-            atomicMin(&tab[k1 & (kLowSize - 1)], v);
+        constexpr int kBatch = 8;  // records loaded together per thread
+        for (uint32_t i0 = 0; i0 < m; i0 += kBatch * kBlock) {
+            uint32_t k1[kBatch];
+            u64 v[kBatch];  // k2 << 32 | index
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const uint32_t i = i0 + u * kBlock + tid;
+                k1[u] = i < m ? key[off + i] : 0u;
+                v[u] = i < m ? val[off + i] : ~0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                if (v[u] != ~0ull) atomicMin(&tab[k1[u] & (kLowSize - 1)], v[u]);
         }
         __syncthreads();
         // exclusive prefix minimum of k2 over the table, seeded with the
@@ -1066,15 +1129,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
         const uint32_t k1base = (b & ((1u << kBucketBits) - 1)) << kLowBits;
 #pragma unroll
         for (int k = 0; k < kPerThreadLow; ++k) {
-            if ((keep >> k) & 1u) {
-                const uint32_t k1 = k1base + tid * kPerThreadLow + k, k2 = (uint32_t)(e[k] >> 32);
-                // invert the frame: x = (k1, M-k2, M-k1, k2), y = (k2, k1, M-k2, M-k1)
-                const uint32_t a = (q & 1u) ? k2 : k1;
-                const uint32_t bb = (q & 1u) ? k1 : k2;
-                const uint32_t X = ((q ^ (q >> 1)) & 1u) ? a ^ kM : a;
-                const uint32_t Y = (q & 2u) ? bb ^ kM : bb;
-                dev_chain[pos++] = PolyRec{(int32_t)(uint32_t)e[k], (int32_t)X, (int32_t)Y};
-            }
+            if ((keep >> k) & 1u)
+                dev_chain[pos++] = chain_rec(q, k1base + tid * kPerThreadLow + k, (uint32_t)(e[k] >> 32), (uint32_t)e[k]);
         }
         if (tid == 0) bk.surv[b] = total;
         __syncthreads();
@@ -1086,24 +1142,23 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
 // order, cut into segments of kSeg points, each shortened by a pre-hull and
 // written to pinned host memory.
 //
-// Pre-hull: a chain point whose two neighbours (in the segment, after the
-// removals so far) belong to its region and with which it makes no left
-// turn in the region's frame lies on or above the segment joining two
-// points of the region, so its support value never strictly exceeds theirs
-// for any outward direction of that corner: it is not a strict hull vertex.
-// All such points are removed at once, and again, until none is left (at
-// most kPrehullRounds times).  Only non-vertices go, so the hull of the
-// polygon the finish scans is unchanged; the frames are rotations, so turns
-// keep their sign.
+// Pre-hull: a chain point that makes no left turn, in its region's frame,
+// with two other points of its region around it (in chain order) lies on or
+// above the segment joining them, so its support value never strictly
+// exceeds theirs for any outward direction of that corner: it is not a
+// strict hull vertex.  All such points (with their current neighbours) go
+// at once, round after round, until the segment's chains are convex.  Only
+// non-vertices go, so the hull of the polygon the finish scans is
+// unchanged; the frames are rotations, so turns keep their sign.
 //
 // Segment s keeps its points at [s*kSeg, ...) of the host chain buffer and
 // writes how many of each region it kept to segcnt[4s .. 4s+3].  Workgroup
 // 0 also publishes the SPA survivor counts per region.
 // ---------------------------------------------------------------------------
-constexpr int kSeg = 4096;
-constexpr int kPerThreadSeg = kSeg / kBlock;  // 16
+constexpr int kSeg = 1024;
+constexpr int kPerThreadSeg = kSeg / kBlock;  // 4
 constexpr int kChainGrid = 256;
-constexpr int kPrehullRounds = 24;
+constexpr int kPrehullRounds = 16;
 
 __device__ inline void to_frame(uint32_t q, uint32_t X, uint32_t Y, uint32_t& k1, uint32_t& k2)
 {
@@ -1124,16 +1179,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                                                   DevHeader* __restrict__ hdr, Buckets bk,
                                                   PolyRec* __restrict__ host_chain, uint32_t host_cap,
                                                   PolyRec* __restrict__ spill, uint32_t* __restrict__ segcnt,
-                                                  int prehull)
+                                                  DevHeader* __restrict__ host_hdr, int prehull)
 {
     __shared__ uint32_t pre[kBuckets];  // chain points before each bucket
     __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
     __shared__ uint16_t lst[kSeg];
     __shared__ uint8_t reg[kSeg], alive[kSeg];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_removed, s_cnt[4];
+    __shared__ uint32_t s_removed[2], s_cnt[4];
     const uint32_t tid = threadIdx.x;
-    if (hdr->err) return;
+    // the header, for the host, once every field is final
+    auto publish_header = [&]() {
+        if (blockIdx.x != 0) return;
+        __syncthreads();
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(hdr);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(host_hdr);
+        for (uint32_t e = tid; e < sizeof(DevHeader) / 4; e += kBlock) dst[e] = src[e];
+    };
+    if (hdr->err) {
+        publish_header();
+        return;
+    }
 
     uint32_t total;
     {
@@ -1161,25 +1227,46 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
     for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
         const uint32_t base = sg * kSeg, len = min((uint32_t)kSeg, total - base);
         // every point: its bucket (the last with pre <= position: its range
-        // holds the position), region, place in dev_chain, frame coordinates
-        for (uint32_t i = tid; i < len; i += kBlock) {
-            const uint32_t g = base + i;
+        // holds the position), region, place in dev_chain, frame coordinates;
+        // all loads of a kind issued together
+        uint32_t bb[kPerThreadSeg], aa[kPerThreadSeg];
+        const int kmax = (int)((len + kBlock - 1) / kBlock);  // rounds that hold points
+#pragma unroll
+        for (int k = 0; k < kPerThreadSeg; ++k) {
+            bb[k] = 0;
+            if (k >= kmax) continue;
+            const uint32_t i = k * kBlock + tid, g = base + min(i, len - 1);
             uint32_t lo = 0, hi = kBuckets - 1;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi + 1) / 2;
                 if (pre[mid] <= g) lo = mid;
                 else hi = mid - 1;
             }
-            const uint32_t q = lo >> kBucketBits;
-            const uint32_t a = bk.off[lo] + (g - pre[lo]);
-            const PolyRec r = dev_chain[a];
-            uint32_t k1, k2;
-            to_frame(q, (uint32_t)r.x, (uint32_t)r.y, k1, k2);
-            at[i] = a;
-            reg[i] = (uint8_t)q;
-            ka[i] = k1;
-            kb[i] = k2;
-            alive[i] = 1;
+            bb[k] = lo;
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThreadSeg; ++k) aa[k] = k < kmax ? bk.off[bb[k]] : 0u;
+        PolyRec rr[kPerThreadSeg];
+#pragma unroll
+        for (int k = 0; k < kPerThreadSeg; ++k) {
+            if (k >= kmax) continue;
+            const uint32_t i = k * kBlock + tid, g = base + min(i, len - 1);
+            aa[k] += g - pre[bb[k]];
+            rr[k] = dev_chain[aa[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThreadSeg; ++k) {
+            const uint32_t i = k * kBlock + tid;
+            if (k < kmax && i < len) {
+                const uint32_t q = bb[k] >> kBucketBits;
+                uint32_t k1, k2;
+                to_frame(q, (uint32_t)rr[k].x, (uint32_t)rr[k].y, k1, k2);
+                at[i] = aa[k];
+                reg[i] = (uint8_t)q;
+                ka[i] = k1;
+                kb[i] = k2;
+                alive[i] = 1;
+            }
         }
         if (tid < 4) s_cnt[tid] = 0;
         __syncthreads();
@@ -1201,21 +1288,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
             __syncthreads();
             return n_alive;
         };
+        // Pre-hull rounds: every alive point that makes no left turn with
+        // its alive neighbours of the same region goes at once; repeat
+        // until none does (at most kPrehullRounds times).
+        if (tid < 2) s_removed[tid] = 0;
         uint32_t n_alive = compact();
         for (int round = 0; prehull && round < kPrehullRounds; ++round) {
-            if (tid == 0) s_removed = 0;
-            __syncthreads();
+            if (tid == 0) s_removed[(round + 1) & 1] = 0;  // the flag of the next round
+            bool removed = false;
             for (uint32_t p = tid + 1; p + 1 < n_alive; p += kBlock) {
                 const uint32_t a = lst[p - 1], i = lst[p], c = lst[p + 1];
                 if (reg[a] == reg[i] && reg[c] == reg[i] &&
                     frame_turn(ka[a], kb[a], ka[i], kb[i], ka[c], kb[c]) <= 0) {
                     alive[i] = 0;
-                    s_removed = 1;
+                    removed = true;
                 }
             }
+            if (removed) s_removed[round & 1] = 1;
             __syncthreads();
-            if (!s_removed) break;
+            const bool any = s_removed[round & 1] != 0;
             n_alive = compact();
+            if (!any) break;
         }
         // the kept points, in order, at base + rank
         for (uint32_t p = tid; p < n_alive; p += kBlock) {
@@ -1230,6 +1323,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         if (tid < 4) segcnt[4 * sg + tid] = s_cnt[tid];
         __syncthreads();
     }
+    publish_header();
 }
 
 // The finished hull, from pinned host memory into the caller's buffers.  The
@@ -1271,7 +1365,8 @@ struct Workspace {
     u64* val[2] = {nullptr, nullptr};
     Buckets bk = {};
     PolyRec* dev_chain = nullptr;
-    DevHeader* h_hdr = nullptr;     // pinned
+    DevHeader* h_hdr = nullptr;     // pinned, device-visible: written by k_chain
+    DevHeader* h_hdr_dev = nullptr; // its device address
     PolyRec* h_chain = nullptr;     // pinned, device-visible
     PolyRec* h_chain_dev = nullptr; // its device address
     size_t h_chain_cap = 0;
@@ -1324,7 +1419,7 @@ size_t device_bytes(size_t cap)
     size_t b = 0;
     b += align_up(sizeof(DevHeader), 256);
     b += align_up(sizeof(ExtPartial) * kStreamGrid, 256);
-    b += 6 * align_up(sizeof(uint32_t) * kBuckets, 256);
+    b += 5 * align_up(sizeof(uint32_t) * kBuckets, 256) + align_up(sizeof(u64) * kBuckets, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
     b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
     b += 2 * align_up(sizeof(uint32_t) * kStreamGrid, 256);
@@ -1386,7 +1481,7 @@ int ensure_device(Workspace& w, size_t n)
     w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
     w.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.bk.kmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    w.bk.kmin = reinterpret_cast<u64*>(take(sizeof(u64) * kBuckets));
     w.bk.cur = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     w.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     w.bk.thr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
@@ -1407,7 +1502,10 @@ int ensure_device(Workspace& w, size_t n)
 
 int ensure_host(Workspace& w, size_t out)
 {
-    if (!w.h_hdr) CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_hdr), sizeof(DevHeader), hipHostMallocDefault));
+    if (!w.h_hdr) {
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_hdr), sizeof(DevHeader), hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_hdr_dev), w.h_hdr, 0));
+    }
     if (!w.h_chain) {
         CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_chain), sizeof(PolyRec) * kHostChainDefault,
                              hipHostMallocMapped));
@@ -1508,9 +1606,9 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
     CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1], w.val[1],
                                  w.hdr, w.bk, w.dev_chain));
     CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kChainGrid), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
-                                 w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill, w.h_segcnt_dev, stats ? 0 : 1));
+                                 w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill, w.h_segcnt_dev, w.h_hdr_dev,
+                                 stats ? 0 : 1));
     CH_TRY(record(w, 5));
-    CH_TRY(hipMemcpyAsync(w.h_hdr, w.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, s));
     CH_TRY(record(w, 6));
     CH_TRY(hipStreamSynchronize(s));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
