@@ -202,7 +202,7 @@ def main():
                    "n_points": n, "inputs_per_step": len(DISTS), "seeds": [s for _, s in DISTS]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "copy_out", "finish")
+        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish")
                       for v in [stage_ms[k]]},
         "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
         "preprocess_b_alg_frac": round(pre_frac, 4),

@@ -62,15 +62,17 @@ typedef struct {
     int64_t candidates;   /* records the dominance filters pass to the region sort */
     int64_t s2[4];        /* SPA survivors in R1..R4 (Figure 2) */
     int64_t polygon;      /* vertices of the polygon handed to the finish, the
-                             four extreme points included, before de-duplication */
+                             four extreme points included, before de-duplication
+                             (after the pre-hull in hull2d) */
     int64_t hull;         /* hull vertices */
     /* Milliseconds per stage when timing is on (chainhull_set_timing), from
      * HIP events on the call's stream: 0 sampled staircases, 1 the pass over
-     * the points (extreme-point keys, validation, staircase test), 2 extreme
-     * points reduced, quadrilateral discard + region distribution + second
-     * dominance filter (and, in chainhull_polygon, the round-1 counts),
-     * 3 region sort, 4 SPA + chain concatenation, 5 copy of the counts to
-     * the host, 7 host finish (wall clock); 6 is unused. */
+     * the points (validation, staircase test), 2 extreme points reduced,
+     * quadrilateral discard + region distribution + chunk dominance filter
+     * (and, in chainhull_polygon, the round-1 counts), 3 region sort, first
+     * level (records placed by bucket), 4 region sort, second level + SPA +
+     * chain concatenation (+ pre-hull in hull2d), 7 host finish (wall clock);
+     * 5 and 6 are unused. */
     float ms[8];
 } ch_stats;
 

@@ -24,7 +24,7 @@ EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_ho
            "chainhull_last_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_workspace_bytes")
 
-STAGES = ("sample", "stream", "cand", "sort", "spa", "copy_out", "unused6", "finish")
+STAGES = ("sample", "stream", "cand", "sort", "spa", "unused5", "unused6", "finish")
 
 
 class ChainHullError(RuntimeError):

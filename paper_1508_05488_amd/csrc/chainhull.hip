@@ -4,31 +4,34 @@
 // Kernels of one hull (all on the caller's stream):
 //   k_sample        a strided sample of the points: per-frame slot minima
 //   k_stair         the sampled staircases (prefix minima); clears counters
-//   k_stream        the one full pass over the points: step 1's extreme
-//                   keys and the domain check, and the sampled-staircase
-//                   dominance test; lists the points that pass it
-//   k_cand          reduces the extreme points (quadrilateral), step 2's
-//                   exact region test on the listed points, a second
-//                   dominance filter; writes the sort records
-//   k_sort_prep     digit counts of the region sort; clears the look-back
-//   k_sort_pass x3  steps 3-4: stable LSD radix passes over (region, k1)
-//   k_spa_chain     steps 5-6: SPA as a segmented prefix minimum, ordered
-//                   compaction of the chains straight into host memory
-// then one device-to-host copy of the header, Melkman on the host (step 7),
-// and the result copied into the caller's device buffers.
+//   k_stream        the one full pass over the points: the domain check and
+//                   the sampled-staircase dominance test; lists the points
+//                   that pass it (the extreme points are among them)
+//   k_cand          step 1's reduction (the quadrilateral), step 2's exact
+//                   region test on the listed points, a chunk staircase;
+//                   writes the records and counts them per sort bucket
+//   k_bucket        steps 3-4, level 1: records placed by bucket (region,
+//                   top k1 bits), after a bucket-staircase filter
+//   k_bucket_spa    steps 3-5, level 2: each bucket ordered by its low k1
+//                   bits and filtered by SPA
+//   k_chain         step 6: the chains concatenated, shortened by a
+//                   pre-hull, written to pinned host memory with the header
+// then Melkman on the host (step 7), and the result copied into the
+// caller's device buffers by k_put_result.
 //
 // Data layout in HBM (one workspace per device and stream):
 //   points           caller's n x float32[2], read once in full (k_stream)
 //   samp, stair      sampled slot minima, staircases (4 x 1024 u32 each)
 //   ExtPartial[G]    per-workgroup extreme keys
-//   open lists       the points k_stream lists (index; x, y, frame mask),
-//                    held in the second sort buffers
+//   open lists       per k_stream workgroup: index; x | y << 23 | mask << 46
 //   DevHeader        extreme points, quadrilateral edges, frames, counters
-//   ghist[1024]      digit counts of the three sort passes (256, 256, 512)
-//   key[2][cap]      u32 sort key  q << 23 | k1      (double buffer)
-//   val[2][cap]      u64 payload   k2 << 32 | index  (double buffer)
-//   look[...]        u64 look-back words of the sort passes and of SPA
-//   chain[cap]       SPA survivors that do not fit the pinned host buffer
+//   key[2], val[2]   records: u32 q << 23 | k1, u64 k2 << 32 | index; [0]
+//                    holds k_cand's per-workgroup regions, [1] the records
+//                    in bucket order
+//   bucket arrays    counts, minima, cursors, offsets, thresholds, survivors
+//                    (8192 buckets each)
+//   chain, spill     SPA survivors (index, x, y) at their bucket's place;
+//                    kept chain points beyond the pinned host buffer
 //
 // Regions follow the paper (R1 lower left, R2 lower right, R3 upper right,
 // R4 upper left); q = r - 1 is the region code in the sort key, so ascending
