@@ -214,3 +214,21 @@ def test_long_groups_across_tiles(seed):
     pts = pts[rng.permutation(pts.shape[0])]
     assert_parity(pts, f"long groups seed={seed}")
     stage_parity(pts, f"long groups seed={seed}")
+
+
+@pytest.mark.parametrize("m", [10, 63, 64, 65, 300, 4096])
+def test_bucket_paths(m):
+    """m hull vertices of region R1 in one sort bucket (k1 = x in [0, 4096)):
+    a bucket of at most 64 records goes to one wave, a larger one to the
+    LDS table; a chain longer than a pre-hull segment spans several."""
+    rng = wl.rng_for(90 + m)
+    i = np.arange(m, dtype=np.int64)
+    x = (i * 4095) // max(m - 1, 1)
+    y = 3_000_000 + ((m - i) ** 2 * 2_000_000) // (m * m)   # convex, decreasing
+    arc = np.stack([x, y], 1)
+    box = np.array([[0, 6_000_000], [4_000_000, 0], [8_000_000, 4_000_000], [5_000_000, 8_000_000]])
+    inner = rng.integers(2_000_000, 6_000_000, size=(20_000, 2))
+    pts = np.concatenate([arc, box, inner]).astype(np.float32)
+    pts = pts[rng.permutation(pts.shape[0])]
+    assert_parity(pts, f"bucket m={m}")
+    stage_parity(pts, f"bucket m={m}")
