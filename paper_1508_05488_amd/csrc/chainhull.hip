@@ -463,6 +463,25 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     __shared__ uint32_t s_fill;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     const u64 lt = (1ull << lane) - 1ull;
+
+    // Workgroup b streams float4s [b*per, (b+1)*per) of the aligned part, a
+    // round of kBlock*kStreamUnroll at a time.  Every lane runs the same
+    // number of rounds (the list append is wave-wide); lanes past the range
+    // reread the last float4, which changes nothing and lists nothing.  The
+    // first round's loads are issued before the staircase is staged.
+    const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
+    const uint32_t n4 = (n - head) / 2;
+    constexpr uint32_t kRound = kBlock * kStreamUnroll;
+    const uint32_t lo = min(n4, blockIdx.x * per), hi = min(n4, lo + per);
+    const uint32_t rounds = (hi - lo + kRound - 1) / kRound;
+    auto load_round = [&](uint32_t r, v4f* v) {
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
+    };
+    v4f va[kStreamUnroll];
+    if (rounds) load_round(0, va);
+
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
     if (tid == 0) s_fill = 0;
     __syncthreads();
@@ -521,21 +540,6 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     };
 
     if (blockIdx.x == 0 && wave == 0 && head) visit_one(pts[0], pts[1], 0, lane == 0);
-    // Workgroup b streams float4s [b*per, (b+1)*per) of the aligned part, a
-    // round of kBlock*kStreamUnroll at a time, the next round's loads in
-    // flight while this round is tested.  Every lane runs the same number of
-    // rounds (the list append is wave-wide); lanes past the range reread the
-    // last float4, which changes nothing and lists nothing.
-    const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
-    const uint32_t n4 = (n - head) / 2;
-    constexpr uint32_t kRound = kBlock * kStreamUnroll;
-    const uint32_t lo = min(n4, blockIdx.x * per), hi = min(n4, lo + per);
-    const uint32_t rounds = (hi - lo + kRound - 1) / kRound;
-    auto load_round = [&](uint32_t r, v4f* v) {
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u)
-            v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
-    };
     auto test_round = [&](uint32_t r, const v4f* v) {
         constexpr int kP = 2 * kStreamUnroll;
         float fxy[2 * kP];
@@ -567,14 +571,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
 #pragma unroll
         for (int p = 0; p < kP; ++p) list_point(X[p], Y[p], idx[p], valid[p], sxv[p], syv[p]);
     };
-    v4f va[kStreamUnroll], vb[kStreamUnroll];
-    if (rounds) load_round(0, va);
-    for (uint32_t r = 0; r < rounds; r += 2) {
-        if (r + 1 < rounds) load_round(r + 1, vb);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        if (r) load_round(r, va);
         test_round(r, va);
-        if (r + 1 >= rounds) break;
-        if (r + 2 < rounds) load_round(r + 2, va);
-        test_round(r + 1, vb);
     }
     if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u))
         visit_one(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
