@@ -170,7 +170,9 @@ __device__ inline uint32_t wave_incl_min(uint32_t v)
     return v;
 }
 
-// Exclusive workgroup sum of one value per thread; `total` gets the sum.
+// Exclusive workgroup sum of one value per thread (W waves); `total` gets
+// the sum.
+template <int W = kWaves>
 __device__ inline uint32_t block_excl_sum(uint32_t v, uint32_t* scratch, uint32_t& total)
 {
     const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
@@ -179,7 +181,7 @@ __device__ inline uint32_t block_excl_sum(uint32_t v, uint32_t* scratch, uint32_
     __syncthreads();
     uint32_t before = 0, all = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < W; ++w) {
         const uint32_t s = scratch[w];
         before += (w < (int)wave) ? s : 0u;
         all += s;
@@ -189,7 +191,9 @@ __device__ inline uint32_t block_excl_sum(uint32_t v, uint32_t* scratch, uint32_
     return before + incl - v;
 }
 
-// Exclusive workgroup minimum (identity ~0u); `total` gets the minimum.
+// Exclusive workgroup minimum (identity ~0u, W waves); `total` gets the
+// minimum.
+template <int W = kWaves>
 __device__ inline uint32_t block_excl_min(uint32_t v, uint32_t* scratch, uint32_t& total)
 {
     const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
@@ -200,7 +204,7 @@ __device__ inline uint32_t block_excl_min(uint32_t v, uint32_t* scratch, uint32_
     __syncthreads();
     uint32_t before = ~0u, all = ~0u;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < W; ++w) {
         const uint32_t s = scratch[w];
         if (w < (int)wave) before = min(before, s);
         all = min(all, s);
@@ -1328,6 +1332,495 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
     publish_header();
 }
 
+// ---------------------------------------------------------------------------
+// Batched hulls: the method on many independent point sets in one launch,
+// one workgroup of kBatchBlock threads per set (larger sets first), every
+// step inside the workgroup, the finish included:
+//   pass A   the domain check, the lexicographic extreme keys (ties to the
+//            smaller index), and a staircase of every kBatchSampleEvery-th
+//            point per frame (slot minima with their points, as k_sample);
+//   pass B   the exact region test; per region and slot the smallest
+//            (k2, k1) of all region points; points that the sampled
+//            staircase does not dominate in their region's frame are listed
+//            in LDS;
+//   filter   a listed record goes when the region's first point or a record
+//            of an earlier slot has k2 <= its k2, or when its slot's
+//            smallest point precedes it with k1 <= its k1 (the dominance
+//            argument of Figure 3 with the exact slot minima);
+//   sort     bitonic, in LDS, by (region, k1, k2, list position);
+//   SPA      a tagged exclusive prefix minimum (as Figure 2's running
+//            threshold), the run of exact duplicates reporting its
+//            smallest index;
+//   polygon  [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] in LDS,
+//            shortened by pre-hull rounds (reflex-vertex removal inside a
+//            region), then Melkman by one thread (Section 2.1.3).
+// A set whose listed records or chain exceed the LDS capacities gets
+// kBatchRedo in out_counts and is run by the single-hull path afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kBatchBlock = 1024;
+constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kBatchCand = 8192;                  // listed records per set
+constexpr int kBatchPolyMax = 4096;               // polygon vertices kept in LDS
+constexpr int kBatchSampleEvery = 8;
+constexpr int kBatchRounds = 16;
+constexpr int32_t kBatchRedo = INT32_MIN;
+// LDS: [cidx u32 x kBatchCand][crec/keys u64 x kBatchCand][smin u64 x 4*kSlots]
+//      [stair: excl u32 x 4*kSlots, min point u64 x 4*kSlots]
+constexpr size_t kBatchLds = 4 * kBatchCand + 8 * kBatchCand + 8 * 4 * kSlots + 12 * 4 * kSlots;
+
+struct BatchPoly {  // phase-4 view of the LDS
+    int32_t* x;
+    int32_t* y;
+    int32_t* idx;
+    uint32_t* ka;
+    uint32_t* kb;
+    uint8_t* reg;
+    uint8_t* alive;
+    uint16_t* lst;
+    uint16_t* dq;
+};
+
+// Melkman on the polygon lst[0..n) of vertices (x, y, idx) by one thread,
+// with the conventions of the host finish (consecutive duplicates dropped,
+// collinear prefix, newest vertex dropped when collinear).  Writes the hull,
+// rotated to the lowest-then-leftmost vertex, to out; returns its size, or
+// -1 when the deque would leave its room (not a simple polygon).
+__device__ inline i64 turn_xy(const BatchPoly& P, uint32_t a, uint32_t b, uint32_t c)
+{
+    return (i64)(P.x[b] - P.x[a]) * (i64)(P.y[c] - P.y[a]) - (i64)(P.y[b] - P.y[a]) * (i64)(P.x[c] - P.x[a]);
+}
+
+__device__ int batch_melkman(const BatchPoly& P, uint32_t n0, int32_t* __restrict__ out)
+{
+    // consecutive duplicates, cyclically
+    uint16_t* const p = P.lst;  // compacted in place
+    uint32_t np = 0;
+    for (uint32_t i = 0; i < n0; ++i) {
+        const uint32_t v = p[i];
+        if (np && P.x[p[np - 1]] == P.x[v] && P.y[p[np - 1]] == P.y[v]) continue;
+        p[np++] = (uint16_t)v;
+    }
+    while (np > 1 && P.x[p[np - 1]] == P.x[p[0]] && P.y[p[np - 1]] == P.y[p[0]]) --np;
+    uint16_t* const d = P.dq;
+    uint32_t h = 0;
+    if (np <= 2) {
+        for (uint32_t i = 0; i < np; ++i) d[i] = p[i];
+        h = np;
+    } else {
+        uint32_t k = 2;
+        while (k < np && turn_xy(P, p[0], p[1], p[k]) == 0) ++k;
+        const i64 dx = P.x[p[1]] - P.x[p[0]], dy = P.y[p[1]] - P.y[p[0]];
+        uint32_t lo = 0, hi = 0;
+        i64 tlo = 0, thi = 0;
+        for (uint32_t i = 0; i < k; ++i) {
+            const i64 t = dx * (P.x[p[i]] - P.x[p[0]]) + dy * (P.y[p[i]] - P.y[p[0]]);
+            if (t < tlo) { tlo = t; lo = i; }
+            if (t > thi) { thi = t; hi = i; }
+        }
+        if (k == np) {
+            d[0] = p[lo];
+            d[1] = p[hi];
+            h = 2;
+        } else {
+            const int cap = 2 * (int)np + 8;
+            int bot = (int)np + 2, top = bot + 3;
+            d[bot] = p[k];
+            d[top] = p[k];
+            if (turn_xy(P, p[lo], p[hi], p[k]) > 0) {
+                d[bot + 1] = p[lo];
+                d[bot + 2] = p[hi];
+            } else {
+                d[bot + 1] = p[hi];
+                d[bot + 2] = p[lo];
+            }
+            for (uint32_t i = k + 1; i < np; ++i) {
+                const uint32_t v = p[i];
+                if (turn_xy(P, d[bot], d[bot + 1], v) > 0 && turn_xy(P, d[top - 1], d[top], v) > 0) continue;
+                while (turn_xy(P, d[bot], d[bot + 1], v) <= 0) {
+                    if (top - bot < 2) return -1;
+                    ++bot;
+                }
+                if (bot < 1) return -1;
+                d[--bot] = (uint16_t)v;
+                while (turn_xy(P, d[top - 1], d[top], v) <= 0) {
+                    if (top - bot < 2) return -1;
+                    --top;
+                }
+                if (top + 1 >= cap) return -1;
+                d[++top] = (uint16_t)v;
+            }
+            int first = bot;
+            if (turn_xy(P, d[top - 1], d[bot], d[bot + 1]) <= 0) first = bot + 1;
+            h = 0;
+            for (int i = first; i < top; ++i) d[h++] = d[i];
+        }
+    }
+    uint32_t start = 0;
+    for (uint32_t i = 1; i < h; ++i) {
+        const uint32_t a = d[i], b = d[start];
+        if (P.y[a] < P.y[b] || (P.y[a] == P.y[b] && P.x[a] < P.x[b])) start = i;
+    }
+    for (uint32_t i = 0; i < h; ++i) out[i] = P.idx[d[(start + i) % h]];
+    return (int)h;
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restrict__ pts,
+                                                            const int64_t* __restrict__ offsets,
+                                                            const int32_t* __restrict__ order,
+                                                            int32_t* __restrict__ out_idx,
+                                                            int32_t* __restrict__ out_counts)
+{
+    __shared__ __align__(16) unsigned char smem[kBatchLds];
+    __shared__ ExtAcc sh[kBatchWaves];
+    __shared__ uint32_t scratch[kBatchWaves];
+    __shared__ Quad sq;
+    __shared__ uint32_t s_n, s_flag, s_rcnt[4];
+    __shared__ int s_h;
+    uint32_t* const cidx = reinterpret_cast<uint32_t*>(smem);
+    u64* const crec = reinterpret_cast<u64*>(smem + 4 * kBatchCand);
+    u64* const smin = reinterpret_cast<u64*>(smem + 12 * kBatchCand);
+    uint32_t* const sexc = reinterpret_cast<uint32_t*>(smem + 12 * kBatchCand + 8 * 4 * kSlots);
+    u64* const spt = reinterpret_cast<u64*>(smem + 12 * kBatchCand + 12 * 4 * kSlots);
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
+    const u64 lt = (1ull << lane) - 1ull;
+    const int32_t set = order[blockIdx.x];
+    const int64_t base = offsets[set];
+    const uint32_t m = (uint32_t)(offsets[set + 1] - base);
+    const v2f* const p2 = reinterpret_cast<const v2f*>(pts) + base;
+    if (m == 0) {
+        if (tid == 0) out_counts[set] = 0;
+        return;
+    }
+
+    // ---- pass A: domain, extreme keys, sampled staircase (slot minima) ----
+    for (int e = tid; e < 4 * kSlots; e += kBatchBlock) spt[e] = ~0ull;
+    __syncthreads();
+    ExtAcc a;
+    ext_init(a);
+    for (uint32_t i0 = 0; i0 < m; i0 += 4 * kBatchBlock) {
+        v2f v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = p2[min(i0 + u * kBatchBlock + tid, m - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + u * kBatchBlock + tid;
+            if (i >= m) continue;
+            const uint32_t X = cvt_u32_sat(v[u].x), Y = cvt_u32_sat(v[u].y);
+            ext_check(a, v[u].x, v[u].y, X, Y);
+            ext_take(a, X & kM, Y & kM, i);
+            if (i % kBatchSampleEvery == 0) {
+                const uint32_t x = X & kM, y = Y & kM, xm = x ^ kM, ym = y ^ kM;
+                atomicMin(&spt[0 * kSlots + (x >> (23 - kSlotBits))], ((u64)y << 23) | x);    // R1
+                atomicMin(&spt[1 * kSlots + (y >> (23 - kSlotBits))], ((u64)xm << 23) | y);   // R2
+                atomicMin(&spt[2 * kSlots + (xm >> (23 - kSlotBits))], ((u64)ym << 23) | xm); // R3
+                atomicMin(&spt[3 * kSlots + (ym >> (23 - kSlotBits))], ((u64)x << 23) | ym);  // R4
+            }
+        }
+    }
+    ext_wave_reduce(a);
+    if (lane == 0) sh[wave] = a;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kBatchWaves; ++w) ext_combine(a, sh[w]);
+        a.bad = a.bad || a.hi > kM;
+        make_quad(a, sq);
+        s_n = 0;
+        s_flag = 0;
+        for (int q = 0; q < 4; ++q) s_rcnt[q] = 0;
+    }
+    __syncthreads();
+    if (sq.err) {
+        if (tid == 0) out_counts[set] = CH_EDOMAIN;
+        return;
+    }
+    // sampled staircase: exclusive prefix minimum of k2 over the slots of each
+    // frame (wave f*4 .. f*4+3 owns frame f, two slots per thread)
+    {
+        const uint32_t f = tid / (kSlots / 2), j0 = (tid % (kSlots / 2)) * 2;
+        const u64 m0 = spt[f * kSlots + j0], m1 = spt[f * kSlots + j0 + 1];
+        const uint32_t v0 = m0 == ~0ull ? ~0u : (uint32_t)(m0 >> 23);
+        const uint32_t v1 = m1 == ~0ull ? ~0u : (uint32_t)(m1 >> 23);
+        const uint32_t incl = wave_incl_min(min(v0, v1));
+        uint32_t excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = ~0u;
+        if (lane == 63) scratch[wave] = incl;
+        __syncthreads();
+        for (uint32_t w = f * 4; w < wave; ++w) excl = min(excl, scratch[w]);
+        sexc[f * kSlots + j0] = excl;
+        sexc[f * kSlots + j0 + 1] = min(excl, v0);
+        for (int e = tid; e < 4 * kSlots; e += kBatchBlock) smin[e] = ~0ull;
+        __syncthreads();
+    }
+
+    // ---- pass B: region test, exact slot minima, list the open points ----
+    const Quad Q = sq;
+    for (uint32_t i0 = 0; i0 < m; i0 += 4 * kBatchBlock) {
+        v2f v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = p2[min(i0 + u * kBatchBlock + tid, m - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + u * kBatchBlock + tid;
+            bool open = false;
+            u64 rec = 0;
+            if (i < m) {
+                const uint32_t X = (uint32_t)v[u].x, Y = (uint32_t)v[u].y;
+                const uint32_t q = region_of(Q, X, Y);
+                if (q < 4) {
+                    uint32_t k1, k2;
+                    to_frame(q, X, Y, k1, k2);
+                    const uint32_t sl = q * kSlots + (k1 >> (23 - kSlotBits));
+                    const u64 me = ((u64)k2 << 23) | k1;
+                    atomicMin(&smin[sl], me);
+                    const u64 sp = spt[sl];
+                    open = k2 < sexc[sl] && !(sp < me && (uint32_t)(sp & kM) <= k1);
+                    rec = ((u64)q << 46) | ((u64)k1 << 23) | k2;
+                }
+            }
+            const u64 bal = __ballot(open);
+            if (bal) {
+                uint32_t first = 0;
+                const int lead = __ffsll((long long)bal) - 1;
+                if (lane == (uint32_t)lead) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
+                first = __shfl(first, lead);
+                if (open) {
+                    const uint32_t pos = first + (uint32_t)__popcll(bal & lt);
+                    if (pos < (uint32_t)kBatchCand) {
+                        cidx[pos] = i;
+                        crec[pos] = rec;
+                    } else {
+                        s_flag = 1;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (s_flag) {
+        if (tid == 0) out_counts[set] = kBatchRedo;
+        return;
+    }
+    const uint32_t ncand = s_n;
+
+    // ---- filter with the exact slot minima ----
+    {
+        // exclusive prefix minimum per region over its slots, seeded with the
+        // region's first point (wave q*4 .. q*4+3 owns region q)
+        const uint32_t q = tid / (kSlots / 2), j0 = (tid % (kSlots / 2)) * 2;
+        const u64 m0 = smin[q * kSlots + j0], m1 = smin[q * kSlots + j0 + 1];
+        const uint32_t v0 = m0 == ~0ull ? ~0u : (uint32_t)(m0 >> 23);
+        const uint32_t v1 = m1 == ~0ull ? ~0u : (uint32_t)(m1 >> 23);
+        const uint32_t incl = wave_incl_min(min(v0, v1));
+        uint32_t excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = ~0u;
+        if (lane == 63) scratch[wave] = incl;
+        __syncthreads();
+        for (uint32_t w = q * 4; w < wave; ++w) excl = min(excl, scratch[w]);
+        excl = min(excl, Q.sigma[q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : 3]);
+        sexc[q * kSlots + j0] = excl;
+        sexc[q * kSlots + j0 + 1] = min(excl, v0);
+        __syncthreads();
+    }
+    // survivors become sort keys: record << 13 | list position (in place)
+    constexpr int kPerCand = kBatchCand / kBatchBlock;  // 8
+    u64 keys[kPerCand];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int k = 0; k < kPerCand; ++k) {
+        const uint32_t r = tid * kPerCand + k;
+        keys[k] = ~0ull;
+        if (r < ncand) {
+            const u64 rec = crec[r];
+            const uint32_t q = (uint32_t)(rec >> 46), k1 = (uint32_t)(rec >> 23) & kM, k2 = (uint32_t)rec & kM;
+            const uint32_t sl = q * kSlots + (k1 >> (23 - kSlotBits));
+            const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
+            if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) {
+                keep |= 1u << k;
+                keys[k] = (rec << 13) | r;
+            }
+        }
+    }
+    uint32_t nsort;
+    uint32_t at = block_excl_sum<kBatchWaves>(__popc(keep), scratch, nsort);
+    u64* const skey = crec;
+#pragma unroll
+    for (int k = 0; k < kPerCand; ++k) {
+        if ((keep >> k) & 1u) skey[at++] = keys[k];
+    }
+    uint32_t P2 = 1;
+    while (P2 < nsort) P2 <<= 1;
+    for (uint32_t e = nsort + tid; e < P2; e += kBatchBlock) skey[e] = ~0ull;
+    __syncthreads();
+
+    // ---- sort (bitonic, ascending) ----
+    for (uint32_t size = 2; size <= P2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = tid; t < P2 / 2; t += kBatchBlock) {
+                const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+                const bool up = (i & size) == 0;
+                const u64 x = skey[i], y = skey[j];
+                if ((x > y) == up) {
+                    skey[i] = y;
+                    skey[j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- SPA over the sorted records; chain positions ----
+    // thread t holds sorted records [t*per, t*per + per)
+    const uint32_t per = (P2 + kBatchBlock - 1) / kBatchBlock;
+    uint32_t run = ~0u;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t r = tid * per + k;
+        if (r < nsort) {
+            const u64 key = skey[r] >> 13;
+            run = min(run, ((3u - (uint32_t)(key >> 46)) << 23) | (uint32_t)(key & kM));
+        }
+    }
+    uint32_t unused;
+    uint32_t pm = block_excl_min<kBatchWaves>(run, scratch, unused);
+    // keep flags in a bit mask (per <= 8 since nsort <= kBatchCand)
+    uint32_t kmask = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+        const uint32_t r = tid * per + k;
+        if (r >= nsort) break;
+        const u64 key = skey[r] >> 13;
+        const uint32_t q = (uint32_t)(key >> 46), k2 = (uint32_t)(key & kM);
+        uint32_t thr = Q.sigma[q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : 3];
+        if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
+        if (k2 < thr) kmask |= 1u << k;
+        pm = min(pm, ((3u - q) << 23) | k2);
+    }
+    uint32_t nchain;
+    uint32_t rank = block_excl_sum<kBatchWaves>(__popc(kmask), scratch, nchain);
+    if (nchain + 4 > (uint32_t)kBatchPolyMax) {
+        if (tid == 0) out_counts[set] = kBatchRedo;
+        return;
+    }
+    // the kept records: region counts, then polygon positions
+    uint32_t kq[8], kk1[8], kk2[8], kid[8];
+    int nk = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+        if (!((kmask >> k) & 1u)) continue;
+        const uint32_t r = tid * per + k;
+        const u64 key = skey[r];
+        const u64 rec = key >> 13;
+        // the run of exact duplicates reports its smallest index
+        uint32_t idx = cidx[(uint32_t)(key & 8191u)];
+        for (uint32_t j = r + 1; j < nsort && (skey[j] >> 13) == rec; ++j) idx = min(idx, cidx[(uint32_t)(skey[j] & 8191u)]);
+        kq[nk] = (uint32_t)(rec >> 46);
+        kk1[nk] = (uint32_t)(rec >> 23) & kM;
+        kk2[nk] = (uint32_t)rec & kM;
+        kid[nk] = idx;
+        atomicAdd(&s_rcnt[kq[nk]], 1u);
+        ++nk;
+    }
+    __syncthreads();
+    // phase-4 view of the LDS (everything above is dead now except kept data
+    // in registers)
+    BatchPoly Pl;
+    {
+        unsigned char* b = smem;
+        Pl.x = reinterpret_cast<int32_t*>(b);
+        b += 4 * kBatchPolyMax;
+        Pl.y = reinterpret_cast<int32_t*>(b);
+        b += 4 * kBatchPolyMax;
+        Pl.idx = reinterpret_cast<int32_t*>(b);
+        b += 4 * kBatchPolyMax;
+        Pl.ka = reinterpret_cast<uint32_t*>(b);
+        b += 4 * kBatchPolyMax;
+        Pl.kb = reinterpret_cast<uint32_t*>(b);
+        b += 4 * kBatchPolyMax;
+        Pl.lst = reinterpret_cast<uint16_t*>(b);
+        b += 2 * kBatchPolyMax;
+        Pl.dq = reinterpret_cast<uint16_t*>(b);
+        b += 2 * (2 * kBatchPolyMax + 8);
+        Pl.reg = b;
+        b += kBatchPolyMax;
+        Pl.alive = b;
+    }
+    __syncthreads();
+    const uint32_t npoly = nchain + 4;
+    uint32_t rbase[4];
+    {
+        uint32_t acc = 0;
+        for (int q = 0; q < 4; ++q) {
+            rbase[q] = acc;  // position of E_q
+            acc += 1 + s_rcnt[q];
+        }
+    }
+    if (tid < 4) {
+        const uint32_t q = tid, o = rbase[q];
+        Pl.x[o] = (int32_t)sq.X[q];
+        Pl.y[o] = (int32_t)sq.Y[q];
+        Pl.idx[o] = (int32_t)sq.idx[q];
+        Pl.reg[o] = 4;  // an extreme point: never removed
+        Pl.alive[o] = 1;
+    }
+    {
+        // kept records in sorted (chain) order: rank over all regions, so
+        // the position is rank + 1 + (regions before) extra for extremes
+        uint32_t rr = rank;
+        for (int t = 0; t < nk; ++t, ++rr) {
+            const uint32_t q = kq[t];
+            const uint32_t o = rr + q + 1;  // the extremes E_0..E_q precede it
+            const uint32_t a2 = (q & 1u) ? kk2[t] : kk1[t];
+            const uint32_t b2 = (q & 1u) ? kk1[t] : kk2[t];
+            Pl.x[o] = (int32_t)(((q ^ (q >> 1)) & 1u) ? a2 ^ kM : a2);
+            Pl.y[o] = (int32_t)((q & 2u) ? b2 ^ kM : b2);
+            Pl.idx[o] = (int32_t)kid[t];
+            Pl.ka[o] = kk1[t];
+            Pl.kb[o] = kk2[t];
+            Pl.reg[o] = (uint8_t)q;
+            Pl.alive[o] = 1;
+        }
+    }
+    __syncthreads();
+
+    // ---- pre-hull rounds, then Melkman ----
+    auto compact = [&]() -> uint32_t {
+        constexpr int kPer = kBatchPolyMax / kBatchBlock;  // 4
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = tid * kPer + k;
+            mine += (i < npoly && Pl.alive[i]) ? 1u : 0u;
+        }
+        uint32_t n_alive;
+        uint32_t o = block_excl_sum<kBatchWaves>(mine, scratch, n_alive);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = tid * kPer + k;
+            if (i < npoly && Pl.alive[i]) Pl.lst[o++] = (uint16_t)i;
+        }
+        __syncthreads();
+        return n_alive;
+    };
+    uint32_t n_alive = compact();
+    for (int round = 0; round < kBatchRounds; ++round) {
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+        for (uint32_t p = tid + 1; p + 1 < n_alive; p += kBatchBlock) {
+            const uint32_t u = Pl.lst[p - 1], i = Pl.lst[p], c = Pl.lst[p + 1];
+            if (Pl.reg[i] < 4 && Pl.reg[u] == Pl.reg[i] && Pl.reg[c] == Pl.reg[i] &&
+                frame_turn(Pl.ka[u], Pl.kb[u], Pl.ka[i], Pl.kb[i], Pl.ka[c], Pl.kb[c]) <= 0) {
+                Pl.alive[i] = 0;
+                s_flag = 1;
+            }
+        }
+        __syncthreads();
+        const bool any = s_flag != 0;
+        n_alive = compact();
+        if (!any) break;
+    }
+    if (tid == 0) {
+        const int h = batch_melkman(Pl, n_alive, out_idx + base);
+        out_counts[set] = h < 0 ? kBatchRedo : h;
+    }
+}
+
 // The finished hull, from pinned host memory into the caller's buffers.  The
 // host rewrites that memory between calls, so it is read with system-scope
 // loads, which no stale cache line can serve.
@@ -1382,6 +1875,13 @@ struct Workspace {
     uint32_t* h_segcnt_dev = nullptr;
     size_t h_segcnt_cap = 0;        // segments
     int64_t s2[4] = {}, w2[4] = {}, chain = 0;  // counts of the last call
+    // batched calls: set offsets and launch order (device), staging (pinned)
+    int64_t* b_offsets = nullptr;
+    int32_t* b_order = nullptr;
+    size_t b_cap = 0;  // sets
+    int64_t* h_b_offsets = nullptr;
+    int32_t* h_b_order = nullptr;
+    int32_t* h_b_counts = nullptr;
     hipEvent_t ev[8] = {};
     bool events = false;
 };
@@ -1560,6 +2060,11 @@ void free_workspace(Workspace* w)
     if (w->h_chain) (void)hipHostFree(w->h_chain);
     if (w->h_out) (void)hipHostFree(w->h_out);
     if (w->h_segcnt) (void)hipHostFree(w->h_segcnt);
+    if (w->b_offsets) (void)hipFree(w->b_offsets);
+    if (w->b_order) (void)hipFree(w->b_order);
+    if (w->h_b_offsets) (void)hipHostFree(w->h_b_offsets);
+    if (w->h_b_order) (void)hipHostFree(w->h_b_order);
+    if (w->h_b_counts) (void)hipHostFree(w->h_b_counts);
     if (w->events) {
         for (auto& e : w->ev) (void)hipEventDestroy(e);
     }
@@ -1775,14 +2280,66 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
     }
     if (offsets[num_sets] > 0 && (!points || !out_idx)) return CH_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int rc = CH_OK;
+    Workspace* w = workspace_for(st, &rc);
+    if (!w) return rc;
+    std::vector<int32_t> redo;
+    {
+        std::lock_guard<std::mutex> lk(w->mu);
+        const size_t ns = (size_t)num_sets;
+        if (w->b_cap < ns) {
+            CH_TRY(hipStreamSynchronize(st));
+            if (w->b_offsets) CH_TRY(hipFree(w->b_offsets));
+            if (w->b_order) CH_TRY(hipFree(w->b_order));
+            if (w->h_b_offsets) CH_TRY(hipHostFree(w->h_b_offsets));
+            if (w->h_b_order) CH_TRY(hipHostFree(w->h_b_order));
+            if (w->h_b_counts) CH_TRY(hipHostFree(w->h_b_counts));
+            w->b_offsets = nullptr;
+            w->b_order = nullptr;
+            w->h_b_offsets = nullptr;
+            w->h_b_order = nullptr;
+            w->h_b_counts = nullptr;
+            w->b_cap = 0;
+            const size_t cap = std::max<size_t>(ns, 1024);
+            CH_TRY(hipMalloc(reinterpret_cast<void**>(&w->b_offsets), sizeof(int64_t) * (cap + 1)));
+            CH_TRY(hipMalloc(reinterpret_cast<void**>(&w->b_order), sizeof(int32_t) * cap));
+            CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w->h_b_offsets), sizeof(int64_t) * (cap + 1),
+                                 hipHostMallocDefault));
+            CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w->h_b_order), sizeof(int32_t) * cap, hipHostMallocDefault));
+            CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w->h_b_counts), sizeof(int32_t) * cap,
+                                 hipHostMallocDefault));
+            w->b_cap = cap;
+        }
+        // the staging buffers may still feed an earlier call's copies
+        CH_TRY(hipStreamSynchronize(st));
+        std::memcpy(w->h_b_offsets, offsets, sizeof(int64_t) * (ns + 1));
+        // larger sets first, so that the last workgroups to start are short
+        for (int32_t s = 0; s < num_sets; ++s) w->h_b_order[s] = s;
+        std::stable_sort(w->h_b_order, w->h_b_order + ns, [&](int32_t a, int32_t b) {
+            return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+        });
+        CH_TRY(hipMemcpyAsync(w->b_offsets, w->h_b_offsets, sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+        CH_TRY(hipMemcpyAsync(w->b_order, w->h_b_order, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+        CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3(num_sets), dim3(kBatchBlock), 0, st, points, w->b_offsets,
+                                     w->b_order, out_idx, out_counts));
+        CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        CH_TRY(hipStreamSynchronize(st));
+        for (int32_t s = 0; s < num_sets; ++s)
+            if (w->h_b_counts[s] == kBatchRedo) redo.push_back(s);
+    }
     int first_err = CH_OK;
     for (int32_t s = 0; s < num_sets; ++s) {
+        const int32_t c = w->h_b_counts[s];
+        if (c < 0 && c != kBatchRedo && first_err == CH_OK) first_err = c;
+    }
+    // sets beyond the workgroup's capacities: the single-hull path
+    for (const int32_t s : redo) {
         const int64_t lo = offsets[s], m = offsets[s + 1] - lo;
-        const int rc = hull_one(points + 2 * lo, m, out_idx + lo, out_counts + s, st);
-        if (rc != CH_OK) {
-            int32_t code = rc;
+        const int r = hull_one(points + 2 * lo, m, out_idx + lo, out_counts + s, st);
+        if (r != CH_OK) {
+            int32_t code = r;
             (void)hipMemcpy(out_counts + s, &code, sizeof(code), hipMemcpyHostToDevice);
-            if (first_err == CH_OK) first_err = rc;
+            if (first_err == CH_OK) first_err = r;
         }
     }
     return first_err;
