@@ -98,18 +98,44 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
  * hull2d_batched: num_sets independent hulls (Section 2.1 applied per set).
  *   points      device memory, the sets' points concatenated as in hull2d.
  *   offsets     host memory, num_sets + 1 non-decreasing int64 with
- *               offsets[0] == 0; set s is points[offsets[s] .. offsets[s+1]).
+ *               offsets[0] == 0 and offsets[num_sets] <= 2^31 - 1; set s is
+ *               points[offsets[s] .. offsets[s+1]).
  *   num_sets    >= 0.
  *   out_idx     device memory, room for offsets[num_sets] int32; set s
  *               writes its hull at out_idx + offsets[s], with indices local
- *               to the set.
+ *               to the set, in the output convention above.
  *   out_counts  device memory, num_sets int32: the hull size of each set, or
- *               that set's negative ch_status if it failed.
+ *               that set's negative ch_status if it failed (CH_EDOMAIN for a
+ *               set with an out-of-domain coordinate; the other sets are
+ *               still computed).
  *   stream      as in hull2d.
- * Returns CH_OK if every set succeeded, else the first failing status.
+ * One kernel launch computes every set of at most 2^22 points, one
+ * workgroup per set, all seven steps on the device.  A set beyond that
+ * size, or one whose open points, sort records or chain exceed the
+ * workgroup's on-chip capacities (for instance many points on the hull),
+ * is then computed by the single-hull path, with the same result.
+ * Blocking: returns after every count is known; the results are ordered on
+ * `stream` as in hull2d.
+ * Returns CH_OK if every set succeeded, else the first failing status
+ * (CH_EINVAL for bad arguments, before any work).
  */
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets,
                    int32_t* out_idx, int32_t* out_counts, void* stream);
+
+/* Counts and timings of the calling thread's last hull2d_batched call. */
+typedef struct {
+    int32_t num_sets;     /* sets in the call */
+    int32_t device_sets;  /* sets given to the one-launch kernel */
+    int32_t redo_sets;    /* sets computed by the single-hull path */
+    int64_t points;       /* points over all sets */
+    float ms_kernel;      /* the one-launch kernel, from HIP events on the call's
+                             stream when timing is on (chainhull_set_timing) */
+    float ms_total;       /* wall clock of the whole call */
+} ch_batch_stats;
+
+/* Copy the calling thread's last hull2d_batched counts into *out.  Returns
+ * CH_OK, or CH_EINVAL for a null pointer. */
+int chainhull_last_batch_stats(ch_batch_stats* out);
 
 /*
  * chainhull_polygon: steps 1-6 only (Section 2.1): the simple polygon

@@ -21,7 +21,7 @@ CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4,
 
 # C entry points declared in include/chainhull.h
 EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_host",
-           "chainhull_last_stats", "chainhull_set_timing", "chainhull_strerror",
+           "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_workspace_bytes")
 
 STAGES = ("sample", "stream", "cand", "sort", "spa", "unused5", "unused6", "finish")
@@ -63,6 +63,20 @@ class ChStats(ctypes.Structure):
         }
 
 
+class ChBatchStats(ctypes.Structure):
+    _fields_ = [
+        ("num_sets", ctypes.c_int32),
+        ("device_sets", ctypes.c_int32),
+        ("redo_sets", ctypes.c_int32),
+        ("points", ctypes.c_int64),
+        ("ms_kernel", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -85,6 +99,8 @@ def lib():
     L.chainhull_finish_host.restype = ctypes.c_int
     L.chainhull_last_stats.argtypes = [ctypes.POINTER(ChStats)]
     L.chainhull_last_stats.restype = ctypes.c_int
+    L.chainhull_last_batch_stats.argtypes = [ctypes.POINTER(ChBatchStats)]
+    L.chainhull_last_batch_stats.restype = ctypes.c_int
     L.chainhull_set_timing.argtypes = [ctypes.c_int]
     L.chainhull_set_timing.restype = None
     L.chainhull_strerror.argtypes = [ctypes.c_int]
@@ -191,6 +207,12 @@ def finish_host(poly_xy, poly_idx) -> np.ndarray:
 def last_stats() -> dict:
     st = ChStats()
     _check(lib().chainhull_last_stats(ctypes.byref(st)), "chainhull_last_stats")
+    return st.as_dict()
+
+
+def last_batch_stats() -> dict:
+    st = ChBatchStats()
+    _check(lib().chainhull_last_batch_stats(ctypes.byref(st)), "chainhull_last_batch_stats")
     return st.as_dict()
 
 

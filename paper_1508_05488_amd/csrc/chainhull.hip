@@ -367,7 +367,6 @@ constexpr int kStairShift = 23 - kStairBits;
 constexpr int kStreamGrid = 1024;   // persistent workgroups of k_stream
 constexpr int kStreamUnroll = 4;    // float4 loads in flight per thread
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
-constexpr int kCandGrid = 256;      // persistent workgroups of k_cand
 constexpr int kCandChunk = 1024;    // records filtered together
 
 // Open-point record: X | Y << 23 | frame mask << 46.
@@ -608,6 +607,22 @@ struct Quad {
     uint32_t err;
 };
 
+// The edges and the regions' first keys from the extreme points Q.X, Q.Y.
+__device__ inline void quad_edges(Quad& Q)
+{
+    // region q lies strictly right of edge q: ex*(y - E_q.y) - ey*(x - E_q.x) < 0
+    for (int q = 0; q < 4; ++q) {
+        const int s = (q + 1) & 3;
+        Q.ex[q] = (int32_t)Q.X[s] - (int32_t)Q.X[q];
+        Q.ey[q] = (int32_t)Q.Y[s] - (int32_t)Q.Y[q];
+        Q.ec[q] = (double)Q.ex[q] * (double)Q.Y[q] - (double)Q.ey[q] * (double)Q.X[q];
+    }
+    Q.sigma[0] = Q.Y[0];        // R1 starts at P_minx
+    Q.sigma[1] = Q.X[1] ^ kM;   // R2 starts at P_miny
+    Q.sigma[2] = Q.Y[2] ^ kM;   // R3 starts at P_maxx
+    Q.sigma[3] = Q.X[3];        // R4 starts at P_maxy
+}
+
 __device__ inline void make_quad(ExtAcc r, Quad& Q)
 {
     for (int e = 0; e < 2; ++e) {
@@ -626,17 +641,7 @@ __device__ inline void make_quad(ExtAcc r, Quad& Q)
     Q.Y[1] = (uint32_t)(key[1] >> 32) & kM; Q.X[1] = (uint32_t)key[1] & kM;
     Q.X[2] = (uint32_t)(key[2] >> 32) & kM; Q.Y[2] = ((uint32_t)key[2] & kM) ^ kM;
     Q.Y[3] = (uint32_t)(key[3] >> 32) & kM; Q.X[3] = (uint32_t)key[3] & kM;
-    // region q lies strictly right of edge q: ex*(y - E_q.y) - ey*(x - E_q.x) < 0
-    for (int q = 0; q < 4; ++q) {
-        const int s = (q + 1) & 3;
-        Q.ex[q] = (int32_t)Q.X[s] - (int32_t)Q.X[q];
-        Q.ey[q] = (int32_t)Q.Y[s] - (int32_t)Q.Y[q];
-        Q.ec[q] = (double)Q.ex[q] * (double)Q.Y[q] - (double)Q.ey[q] * (double)Q.X[q];
-    }
-    Q.sigma[0] = Q.Y[0];        // R1 starts at P_minx
-    Q.sigma[1] = Q.X[1] ^ kM;   // R2 starts at P_miny
-    Q.sigma[2] = Q.Y[2] ^ kM;   // R3 starts at P_maxx
-    Q.sigma[3] = Q.X[3];        // R4 starts at P_maxy
+    quad_edges(Q);
     Q.err = r.bad ? kErrDomain : 0u;
 }
 
@@ -1335,61 +1340,93 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
 // ---------------------------------------------------------------------------
 // Batched hulls: the method on many independent point sets in one launch,
 // one workgroup of kBatchBlock threads per set (larger sets first), every
-// step inside the workgroup, the finish included:
-//   pass A   the domain check, the lexicographic extreme keys (ties to the
-//            smaller index), and a staircase of every kBatchSampleEvery-th
-//            point per frame (slot minima with their points, as k_sample);
-//   pass B   the exact region test; per region and slot the smallest
-//            (k2, k1) of all region points; points that the sampled
-//            staircase does not dominate in their region's frame are listed
-//            in LDS;
-//   filter   a listed record goes when the region's first point or a record
-//            of an earlier slot has k2 <= its k2, or when its slot's
-//            smallest point precedes it with k1 <= its k1 (the dominance
-//            argument of Figure 3 with the exact slot minima);
-//   sort     bitonic, in LDS, by (region, k1, k2, list position);
-//   SPA      a tagged exclusive prefix minimum (as Figure 2's running
-//            threshold), the run of exact duplicates reporting its
-//            smallest index;
-//   polygon  [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] in LDS,
-//            shortened by pre-hull rounds (reflex-vertex removal inside a
-//            region), then Melkman by one thread (Section 2.1.3).
-// A set whose listed records or chain exceed the LDS capacities gets
-// kBatchRedo in out_counts and is run by the single-hull path afterwards.
+// step inside the workgroup, the finish included.
+//
+//   stream   one read of the set: the domain check and the four-frame
+//            staircase test of k_stream, against a staircase that tightens
+//            itself.  It starts from a sample (kBatchChunks runs of
+//            kBatchChunk consecutive points) and every listed point lowers
+//            the slot minima it falls in.  Listed ("open") point indices go
+//            to an LDS list.  When the next round could overflow the list,
+//            the staircase is rebuilt from the slot minima and the list is
+//            tested against it again; a point that fails is dominated in
+//            every frame by a point of the set, as in k_stream.  The extreme
+//            points are found among the listed points (they are always
+//            open).
+//   regions  the exact region test on the listed points; per region and
+//            slot the smallest (k2, k1).  A record goes when the region's
+//            first point or a record of an earlier slot has k2 <= its k2,
+//            or when its slot's smallest point precedes it with k1 <= its
+//            k1 (the dominance argument of Figure 3).
+//   sort     bitonic, in LDS, by (region, k1, k2, list position).
+//   SPA      a tagged exclusive prefix minimum (Figure 2's running
+//            threshold); the run of exact duplicates reports its smallest
+//            index.
+//   polygon  [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy, R4] in LDS.  After
+//            the SPA every region chain is monotone in both frame keys, so
+//            the polygon is monotone in x above and below: simple.
+//   pre-hull rounds: a chain vertex whose turn with its current neighbours
+//            (chain points of its region or the region's two extreme
+//            points) is not a left turn lies between the chord of those
+//            neighbours and the quadrilateral edge, inside the convex hull
+//            of four points of the set, so it goes; all such vertices go
+//            together.  When a round removes nothing and every vertex,
+//            extreme points included, is a strict left turn, the simple
+//            polygon is convex: it is the hull, written out in parallel from
+//            P_miny (the lowest, then leftmost, point).  Otherwise one
+//            thread finishes with Melkman (Section 2.1.3).
+// A set whose list, sort records or chain exceed the LDS capacities gets
+// kBatchRedo in out_counts and is run by the single-hull path afterwards, as
+// are sets larger than kBatchMaxSet (one workgroup would stream them for a
+// long time while the rest of the device idles).
 // ---------------------------------------------------------------------------
 constexpr int kBatchBlock = 1024;
 constexpr int kBatchWaves = kBatchBlock / 64;
-constexpr int kBatchCand = 8192;                  // listed records per set
-constexpr int kBatchPolyMax = 4096;               // polygon vertices kept in LDS
-constexpr int kBatchSampleEvery = 8;
-constexpr int kBatchRounds = 16;
+constexpr int kBatchUnroll = 3;                                    // float4 loads per thread and round
+constexpr uint32_t kBatchRound = 2u * kBatchUnroll * kBatchBlock;  // points per round
+constexpr int kBatchList = 16384;                                  // listed points per set
+constexpr int kBatchPerList = kBatchList / kBatchBlock;
+constexpr int kBatchCand = 8192;                                   // sort records per set
+constexpr int kBatchPolyMax = 4096;                                // polygon vertices per set
+constexpr int kBatchChunks = 64, kBatchChunk = 128;                // the first staircase sample
+constexpr int kBatchRounds = 32;                                   // pre-hull rounds at most
+constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger sets: single-hull path
 constexpr int32_t kBatchRedo = INT32_MIN;
-// LDS: [cidx u32 x kBatchCand][crec/keys u64 x kBatchCand][smin u64 x 4*kSlots]
-//      [stair: excl u32 x 4*kSlots, min point u64 x 4*kSlots]
-constexpr size_t kBatchLds = 4 * kBatchCand + 8 * kBatchCand + 8 * 4 * kSlots + 12 * 4 * kSlots;
+static_assert(kBatchList >= 2 * (int)kBatchRound, "a round must fit beside a compacted list");
+static_assert(kBatchCand / kBatchBlock <= 8 && kBatchPolyMax % kBatchBlock == 0, "per-thread shares");
+// LDS: [list: u32 x kBatchList][raw slot minima u32 x 4S][staircase u32 x 4S]
+//      [region slot minima u64 x 4*kSlots][region staircase u32 x 4*kSlots]
+// with the sort keys (u64 x kBatchCand) over everything after the list once
+// the stream is done, and the polygon view over everything once the SPA is.
+constexpr size_t kBatchOffRaw = 4 * (size_t)kBatchList;
+constexpr size_t kBatchOffStair = kBatchOffRaw + 4 * 4 * (size_t)kStairSlots;
+constexpr size_t kBatchOffSmin = kBatchOffStair + 4 * 4 * (size_t)kStairSlots;
+constexpr size_t kBatchOffSexc = kBatchOffSmin + 8 * 4 * (size_t)kSlots;
+constexpr size_t kBatchOffKey = kBatchOffRaw;
+constexpr size_t kBatchLds = kBatchOffKey + 8 * (size_t)kBatchCand;
+static_assert(kBatchOffSexc + 4 * 4 * kSlots <= kBatchLds, "LDS layout");
+static_assert(kBatchPolyMax * 16 + 2 * (2 * kBatchPolyMax + 8) <= (int)kBatchLds, "polygon view");
 
-struct BatchPoly {  // phase-4 view of the LDS
+struct BatchPoly {  // polygon view of the LDS
     int32_t* x;
     int32_t* y;
     int32_t* idx;
-    uint32_t* ka;
-    uint32_t* kb;
-    uint8_t* reg;
+    uint8_t* reg;  // region 0..3, 4 for an extreme point
     uint8_t* alive;
     uint16_t* lst;
     uint16_t* dq;
 };
+
+__device__ inline i64 turn_xy(const BatchPoly& P, uint32_t a, uint32_t b, uint32_t c)
+{
+    return (i64)(P.x[b] - P.x[a]) * (i64)(P.y[c] - P.y[a]) - (i64)(P.y[b] - P.y[a]) * (i64)(P.x[c] - P.x[a]);
+}
 
 // Melkman on the polygon lst[0..n) of vertices (x, y, idx) by one thread,
 // with the conventions of the host finish (consecutive duplicates dropped,
 // collinear prefix, newest vertex dropped when collinear).  Writes the hull,
 // rotated to the lowest-then-leftmost vertex, to out; returns its size, or
 // -1 when the deque would leave its room (not a simple polygon).
-__device__ inline i64 turn_xy(const BatchPoly& P, uint32_t a, uint32_t b, uint32_t c)
-{
-    return (i64)(P.x[b] - P.x[a]) * (i64)(P.y[c] - P.y[a]) - (i64)(P.y[b] - P.y[a]) * (i64)(P.x[c] - P.x[a]);
-}
-
 __device__ int batch_melkman(const BatchPoly& P, uint32_t n0, int32_t* __restrict__ out)
 {
     // consecutive duplicates, cyclically
@@ -1464,148 +1501,321 @@ __device__ int batch_melkman(const BatchPoly& P, uint32_t n0, int32_t* __restric
     return (int)h;
 }
 
+// The staircase of the batched stream from its slot minima raw[f*S + s]
+// (frames R1..R4, S = kStairSlots): per frame the exclusive prefix minimum
+// over the slots, stored in k_stream's layout.  Every thread of the
+// workgroup takes part; ends with a workgroup barrier.
+__device__ inline void batch_stair(const uint32_t* raw, uint32_t* sst, uint32_t* scratch)
+{
+    constexpr uint32_t S = kStairSlots, kPer = 4 * S / kBatchBlock, kThreadsPerFrame = S / kPer;
+    constexpr uint32_t kWavesPerFrame = kThreadsPerFrame / 64;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    const uint32_t f = tid / kThreadsPerFrame, j0 = (tid % kThreadsPerFrame) * kPer;
+    uint32_t v[kPer];
+    uint32_t m = ~0u;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        v[k] = raw[f * S + j0 + k];
+        m = min(m, v[k]);
+    }
+    const uint32_t incl = wave_incl_min(m);
+    uint32_t excl = __shfl_up(incl, 1);
+    if (lane == 0) excl = ~0u;
+    if (lane == 63) scratch[wave] = incl;
+    __syncthreads();
+    for (uint32_t w = f * kWavesPerFrame; w < wave; ++w) excl = min(excl, scratch[w]);
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t s = j0 + k;
+        const uint32_t at = f == 0 ? 2 * s : f == 1 ? 2 * S + 2 * s : f == 2 ? 2 * (S - 1 - s) + 1 : 2 * S + 2 * (S - 1 - s) + 1;
+        sst[at] = excl;
+        excl = min(excl, v[k]);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restrict__ pts,
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ order,
                                                             int32_t* __restrict__ out_idx,
-                                                            int32_t* __restrict__ out_counts)
+                                                            int32_t* __restrict__ out_counts, uint32_t pts_odd)
 {
     __shared__ __align__(16) unsigned char smem[kBatchLds];
-    __shared__ ExtAcc sh[kBatchWaves];
+    __shared__ u64 s_ek[kBatchWaves][4];
+    __shared__ uint32_t s_bad[kBatchWaves], s_eidx[4];
     __shared__ uint32_t scratch[kBatchWaves];
+    __shared__ uint32_t wcnt[2][kBatchWaves];
     __shared__ Quad sq;
-    __shared__ uint32_t s_n, s_flag, s_rcnt[4];
-    __shared__ int s_h;
-    uint32_t* const cidx = reinterpret_cast<uint32_t*>(smem);
-    u64* const crec = reinterpret_cast<u64*>(smem + 4 * kBatchCand);
-    u64* const smin = reinterpret_cast<u64*>(smem + 12 * kBatchCand);
-    uint32_t* const sexc = reinterpret_cast<uint32_t*>(smem + 12 * kBatchCand + 8 * 4 * kSlots);
-    u64* const spt = reinterpret_cast<u64*>(smem + 12 * kBatchCand + 12 * 4 * kSlots);
-    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
+    __shared__ uint32_t s_n, s_flag, s_ext, s_start, s_rcnt[4];
+    uint32_t* const lidx = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* const raw = reinterpret_cast<uint32_t*>(smem + kBatchOffRaw);
+    uint32_t* const sst = reinterpret_cast<uint32_t*>(smem + kBatchOffStair);
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / 64);  // a scalar
     const u64 lt = (1ull << lane) - 1ull;
     const int32_t set = order[blockIdx.x];
     const int64_t base = offsets[set];
     const uint32_t m = (uint32_t)(offsets[set + 1] - base);
-    const v2f* const p2 = reinterpret_cast<const v2f*>(pts) + base;
+    const float* const ps = pts + 2 * base;
+    const v2f* const p2 = reinterpret_cast<const v2f*>(ps);
     if (m == 0) {
         if (tid == 0) out_counts[set] = 0;
         return;
     }
+    constexpr uint32_t S = kStairSlots;
 
-    // ---- pass A: domain, extreme keys, sampled staircase (slot minima) ----
-    for (int e = tid; e < 4 * kSlots; e += kBatchBlock) spt[e] = ~0ull;
+    // ---- the first staircase, from a sample of runs of consecutive points ----
+    for (uint32_t e = tid; e < 4 * S; e += kBatchBlock) raw[e] = ~0u;
+    if (tid == 0) s_n = 0;
     __syncthreads();
-    ExtAcc a;
-    ext_init(a);
-    for (uint32_t i0 = 0; i0 < m; i0 += 4 * kBatchBlock) {
-        v2f v[4];
+    auto lower = [&](uint32_t x, uint32_t y) {  // x, y in [0, M]
+        atomicMin(&raw[0 * S + (x >> kStairShift)], y);         // R1: (x, y)
+        atomicMin(&raw[1 * S + (y >> kStairShift)], x ^ kM);    // R2: (y, M-x)
+        atomicMin(&raw[2 * S + ((x ^ kM) >> kStairShift)], y ^ kM);  // R3: (M-x, M-y)
+        atomicMin(&raw[3 * S + ((y ^ kM) >> kStairShift)], x);  // R4: (M-y, x)
+    };
+    if (m > kBatchRound) {
+        constexpr uint32_t kThreads = kBatchBlock / kBatchChunks, kPer = kBatchChunk / kThreads;
+        const uint32_t c = tid / kThreads, sub = tid % kThreads;
+        const uint32_t start = (uint32_t)(((u64)c * (m - kBatchChunk)) / (kBatchChunks - 1));
+        v2f v[kPer];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = p2[min(i0 + u * kBatchBlock + tid, m - 1)];
+        for (uint32_t k = 0; k < kPer; ++k) v[k] = p2[start + k * kThreads + sub];
+        // out-of-domain values only need to stay in range here: such a set
+        // fails with a domain error
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + u * kBatchBlock + tid;
-            if (i >= m) continue;
-            const uint32_t X = cvt_u32_sat(v[u].x), Y = cvt_u32_sat(v[u].y);
-            ext_check(a, v[u].x, v[u].y, X, Y);
-            ext_take(a, X & kM, Y & kM, i);
-            if (i % kBatchSampleEvery == 0) {
-                const uint32_t x = X & kM, y = Y & kM, xm = x ^ kM, ym = y ^ kM;
-                atomicMin(&spt[0 * kSlots + (x >> (23 - kSlotBits))], ((u64)y << 23) | x);    // R1
-                atomicMin(&spt[1 * kSlots + (y >> (23 - kSlotBits))], ((u64)xm << 23) | y);   // R2
-                atomicMin(&spt[2 * kSlots + (xm >> (23 - kSlotBits))], ((u64)ym << 23) | xm); // R3
-                atomicMin(&spt[3 * kSlots + (ym >> (23 - kSlotBits))], ((u64)x << 23) | ym);  // R4
+        for (uint32_t k = 0; k < kPer; ++k) lower(coord_u32(v[k].x) & kM, coord_u32(v[k].y) & kM);
+    }
+    __syncthreads();
+    batch_stair(raw, sst, scratch);
+
+    // ---- stream: domain check, staircase test, list the open points ----
+    // points before the first 16-byte boundary of the set (pts_odd: whether
+    // pts itself starts 8 bytes past one)
+    const uint32_t head = (uint32_t)(((uint64_t)base + pts_odd) & 1u);
+    const uint32_t n4 = (m - head) / 2;
+    const bool tail = ((m - head) & 1u) != 0;
+    const v4f* const p4 = reinterpret_cast<const v4f*>(ps + 2 * head);
+    const u64* const sx64 = reinterpret_cast<const u64*>(sst);
+    const u64* const sy64 = sx64 + S;
+    auto slot_of = [](uint32_t v) { return (v >> kStairShift) & (S - 1); };
+    // the extreme keys of the listed points: K0 = (x, M - y), K1 = (y, x);
+    // minima then maxima (coordinates only: the smallest index among a
+    // point's exact duplicates is found later, in the list)
+    u64 ek[4] = {~0ull, ~0ull, 0ull, 0ull};
+    bool bad = false;  // a coordinate out of the domain
+    auto check = [&](float fx, float fy, uint32_t X, uint32_t Y) {
+        bad = bad | ((float)X != fx) | ((float)Y != fy) | ((X | Y) > kM);
+    };
+    uint32_t wtot = 0;  // points this wave listed since the last compaction (uniform in the wave)
+
+    // one point of every lane, the whole wave together (the append is
+    // wave-wide)
+    auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
+        const bool o1 = Y < (uint32_t)sxv;                 // R1: k2 = y
+        const bool o2 = (X ^ kM) < (uint32_t)syv;          // R2: k2 = M - x
+        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);  // R3: k2 = M - y
+        const bool o4 = X < (uint32_t)(syv >> 32);         // R4: k2 = x
+        const bool open = valid && (o1 || o2 || o3 || o4);
+        const u64 bal = __ballot(open);
+        if (bal) {
+            uint32_t first = 0;
+            if (lane == 0) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
+            first = __shfl(first, 0);
+            if (open) {
+                lidx[first + (uint32_t)__popcll(bal & lt)] = idx;
+                const uint32_t x = X & kM, y = Y & kM;
+                lower(x, y);
+                const u64 k0 = ((u64)x << 32) | (y ^ kM), k1 = ((u64)y << 32) | x;
+                ek[0] = min(ek[0], k0);
+                ek[1] = min(ek[1], k1);
+                ek[2] = max(ek[2], k0);
+                ek[3] = max(ek[3], k1);
             }
+            wtot += (uint32_t)__popcll(bal);
+        }
+    };
+    auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
+        const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
+        if (valid) check(fx, fy, X, Y);
+        list_point(X, Y, idx, valid, sx64[slot_of(X)], sy64[slot_of(Y)]);
+    };
+    // the list again against the staircase rebuilt from the slot minima;
+    // every thread takes part, after a workgroup barrier with no append
+    // pending
+    auto compact = [&]() -> uint32_t {
+        batch_stair(raw, sst, scratch);
+        const uint32_t n = s_n;
+        uint32_t id[kBatchPerList];
+        v2f v[kBatchPerList];
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t e = k * kBatchBlock + tid;
+            id[k] = e < n ? lidx[e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) v[k] = p2[id[k]];
+        uint32_t keep = 0;
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t X = cvt_u32_sat(v[k].x) & kM, Y = cvt_u32_sat(v[k].y) & kM;
+            const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
+            const bool open = Y < (uint32_t)sxv || (X ^ kM) < (uint32_t)syv || (Y ^ kM) < (uint32_t)(sxv >> 32) ||
+                              X < (uint32_t)(syv >> 32);
+            if (k * kBatchBlock + tid < n && open) keep |= 1u << k;
+        }
+        uint32_t kept;
+        uint32_t at = block_excl_sum<kBatchWaves>((uint32_t)__popc(keep), scratch, kept);
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            if ((keep >> k) & 1u) lidx[at++] = id[k];
+        }
+        if (tid == 0) s_n = kept;
+        wtot = wave == 0 ? kept : 0u;
+        __syncthreads();
+        return kept;
+    };
+
+    if (wave == 0) {
+        if (head) visit_one(ps[0], ps[1], 0, lane == 0);
+        if (tail) visit_one(ps[2 * (m - 1)], ps[2 * (m - 1) + 1], m - 1, lane == 0);
+    }
+    constexpr uint32_t kR4 = (uint32_t)kBatchUnroll * kBatchBlock;  // float4s per round
+    const uint32_t rounds = (n4 + kR4 - 1) / kR4;
+    auto load_round = [&](uint32_t r, v4f* v) {
+#pragma unroll
+        for (int u = 0; u < kBatchUnroll; ++u)
+            v[u] = __builtin_nontemporal_load(p4 + min(r * kR4 + u * kBatchBlock + tid, n4 - 1));
+    };
+    // loads run two rounds ahead of the tests
+    v4f va[kBatchUnroll], vb[kBatchUnroll], vc[kBatchUnroll];
+    if (rounds > 0) load_round(0, va);
+    if (rounds > 1) load_round(1, vb);
+    bool full = false;  // the same in every thread
+    for (uint32_t r = 0; r < rounds; ++r) {
+        if (r + 2 < rounds) load_round(r + 2, vc);
+#pragma unroll
+        for (int u = 0; u < kBatchUnroll; ++u) {
+            const uint32_t g = r * kR4 + u * kBatchBlock + tid;
+            const bool valid = g < n4;
+            const uint32_t i0 = head + 2 * min(g, n4 - 1);
+            const uint32_t X0 = cvt_u32_sat(va[u].x), Y0 = cvt_u32_sat(va[u].y);
+            const uint32_t X1 = cvt_u32_sat(va[u].z), Y1 = cvt_u32_sat(va[u].w);
+            const u64 sx0 = sx64[slot_of(X0)], sy0 = sy64[slot_of(Y0)];
+            const u64 sx1 = sx64[slot_of(X1)], sy1 = sy64[slot_of(Y1)];
+            if (valid) {
+                check(va[u].x, va[u].y, X0, Y0);
+                check(va[u].z, va[u].w, X1, Y1);
+            }
+            list_point(X0, Y0, i0, valid, sx0, sy0);
+            list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
+        }
+        // the list's fill after this round, the same in every thread: each
+        // wave posts its own count (double-buffered: a wave that runs ahead
+        // writes the other buffer)
+        if (lane == 0) wcnt[r & 1][wave] = wtot;
+        __syncthreads();
+        uint32_t fill = 0;
+#pragma unroll
+        for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[r & 1][w];
+        // a list still too full after the compaction: the set has too many
+        // open points for the workgroup
+        if (fill > (uint32_t)kBatchList - kBatchRound && compact() > (uint32_t)kBatchList - kBatchRound) {
+            full = true;
+            break;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatchUnroll; ++u) {
+            va[u] = vb[u];
+            vb[u] = vc[u];
         }
     }
-    ext_wave_reduce(a);
-    if (lane == 0) sh[wave] = a;
+    if (full) {
+        if (tid == 0) out_counts[set] = kBatchRedo;
+        return;
+    }
+
+    // ---- the extreme points and the quadrilateral ----
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ek[0] = min(ek[0], (u64)__shfl_xor(ek[0], off));
+        ek[1] = min(ek[1], (u64)__shfl_xor(ek[1], off));
+        ek[2] = max(ek[2], (u64)__shfl_xor(ek[2], off));
+        ek[3] = max(ek[3], (u64)__shfl_xor(ek[3], off));
+    }
+    const bool wave_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s_ek[wave][e] = ek[e];
+        s_bad[wave] = wave_bad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (tid < 4) {  // thread e combines key e over the waves
+        u64 v = s_ek[0][tid];
+        for (int w = 1; w < kBatchWaves; ++w) v = tid < 2 ? min(v, s_ek[w][tid]) : max(v, s_ek[w][tid]);
+        const uint32_t hi = (uint32_t)(v >> 32) & kM, lo = (uint32_t)v & kM;
+        // K0 gives (x, M - y) of P_minx and P_maxx, K1 (y, x) of P_miny and P_maxy
+        const uint32_t e = tid == 0 ? 0u : tid == 1 ? 1u : tid == 2 ? 2u : 3u;
+        sq.X[e] = (e & 1u) ? lo : hi;
+        sq.Y[e] = (e & 1u) ? hi : lo ^ kM;
+        s_eidx[tid] = ~0u;
+        s_rcnt[tid] = 0;
+    }
     __syncthreads();
     if (tid == 0) {
-        for (int w = 1; w < kBatchWaves; ++w) ext_combine(a, sh[w]);
-        a.bad = a.bad || a.hi > kM;
-        make_quad(a, sq);
-        s_n = 0;
+        quad_edges(sq);
+        uint32_t any = 0;
+        for (int w = 0; w < kBatchWaves; ++w) any |= s_bad[w];
+        sq.err = any ? kErrDomain : 0u;
         s_flag = 0;
-        for (int q = 0; q < 4; ++q) s_rcnt[q] = 0;
     }
+    u64* const smin = reinterpret_cast<u64*>(smem + kBatchOffSmin);
+    uint32_t* const sexc = reinterpret_cast<uint32_t*>(smem + kBatchOffSexc);
+    for (int e = tid; e < 4 * kSlots; e += kBatchBlock) smin[e] = ~0ull;
     __syncthreads();
     if (sq.err) {
         if (tid == 0) out_counts[set] = CH_EDOMAIN;
         return;
     }
-    // sampled staircase: exclusive prefix minimum of k2 over the slots of each
-    // frame (wave f*4 .. f*4+3 owns frame f, two slots per thread)
-    {
-        const uint32_t f = tid / (kSlots / 2), j0 = (tid % (kSlots / 2)) * 2;
-        const u64 m0 = spt[f * kSlots + j0], m1 = spt[f * kSlots + j0 + 1];
-        const uint32_t v0 = m0 == ~0ull ? ~0u : (uint32_t)(m0 >> 23);
-        const uint32_t v1 = m1 == ~0ull ? ~0u : (uint32_t)(m1 >> 23);
-        const uint32_t incl = wave_incl_min(min(v0, v1));
-        uint32_t excl = __shfl_up(incl, 1);
-        if (lane == 0) excl = ~0u;
-        if (lane == 63) scratch[wave] = incl;
-        __syncthreads();
-        for (uint32_t w = f * 4; w < wave; ++w) excl = min(excl, scratch[w]);
-        sexc[f * kSlots + j0] = excl;
-        sexc[f * kSlots + j0 + 1] = min(excl, v0);
-        for (int e = tid; e < 4 * kSlots; e += kBatchBlock) smin[e] = ~0ull;
-        __syncthreads();
-    }
-
-    // ---- pass B: region test, exact slot minima, list the open points ----
+    const uint32_t L = s_n;
     const Quad Q = sq;
-    for (uint32_t i0 = 0; i0 < m; i0 += 4 * kBatchBlock) {
-        v2f v[4];
+
+    // ---- exact regions and region slot minima of the listed points ----
+    u64 rec[kBatchPerList];
+    {
+        uint32_t id[kBatchPerList];
+        v2f v[kBatchPerList];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = p2[min(i0 + u * kBatchBlock + tid, m - 1)];
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t e = k * kBatchBlock + tid;
+            id[k] = e < L ? lidx[e] : 0u;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + u * kBatchBlock + tid;
-            bool open = false;
-            u64 rec = 0;
-            if (i < m) {
-                const uint32_t X = (uint32_t)v[u].x, Y = (uint32_t)v[u].y;
+        for (int k = 0; k < kBatchPerList; ++k) v[k] = p2[id[k]];
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            rec[k] = ~0ull;
+            if (k * kBatchBlock + tid < L) {
+                const uint32_t X = (uint32_t)v[k].x, Y = (uint32_t)v[k].y;
+                // the extreme points' smallest indices among their duplicates
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (X == Q.X[e] && Y == Q.Y[e]) atomicMin(&s_eidx[e], id[k]);
+                }
                 const uint32_t q = region_of(Q, X, Y);
                 if (q < 4) {
                     uint32_t k1, k2;
                     to_frame(q, X, Y, k1, k2);
-                    const uint32_t sl = q * kSlots + (k1 >> (23 - kSlotBits));
-                    const u64 me = ((u64)k2 << 23) | k1;
-                    atomicMin(&smin[sl], me);
-                    const u64 sp = spt[sl];
-                    open = k2 < sexc[sl] && !(sp < me && (uint32_t)(sp & kM) <= k1);
-                    rec = ((u64)q << 46) | ((u64)k1 << 23) | k2;
-                }
-            }
-            const u64 bal = __ballot(open);
-            if (bal) {
-                uint32_t first = 0;
-                const int lead = __ffsll((long long)bal) - 1;
-                if (lane == (uint32_t)lead) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
-                first = __shfl(first, lead);
-                if (open) {
-                    const uint32_t pos = first + (uint32_t)__popcll(bal & lt);
-                    if (pos < (uint32_t)kBatchCand) {
-                        cidx[pos] = i;
-                        crec[pos] = rec;
-                    } else {
-                        s_flag = 1;
-                    }
+                    atomicMin(&smin[q * kSlots + (k1 >> (23 - kSlotBits))], ((u64)k2 << 23) | k1);
+                    rec[k] = ((u64)q << 46) | ((u64)k1 << 23) | k2;
                 }
             }
         }
     }
     __syncthreads();
-    if (s_flag) {
-        if (tid == 0) out_counts[set] = kBatchRedo;
-        return;
-    }
-    const uint32_t ncand = s_n;
-
-    // ---- filter with the exact slot minima ----
     {
         // exclusive prefix minimum per region over its slots, seeded with the
-        // region's first point (wave q*4 .. q*4+3 owns region q)
+        // region's first point (waves 4q .. 4q+3 own region q)
         const uint32_t q = tid / (kSlots / 2), j0 = (tid % (kSlots / 2)) * 2;
         const u64 m0 = smin[q * kSlots + j0], m1 = smin[q * kSlots + j0 + 1];
         const uint32_t v0 = m0 == ~0ull ? ~0u : (uint32_t)(m0 >> 23);
@@ -1616,36 +1826,32 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         if (lane == 63) scratch[wave] = incl;
         __syncthreads();
         for (uint32_t w = q * 4; w < wave; ++w) excl = min(excl, scratch[w]);
-        excl = min(excl, Q.sigma[q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : 3]);
+        excl = min(excl, sq.sigma[q]);
         sexc[q * kSlots + j0] = excl;
         sexc[q * kSlots + j0 + 1] = min(excl, v0);
         __syncthreads();
     }
-    // survivors become sort keys: record << 13 | list position (in place)
-    constexpr int kPerCand = kBatchCand / kBatchBlock;  // 8
-    u64 keys[kPerCand];
+    // survivors become sort keys: record << 14 | list position
     uint32_t keep = 0;
 #pragma unroll
-    for (int k = 0; k < kPerCand; ++k) {
-        const uint32_t r = tid * kPerCand + k;
-        keys[k] = ~0ull;
-        if (r < ncand) {
-            const u64 rec = crec[r];
-            const uint32_t q = (uint32_t)(rec >> 46), k1 = (uint32_t)(rec >> 23) & kM, k2 = (uint32_t)rec & kM;
+    for (int k = 0; k < kBatchPerList; ++k) {
+        if (rec[k] != ~0ull) {
+            const uint32_t q = (uint32_t)(rec[k] >> 46), k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
             const uint32_t sl = q * kSlots + (k1 >> (23 - kSlotBits));
             const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
-            if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) {
-                keep |= 1u << k;
-                keys[k] = (rec << 13) | r;
-            }
+            if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) keep |= 1u << k;
         }
     }
     uint32_t nsort;
-    uint32_t at = block_excl_sum<kBatchWaves>(__popc(keep), scratch, nsort);
-    u64* const skey = crec;
+    uint32_t at = block_excl_sum<kBatchWaves>((uint32_t)__popc(keep), scratch, nsort);
+    if (nsort > (uint32_t)kBatchCand) {
+        if (tid == 0) out_counts[set] = kBatchRedo;
+        return;
+    }
+    u64* const skey = reinterpret_cast<u64*>(smem + kBatchOffKey);
 #pragma unroll
-    for (int k = 0; k < kPerCand; ++k) {
-        if ((keep >> k) & 1u) skey[at++] = keys[k];
+    for (int k = 0; k < kBatchPerList; ++k) {
+        if ((keep >> k) & 1u) skey[at++] = (rec[k] << 14) | (u64)(k * kBatchBlock + tid);
     }
     uint32_t P2 = 1;
     while (P2 < nsort) P2 <<= 1;
@@ -1669,57 +1875,56 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     }
 
     // ---- SPA over the sorted records; chain positions ----
-    // thread t holds sorted records [t*per, t*per + per)
+    // thread t holds sorted records [t*per, t*per + per), per <= 8
     const uint32_t per = (P2 + kBatchBlock - 1) / kBatchBlock;
     uint32_t run = ~0u;
     for (uint32_t k = 0; k < per; ++k) {
         const uint32_t r = tid * per + k;
         if (r < nsort) {
-            const u64 key = skey[r] >> 13;
+            const u64 key = skey[r] >> 14;
             run = min(run, ((3u - (uint32_t)(key >> 46)) << 23) | (uint32_t)(key & kM));
         }
     }
     uint32_t unused;
     uint32_t pm = block_excl_min<kBatchWaves>(run, scratch, unused);
-    // keep flags in a bit mask (per <= 8 since nsort <= kBatchCand)
     uint32_t kmask = 0;
     for (uint32_t k = 0; k < per; ++k) {
         const uint32_t r = tid * per + k;
         if (r >= nsort) break;
-        const u64 key = skey[r] >> 13;
+        const u64 key = skey[r] >> 14;
         const uint32_t q = (uint32_t)(key >> 46), k2 = (uint32_t)(key & kM);
-        uint32_t thr = Q.sigma[q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : 3];
+        uint32_t thr = sq.sigma[q];
         if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
         if (k2 < thr) kmask |= 1u << k;
         pm = min(pm, ((3u - q) << 23) | k2);
     }
     uint32_t nchain;
-    uint32_t rank = block_excl_sum<kBatchWaves>(__popc(kmask), scratch, nchain);
+    const uint32_t rank = block_excl_sum<kBatchWaves>((uint32_t)__popc(kmask), scratch, nchain);
     if (nchain + 4 > (uint32_t)kBatchPolyMax) {
         if (tid == 0) out_counts[set] = kBatchRedo;
         return;
     }
-    // the kept records: region counts, then polygon positions
-    uint32_t kq[8], kk1[8], kk2[8], kid[8];
-    int nk = 0;
-    for (uint32_t k = 0; k < per; ++k) {
-        if (!((kmask >> k) & 1u)) continue;
-        const uint32_t r = tid * per + k;
-        const u64 key = skey[r];
-        const u64 rec = key >> 13;
-        // the run of exact duplicates reports its smallest index
-        uint32_t idx = cidx[(uint32_t)(key & 8191u)];
-        for (uint32_t j = r + 1; j < nsort && (skey[j] >> 13) == rec; ++j) idx = min(idx, cidx[(uint32_t)(skey[j] & 8191u)]);
-        kq[nk] = (uint32_t)(rec >> 46);
-        kk1[nk] = (uint32_t)(rec >> 23) & kM;
-        kk2[nk] = (uint32_t)rec & kM;
-        kid[nk] = idx;
-        atomicAdd(&s_rcnt[kq[nk]], 1u);
-        ++nk;
+    // the kept records and their smallest duplicate index, in registers
+    u64 krec[8];
+    uint32_t kidx[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        krec[k] = 0;
+        kidx[k] = 0;
+        if ((kmask >> k) & 1u) {
+            const uint32_t r = tid * per + k;
+            const u64 key = skey[r], rc = key >> 14;
+            uint32_t idx = lidx[(uint32_t)(key & 16383u)];
+            for (uint32_t j = r + 1; j < nsort && (skey[j] >> 14) == rc; ++j)
+                idx = min(idx, lidx[(uint32_t)(skey[j] & 16383u)]);
+            krec[k] = rc;
+            kidx[k] = idx;
+            atomicAdd(&s_rcnt[(uint32_t)(rc >> 46)], 1u);
+        }
     }
     __syncthreads();
-    // phase-4 view of the LDS (everything above is dead now except kept data
-    // in registers)
+
+    // ---- the polygon in LDS (everything above is dead now) ----
     BatchPoly Pl;
     {
         unsigned char* b = smem;
@@ -1729,10 +1934,6 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         b += 4 * kBatchPolyMax;
         Pl.idx = reinterpret_cast<int32_t*>(b);
         b += 4 * kBatchPolyMax;
-        Pl.ka = reinterpret_cast<uint32_t*>(b);
-        b += 4 * kBatchPolyMax;
-        Pl.kb = reinterpret_cast<uint32_t*>(b);
-        b += 4 * kBatchPolyMax;
         Pl.lst = reinterpret_cast<uint16_t*>(b);
         b += 2 * kBatchPolyMax;
         Pl.dq = reinterpret_cast<uint16_t*>(b);
@@ -1741,47 +1942,49 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         b += kBatchPolyMax;
         Pl.alive = b;
     }
-    __syncthreads();
     const uint32_t npoly = nchain + 4;
-    uint32_t rbase[4];
+    uint32_t rbase[4];  // polygon position of E_q
     {
         uint32_t acc = 0;
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
-            rbase[q] = acc;  // position of E_q
+            rbase[q] = acc;
             acc += 1 + s_rcnt[q];
         }
     }
     if (tid < 4) {
-        const uint32_t q = tid, o = rbase[q];
+        const uint32_t q = tid, o = q == 0 ? rbase[0] : q == 1 ? rbase[1] : q == 2 ? rbase[2] : rbase[3];
         Pl.x[o] = (int32_t)sq.X[q];
         Pl.y[o] = (int32_t)sq.Y[q];
-        Pl.idx[o] = (int32_t)sq.idx[q];
-        Pl.reg[o] = 4;  // an extreme point: never removed
+        Pl.idx[o] = (int32_t)s_eidx[q];
+        Pl.reg[o] = 4;
         Pl.alive[o] = 1;
     }
     {
-        // kept records in sorted (chain) order: rank over all regions, so
-        // the position is rank + 1 + (regions before) extra for extremes
+        // chain rank over all regions; E_0 .. E_q precede a record of region q
         uint32_t rr = rank;
-        for (int t = 0; t < nk; ++t, ++rr) {
-            const uint32_t q = kq[t];
-            const uint32_t o = rr + q + 1;  // the extremes E_0..E_q precede it
-            const uint32_t a2 = (q & 1u) ? kk2[t] : kk1[t];
-            const uint32_t b2 = (q & 1u) ? kk1[t] : kk2[t];
-            Pl.x[o] = (int32_t)(((q ^ (q >> 1)) & 1u) ? a2 ^ kM : a2);
-            Pl.y[o] = (int32_t)((q & 2u) ? b2 ^ kM : b2);
-            Pl.idx[o] = (int32_t)kid[t];
-            Pl.ka[o] = kk1[t];
-            Pl.kb[o] = kk2[t];
-            Pl.reg[o] = (uint8_t)q;
-            Pl.alive[o] = 1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if ((kmask >> k) & 1u) {
+                const uint32_t q = (uint32_t)(krec[k] >> 46), k1 = (uint32_t)(krec[k] >> 23) & kM,
+                               k2 = (uint32_t)krec[k] & kM;
+                const uint32_t o = rr + q + 1;
+                const uint32_t a2 = (q & 1u) ? k2 : k1;
+                const uint32_t b2 = (q & 1u) ? k1 : k2;
+                Pl.x[o] = (int32_t)(((q ^ (q >> 1)) & 1u) ? a2 ^ kM : a2);
+                Pl.y[o] = (int32_t)((q & 2u) ? b2 ^ kM : b2);
+                Pl.idx[o] = (int32_t)kidx[k];
+                Pl.reg[o] = (uint8_t)q;
+                Pl.alive[o] = 1;
+                ++rr;
+            }
         }
     }
     __syncthreads();
 
-    // ---- pre-hull rounds, then Melkman ----
-    auto compact = [&]() -> uint32_t {
-        constexpr int kPer = kBatchPolyMax / kBatchBlock;  // 4
+    // ---- pre-hull rounds; the convex case written out in parallel ----
+    auto compact_poly = [&]() -> uint32_t {
+        constexpr int kPer = kBatchPolyMax / kBatchBlock;
         uint32_t mine = 0;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -1798,24 +2001,46 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         __syncthreads();
         return n_alive;
     };
-    uint32_t n_alive = compact();
+    uint32_t n_alive = compact_poly();
+    bool convex = false;
     for (int round = 0; round < kBatchRounds; ++round) {
-        if (tid == 0) s_flag = 0;
+        if (tid == 0) {
+            s_flag = 0;
+            s_ext = 0;
+        }
         __syncthreads();
-        for (uint32_t p = tid + 1; p + 1 < n_alive; p += kBatchBlock) {
-            const uint32_t u = Pl.lst[p - 1], i = Pl.lst[p], c = Pl.lst[p + 1];
-            if (Pl.reg[i] < 4 && Pl.reg[u] == Pl.reg[i] && Pl.reg[c] == Pl.reg[i] &&
-                frame_turn(Pl.ka[u], Pl.kb[u], Pl.ka[i], Pl.kb[i], Pl.ka[c], Pl.kb[c]) <= 0) {
-                Pl.alive[i] = 0;
-                s_flag = 1;
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            const uint32_t u = Pl.lst[p == 0 ? n_alive - 1 : p - 1], i = Pl.lst[p],
+                           c = Pl.lst[p + 1 == n_alive ? 0 : p + 1];
+            if (turn_xy(Pl, u, i, c) <= 0) {
+                if (Pl.reg[i] < 4) {
+                    Pl.alive[i] = 0;
+                    s_flag = 1;
+                } else {
+                    s_ext = 1;
+                }
             }
         }
         __syncthreads();
-        const bool any = s_flag != 0;
-        n_alive = compact();
-        if (!any) break;
+        const bool removed = s_flag != 0, ext_flat = s_ext != 0;
+        if (!removed) {
+            convex = !ext_flat && n_alive >= 3;
+            break;
+        }
+        n_alive = compact_poly();
     }
-    if (tid == 0) {
+    if (convex) {
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            if (Pl.lst[p] == rbase[1]) s_start = p;
+        }
+        __syncthreads();
+        const uint32_t start = s_start;
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            const uint32_t o = p >= start ? p - start : p + n_alive - start;
+            out_idx[base + o] = Pl.idx[Pl.lst[p]];
+        }
+        if (tid == 0) out_counts[set] = (int32_t)n_alive;
+    } else if (tid == 0) {
         const int h = batch_melkman(Pl, n_alive, out_idx + base);
         out_counts[set] = h < 0 ? kBatchRedo : h;
     }
@@ -1936,6 +2161,7 @@ std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 bool g_timing = false;
 thread_local ch_stats t_stats;
+thread_local ch_batch_stats t_bstats;
 
 int hip_status(hipError_t e)
 {
@@ -2272,6 +2498,10 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets, int32_t* out_idx,
                    int32_t* out_counts, void* stream)
 {
+    const auto t0 = std::chrono::steady_clock::now();
+    ch_batch_stats& bs = t_bstats;
+    std::memset(&bs, 0, sizeof(bs));
+    bs.num_sets = num_sets;
     if (num_sets < 0 || (num_sets > 0 && (!offsets || !out_counts))) return CH_EINVAL;
     if (num_sets == 0) return CH_OK;
     if (offsets[0] != 0) return CH_EINVAL;
@@ -2279,6 +2509,8 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
         if (offsets[s + 1] < offsets[s] || offsets[s + 1] > INT32_MAX) return CH_EINVAL;
     }
     if (offsets[num_sets] > 0 && (!points || !out_idx)) return CH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
+    bs.points = offsets[num_sets];
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int rc = CH_OK;
     Workspace* w = workspace_for(st, &rc);
@@ -2313,35 +2545,58 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
         // the staging buffers may still feed an earlier call's copies
         CH_TRY(hipStreamSynchronize(st));
         std::memcpy(w->h_b_offsets, offsets, sizeof(int64_t) * (ns + 1));
-        // larger sets first, so that the last workgroups to start are short
-        for (int32_t s = 0; s < num_sets; ++s) w->h_b_order[s] = s;
-        std::stable_sort(w->h_b_order, w->h_b_order + ns, [&](int32_t a, int32_t b) {
+        // the kernel takes the sets up to kBatchMaxSet points, larger ones
+        // first so that the last workgroups to start are short
+        int32_t nk = 0;
+        for (int32_t s = 0; s < num_sets; ++s) {
+            if (offsets[s + 1] - offsets[s] <= kBatchMaxSet) w->h_b_order[nk++] = s;
+        }
+        std::stable_sort(w->h_b_order, w->h_b_order + nk, [&](int32_t a, int32_t b) {
             return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
         });
-        CH_TRY(hipMemcpyAsync(w->b_offsets, w->h_b_offsets, sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
-        CH_TRY(hipMemcpyAsync(w->b_order, w->h_b_order, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
-        CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3(num_sets), dim3(kBatchBlock), 0, st, points, w->b_offsets,
-                                     w->b_order, out_idx, out_counts));
-        CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        bs.device_sets = nk;
+        if (nk > 0) {
+            CH_TRY(hipMemcpyAsync(w->b_offsets, w->h_b_offsets, sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice,
+                                  st));
+            CH_TRY(hipMemcpyAsync(w->b_order, w->h_b_order, sizeof(int32_t) * (size_t)nk, hipMemcpyHostToDevice, st));
+            CH_TRY(record(*w, 0));
+            const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
+            CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
+                                         w->b_offsets, w->b_order, out_idx, out_counts, pts_odd));
+            CH_TRY(record(*w, 1));
+            CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+        }
         CH_TRY(hipStreamSynchronize(st));
-        for (int32_t s = 0; s < num_sets; ++s)
+        if (g_timing && w->events && nk > 0) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) bs.ms_kernel = ms;
+        }
+        for (int32_t s = 0; s < num_sets; ++s) {
+            if (offsets[s + 1] - offsets[s] > kBatchMaxSet) w->h_b_counts[s] = kBatchRedo;
             if (w->h_b_counts[s] == kBatchRedo) redo.push_back(s);
+        }
     }
     int first_err = CH_OK;
     for (int32_t s = 0; s < num_sets; ++s) {
         const int32_t c = w->h_b_counts[s];
         if (c < 0 && c != kBatchRedo && first_err == CH_OK) first_err = c;
     }
-    // sets beyond the workgroup's capacities: the single-hull path
+    // sets beyond the kernel's limit or capacities: the single-hull path
+    bs.redo_sets = (int32_t)redo.size();
     for (const int32_t s : redo) {
         const int64_t lo = offsets[s], m = offsets[s + 1] - lo;
         const int r = hull_one(points + 2 * lo, m, out_idx + lo, out_counts + s, st);
         if (r != CH_OK) {
-            int32_t code = r;
-            (void)hipMemcpy(out_counts + s, &code, sizeof(code), hipMemcpyHostToDevice);
+            // hull_one leaves the stream usable and has set the count to 0;
+            // the set's own status replaces it, in stream order
+            int32_t* code = w->h_b_counts + s;
+            *code = r;
+            CH_TRY(hipMemcpyAsync(out_counts + s, code, sizeof(int32_t), hipMemcpyHostToDevice, st));
+            CH_TRY(hipStreamSynchronize(st));
             if (first_err == CH_OK) first_err = r;
         }
     }
+    bs.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return first_err;
 }
 
@@ -2380,6 +2635,13 @@ int chainhull_finish_host(const int32_t* poly_xy, const int32_t* poly_idx, int64
     if (out_count) *out_count = 0;
     if (m < 0 || !out_count || (m > 0 && (!poly_xy || !poly_idx || !out_idx))) return CH_EINVAL;
     return melkman_finish(poly_xy, poly_idx, m, out_idx, out_count) == 0 ? CH_OK : CH_EINVAL;
+}
+
+int chainhull_last_batch_stats(ch_batch_stats* out)
+{
+    if (!out) return CH_EINVAL;
+    *out = t_bstats;
+    return CH_OK;
 }
 
 int chainhull_last_stats(ch_stats* out)
