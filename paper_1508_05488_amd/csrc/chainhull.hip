@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         const bool o2 = (X ^ kM) < (uint32_t)syv;           // R2: k2 = M - x
         const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);   // R3: k2 = M - y
         const bool o4 = X < (uint32_t)(syv >> 32);          // R4: k2 = x
-        const bool open = valid && (o1 || o2 || o3 || o4);
+        const bool open = (o1 | o2 | o3 | o4) & valid;
         const u64 bal = __ballot(open);
         if (bal) {
             if (open) {
@@ -1382,7 +1382,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
 // ---------------------------------------------------------------------------
 constexpr int kBatchBlock = 1024;
 constexpr int kBatchWaves = kBatchBlock / 64;
-constexpr int kBatchUnroll = 3;                                    // float4 loads per thread and round
+constexpr int kBatchUnroll = 2;                                    // float4 loads per thread and round
 constexpr uint32_t kBatchRound = 2u * kBatchUnroll * kBatchBlock;  // points per round
 constexpr int kBatchList = 16384;                                  // listed points per set
 constexpr int kBatchPerList = kBatchList / kBatchBlock;
@@ -1394,17 +1394,20 @@ constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger set
 constexpr int32_t kBatchRedo = INT32_MIN;
 static_assert(kBatchList >= 2 * (int)kBatchRound, "a round must fit beside a compacted list");
 static_assert(kBatchCand / kBatchBlock <= 8 && kBatchPolyMax % kBatchBlock == 0, "per-thread shares");
-// LDS: [list: u32 x kBatchList][raw slot minima u32 x 4S][staircase u32 x 4S]
-//      [region slot minima u64 x 4*kSlots][region staircase u32 x 4*kSlots]
-// with the sort keys (u64 x kBatchCand) over everything after the list once
-// the stream is done, and the polygon view over everything once the SPA is.
-constexpr size_t kBatchOffRaw = 4 * (size_t)kBatchList;
-constexpr size_t kBatchOffStair = kBatchOffRaw + 4 * 4 * (size_t)kStairSlots;
-constexpr size_t kBatchOffSmin = kBatchOffStair + 4 * 4 * (size_t)kStairSlots;
+// LDS: [staircase u32 x 4S][raw slot minima u32 x 4S][region slot minima
+//      u64 x 4*kSlots][region staircase u32 x 4*kSlots] .. [list u32 x
+//      kBatchList], with the sort keys (u64 x kBatchCand) over everything
+// before the list once the regions are filtered, and the polygon view over
+// everything once the SPA is done.  The staircase sits at offset 0 so that
+// its reads need no base address.
+constexpr size_t kBatchOffStair = 0;
+constexpr size_t kBatchOffRaw = kBatchOffStair + 4 * 4 * (size_t)kStairSlots;
+constexpr size_t kBatchOffSmin = kBatchOffRaw + 4 * 4 * (size_t)kStairSlots;
 constexpr size_t kBatchOffSexc = kBatchOffSmin + 8 * 4 * (size_t)kSlots;
-constexpr size_t kBatchOffKey = kBatchOffRaw;
-constexpr size_t kBatchLds = kBatchOffKey + 8 * (size_t)kBatchCand;
-static_assert(kBatchOffSexc + 4 * 4 * kSlots <= kBatchLds, "LDS layout");
+constexpr size_t kBatchOffKey = 0;
+constexpr size_t kBatchOffList = kBatchOffKey + 8 * (size_t)kBatchCand;
+constexpr size_t kBatchLds = kBatchOffList + 4 * (size_t)kBatchList;
+static_assert(kBatchOffSexc + 4 * 4 * kSlots <= kBatchOffList, "LDS layout");
 static_assert(kBatchPolyMax * 16 + 2 * (2 * kBatchPolyMax + 8) <= (int)kBatchLds, "polygon view");
 
 struct BatchPoly {  // polygon view of the LDS
@@ -1547,7 +1550,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     __shared__ uint32_t wcnt[2][kBatchWaves];
     __shared__ Quad sq;
     __shared__ uint32_t s_n, s_flag, s_ext, s_start, s_rcnt[4];
-    uint32_t* const lidx = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* const lidx = reinterpret_cast<uint32_t*>(smem + kBatchOffList);
     uint32_t* const raw = reinterpret_cast<uint32_t*>(smem + kBatchOffRaw);
     uint32_t* const sst = reinterpret_cast<uint32_t*>(smem + kBatchOffStair);
     const uint32_t tid = threadIdx.x, lane = lane_id();
@@ -1603,9 +1606,13 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     // minima then maxima (coordinates only: the smallest index among a
     // point's exact duplicates is found later, in the list)
     u64 ek[4] = {~0ull, ~0ull, 0ull, 0ull};
-    bool bad = false;  // a coordinate out of the domain
+    // the domain check: a coordinate is in the domain iff its conversion
+    // converts back to the same float (up to the sign of 0) and is at most
+    // M; differing bits and the largest conversion accumulate
+    uint32_t err = 0, hi = 0;
     auto check = [&](float fx, float fy, uint32_t X, uint32_t Y) {
-        bad = bad | ((float)X != fx) | ((float)Y != fy) | ((X | Y) > kM);
+        err |= (__float_as_uint((float)X) ^ __float_as_uint(fx)) | (__float_as_uint((float)Y) ^ __float_as_uint(fy));
+        hi = max(hi, max(X, Y));
     };
     uint32_t wtot = 0;  // points this wave listed since the last compaction (uniform in the wave)
 
@@ -1637,7 +1644,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     };
     auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
         const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
-        if (valid) check(fx, fy, X, Y);
+        check(fx, fy, X, Y);  // a lane without a point rechecks point idx
         list_point(X, Y, idx, valid, sx64[slot_of(X)], sy64[slot_of(Y)]);
     };
     // the list again against the staircase rebuilt from the slot minima;
@@ -1703,10 +1710,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
             const uint32_t X1 = cvt_u32_sat(va[u].z), Y1 = cvt_u32_sat(va[u].w);
             const u64 sx0 = sx64[slot_of(X0)], sy0 = sy64[slot_of(Y0)];
             const u64 sx1 = sx64[slot_of(X1)], sy1 = sy64[slot_of(Y1)];
-            if (valid) {
-                check(va[u].x, va[u].y, X0, Y0);
-                check(va[u].z, va[u].w, X1, Y1);
-            }
+            // (a lane past the end rechecks the last points)
+            check(va[u].x, va[u].y, X0, Y0);
+            check(va[u].z, va[u].w, X1, Y1);
             list_point(X0, Y0, i0, valid, sx0, sy0);
             list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
         }
@@ -1743,7 +1749,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         ek[2] = max(ek[2], (u64)__shfl_xor(ek[2], off));
         ek[3] = max(ek[3], (u64)__shfl_xor(ek[3], off));
     }
-    const bool wave_bad = __ballot(bad) != 0;
+    const bool wave_bad = __ballot((err & 0x7fffffffu) != 0 || hi > kM) != 0;
     if (lane == 0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) s_ek[wave][e] = ek[e];
