@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 DISTS = (("square", 2), ("disk", 3), ("gaussian", 4))
 N_POINTS = 20_000_000
+BATCH_SETS, BATCH_LO, BATCH_HI, BATCH_SEED = 4096, 1_000, 1_000_000, 7
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1508_05488_amd", "csrc", "chainhull.hip")
 
@@ -40,6 +41,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_POINTS, help="points per input (default 20M)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-sets measurement")
+    ap.add_argument("--batch-sets", type=int, default=BATCH_SETS)
+    ap.add_argument("--batch-calls", type=int, default=30)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -70,6 +74,98 @@ def load_traffic(kernel: str):
         return float(rec["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measure_batched(ch, wl, torch, dev, args):
+    """Independent sets in one call: 4096 sets with sizes log-uniform in
+    [1e3, 1e6], each uniform square, uniform disk or Gaussian.  Times
+    blocking hull2d_batched calls (inputs resident in HBM) for hulls/s and
+    the p50/p99 call latency, the batched kernel alone with HIP events, and
+    the same sets through the plain path, one hull2d call per set."""
+    num = args.batch_sets
+    pts, offs, dists = wl.batched_sets(num, BATCH_LO, BATCH_HI, BATCH_SEED)
+    n_total = int(offs[-1])
+    d_pts = torch.from_numpy(pts).to(dev)
+    out = torch.empty(max(n_total, 1), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(max(num, 1), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    lib = ch.lib()
+
+    def call():
+        rc = lib.hull2d_batched(d_pts.data_ptr(), offs.ctypes.data, num, out.data_ptr(), cnt.data_ptr(),
+                                stream.cuda_stream)
+        if rc != ch.CH_OK:
+            raise ch.ChainHullError(rc, "hull2d_batched")
+
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.batch_calls):
+        a = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    elapsed = time.perf_counter() - t0
+    bstats = ch.last_batch_stats()
+    ch.set_timing(True)
+    kms = []
+    for _ in range(5):
+        call()
+        kms.append(ch.last_batch_stats()["ms_kernel"])
+    ch.set_timing(False)
+    torch.cuda.synchronize()
+    lat_ms = np.array(lat) * 1e3
+    k_ms = float(np.median(kms))
+    k_bytes = 8.0 * n_total  # one read of every point
+    # the plain path on the same sets: one blocking hull2d call per set
+    o1 = torch.empty(max(n_total, 1), dtype=torch.int32, device=dev)
+    c1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    plain_lat = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        plain_lat = []
+        for k in range(num):
+            lo, hi = int(offs[k]), int(offs[k + 1])
+            a = time.perf_counter()
+            rc = lib.hull2d(d_pts.data_ptr() + 8 * lo, hi - lo, o1.data_ptr() + 4 * lo, c1.data_ptr(),
+                            stream.cuda_stream)
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, "hull2d")
+            plain_lat.append(time.perf_counter() - a)
+        torch.cuda.synchronize()
+    plain_s = float(np.sum(plain_lat))
+    # the batched results equal the plain ones (the plain call wrote every
+    # set's hull at its own offset; counts from the batched call)
+    c_host = cnt[:num].cpu().numpy()
+    o_b, o_p = out.cpu().numpy(), o1.cpu().numpy()
+    same = all(np.array_equal(o_b[offs[k]:offs[k] + c_host[k]], o_p[offs[k]:offs[k] + c_host[k]])
+               for k in range(0, num, 1))
+    del d_pts, out, o1
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{num} independent sets, sizes log-uniform in [{BATCH_LO}, {BATCH_HI}], "
+                    "each uniform square, uniform disk or Gaussian (seed 7); one hull2d_batched call",
+        "points": n_total,
+        "hulls_per_s": round(num * args.batch_calls / elapsed, 1),
+        "mpts_per_s": round(n_total * args.batch_calls / elapsed / 1e6, 1),
+        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 4),
+        "calls": args.batch_calls,
+        "kernel_ms": round(k_ms, 4),
+        "kernel_roofline": {"bound": "hbm", "kernel": "k_batch_hull", "achieved": round(k_bytes / (k_ms * 1e-3) / 1e9, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(k_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "algorithmic_bytes_per_launch": k_bytes},
+        "sets_on_single_hull_path": bstats["redo_sets"],
+        "plain_path": {"hulls_per_s": round(num / plain_s, 1), "mpts_per_s": round(n_total / plain_s / 1e6, 1),
+                       "latency_ms_p50": round(float(np.percentile(np.array(plain_lat) * 1e3, 50)), 4),
+                       "latency_ms_p99": round(float(np.percentile(np.array(plain_lat) * 1e3, 99)), 4),
+                       "note": "one blocking hull2d call per set, same sets, same GPU"},
+        "speedup_vs_plain": round((num * args.batch_calls / elapsed) / (num / plain_s), 2),
+        "results_equal_plain": bool(same),
+    }
 
 
 def main():
@@ -177,6 +273,12 @@ def main():
         cpu = {"value": round(n * len(DISTS) / tc / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
                "sample": f"one single-threaded oracle run on each of the three {n}-point inputs ({tc:.1f} s)"}
 
+    batched = None
+    if not args.no_batched:
+        del inputs, outs
+        torch.cuda.empty_cache()
+        batched = measure_batched(ch, wl, torch, dev, args)
+
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -207,6 +309,7 @@ def main():
         "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
         "preprocess_b_alg_frac": round(pre_frac, 4),
         "per_distribution": per_dist,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 
