@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sets measurement")
     ap.add_argument("--batch-sets", type=int, default=BATCH_SETS)
     ap.add_argument("--batch-calls", type=int, default=30)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-set comparison of the batched measurement")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -54,12 +56,12 @@ def src_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of
-    ``kernel`` (``profiles/<kernel>_traffic_20m.md``), if its counters were
-    taken on the current kernel source.  The summary holds ``key: value``
-    lines, among them ``source_sha256_16`` and ``bytes_per_launch``."""
-    path = os.path.join(PROFILE_DIR, f"{kernel}_traffic_20m.md")
+def load_traffic(name: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (``profiles/<name>.md``), if its counters were taken on the current
+    kernel source.  The summary holds ``key: value`` lines, among them
+    ``source_sha256_16`` and ``bytes_per_launch``."""
+    path = os.path.join(PROFILE_DIR, f"{name}.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -119,30 +121,39 @@ def measure_batched(ch, wl, torch, dev, args):
     lat_ms = np.array(lat) * 1e3
     k_ms = float(np.median(kms))
     k_bytes = 8.0 * n_total  # one read of every point
-    # the plain path on the same sets: one blocking hull2d call per set
-    o1 = torch.empty(max(n_total, 1), dtype=torch.int32, device=dev)
-    c1 = torch.zeros(1, dtype=torch.int32, device=dev)
-    plain_lat = []
-    for rep in range(2):
-        torch.cuda.synchronize()
+    plain = None
+    if not args.no_plain:
+        # the plain path on the same sets: one blocking hull2d call per set
+        o1 = torch.empty(max(n_total, 1), dtype=torch.int32, device=dev)
+        c1 = torch.zeros(1, dtype=torch.int32, device=dev)
         plain_lat = []
-        for k in range(num):
-            lo, hi = int(offs[k]), int(offs[k + 1])
-            a = time.perf_counter()
-            rc = lib.hull2d(d_pts.data_ptr() + 8 * lo, hi - lo, o1.data_ptr() + 4 * lo, c1.data_ptr(),
-                            stream.cuda_stream)
-            if rc != ch.CH_OK:
-                raise ch.ChainHullError(rc, "hull2d")
-            plain_lat.append(time.perf_counter() - a)
-        torch.cuda.synchronize()
-    plain_s = float(np.sum(plain_lat))
-    # the batched results equal the plain ones (the plain call wrote every
-    # set's hull at its own offset; counts from the batched call)
-    c_host = cnt[:num].cpu().numpy()
-    o_b, o_p = out.cpu().numpy(), o1.cpu().numpy()
-    same = all(np.array_equal(o_b[offs[k]:offs[k] + c_host[k]], o_p[offs[k]:offs[k] + c_host[k]])
-               for k in range(0, num, 1))
-    del d_pts, out, o1
+        for rep in range(2):
+            torch.cuda.synchronize()
+            plain_lat = []
+            for k in range(num):
+                lo, hi = int(offs[k]), int(offs[k + 1])
+                a = time.perf_counter()
+                rc = lib.hull2d(d_pts.data_ptr() + 8 * lo, hi - lo, o1.data_ptr() + 4 * lo, c1.data_ptr(),
+                                stream.cuda_stream)
+                if rc != ch.CH_OK:
+                    raise ch.ChainHullError(rc, "hull2d")
+                plain_lat.append(time.perf_counter() - a)
+            torch.cuda.synchronize()
+        plain_s = float(np.sum(plain_lat))
+        # the batched results equal the plain ones (the plain calls wrote every
+        # set's hull at its own offset; counts from the batched call)
+        c_host = cnt[:num].cpu().numpy()
+        o_b, o_p = out.cpu().numpy(), o1.cpu().numpy()
+        same = all(np.array_equal(o_b[offs[k]:offs[k] + c_host[k]], o_p[offs[k]:offs[k] + c_host[k]])
+                   for k in range(num))
+        plain = {"hulls_per_s": round(num / plain_s, 1), "mpts_per_s": round(n_total / plain_s / 1e6, 1),
+                 "latency_ms_p50": round(float(np.percentile(np.array(plain_lat) * 1e3, 50)), 4),
+                 "latency_ms_p99": round(float(np.percentile(np.array(plain_lat) * 1e3, 99)), 4),
+                 "note": "one blocking hull2d call per set, same sets, same GPU",
+                 "speedup_of_batched": round((num * args.batch_calls / elapsed) / (num / plain_s), 2),
+                 "results_equal": bool(same)}
+        del o1
+    del d_pts, out
     torch.cuda.empty_cache()
     return {
         "workload": f"{num} independent sets, sizes log-uniform in [{BATCH_LO}, {BATCH_HI}], "
@@ -157,14 +168,10 @@ def measure_batched(ch, wl, torch, dev, args):
         "kernel_roofline": {"bound": "hbm", "kernel": "k_batch_hull", "achieved": round(k_bytes / (k_ms * 1e-3) / 1e9, 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(k_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                            "algorithmic_bytes_per_launch": k_bytes},
+                            "algorithmic_bytes_per_launch": k_bytes,
+                            "traffic": load_traffic("k_batch_hull_4096sets") if num == BATCH_SETS else None},
         "sets_on_single_hull_path": bstats["redo_sets"],
-        "plain_path": {"hulls_per_s": round(num / plain_s, 1), "mpts_per_s": round(n_total / plain_s / 1e6, 1),
-                       "latency_ms_p50": round(float(np.percentile(np.array(plain_lat) * 1e3, 50)), 4),
-                       "latency_ms_p99": round(float(np.percentile(np.array(plain_lat) * 1e3, 99)), 4),
-                       "note": "one blocking hull2d call per set, same sets, same GPU"},
-        "speedup_vs_plain": round((num * args.batch_calls / elapsed) / (num / plain_s), 2),
-        "results_equal_plain": bool(same),
+        "plain_path": plain,
     }
 
 
@@ -252,7 +259,7 @@ def main():
     dom = "k_stream"
     dom_ms, dom_bytes = stage_ms["stream"], 8.0 * n + 12.0 * open_mean
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
-    traffic = load_traffic(dom)
+    traffic = load_traffic("k_stream_traffic_20m")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms}
