@@ -183,8 +183,73 @@ const char* chainhull_strerror(int status);
  * called while another call is running. */
 void chainhull_release(void);
 
+/* Free the cached workspace of one stream on the current device (device and
+ * pinned host memory).  No call on that stream may be running.  Returns
+ * CH_OK (also when the stream has no workspace). */
+int chainhull_release_stream(void* stream);
+
 /* Upper bound on the device workspace bytes a call with n points needs. */
 size_t chainhull_workspace_bytes(int64_t n);
+
+/*
+ * Serving: hull requests of mixed sizes that arrive over time, computed with
+ * continuous batching on the device that is current at creation (Section
+ * 2.1 per request; the result of a request is exactly hull2d's for it
+ * alone, whatever else is in flight).
+ *
+ * Worker threads, each with its own stream, take the oldest pending work
+ * when free: a request of more than 2^18 points alone through the
+ * single-hull path, or every pending smaller request together (gathered
+ * into the worker's staging buffer and computed by one hull2d_batched
+ * launch).  Requests that arrive while others run join the next batch; the
+ * workers' streams overlap on the device.
+ *
+ * Admission: a request holds part of mem_budget from submission until it
+ * completes (12 bytes per point when it is batched, the single-hull
+ * workspace bound otherwise); requests are admitted first come, first
+ * served, as budget frees up.
+ */
+typedef struct ch_server ch_server;
+
+typedef struct {
+    int64_t completed;         /* requests finished */
+    int64_t batches;           /* batched launches */
+    int64_t batched_requests;  /* requests computed in batched launches */
+    int64_t single_requests;   /* requests computed alone */
+    int64_t points;            /* points of the finished requests */
+    int64_t pending;           /* requests submitted and not started */
+    int32_t max_inflight;      /* most requests running at once */
+    int32_t reserved0;
+    uint64_t reserved_bytes;   /* budget held by admitted requests now */
+} ch_server_stats;
+
+/* Create a server with `workers` (1..16) worker threads and streams and a
+ * memory budget in bytes (> 0).  *out receives it.  Returns CH_OK,
+ * CH_EINVAL or CH_EHIP. */
+int chainhull_server_create(int32_t workers, size_t mem_budget, ch_server** out);
+
+/* Submit one request.  points: device memory, n float32 (x, y) pairs as in
+ * hull2d, 8-byte aligned, unchanged until the request completes; out_idx
+ * (room for n int32) and out_count (one int32): device memory that receives
+ * the hull as hull2d writes it.  *ticket receives the request's ticket.
+ * Returns at once: CH_OK, CH_EINVAL (bad argument, or the server is being
+ * destroyed), or CH_EADMIT (the request alone exceeds the budget). */
+int chainhull_server_submit(ch_server* s, const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
+                            uint64_t* ticket);
+
+/* Block until the request completes; its outputs are then written.  *hull
+ * (if not NULL) receives the hull size, *latency_ms (if not NULL) the time
+ * from submission to completion.  A ticket can be waited for once.  Returns
+ * the request's ch_status, or CH_EINVAL for an unknown ticket. */
+int chainhull_server_wait(ch_server* s, uint64_t ticket, int32_t* hull, double* latency_ms);
+
+/* Copy the server's counters into *out.  Returns CH_OK or CH_EINVAL. */
+int chainhull_server_stats(ch_server* s, ch_server_stats* out);
+
+/* Finish every submitted request, stop the workers and free the server.
+ * Requests not yet waited for are discarded (their outputs are written).
+ * Returns CH_OK or CH_EINVAL. */
+int chainhull_server_destroy(ch_server* s);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,9 @@ CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4,
 # C entry points declared in include/chainhull.h
 EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_host",
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
-           "chainhull_release", "chainhull_workspace_bytes")
+           "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes",
+           "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
+           "chainhull_server_stats", "chainhull_server_destroy")
 
 STAGES = ("sample", "stream", "cand", "sort", "spa", "unused5", "unused6", "finish")
 
@@ -77,6 +79,23 @@ class ChBatchStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ChServerStats(ctypes.Structure):
+    _fields_ = [
+        ("completed", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("batched_requests", ctypes.c_int64),
+        ("single_requests", ctypes.c_int64),
+        ("points", ctypes.c_int64),
+        ("pending", ctypes.c_int64),
+        ("max_inflight", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("reserved_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved0"}
+
+
 _lib = None
 
 
@@ -107,6 +126,18 @@ def lib():
     L.chainhull_strerror.restype = ctypes.c_char_p
     L.chainhull_release.argtypes = []
     L.chainhull_release.restype = None
+    L.chainhull_release_stream.argtypes = [vp]
+    L.chainhull_release_stream.restype = ctypes.c_int
+    L.chainhull_server_create.argtypes = [i32, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.chainhull_server_create.restype = ctypes.c_int
+    L.chainhull_server_submit.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.chainhull_server_submit.restype = ctypes.c_int
+    L.chainhull_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.chainhull_server_wait.restype = ctypes.c_int
+    L.chainhull_server_stats.argtypes = [vp, ctypes.POINTER(ChServerStats)]
+    L.chainhull_server_stats.restype = ctypes.c_int
+    L.chainhull_server_destroy.argtypes = [vp]
+    L.chainhull_server_destroy.restype = ctypes.c_int
     L.chainhull_workspace_bytes.argtypes = [i64]
     L.chainhull_workspace_bytes.restype = ctypes.c_size_t
     _lib = L
@@ -226,3 +257,68 @@ def release() -> None:
 
 def workspace_bytes(n: int) -> int:
     return int(lib().chainhull_workspace_bytes(int(n)))
+
+
+class Server:
+    """Continuous-batching hull server on one device (chainhull_server_*).
+
+    ``submit(points)`` takes a CUDA float32 [n, 2] tensor and returns a
+    ticket at once; ``wait(ticket)`` blocks and returns (hull int32 tensor,
+    latency in ms).  The points and output tensors of a request are kept
+    alive here until it is waited for."""
+
+    def __init__(self, workers: int = 4, mem_budget: int = 288 << 30, device=None):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().chainhull_server_create(int(workers), int(mem_budget), ctypes.byref(h)),
+                   "chainhull_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, points, out_idx=None, out_count=None) -> int:
+        import torch
+        pts = _device_points(points)
+        n = pts.shape[0]
+        if out_idx is None:
+            out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+        if out_count is None:
+            out_count = torch.zeros(1, dtype=torch.int32, device=pts.device)
+        t = ctypes.c_uint64(0)
+        rc = lib().chainhull_server_submit(self._h, pts.data_ptr(), n, out_idx.data_ptr(), out_count.data_ptr(),
+                                           ctypes.byref(t))
+        _check(rc, "chainhull_server_submit")
+        self._live[t.value] = (pts, out_idx, out_count)
+        return t.value
+
+    def wait(self, ticket: int):
+        h = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        rc = lib().chainhull_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(h), ctypes.byref(ms))
+        pts, out_idx, _ = self._live.pop(ticket)
+        _check(rc, "chainhull_server_wait")
+        return out_idx[: h.value], ms.value
+
+    def stats(self) -> dict:
+        st = ChServerStats()
+        _check(lib().chainhull_server_stats(self._h, ctypes.byref(st)), "chainhull_server_stats")
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            lib().chainhull_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

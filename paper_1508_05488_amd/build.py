@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libchainhull.so")
-SOURCES = ["chainhull.hip", "finish.cpp"]
+SOURCES = ["chainhull.hip", "finish.cpp", "serve.cpp"]
 
 
 def hipcc() -> str:

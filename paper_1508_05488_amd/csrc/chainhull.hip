@@ -50,6 +50,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <cstring>
@@ -2165,7 +2166,7 @@ size_t device_bytes(size_t cap)
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
-bool g_timing = false;
+std::atomic<bool> g_timing{false};
 thread_local ch_stats t_stats;
 thread_local ch_batch_stats t_bstats;
 
@@ -2677,6 +2678,20 @@ void chainhull_release(void)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) free_workspace(kv.second);
     g_ws.clear();
+}
+
+int chainhull_release_stream(void* stream)
+{
+    int dev = 0;
+    const int rc = hip_status(hipGetDevice(&dev));
+    if (rc != CH_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find(std::make_pair(dev, reinterpret_cast<hipStream_t>(stream)));
+    if (it != g_ws.end()) {
+        free_workspace(it->second);
+        g_ws.erase(it);
+    }
+    return CH_OK;
 }
 
 size_t chainhull_workspace_bytes(int64_t n)
