@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 DISTS = (("square", 2), ("disk", 3), ("gaussian", 4))
 N_POINTS = 20_000_000
 BATCH_SETS, BATCH_LO, BATCH_HI, BATCH_SEED = 4096, 1_000, 1_000_000, 7
+SERVE_LO, SERVE_HI, SERVE_POOL, SERVE_SEED = 10_000, 20_000_000, 48, 8
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1508_05488_amd", "csrc", "chainhull.hip")
 
@@ -44,6 +45,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sets measurement")
     ap.add_argument("--batch-sets", type=int, default=BATCH_SETS)
     ap.add_argument("--batch-calls", type=int, default=30)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-rate", type=float, default=10_000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-set comparison of the batched measurement")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -175,6 +180,108 @@ def measure_batched(ch, wl, torch, dev, args):
     }
 
 
+def measure_serving(ch, wl, torch, dev, args):
+    """Hull requests arriving as a Poisson stream at a fixed rate, sizes
+    log-uniform in [1e4, 2e7], each uniform square, disk or Gaussian (a pool
+    of 48 seeded requests resident in HBM, submitted in turn), served by the
+    continuous-batching server with a 288 GB budget.  Latency is from
+    submission to completion.  The same arrival stream is then served by
+    the plain path, one blocking hull2d call at a time in arrival order."""
+    import threading
+    rng = np.random.default_rng(SERVE_SEED)
+    names = ("square", "disk", "gaussian")
+    sizes = np.floor(np.exp(rng.uniform(np.log(SERVE_LO), np.log(SERVE_HI), size=SERVE_POOL))).astype(np.int64)
+    pool = [torch.from_numpy(wl.generate(names[k % 3], int(n), SERVE_SEED * 1000 + k)).to(dev)
+            for k, n in enumerate(sizes)]
+    nreq = args.serve_requests
+    order = np.arange(nreq) % SERVE_POOL
+    gaps = rng.exponential(1.0 / args.serve_rate, size=nreq)
+    pts_total = int(sum(int(sizes[k]) for k in order))
+
+    def run_server():
+        lat = []
+        with ch.Server(workers=args.serve_workers, mem_budget=288 << 30) as srv:
+            for p in pool[:8]:  # warm the workers' workspaces
+                srv.wait(srv.submit(p))
+            tickets = []
+            done = threading.Event()
+
+            def waiter():
+                k = 0
+                while k < nreq:
+                    if k < len(tickets):
+                        lat.append(srv.wait(tickets[k])[1])
+                        k += 1
+                    else:
+                        time.sleep(0)
+                done.set()
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            t0 = time.perf_counter()
+            due = t0
+            for k in range(nreq):
+                due += gaps[k]
+                while time.perf_counter() < due:
+                    pass
+                tickets.append(srv.submit(pool[order[k]]))
+            th.join()
+            elapsed = time.perf_counter() - t0
+            st = srv.stats()
+        return np.array(lat), elapsed, st
+
+    lat, elapsed, st = run_server()
+    # closed-loop capacity: the same requests all submitted at once
+    with ch.Server(workers=args.serve_workers, mem_budget=288 << 30) as srv:
+        for p in pool[:8]:
+            srv.wait(srv.submit(p))
+        t0 = time.perf_counter()
+        tk = [srv.submit(pool[order[k]]) for k in range(min(nreq, 4 * SERVE_POOL))]
+        for t in tk:
+            srv.wait(t)
+        cap = len(tk) / (time.perf_counter() - t0)
+    # the plain path on the same arrivals: one hull2d at a time
+    out = torch.empty(int(sizes.max()), dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    lib = ch.lib()
+    torch.cuda.synchronize()
+    plat = []
+    t0 = time.perf_counter()
+    arrive = t0
+    for k in range(nreq):
+        arrive += gaps[k]
+        while time.perf_counter() < arrive:
+            pass
+        p = pool[order[k]]
+        rc = lib.hull2d(p.data_ptr(), p.shape[0], out.data_ptr(), cnt.data_ptr(), stream.cuda_stream)
+        if rc != ch.CH_OK:
+            raise ch.ChainHullError(rc, "hull2d")
+        stream.synchronize()
+        plat.append(time.perf_counter() - arrive)
+    pel = time.perf_counter() - t0
+    plat = np.array(plat) * 1e3
+    del pool, out
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"Poisson arrivals at {args.serve_rate:.0f} requests/s, sizes log-uniform in [{SERVE_LO}, "
+                    f"{SERVE_HI}], uniform square, disk or Gaussian (a pool of {SERVE_POOL} seeded requests in HBM, "
+                    f"submitted in turn); {args.serve_workers} worker streams; 288 GB admission budget",
+        "requests": nreq,
+        "points": pts_total,
+        "hulls_per_s": round(nreq / elapsed, 1),
+        "mpts_per_s": round(pts_total / elapsed / 1e6, 1),
+        "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+        "capacity_hulls_per_s": round(cap, 1),
+        "server_stats": st,
+        "plain_path": {"hulls_per_s": round(nreq / pel, 1),
+                       "latency_ms_p50": round(float(np.percentile(plat, 50)), 4),
+                       "latency_ms_p99": round(float(np.percentile(plat, 99)), 4),
+                       "note": "same arrivals, one blocking hull2d call at a time in arrival order"},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -286,6 +393,10 @@ def main():
         torch.cuda.empty_cache()
         batched = measure_batched(ch, wl, torch, dev, args)
 
+    serving = None
+    if not args.no_serving:
+        serving = measure_serving(ch, wl, torch, dev, args)
+
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -317,6 +428,7 @@ def main():
         "preprocess_b_alg_frac": round(pre_frac, 4),
         "per_distribution": per_dist,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 
