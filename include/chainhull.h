@@ -71,9 +71,12 @@ typedef struct {
      * quadrilateral discard + region distribution + chunk dominance filter
      * (and, in chainhull_polygon, the round-1 counts), 3 region sort, first
      * level (records placed by bucket), 4 region sort, second level + SPA +
-     * chain concatenation (+ pre-hull in hull2d), 7 host finish (wall clock);
-     * 5 and 6 are unused. */
+     * chain concatenation (+ pre-hull in hull2d), 5 the device finish of
+     * hull2d, 7 the host finish (wall clock; 0 when the device finished);
+     * 6 is unused. */
     float ms[8];
+    int32_t device_finish;  /* 1 when hull2d finished step 7 on the device */
+    int32_t reserved;
 } ch_stats;
 
 /*
@@ -93,6 +96,9 @@ typedef struct {
  * Returns CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM or CH_EHIP.
  */
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
+/* (Step 7 runs on the device when the polygon left by steps 1-6 and the
+ * pre-hull has at most 4096 vertices, on the host otherwise; the result is
+ * the same.) */
 
 /*
  * hull2d_batched: num_sets independent hulls (Section 2.1 applied per set).

@@ -26,7 +26,7 @@ EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_ho
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
            "chainhull_server_stats", "chainhull_server_destroy")
 
-STAGES = ("sample", "stream", "cand", "sort", "spa", "unused5", "unused6", "finish")
+STAGES = ("sample", "stream", "cand", "sort", "spa", "finish_dev", "unused6", "finish")
 
 
 class ChainHullError(RuntimeError):
@@ -48,6 +48,8 @@ class ChStats(ctypes.Structure):
         ("polygon", ctypes.c_int64),
         ("hull", ctypes.c_int64),
         ("ms", ctypes.c_float * 8),
+        ("device_finish", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -62,6 +64,7 @@ class ChStats(ctypes.Structure):
             "polygon": self.polygon,
             "hull": self.hull,
             "ms": dict(zip(STAGES, list(self.ms))),
+            "device_finish": bool(self.device_finish),
         }
 
 

@@ -94,7 +94,10 @@ struct DevHeader {
     uint32_t open;       // points listed by k_stream
     uint32_t s2[4];      // SPA survivors per region
     uint32_t chain;      // SPA survivors in all (chain points before the pre-hull)
-    uint32_t pad[15];
+    uint32_t fin_done;   // 1 when the device finish wrote the hull
+    int32_t fin_hull;    // its size
+    uint32_t fin_w2[4];  // polygon vertices per region it finished from
+    uint32_t pad[9];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -1191,7 +1194,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                                                   DevHeader* __restrict__ hdr, Buckets bk,
                                                   PolyRec* __restrict__ host_chain, uint32_t host_cap,
                                                   PolyRec* __restrict__ spill, uint32_t* __restrict__ segcnt,
-                                                  DevHeader* __restrict__ host_hdr, int prehull)
+                                                  DevHeader* __restrict__ host_hdr, int prehull,
+                                                  PolyRec* __restrict__ dev_kept, uint32_t* __restrict__ dev_segcnt)
 {
     __shared__ uint32_t pre[kBuckets];  // chain points before each bucket
     __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
@@ -1329,10 +1333,14 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
             const uint32_t o = base + p;
             if (o < host_cap) host_chain[o] = r;
             else spill[o - host_cap] = r;
+            dev_kept[o] = r;  // the device finish reads these
             atomicAdd(&s_cnt[reg[i]], 1u);
         }
         __syncthreads();
-        if (tid < 4) segcnt[4 * sg + tid] = s_cnt[tid];
+        if (tid < 4) {
+            segcnt[4 * sg + tid] = s_cnt[tid];
+            dev_segcnt[4 * sg + tid] = s_cnt[tid];
+        }
         __syncthreads();
     }
     publish_header();
@@ -1409,7 +1417,7 @@ constexpr size_t kBatchOffKey = 0;
 constexpr size_t kBatchOffList = kBatchOffKey + 8 * (size_t)kBatchCand;
 constexpr size_t kBatchLds = kBatchOffList + 4 * (size_t)kBatchList;
 static_assert(kBatchOffSexc + 4 * 4 * kSlots <= kBatchOffList, "LDS layout");
-static_assert(kBatchPolyMax * 16 + 2 * (2 * kBatchPolyMax + 8) <= (int)kBatchLds, "polygon view");
+static_assert(16 * kBatchPolyMax + 2 * (2 * kBatchPolyMax + 8) <= (int)kBatchLds, "polygon view");
 
 struct BatchPoly {  // polygon view of the LDS
     int32_t* x;
@@ -1420,6 +1428,29 @@ struct BatchPoly {  // polygon view of the LDS
     uint16_t* lst;
     uint16_t* dq;
 };
+
+// The polygon view of LDS at b: x, y, idx (int32), the pre-hull list
+// (u16), Melkman's deque (u16, 2 * kBatchPolyMax + 8), region and alive
+// flags (u8); kPolyBytes in all.
+constexpr size_t kPolyBytes = 16 * (size_t)kBatchPolyMax + 2 * (2 * (size_t)kBatchPolyMax + 8);
+__device__ inline BatchPoly poly_view(unsigned char* b)
+{
+    BatchPoly Pl;
+    Pl.x = reinterpret_cast<int32_t*>(b);
+    b += 4 * kBatchPolyMax;
+    Pl.y = reinterpret_cast<int32_t*>(b);
+    b += 4 * kBatchPolyMax;
+    Pl.idx = reinterpret_cast<int32_t*>(b);
+    b += 4 * kBatchPolyMax;
+    Pl.lst = reinterpret_cast<uint16_t*>(b);
+    b += 2 * kBatchPolyMax;
+    Pl.dq = reinterpret_cast<uint16_t*>(b);
+    b += 2 * (2 * kBatchPolyMax + 8);
+    Pl.reg = b;
+    b += kBatchPolyMax;
+    Pl.alive = b;
+    return Pl;
+}
 
 __device__ inline i64 turn_xy(const BatchPoly& P, uint32_t a, uint32_t b, uint32_t c)
 {
@@ -1536,6 +1567,86 @@ __device__ inline void batch_stair(const uint32_t* raw, uint32_t* sst, uint32_t*
         excl = min(excl, v[k]);
     }
     __syncthreads();
+}
+
+// The polygon phase: pre-hull rounds on the polygon Pl[0 .. npoly) (x, y,
+// idx, region 0..3 or 4 for an extreme point, all alive), then the hull into
+// out.  A chain vertex whose turn with its current neighbours (points of its
+// chain or the region's extreme points) is not a left turn lies between the
+// chord of those neighbours and the quadrilateral edge, inside the hull of
+// four points of the set: all such vertices go together, round after round.
+// When a round removes nothing and every vertex, the extreme points
+// included, is a strict left turn, the simple polygon is convex and is the
+// hull: it is written out in parallel from polygon position `first`
+// (P_miny, the lowest then leftmost point).  Otherwise one thread runs
+// Melkman.  Every thread of the workgroup (kBatchBlock) calls it; returns the
+// hull size, the same in every thread, or -1 when Melkman's deque would
+// leave its room.  s_flag, s_ext, s_start: LDS words.
+__device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, int32_t* __restrict__ out,
+                           uint32_t* scratch, uint32_t* s_flag, uint32_t* s_ext, uint32_t* s_start)
+{
+    const uint32_t tid = threadIdx.x;
+    auto compact_poly = [&]() -> uint32_t {
+        constexpr int kPer = kBatchPolyMax / kBatchBlock;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = tid * kPer + k;
+            mine += (i < npoly && Pl.alive[i]) ? 1u : 0u;
+        }
+        uint32_t n_alive;
+        uint32_t o = block_excl_sum<kBatchWaves>(mine, scratch, n_alive);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = tid * kPer + k;
+            if (i < npoly && Pl.alive[i]) Pl.lst[o++] = (uint16_t)i;
+        }
+        __syncthreads();
+        return n_alive;
+    };
+    uint32_t n_alive = compact_poly();
+    bool convex = false;
+    for (int round = 0; round < kBatchRounds; ++round) {
+        if (tid == 0) {
+            *s_flag = 0;
+            *s_ext = 0;
+        }
+        __syncthreads();
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            const uint32_t u = Pl.lst[p == 0 ? n_alive - 1 : p - 1], i = Pl.lst[p],
+                           c = Pl.lst[p + 1 == n_alive ? 0 : p + 1];
+            if (turn_xy(Pl, u, i, c) <= 0) {
+                if (Pl.reg[i] < 4) {
+                    Pl.alive[i] = 0;
+                    *s_flag = 1;
+                } else {
+                    *s_ext = 1;
+                }
+            }
+        }
+        __syncthreads();
+        const bool removed = *s_flag != 0, ext_flat = *s_ext != 0;
+        if (!removed) {
+            convex = !ext_flat && n_alive >= 3;
+            break;
+        }
+        n_alive = compact_poly();
+    }
+    if (convex) {
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            if (Pl.lst[p] == first) *s_start = p;
+        }
+        __syncthreads();
+        const uint32_t start = *s_start;
+        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
+            const uint32_t o = p >= start ? p - start : p + n_alive - start;
+            out[o] = Pl.idx[Pl.lst[p]];
+        }
+        return (int)n_alive;
+    }
+    if (tid == 0) *s_start = (uint32_t)batch_melkman(Pl, n_alive, out);
+    __syncthreads();
+    return (int)*s_start;
 }
 
 __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restrict__ pts,
@@ -1932,23 +2043,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     __syncthreads();
 
     // ---- the polygon in LDS (everything above is dead now) ----
-    BatchPoly Pl;
-    {
-        unsigned char* b = smem;
-        Pl.x = reinterpret_cast<int32_t*>(b);
-        b += 4 * kBatchPolyMax;
-        Pl.y = reinterpret_cast<int32_t*>(b);
-        b += 4 * kBatchPolyMax;
-        Pl.idx = reinterpret_cast<int32_t*>(b);
-        b += 4 * kBatchPolyMax;
-        Pl.lst = reinterpret_cast<uint16_t*>(b);
-        b += 2 * kBatchPolyMax;
-        Pl.dq = reinterpret_cast<uint16_t*>(b);
-        b += 2 * (2 * kBatchPolyMax + 8);
-        Pl.reg = b;
-        b += kBatchPolyMax;
-        Pl.alive = b;
-    }
+    const BatchPoly Pl = poly_view(smem);
     const uint32_t npoly = nchain + 4;
     uint32_t rbase[4];  // polygon position of E_q
     {
@@ -1989,67 +2084,142 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     }
     __syncthreads();
 
-    // ---- pre-hull rounds; the convex case written out in parallel ----
-    auto compact_poly = [&]() -> uint32_t {
-        constexpr int kPer = kBatchPolyMax / kBatchBlock;
-        uint32_t mine = 0;
+    // ---- pre-hull rounds, the finish ----
+    const int h = poly_finish(Pl, npoly, rbase[1], out_idx + base, scratch, &s_flag, &s_ext, &s_start);
+    if (tid == 0) out_counts[set] = h < 0 ? kBatchRedo : h;
+}
+
+// ---------------------------------------------------------------------------
+// Step 7 on the device for the single-hull path (Section 2.1.3): one
+// workgroup assembles the polygon [P_minx, R1, P_miny, R2, P_maxx, R3,
+// P_maxy, R4] from k_chain's device copy of its output (per 1024-position
+// segment and region, the kept points at the segment's start) and finishes
+// it as the batched
+// kernel does (poly_finish), writing the hull into the caller's buffers.
+//   pass 1  a scan over the segments' counts: a table of the non-empty
+//           segments (segment, first polygon rank, cumulative region counts)
+//           and the points per region;
+//   pass 2  each kept point finds its segment by binary search in the table
+//           and goes to its polygon position (its rank plus the extreme
+//           points before its region).
+// A polygon of more than kBatchPolyMax vertices, or one that Melkman cannot
+// finish in LDS, is left to the host (fin_done = 0 in the header).
+// ---------------------------------------------------------------------------
+struct SegEnt {
+    uint32_t sg, pre;  // segment, rank of its first kept point
+    uint16_t cum[4];   // kept points in regions <= q inside the segment
+};
+constexpr size_t kFinishLds = kPolyBytes + sizeof(SegEnt) * (size_t)kBatchPolyMax;
+
+__global__ __launch_bounds__(kBatchBlock) void k_finish(const DevHeader* __restrict__ hdr,
+                                                        const uint32_t* __restrict__ segcnt,
+                                                        const PolyRec* __restrict__ kept,
+                                                        int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count,
+                                                        DevHeader* __restrict__ host_hdr)
+{
+    __shared__ __align__(16) unsigned char smem[kFinishLds];
+    __shared__ uint32_t scratch[kBatchWaves];
+    __shared__ uint32_t s_flag, s_ext, s_start, s_reg[4];
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    SegEnt* const tab = reinterpret_cast<SegEnt*>(smem + kPolyBytes);
+    if (hdr->err) {
+        if (tid == 0) host_hdr->fin_done = 0;
+        return;
+    }
+    const uint32_t chain = hdr->chain;
+    const uint32_t nseg = (chain + kSeg - 1) / kSeg;
+    if (tid < 4) s_reg[tid] = 0;
+    __syncthreads();
+
+    // ---- pass 1: the non-empty segments ----
+    uint32_t total = 0, nt = 0, reg[4] = {0, 0, 0, 0};
+    bool fits = true;
+    for (uint32_t c0 = 0; c0 < nseg; c0 += kBatchBlock) {
+        const uint32_t sg = c0 + tid;
+        uint32_t c[4] = {0, 0, 0, 0};
+        if (sg < nseg) {
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t i = tid * kPer + k;
-            mine += (i < npoly && Pl.alive[i]) ? 1u : 0u;
+            for (int q = 0; q < 4; ++q) c[q] = segcnt[4 * sg + q];
         }
-        uint32_t n_alive;
-        uint32_t o = block_excl_sum<kBatchWaves>(mine, scratch, n_alive);
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t i = tid * kPer + k;
-            if (i < npoly && Pl.alive[i]) Pl.lst[o++] = (uint16_t)i;
-        }
-        __syncthreads();
-        return n_alive;
-    };
-    uint32_t n_alive = compact_poly();
-    bool convex = false;
-    for (int round = 0; round < kBatchRounds; ++round) {
-        if (tid == 0) {
-            s_flag = 0;
-            s_ext = 0;
-        }
-        __syncthreads();
-        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
-            const uint32_t u = Pl.lst[p == 0 ? n_alive - 1 : p - 1], i = Pl.lst[p],
-                           c = Pl.lst[p + 1 == n_alive ? 0 : p + 1];
-            if (turn_xy(Pl, u, i, c) <= 0) {
-                if (Pl.reg[i] < 4) {
-                    Pl.alive[i] = 0;
-                    s_flag = 1;
-                } else {
-                    s_ext = 1;
-                }
-            }
-        }
-        __syncthreads();
-        const bool removed = s_flag != 0, ext_flat = s_ext != 0;
-        if (!removed) {
-            convex = !ext_flat && n_alive >= 3;
+        const uint32_t tot = c[0] + c[1] + c[2] + c[3];
+        uint32_t all, nz;
+        const uint32_t ex = block_excl_sum<kBatchWaves>(tot, scratch, all);
+        const uint32_t at = block_excl_sum<kBatchWaves>(tot ? 1u : 0u, scratch, nz);
+        if (total + all + 4 > (uint32_t)kBatchPolyMax) {  // the same in every thread
+            fits = false;
             break;
         }
-        n_alive = compact_poly();
+        if (tot) {
+            SegEnt e;
+            e.sg = sg;
+            e.pre = total + ex;
+            e.cum[0] = (uint16_t)c[0];
+            e.cum[1] = (uint16_t)(c[0] + c[1]);
+            e.cum[2] = (uint16_t)(c[0] + c[1] + c[2]);
+            e.cum[3] = (uint16_t)tot;
+            tab[nt + at] = e;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reg[q] += c[q];
+        total += all;
+        nt += nz;
     }
-    if (convex) {
-        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
-            if (Pl.lst[p] == rbase[1]) s_start = p;
+    if (!fits) {
+        if (tid == 0) host_hdr->fin_done = 0;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t v = wave_sum(reg[q]);
+        if (lane == 0 && v) atomicAdd(&s_reg[q], v);
+    }
+    __syncthreads();
+
+    // ---- pass 2: the polygon ----
+    BatchPoly Pl = poly_view(smem);
+    uint32_t rbase[4];  // polygon position of E_q
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rbase[q] = acc;
+            acc += 1 + s_reg[q];
         }
-        __syncthreads();
-        const uint32_t start = s_start;
-        for (uint32_t p = tid; p < n_alive; p += kBatchBlock) {
-            const uint32_t o = p >= start ? p - start : p + n_alive - start;
-            out_idx[base + o] = Pl.idx[Pl.lst[p]];
+    }
+    if (tid < 4) {
+        const uint32_t q = tid, o = q == 0 ? rbase[0] : q == 1 ? rbase[1] : q == 2 ? rbase[2] : rbase[3];
+        Pl.x[o] = (int32_t)hdr->ext_x[q];
+        Pl.y[o] = (int32_t)hdr->ext_y[q];
+        Pl.idx[o] = (int32_t)hdr->ext_idx[q];
+        Pl.reg[o] = 4;
+        Pl.alive[o] = 1;
+    }
+    for (uint32_t p = tid; p < total; p += kBatchBlock) {
+        uint32_t lo = 0, hi = nt;  // the last entry with pre <= p
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (tab[mid].pre <= p) lo = mid;
+            else hi = mid;
         }
-        if (tid == 0) out_counts[set] = (int32_t)n_alive;
-    } else if (tid == 0) {
-        const int h = batch_melkman(Pl, n_alive, out_idx + base);
-        out_counts[set] = h < 0 ? kBatchRedo : h;
+        const SegEnt e = tab[lo];
+        const uint32_t j = p - e.pre;
+        const uint32_t q = j < e.cum[0] ? 0u : j < e.cum[1] ? 1u : j < e.cum[2] ? 2u : 3u;
+        const uint32_t at = e.sg * kSeg + j;
+        const PolyRec r = kept[at];
+        const uint32_t o = p + q + 1;
+        Pl.x[o] = r.x;
+        Pl.y[o] = r.y;
+        Pl.idx[o] = r.idx;
+        Pl.reg[o] = (uint8_t)q;
+        Pl.alive[o] = 1;
+    }
+    __syncthreads();
+    const int h = poly_finish(Pl, total + 4, rbase[1], out_idx, scratch, &s_flag, &s_ext, &s_start);
+    if (tid == 0) {
+        if (h >= 0) *out_count = h;
+        host_hdr->fin_hull = h;
+        for (int q = 0; q < 4; ++q) host_hdr->fin_w2[q] = s_reg[q];
+        host_hdr->fin_done = h >= 0 ? 1u : 0u;
     }
 }
 
@@ -2103,6 +2273,8 @@ struct Workspace {
     std::vector<int32_t> xy, idx;   // finish input
     std::vector<PolyRec> spill;     // chain records beyond the pinned buffer
     PolyRec* dev_spill = nullptr;   // device: chain records beyond the pinned buffer
+    PolyRec* dev_kept = nullptr;    // device copies of the kept chain points and
+    uint32_t* dev_segcnt = nullptr; // their per-segment counts (the device finish)
     uint32_t* h_segcnt = nullptr;   // pinned, device-visible: kept points per segment and region
     uint32_t* h_segcnt_dev = nullptr;
     size_t h_segcnt_cap = 0;        // segments
@@ -2160,7 +2332,8 @@ size_t device_bytes(size_t cap)
     b += align_up(sizeof(uint32_t) * rc, 256) + align_up(sizeof(u64) * rc, 256);
     b += 2 * align_up(sizeof(uint32_t) * rc, 256);
     b += 2 * align_up(sizeof(u64) * rc, 256);
-    b += 2 * align_up(sizeof(PolyRec) * cap, 256);
+    b += 3 * align_up(sizeof(PolyRec) * cap, 256);
+    b += align_up(sizeof(uint32_t) * 4 * (cap / kSeg + 1), 256);
     return b;
 }
 
@@ -2232,6 +2405,8 @@ int ensure_device(Workspace& w, size_t n)
     for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
     w.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
     w.dev_spill = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    w.dev_kept = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    w.dev_segcnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * (cap / kSeg + 1)));
     return CH_OK;
 }
 
@@ -2316,10 +2491,13 @@ int record(Workspace& w, int k)
 }
 
 // Steps 1-6 on the device; the chains end in w.h_chain (and w.spill), the
-// counts in w.h_hdr.  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
+// counts in w.h_hdr.  With fin_idx, k_finish then finishes the hull on the
+// device into fin_idx / fin_count when the polygon fits its workgroup
+// (h_hdr->fin_done).  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
 // 2 | k_cand (+ k_count_regions) | 3 | sort | 4 | SPA + chains | 5 |
-// copy-out | 6.
-int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
+// k_finish | 6.
+int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
+                   int32_t* fin_count = nullptr)
 {
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
@@ -2347,12 +2525,17 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats)
                                  w.hdr, w.bk, w.dev_chain));
     CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kChainGrid), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
                                  w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill, w.h_segcnt_dev, w.h_hdr_dev,
-                                 stats ? 0 : 1));
+                                 stats ? 0 : 1, w.dev_kept, w.dev_segcnt));
     CH_TRY(record(w, 5));
+    if (fin_idx) {
+        CH_LAUNCH(hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBatchBlock), 0, s, w.hdr, w.dev_segcnt, w.dev_kept,
+                                     fin_idx, fin_count, w.h_hdr_dev));
+    }
     CH_TRY(record(w, 6));
     CH_TRY(hipStreamSynchronize(s));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
+    if (fin_idx && w.h_hdr->fin_done) return CH_OK;  // the hull is written
     // kept chain points sit below the chain length
     const size_t m = w.h_hdr->chain;
     w.spill.clear();
@@ -2433,7 +2616,7 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
     st->polygon = w.w2[0] + w.w2[1] + w.w2[2] + w.w2[3] + 4;
     if (g_timing && w.events) {
         // stage slots: 0 sample + staircases, 1 k_stream, 2 k_cand, 3 sort,
-        // 4 SPA + chains, 5 copy-out (6 is unused, 7 the host finish)
+        // 4 SPA + chains, 5 device finish (6 is unused, 7 the host finish)
         for (int k = 0; k < 6; ++k) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
@@ -2459,7 +2642,19 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     }
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0));  // after the device part: sized by its capacity
-    rc = run_preprocess(*w, points, (uint32_t)n, false);
+    rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
+    if (rc == CH_OK && w->h_hdr->fin_done) {
+        // finished on the device: the hull is in out_idx / out_count
+        for (int q = 0; q < 4; ++q) {
+            w->w2[q] = w->h_hdr->fin_w2[q];
+            w->s2[q] = w->h_hdr->s2[q];
+        }
+        w->chain = w->h_hdr->chain;
+        fill_stats(*w, n, &st, false);
+        st.hull = w->h_hdr->fin_hull;
+        st.device_finish = 1;
+        return CH_OK;
+    }
     int64_t h = 0;
     if (rc == CH_OK) {
         const auto t0 = std::chrono::steady_clock::now();
