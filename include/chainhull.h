@@ -189,6 +189,24 @@ const char* chainhull_strerror(int status);
  * called while another call is running. */
 void chainhull_release(void);
 
+/*
+ * chainhull_spa_chunked: the divide-and-conquer SPA that the paper
+ * implements (Section 2.2.2; its limitation, Section 4.3), for
+ * discard-effectiveness experiments; the hull path runs the exact rule.
+ *   k2_sorted  device memory, m uint32: one region's k2 values in its sorted
+ *              order (Table 1, in the region's frame).
+ *   sigma      k2 of the region's first point.
+ *   chunk      subset length, >= 1: subset j is points [j*chunk, (j+1)*chunk).
+ *   keep       device memory, m bytes: 1 where the point survives.
+ * Each subset applies the rule of Figure 2 on its own (a point survives iff
+ * its k2 is below the subset's running threshold); subset 0 starts from
+ * sigma, a later subset keeps its first point and starts from it.  With
+ * chunk >= m this is the exact SPA.  Stream-ordered, no synchronisation.
+ * Returns CH_OK, CH_EINVAL or CH_EHIP.
+ */
+int chainhull_spa_chunked(const uint32_t* k2_sorted, int64_t m, uint32_t sigma, int64_t chunk, uint8_t* keep,
+                          void* stream);
+
 /* Free the cached workspace of one stream on the current device (device and
  * pinned host memory).  No call on that stream may be running.  Returns
  * CH_OK (also when the stream has no workspace). */

@@ -173,16 +173,41 @@ def spa_keep_loop(k2_sorted, sigma: int) -> list:
     return keep
 
 
+def spa_keep_chunked(k2_sorted: np.ndarray, sigma: int, chunk: int) -> np.ndarray:
+    """The divide-and-conquer variant of SPA that the paper implements
+    (Section 2.2.2; its limitation in Section 4.3): the region's sorted
+    points are split into consecutive subsets of ``chunk`` points, and each
+    subset is checked on its own with the rule of Figure 2, in parallel.
+
+    Reading (the paper does not say how a subset starts): the first subset
+    starts from the region's first point (threshold ``sigma``), as the whole
+    region would; a later subset knows no earlier point of the chain, so its
+    first point is kept and starts its threshold.  With one subset this is
+    exactly ``spa_keep``; with smaller subsets it keeps a superset.
+    """
+    k2 = np.asarray(k2_sorted, dtype=np.int64)
+    m = k2.shape[0]
+    keep = np.zeros(m, dtype=bool)
+    if chunk < 1:
+        raise ValueError("chunk must be positive")
+    for s0 in range(0, m, chunk):
+        part = k2[s0:s0 + chunk]
+        start = sigma if s0 == 0 else np.iinfo(np.int64).max
+        keep[s0:s0 + chunk] = spa_keep(part, start)
+    return keep
+
+
 # --- Steps 5-6: chains and the simple polygon ---
 
-def simple_polygon(X, Y, ext: dict, code: np.ndarray):
+def simple_polygon(X, Y, ext: dict, code: np.ndarray, chunk: int | None = None):
     """Chains of the four regions joined counter-clockwise.
 
     Returns ``(poly_idx, chains, s1, s2)``: the polygon
     [P_minx, R1 chain, P_miny, R2 chain, P_maxx, R3 chain, P_maxy, R4 chain]
     as point indices with consecutive coincident vertices dropped (cyclic),
     the per-region kept indices, and per-region round-1 and SPA survivor
-    counts.
+    counts.  With ``chunk``, SPA runs in subsets of that many points
+    (``spa_keep_chunked``) instead of over the whole region.
     """
     n = X.shape[0]
     all_idx = np.arange(n, dtype=np.int64)
@@ -193,7 +218,7 @@ def simple_polygon(X, Y, ext: dict, code: np.ndarray):
         order = sort_region(sel, k1, k2)
         first, _ = region_endpoints(r, ext)
         sigma = int(frame(r, X[first:first + 1], Y[first:first + 1])[1][0])
-        keep = spa_keep(k2[order], sigma)
+        keep = spa_keep(k2[order], sigma) if chunk is None else spa_keep_chunked(k2[order], sigma, chunk)
         chains[r] = sel[order][keep]
         s1[r] = int(sel.shape[0])
         s2[r] = int(keep.sum())
@@ -278,15 +303,34 @@ def rotate_to_lowest(hull, X, Y) -> list:
     return list(hull[start:]) + list(hull[:start])
 
 
-def cudachain(points) -> dict:
-    """All seven steps.  Returns every intermediate and the hull indices."""
+def region_sequences(points) -> dict:
+    """Per region r: (k2 of its points in sorted order, the k2 of its first
+    point), the input of SPA (steps 1-4)."""
+    X, Y = to_int(points)
+    ext = extreme_points(X, Y)
+    code, _ = regions(X, Y, ext)
+    out = {}
+    all_idx = np.arange(X.shape[0], dtype=np.int64)
+    for r in REGIONS:
+        sel = all_idx[code == r]
+        k1, k2 = frame(r, X[sel], Y[sel])
+        order = sort_region(sel, k1, k2)
+        first, _ = region_endpoints(r, ext)
+        sigma = int(frame(r, X[first:first + 1], Y[first:first + 1])[1][0])
+        out[r] = (k2[order], sigma)
+    return out
+
+
+def cudachain(points, chunk: int | None = None) -> dict:
+    """All seven steps.  Returns every intermediate and the hull indices.
+    ``chunk``: run SPA in subsets (the paper's divide-and-conquer variant)."""
     X, Y = to_int(points)
     n = X.shape[0]
     if n == 0:
         return {"n": 0, "hull": np.zeros(0, np.int32)}
     ext = extreme_points(X, Y)
     code, outside = regions(X, Y, ext)
-    poly, chains, s1, s2 = simple_polygon(X, Y, ext, code)
+    poly, chains, s1, s2 = simple_polygon(X, Y, ext, code, chunk)
     hull = rotate_to_lowest(melkman(poly, X, Y), X, Y)
     return {
         "n": n,

@@ -22,7 +22,7 @@ CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4,
 # C entry points declared in include/chainhull.h
 EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_host",
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
-           "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes",
+           "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes", "chainhull_spa_chunked",
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
            "chainhull_server_stats", "chainhull_server_destroy")
 
@@ -129,6 +129,8 @@ def lib():
     L.chainhull_strerror.restype = ctypes.c_char_p
     L.chainhull_release.argtypes = []
     L.chainhull_release.restype = None
+    L.chainhull_spa_chunked.argtypes = [vp, i64, ctypes.c_uint32, i64, vp, vp]
+    L.chainhull_spa_chunked.restype = ctypes.c_int
     L.chainhull_release_stream.argtypes = [vp]
     L.chainhull_release_stream.restype = ctypes.c_int
     L.chainhull_server_create.argtypes = [i32, ctypes.c_size_t, ctypes.POINTER(vp)]
@@ -260,6 +262,23 @@ def release() -> None:
 
 def workspace_bytes(n: int) -> int:
     return int(lib().chainhull_workspace_bytes(int(n)))
+
+
+def spa_chunked(k2_sorted, sigma: int, chunk: int, stream=None):
+    """The paper's SPA in subsets of ``chunk`` points over one region's
+    sorted k2 values (a CUDA int32 tensor holding values in [0, 2^23)).
+    Returns a bool tensor of survivors."""
+    import torch
+    if not isinstance(k2_sorted, torch.Tensor) or not k2_sorted.is_cuda or k2_sorted.dtype != torch.int32:
+        raise TypeError("k2_sorted must be a CUDA int32 tensor")
+    k2 = k2_sorted.contiguous()
+    m = k2.numel()
+    keep = torch.empty(max(m, 1), dtype=torch.uint8, device=k2.device)
+    with torch.cuda.device(k2.device):
+        rc = lib().chainhull_spa_chunked(k2.data_ptr(), m, int(sigma), int(chunk), keep.data_ptr(),
+                                         _stream_ptr(stream))
+    _check(rc, "chainhull_spa_chunked")
+    return keep[:m].bool()
 
 
 class Server:

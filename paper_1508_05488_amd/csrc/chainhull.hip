@@ -2223,6 +2223,31 @@ __global__ __launch_bounds__(kBatchBlock) void k_finish(const DevHeader* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// SPA in subsets (Section 2.2.2; the limitation of Section 4.3): the
+// divide-and-conquer variant that the paper implements, kept for the
+// discard-effectiveness experiments (the path itself runs the exact rule).
+// Thread t checks subset t, `chunk` consecutive points of a region's sorted
+// k2 sequence, with the rule of Figure 2: subset 0 starts from the region's
+// first point (sigma), a later subset from its own first point, which it
+// keeps.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_spa_chunked(const uint32_t* __restrict__ k2, uint32_t m, uint32_t sigma,
+                                                        uint32_t chunk, uint8_t* __restrict__ keep)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t s0 = t * chunk;
+    if (s0 >= m) return;
+    const uint32_t e = (uint32_t)min((uint64_t)m, s0 + chunk);
+    u64 thr = t == 0 ? (u64)sigma : ~0ull;
+    for (uint32_t i = (uint32_t)s0; i < e; ++i) {
+        const uint32_t v = k2[i];
+        const bool k = (u64)v < thr;
+        keep[i] = k ? 1 : 0;
+        if (k) thr = v;
+    }
+}
+
 // The finished hull, from pinned host memory into the caller's buffers.  The
 // host rewrites that memory between calls, so it is read with system-scope
 // loads, which no stale cache line can serve.
@@ -2873,6 +2898,20 @@ void chainhull_release(void)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) free_workspace(kv.second);
     g_ws.clear();
+}
+
+int chainhull_spa_chunked(const uint32_t* k2_sorted, int64_t m, uint32_t sigma, int64_t chunk, uint8_t* keep,
+                          void* stream)
+{
+    if (m < 0 || m > INT32_MAX || chunk < 1 || (m > 0 && (!k2_sorted || !keep))) return CH_EINVAL;
+    if (m == 0) return CH_OK;
+    const int64_t subsets = (m + chunk - 1) / chunk;
+    const uint32_t grid = (uint32_t)((subsets + kBlock - 1) / kBlock);
+    const uint32_t c = (uint32_t)std::min<int64_t>(chunk, m);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CH_LAUNCH(hipLaunchKernelGGL(k_spa_chunked, dim3(grid), dim3(kBlock), 0, st, k2_sorted, (uint32_t)m, sigma, c,
+                                 keep));
+    return CH_OK;
 }
 
 int chainhull_release_stream(void* stream)

@@ -146,6 +146,23 @@ def batched_sets(num_sets: int, lo: int, hi: int, seed: int):
     return pts, offsets, dists
 
 
+def tie_free(dist: str, n: int, seed: int) -> np.ndarray:
+    """``dist`` (square, disk or gaussian) with every x and every y distinct:
+    points that repeat an earlier point's x or y are dropped and more are
+    drawn (inputs for SPA experiments that must avoid key ties)."""
+    rng = rng_for(seed)
+    have = np.zeros((0, 2), np.float32)
+    draw = 2 * n + 64
+    while have.shape[0] < n:
+        cand = np.concatenate([have, _GEN[dist](draw, rng)])
+        _, ix = np.unique(cand[:, 0], return_index=True)
+        cand = cand[np.sort(ix)]
+        _, iy = np.unique(cand[:, 1], return_index=True)
+        have = cand[np.sort(iy)]
+        draw *= 2
+    return np.ascontiguousarray(have[:n])
+
+
 def small_lattice(n: int, k: int, rng: np.random.Generator) -> np.ndarray:
     """Points with coordinates in ``[0, k)``: heavy duplicates and collinearity."""
     xy = rng.integers(0, k, size=(n, 2), dtype=np.int64)

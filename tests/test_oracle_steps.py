@@ -224,3 +224,46 @@ def test_steps_invariants_on_adversarial_circle():
     res = steps.cudachain(pts)
     check_hull(pts, res["hull"])
     assert res["hull"].tolist() == oracle.hull(pts).tolist()
+
+
+# --- the paper's divide-and-conquer SPA (Section 2.2.2, Section 4.3) ---
+
+def test_spa_chunked_pins():
+    rng = np.random.default_rng(91)
+    for _ in range(200):
+        m = int(rng.integers(0, 40))
+        k2 = rng.integers(0, 30, size=m)
+        sigma = int(rng.integers(0, 35))
+        exact = steps.spa_keep(k2, sigma)
+        # one subset: the exact rule
+        assert np.array_equal(steps.spa_keep_chunked(k2, sigma, max(m, 1)), exact)
+        for chunk in (1, 2, 3, 7):
+            got = steps.spa_keep_chunked(k2, sigma, chunk)
+            # a superset of the exact survivors
+            assert np.all(got[exact])
+            # each subset by the literal loop, a later one from its first point
+            want = []
+            for s0 in range(0, m, chunk):
+                part = list(k2[s0:s0 + chunk])
+                if s0 == 0:
+                    want += steps.spa_keep_loop(part, sigma)
+                else:
+                    want += [True] + steps.spa_keep_loop(part[1:], part[0])
+            assert got.tolist() == want
+        if m:
+            one = steps.spa_keep_chunked(k2, sigma, 1)
+            assert one[0] == (k2[0] < sigma) and bool(np.all(one[1:]))
+
+
+@pytest.mark.parametrize("dist", ["square", "disk", "gaussian"])
+def test_chunked_spa_keeps_the_hull_on_tie_free_inputs(dist):
+    # without ties in x or y every chain stays monotone in k1, so the polygon
+    # is still simple and Melkman still returns the hull
+    pts = wl.tie_free(dist, 3000, 92)
+    assert np.unique(pts[:, 0]).size == pts.shape[0] and np.unique(pts[:, 1]).size == pts.shape[0]
+    want = oracle.hull(pts)
+    for chunk in (1, 2, 5, 16, 100):
+        r = steps.cudachain(pts, chunk=chunk)
+        assert np.array_equal(r["hull"], want), chunk
+        exact = steps.cudachain(pts)
+        assert sum(r["s2"].values()) >= sum(exact["s2"].values())
