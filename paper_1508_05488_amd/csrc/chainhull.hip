@@ -1389,35 +1389,45 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
 // are sets larger than kBatchMaxSet (one workgroup would stream them for a
 // long time while the rest of the device idles).
 // ---------------------------------------------------------------------------
-constexpr int kBatchBlock = 1024;
+constexpr int kBatchBlock = 512;                                   // two workgroups per CU
 constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kBatchWavesPerSimd = 4;                              // 128 VGPRs: two workgroups fit
 constexpr int kBatchUnroll = 2;                                    // float4 loads per thread and round
 constexpr uint32_t kBatchRound = 2u * kBatchUnroll * kBatchBlock;  // points per round
-constexpr int kBatchList = 16384;                                  // listed points per set
+constexpr int kBatchList = 8192;                                   // listed points per set
 constexpr int kBatchPerList = kBatchList / kBatchBlock;
-constexpr int kBatchCand = 8192;                                   // sort records per set
-constexpr int kBatchPolyMax = 4096;                                // polygon vertices per set
+constexpr int kBatchCand = 4096;                                   // sort records per set
+constexpr int kBatchPolyMax = 3584;                                // polygon vertices per set
+constexpr int kBatchSlots = 512;                                   // k1 slots per region (exact filter)
+constexpr int kBatchSlotShift = 23 - 9;                            // log2(kBatchSlots) = 9
+constexpr int kBatchPosBits = 14;                                  // list position in a sort key
+static_assert(kBatchSlots == 1 << (23 - kBatchSlotShift) && kBatchList <= 1 << kBatchPosBits, "slots");
 constexpr int kBatchChunks = 64, kBatchChunk = 128;                // the first staircase sample
 constexpr int kBatchRounds = 32;                                   // pre-hull rounds at most
 constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger sets: single-hull path
 constexpr int32_t kBatchRedo = INT32_MIN;
 static_assert(kBatchList >= 2 * (int)kBatchRound, "a round must fit beside a compacted list");
 static_assert(kBatchCand / kBatchBlock <= 8 && kBatchPolyMax % kBatchBlock == 0, "per-thread shares");
-// LDS: [staircase u32 x 4S][raw slot minima u32 x 4S][region slot minima
-//      u64 x 4*kSlots][region staircase u32 x 4*kSlots] .. [list u32 x
-//      kBatchList], with the sort keys (u64 x kBatchCand) over everything
-// before the list once the regions are filtered, and the polygon view over
-// everything once the SPA is done.  The staircase sits at offset 0 so that
-// its reads need no base address.
+// LDS: [staircase u32 x 4S][raw slot minima u32 x 4S] [list u32 x
+// kBatchList].  Once the stream is done the region slot minima (u64 x
+// 4*kBatchSlots) and region staircase (u32 x 4*kBatchSlots) take the
+// staircase's place, the sort keys (u64 x kBatchCand) theirs once the
+// regions are filtered, and the polygon view everything once the SPA is
+// done.  The staircase sits at offset 0 so that its reads need no base
+// address.
 constexpr size_t kBatchOffStair = 0;
 constexpr size_t kBatchOffRaw = kBatchOffStair + 4 * 4 * (size_t)kStairSlots;
-constexpr size_t kBatchOffSmin = kBatchOffRaw + 4 * 4 * (size_t)kStairSlots;
-constexpr size_t kBatchOffSexc = kBatchOffSmin + 8 * 4 * (size_t)kSlots;
+constexpr size_t kBatchOffSmin = 0;
+constexpr size_t kBatchOffSexc = kBatchOffSmin + 8 * 4 * (size_t)kBatchSlots;
 constexpr size_t kBatchOffKey = 0;
-constexpr size_t kBatchOffList = kBatchOffKey + 8 * (size_t)kBatchCand;
-constexpr size_t kBatchLds = kBatchOffList + 4 * (size_t)kBatchList;
-static_assert(kBatchOffSexc + 4 * 4 * kSlots <= kBatchOffList, "LDS layout");
-static_assert(16 * kBatchPolyMax + 2 * (2 * kBatchPolyMax + 8) <= (int)kBatchLds, "polygon view");
+constexpr size_t kBatchOffList =
+    std::max(std::max(kBatchOffRaw + 4 * 4 * (size_t)kStairSlots, kBatchOffSexc + 4 * 4 * (size_t)kBatchSlots),
+             8 * (size_t)kBatchCand);
+// (the polygon view may reach past the list: it is built after the list's
+// last read)
+constexpr size_t kBatchLds = std::max(kBatchOffList + 4 * (size_t)kBatchList,
+                                      16 * (size_t)kBatchPolyMax + 2 * (2 * (size_t)kBatchPolyMax + 8));
+static_assert(kBatchLds <= 78 * 1024, "two workgroups per CU");
 
 struct BatchPoly {  // polygon view of the LDS
     int32_t* x;
@@ -1649,7 +1659,7 @@ __device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, 
     return (int)*s_start;
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restrict__ pts,
+__global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(const float* __restrict__ pts,
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ order,
                                                             int32_t* __restrict__ out_idx,
@@ -1889,7 +1899,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     }
     u64* const smin = reinterpret_cast<u64*>(smem + kBatchOffSmin);
     uint32_t* const sexc = reinterpret_cast<uint32_t*>(smem + kBatchOffSexc);
-    for (int e = tid; e < 4 * kSlots; e += kBatchBlock) smin[e] = ~0ull;
+    for (int e = tid; e < 4 * kBatchSlots; e += kBatchBlock) smin[e] = ~0ull;
     __syncthreads();
     if (sq.err) {
         if (tid == 0) out_counts[set] = CH_EDOMAIN;
@@ -1924,7 +1934,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
                 if (q < 4) {
                     uint32_t k1, k2;
                     to_frame(q, X, Y, k1, k2);
-                    atomicMin(&smin[q * kSlots + (k1 >> (23 - kSlotBits))], ((u64)k2 << 23) | k1);
+                    atomicMin(&smin[q * kBatchSlots + (k1 >> kBatchSlotShift)], ((u64)k2 << 23) | k1);
                     rec[k] = ((u64)q << 46) | ((u64)k1 << 23) | k2;
                 }
             }
@@ -1933,29 +1943,40 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     __syncthreads();
     {
         // exclusive prefix minimum per region over its slots, seeded with the
-        // region's first point (waves 4q .. 4q+3 own region q)
-        const uint32_t q = tid / (kSlots / 2), j0 = (tid % (kSlots / 2)) * 2;
-        const u64 m0 = smin[q * kSlots + j0], m1 = smin[q * kSlots + j0 + 1];
-        const uint32_t v0 = m0 == ~0ull ? ~0u : (uint32_t)(m0 >> 23);
-        const uint32_t v1 = m1 == ~0ull ? ~0u : (uint32_t)(m1 >> 23);
-        const uint32_t incl = wave_incl_min(min(v0, v1));
+        // region's first point (a quarter of the threads own each region,
+        // kPer consecutive slots per thread)
+        constexpr uint32_t kPer = 4 * kBatchSlots / kBatchBlock;
+        constexpr uint32_t kThreadsPerRegion = kBatchSlots / kPer, kWavesPerRegion = kThreadsPerRegion / 64;
+        const uint32_t q = tid / kThreadsPerRegion, j0 = (tid % kThreadsPerRegion) * kPer;
+        uint32_t v[kPer];
+        uint32_t mn = ~0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const u64 mk = smin[q * kBatchSlots + j0 + k];
+            v[k] = mk == ~0ull ? ~0u : (uint32_t)(mk >> 23);
+            mn = min(mn, v[k]);
+        }
+        const uint32_t incl = wave_incl_min(mn);
         uint32_t excl = __shfl_up(incl, 1);
         if (lane == 0) excl = ~0u;
         if (lane == 63) scratch[wave] = incl;
         __syncthreads();
-        for (uint32_t w = q * 4; w < wave; ++w) excl = min(excl, scratch[w]);
+        for (uint32_t w = q * kWavesPerRegion; w < wave; ++w) excl = min(excl, scratch[w]);
         excl = min(excl, sq.sigma[q]);
-        sexc[q * kSlots + j0] = excl;
-        sexc[q * kSlots + j0 + 1] = min(excl, v0);
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            sexc[q * kBatchSlots + j0 + k] = excl;
+            excl = min(excl, v[k]);
+        }
         __syncthreads();
     }
-    // survivors become sort keys: record << 14 | list position
+    // survivors become sort keys: record << kBatchPosBits | list position
     uint32_t keep = 0;
 #pragma unroll
     for (int k = 0; k < kBatchPerList; ++k) {
         if (rec[k] != ~0ull) {
             const uint32_t q = (uint32_t)(rec[k] >> 46), k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
-            const uint32_t sl = q * kSlots + (k1 >> (23 - kSlotBits));
+            const uint32_t sl = q * kBatchSlots + (k1 >> kBatchSlotShift);
             const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
             if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) keep |= 1u << k;
         }
@@ -1969,7 +1990,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     u64* const skey = reinterpret_cast<u64*>(smem + kBatchOffKey);
 #pragma unroll
     for (int k = 0; k < kBatchPerList; ++k) {
-        if ((keep >> k) & 1u) skey[at++] = (rec[k] << 14) | (u64)(k * kBatchBlock + tid);
+        if ((keep >> k) & 1u) skey[at++] = (rec[k] << kBatchPosBits) | (u64)(k * kBatchBlock + tid);
     }
     uint32_t P2 = 1;
     while (P2 < nsort) P2 <<= 1;
@@ -1999,7 +2020,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     for (uint32_t k = 0; k < per; ++k) {
         const uint32_t r = tid * per + k;
         if (r < nsort) {
-            const u64 key = skey[r] >> 14;
+            const u64 key = skey[r] >> kBatchPosBits;
             run = min(run, ((3u - (uint32_t)(key >> 46)) << 23) | (uint32_t)(key & kM));
         }
     }
@@ -2009,7 +2030,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
     for (uint32_t k = 0; k < per; ++k) {
         const uint32_t r = tid * per + k;
         if (r >= nsort) break;
-        const u64 key = skey[r] >> 14;
+        const u64 key = skey[r] >> kBatchPosBits;
         const uint32_t q = (uint32_t)(key >> 46), k2 = (uint32_t)(key & kM);
         uint32_t thr = sq.sigma[q];
         if ((pm >> 23) == 3u - q) thr = min(thr, pm & kM);
@@ -2031,10 +2052,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_hull(const float* __restr
         kidx[k] = 0;
         if ((kmask >> k) & 1u) {
             const uint32_t r = tid * per + k;
-            const u64 key = skey[r], rc = key >> 14;
-            uint32_t idx = lidx[(uint32_t)(key & 16383u)];
-            for (uint32_t j = r + 1; j < nsort && (skey[j] >> 14) == rc; ++j)
-                idx = min(idx, lidx[(uint32_t)(skey[j] & 16383u)]);
+            constexpr u64 kPosMask = (1ull << kBatchPosBits) - 1;
+            const u64 key = skey[r], rc = key >> kBatchPosBits;
+            uint32_t idx = lidx[(uint32_t)(key & kPosMask)];
+            for (uint32_t j = r + 1; j < nsort && (skey[j] >> kBatchPosBits) == rc; ++j)
+                idx = min(idx, lidx[(uint32_t)(skey[j] & kPosMask)]);
             krec[k] = rc;
             kidx[k] = idx;
             atomicAdd(&s_rcnt[(uint32_t)(rc >> 46)], 1u);
@@ -2111,7 +2133,7 @@ struct SegEnt {
 };
 constexpr size_t kFinishLds = kPolyBytes + sizeof(SegEnt) * (size_t)kBatchPolyMax;
 
-__global__ __launch_bounds__(kBatchBlock) void k_finish(const DevHeader* __restrict__ hdr,
+__global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(const DevHeader* __restrict__ hdr,
                                                         const uint32_t* __restrict__ segcnt,
                                                         const PolyRec* __restrict__ kept,
                                                         int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count,
