@@ -97,7 +97,7 @@ typedef struct {
  */
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
 /* (Step 7 runs on the device when the polygon left by steps 1-6 and the
- * pre-hull has at most 4096 vertices, on the host otherwise; the result is
+ * pre-hull has at most 3584 vertices, on the host otherwise; the result is
  * the same.) */
 
 /*
