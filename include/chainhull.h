@@ -128,6 +128,29 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets,
                    int32_t* out_idx, int32_t* out_counts, void* stream);
 
+/* The count hull2d_batched_async reports for a set it leaves to the caller
+ * (more than 2^22 points, or beyond the kernel's on-chip capacities): such a
+ * set is computed with hull2d. */
+#define CH_BATCH_REDO (-2147483647 - 1)
+
+/*
+ * hull2d_batched_async: the batched kernel alone, stream-ordered and
+ * allocation-free, so that it can be captured in a HIP graph (Section 2.1
+ * per set, every step on the device).
+ *   points, out_idx  as in hull2d_batched.
+ *   offsets     device memory, num_sets + 1 int64 as in hull2d_batched (they
+ *               must describe `points`; a set with offsets[s+1] < offsets[s]
+ *               or a negative offset gets CH_EINVAL in its count).
+ *   order       device memory, num_sets int32, a permutation of the sets: the
+ *               launch order (larger sets first is fastest); NULL for 0, 1, ..
+ *   out_counts  device memory, num_sets int32: each set's hull size, its
+ *               negative ch_status, or CH_BATCH_REDO for a set left to hull2d.
+ * Returns after queueing one kernel on `stream` (nothing is synchronised or
+ * allocated): CH_OK, CH_EINVAL (bad pointer or num_sets) or CH_EHIP.
+ */
+int hull2d_batched_async(const float* points, const int64_t* offsets, const int32_t* order, int32_t num_sets,
+                         int32_t* out_idx, int32_t* out_counts, void* stream);
+
 /* Counts and timings of the calling thread's last hull2d_batched call. */
 typedef struct {
     int32_t num_sets;     /* sets in the call */

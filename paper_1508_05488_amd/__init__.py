@@ -18,9 +18,10 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libchainhull.so")
 
 CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4, -5
+CH_BATCH_REDO = -(2 ** 31)
 
 # C entry points declared in include/chainhull.h
-EXPORTS = ("hull2d", "hull2d_batched", "chainhull_polygon", "chainhull_finish_host",
+EXPORTS = ("hull2d", "hull2d_batched", "hull2d_batched_async", "chainhull_polygon", "chainhull_finish_host",
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes", "chainhull_spa_chunked",
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
@@ -115,6 +116,8 @@ def lib():
     L.hull2d.restype = ctypes.c_int
     L.hull2d_batched.argtypes = [vp, vp, i32, vp, vp, vp]
     L.hull2d_batched.restype = ctypes.c_int
+    L.hull2d_batched_async.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.hull2d_batched_async.restype = ctypes.c_int
     L.chainhull_polygon.argtypes = [vp, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(ChStats), vp]
     L.chainhull_polygon.restype = ctypes.c_int
     L.chainhull_finish_host.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i64)]
@@ -209,6 +212,25 @@ def hull2d_batched(points, offsets, stream=None):
         _check(rc, "hull2d_batched")
         counts = cnt[:num].cpu().numpy()
     return [out[int(offs[s]): int(offs[s]) + int(counts[s])] for s in range(num)], cnt[:num]
+
+
+def hull2d_batched_async(points, offsets, order, out_idx, out_counts, stream=None) -> int:
+    """The batched kernel alone, queued on the stream (capturable in a
+    graph).  offsets: CUDA int64 [num_sets + 1]; order: CUDA int32
+    [num_sets] or None; out_idx, out_counts: CUDA int32.  Returns the
+    status of the launch."""
+    import torch
+    pts = _device_points(points)
+    for t, dt, name in ((offsets, torch.int64, "offsets"), (out_idx, torch.int32, "out_idx"),
+                        (out_counts, torch.int32, "out_counts")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CUDA {dt} tensor")
+    if order is not None and (not order.is_cuda or order.dtype != torch.int32 or not order.is_contiguous()):
+        raise TypeError("order must be a contiguous CUDA int32 tensor")
+    num = offsets.numel() - 1
+    with torch.cuda.device(pts.device):
+        return lib().hull2d_batched_async(pts.data_ptr(), offsets.data_ptr(), 0 if order is None else order.data_ptr(),
+                                          num, out_idx.data_ptr(), out_counts.data_ptr(), _stream_ptr(stream))
 
 
 def polygon(points, stream=None):

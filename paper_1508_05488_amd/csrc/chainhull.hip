@@ -1663,7 +1663,8 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ order,
                                                             int32_t* __restrict__ out_idx,
-                                                            int32_t* __restrict__ out_counts, uint32_t pts_odd)
+                                                            int32_t* __restrict__ out_counts, uint32_t pts_odd,
+                                                            int32_t num_sets)
 {
     __shared__ __align__(16) unsigned char smem[kBatchLds];
     __shared__ u64 s_ek[kBatchWaves][4];
@@ -1678,9 +1679,20 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / 64);  // a scalar
     const u64 lt = (1ull << lane) - 1ull;
-    const int32_t set = order[blockIdx.x];
-    const int64_t base = offsets[set];
-    const uint32_t m = (uint32_t)(offsets[set + 1] - base);
+    // (order may be absent: set b; offsets are checked here because the
+    // stream-ordered entry point cannot read them on the host)
+    const int32_t set = order ? order[blockIdx.x] : (int32_t)blockIdx.x;
+    if (set < 0 || set >= num_sets) return;
+    const int64_t base = offsets[set], end = offsets[set + 1];
+    if (base < 0 || end < base) {
+        if (threadIdx.x == 0) out_counts[set] = CH_EINVAL;
+        return;
+    }
+    if (end - base > kBatchMaxSet) {
+        if (threadIdx.x == 0) out_counts[set] = kBatchRedo;
+        return;
+    }
+    const uint32_t m = (uint32_t)(end - base);
     const float* const ps = pts + 2 * base;
     const v2f* const p2 = reinterpret_cast<const v2f*>(ps);
     if (m == 0) {
@@ -2811,7 +2823,7 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
             CH_TRY(record(*w, 0));
             const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
             CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
-                                         w->b_offsets, w->b_order, out_idx, out_counts, pts_odd));
+                                         w->b_offsets, w->b_order, out_idx, out_counts, pts_odd, num_sets));
             CH_TRY(record(*w, 1));
             CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
         }
@@ -2847,6 +2859,19 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
     }
     bs.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return first_err;
+}
+
+int hull2d_batched_async(const float* points, const int64_t* offsets, const int32_t* order, int32_t num_sets,
+                         int32_t* out_idx, int32_t* out_counts, void* stream)
+{
+    if (num_sets < 0 || (num_sets > 0 && (!offsets || !out_counts || !points || !out_idx))) return CH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
+    if (num_sets == 0) return CH_OK;
+    const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
+    CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3((uint32_t)num_sets), dim3(kBatchBlock), 0,
+                                 reinterpret_cast<hipStream_t>(stream), points, offsets, order, out_idx, out_counts,
+                                 pts_odd, num_sets));
+    return CH_OK;
 }
 
 int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t* poly_count, ch_stats* stats,
