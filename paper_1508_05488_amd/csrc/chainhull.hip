@@ -334,7 +334,8 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // the region sort and SPA unchanged, so any filter that only drops dominated
 // points may run before them.
 //
-// Sampled staircases.  k_sample takes a strided sample of kSamplePts points
+// Sampled staircases.  k_sample takes a sample of kSamplePts points (64 evenly
+// spaced runs of consecutive points)
 // and records, in each of the four region frames, the smallest k2 per slot of
 // 2^kStairShift k1 values, over all sample points (not only the region's);
 // k_stair turns them into exclusive prefix minima over the slots.  A sample
@@ -387,10 +388,16 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
     __syncthreads();
     uint32_t X[kSamplePerThread], Y[kSamplePerThread];
+    // workgroup b reads a run of kBlock * kSamplePerThread consecutive points
+    // (coalesced), the runs evenly spaced; a smaller input is sampled with
+    // repeats at evenly spaced indices
+    constexpr uint32_t kRun = kBlock * kSamplePerThread;
+    const bool runs = n >= kSamplePts;
+    const uint32_t start = runs ? (uint32_t)(((u64)blockIdx.x * (n - kRun)) / (kSampleBlocks - 1)) : 0u;
 #pragma unroll
     for (int k = 0; k < kSamplePerThread; ++k) {
         const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
-        const uint32_t i = (uint32_t)(((u64)sidx * n) / kSamplePts);
+        const uint32_t i = runs ? start + k * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
         const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
         // out-of-domain values only need to stay in range here: such a call
         // fails with a domain error
