@@ -286,16 +286,19 @@ int chainhull_server_submit(ch_server* s, const float* points, int64_t n, int32_
 
 /* Block until the request completes; its outputs are then written.  *hull
  * (if not NULL) receives the hull size, *latency_ms (if not NULL) the time
- * from submission to completion.  A ticket can be waited for once.  Returns
- * the request's ch_status, or CH_EINVAL for an unknown ticket. */
+ * from submission to completion.  A ticket can be waited for once (by one
+ * thread).  Returns the request's ch_status, or CH_EINVAL for an unknown
+ * ticket or one that another thread is waiting for.  submit, wait and stats
+ * may be called from any threads concurrently. */
 int chainhull_server_wait(ch_server* s, uint64_t ticket, int32_t* hull, double* latency_ms);
 
 /* Copy the server's counters into *out.  Returns CH_OK or CH_EINVAL. */
 int chainhull_server_stats(ch_server* s, ch_server_stats* out);
 
 /* Finish every submitted request, stop the workers and free the server.
- * Requests not yet waited for are discarded (their outputs are written).
- * Returns CH_OK or CH_EINVAL. */
+ * Requests not yet waited for are discarded (their outputs are written).  No
+ * other call on the server may run during or after it.  Returns CH_OK or
+ * CH_EINVAL. */
 int chainhull_server_destroy(ch_server* s);
 
 #ifdef __cplusplus

@@ -55,6 +55,7 @@ struct Request {
     int status = CH_OK;
     int32_t hull = 0;
     bool done = false;
+    bool claimed = false;  // a wait holds it
     Clock::time_point t_submit, t_done;
 };
 
@@ -328,6 +329,8 @@ int chainhull_server_wait(ch_server* s, uint64_t ticket, int32_t* hull, double* 
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return CH_EINVAL;
     Request* r = it->second;
+    if (r->claimed) return CH_EINVAL;  // another thread waits for it
+    r->claimed = true;
     s->cv_done.wait(lk, [&] { return r->done; });
     const int status = r->status;
     if (hull) *hull = r->hull;
