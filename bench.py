@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--batch-sets", type=int, default=BATCH_SETS)
     ap.add_argument("--batch-calls", type=int, default=30)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-other", action="store_true", help="skip the 100K and adversarial single-hull configurations")
     ap.add_argument("--serve-rate", type=float, default=10_000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-workers", type=int, default=4)
@@ -81,6 +82,54 @@ def load_traffic(name: str):
         return float(rec["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def sha16(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measure_other_configs(ch, wl, torch, dev):
+    """The other single-hull configurations: 100K uniform points (latency:
+    median of 21 blocking calls) and 20M adversarial points (10 % on a
+    circle; median of 3 blocking calls, end to end, its finish on the host)."""
+    out = {}
+    for name, dist, n, seed, reps in (("square_100k", "square", 100_000, 1, 21),
+                                      ("adversarial_20m", "adversarial", 20_000_000, 5, 3)):
+        pts = wl.generate(dist, n, seed)
+        d = torch.from_numpy(pts).to(dev)
+        for _ in range(2):
+            ch.hull2d(d)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            h = ch.hull2d(d)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - a)
+        ch.set_timing(True)
+        ch.hull2d(d)
+        torch.cuda.synchronize()
+        ch.set_timing(False)
+        st = ch.last_stats()
+        ms = float(np.median(t)) * 1e3
+        out[name] = {"n": n, "seed": seed, "input_sha256_16": sha16(pts), "ms_median": round(ms, 4),
+                     "mpts_per_s": round(n / ms / 1e3, 1), "hull": int(h.numel()), "polygon": st["polygon"],
+                     "device_finish": st["device_finish"],
+                     "stages_ms": {k: round(v, 4) for k, v in st["ms"].items() if not k.startswith("unused")}}
+        del d
+    torch.cuda.empty_cache()
+    return out
 
 
 def measure_batched(ch, wl, torch, dev, args):
@@ -385,7 +434,10 @@ def main():
             oracle.hull(host[d])
             tc += time.perf_counter() - a
         cpu = {"value": round(n * len(DISTS) / tc / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-               "sample": f"one single-threaded oracle run on each of the three {n}-point inputs ({tc:.1f} s)"}
+               "sample": f"one single-threaded oracle run on each of the three {n}-point inputs ({tc:.1f} s); "
+                         f"host CPU {cpu_model()}, {os.cpu_count()} logical CPUs"}
+
+    other = None if args.no_other else measure_other_configs(ch, wl, torch, dev)
 
     batched = None
     if not args.no_batched:
@@ -419,7 +471,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"exact 2D hull, {n} integer-valued f32 points in [0,2^23), "
                                "three inputs per step: uniform square, uniform disk, Gaussian sigma 2^20",
-                   "n_points": n, "inputs_per_step": len(DISTS), "seeds": [s for _, s in DISTS]},
+                   "n_points": n, "inputs_per_step": len(DISTS), "seeds": [s for _, s in DISTS],
+                   "input_sha256_16": {d: sha16(host[d]) for d, _ in DISTS}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "finish")
@@ -427,6 +480,7 @@ def main():
         "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
         "preprocess_b_alg_frac": round(pre_frac, 4),
         "per_distribution": per_dist,
+        "other_configs": other,
         "batched": batched,
         "serving": serving,
     }
