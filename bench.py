@@ -398,7 +398,7 @@ def main():
             "hull": s["hull"], "s1": int(sum(s["s1"])), "open": s["open"], "candidates": s["candidates"],
             "s2": int(sum(s["s2"])),
         }
-        for key in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "finish"):
+        for key in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish"):
             per_dist[d][key + "_ms"] = float(np.mean([x["ms"][key] for x in stats[d]]))
 
     # counts of the discard rounds (the stats mode of the library counts the
@@ -475,7 +475,7 @@ def main():
                    "input_sha256_16": {d: sha16(host[d]) for d, _ in DISTS}},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "finish")
+        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")
                       for v in [stage_ms[k]]},
         "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
         "preprocess_b_alg_frac": round(pre_frac, 4),

@@ -72,8 +72,9 @@ typedef struct {
      * (and, in chainhull_polygon, the round-1 counts), 3 region sort, first
      * level (records placed by bucket), 4 region sort, second level + SPA +
      * chain concatenation (+ pre-hull in hull2d), 5 the device finish of
-     * hull2d, 7 the host finish (wall clock; 0 when the device finished);
-     * 6 is unused. */
+     * hull2d; the host finish of hull2d in wall-clock time, 0 when the
+     * device finished: 6 the polygon gathered on the device into pinned
+     * memory (one workgroup) and waited for, 7 Melkman's algorithm on it. */
     float ms[8];
     int32_t device_finish;  /* 1 when hull2d finished step 7 on the device */
     int32_t reserved;

@@ -27,7 +27,7 @@ EXPORTS = ("hull2d", "hull2d_batched", "hull2d_batched_async", "chainhull_polygo
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
            "chainhull_server_stats", "chainhull_server_destroy")
 
-STAGES = ("sample", "stream", "cand", "sort", "spa", "finish_dev", "unused6", "finish")
+STAGES = ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")
 
 
 class ChainHullError(RuntimeError):

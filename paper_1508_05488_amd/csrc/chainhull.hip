@@ -97,7 +97,8 @@ struct DevHeader {
     uint32_t fin_done;   // 1 when the device finish wrote the hull
     int32_t fin_hull;    // its size
     uint32_t fin_w2[4];  // polygon vertices per region it finished from
-    uint32_t pad[9];
+    uint32_t gat_count;  // polygon vertices k_gather wrote for the host finish
+    uint32_t pad[8];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -1173,8 +1174,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
 // non-vertices go, so the hull of the polygon the finish scans is
 // unchanged; the frames are rotations, so turns keep their sign.
 //
-// Segment s keeps its points at [s*kSeg, ...) of the host chain buffer and
-// writes how many of each region it kept to segcnt[4s .. 4s+3].  Workgroup
+// Segment s keeps its points at [s*kSeg, ...) of the device copy (and, when
+// host_chain is given, of the host chain buffer) and writes how many of
+// each region it kept to dev_segcnt[4s .. 4s+3] (and segcnt).  Workgroup
 // 0 also publishes the SPA survivor counts per region.
 // ---------------------------------------------------------------------------
 constexpr int kSeg = 1024;
@@ -1338,14 +1340,16 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
             const uint32_t i = lst[p];
             const PolyRec r = dev_chain[at[i]];
             const uint32_t o = base + p;
-            if (o < host_cap) host_chain[o] = r;
-            else spill[o - host_cap] = r;
-            dev_kept[o] = r;  // the device finish reads these
+            if (host_chain) {  // (the host polygon of chainhull_polygon)
+                if (o < host_cap) host_chain[o] = r;
+                else spill[o - host_cap] = r;
+            }
+            dev_kept[o] = r;  // k_finish and k_gather read these
             atomicAdd(&s_cnt[reg[i]], 1u);
         }
         __syncthreads();
         if (tid < 4) {
-            segcnt[4 * sg + tid] = s_cnt[tid];
+            if (segcnt) segcnt[4 * sg + tid] = s_cnt[tid];
             dev_segcnt[4 * sg + tid] = s_cnt[tid];
         }
         __syncthreads();
@@ -2265,6 +2269,109 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
 }
 
 // ---------------------------------------------------------------------------
+// The host finish's input when k_finish leaves the polygon to the host: one
+// workgroup gathers the polygon [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy,
+// R4] from k_chain's device copy (per segment and region, the kept points at
+// the segment's start) into pinned host memory, densely, as (x, y) pairs and
+// indices, so that the host reads one contiguous array.
+//   pass 1  the kept points per region (the polygon position of each
+//           extreme point);
+//   pass 2  per run of kBatchBlock segments, an exclusive scan of their
+//           counts; each kept point of the run finds its segment by binary
+//           search and goes to its polygon position.
+// The header receives the vertex count (gat_count; 0 when it exceeds `cap`)
+// and the per-region counts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBatchBlock) void k_gather(const DevHeader* __restrict__ hdr,
+                                                        const uint32_t* __restrict__ segcnt,
+                                                        const PolyRec* __restrict__ kept, int32_t* __restrict__ out_xy,
+                                                        int32_t* __restrict__ out_idx, uint32_t cap,
+                                                        DevHeader* __restrict__ host_hdr)
+{
+    __shared__ uint32_t s_pre[kBatchBlock], s_cum[kBatchBlock][4], s_sg[kBatchBlock];
+    __shared__ uint32_t scratch[kBatchWaves];
+    __shared__ uint32_t s_reg[4];
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t chain = hdr->chain;
+    const uint32_t nseg = (chain + kSeg - 1) / kSeg;
+    if (tid < 4) s_reg[tid] = 0;
+    __syncthreads();
+
+    // ---- pass 1: points per region ----
+    uint32_t reg[4] = {0, 0, 0, 0};
+    for (uint32_t sg = tid; sg < nseg; sg += kBatchBlock) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reg[q] += segcnt[4 * sg + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t v = wave_sum(reg[q]);
+        if (lane == 0 && v) atomicAdd(&s_reg[q], v);
+    }
+    __syncthreads();
+    uint32_t rbase[4], npoly = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        rbase[q] = npoly;
+        npoly += 1 + s_reg[q];
+    }
+    if (npoly > cap) {  // the same in every thread
+        if (tid == 0) host_hdr->gat_count = 0;
+        return;
+    }
+    if (tid < 4) {
+        const uint32_t q = tid, o = q == 0 ? rbase[0] : q == 1 ? rbase[1] : q == 2 ? rbase[2] : rbase[3];
+        out_xy[2 * o] = (int32_t)hdr->ext_x[q];
+        out_xy[2 * o + 1] = (int32_t)hdr->ext_y[q];
+        out_idx[o] = (int32_t)hdr->ext_idx[q];
+    }
+
+    // ---- pass 2: the kept points ----
+    uint32_t done = 0;  // kept points of the earlier runs
+    for (uint32_t c0 = 0; c0 < nseg; c0 += kBatchBlock) {
+        const uint32_t sg = c0 + tid;
+        uint32_t c[4] = {0, 0, 0, 0};
+        if (sg < nseg) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = segcnt[4 * sg + q];
+        }
+        uint32_t all;
+        const uint32_t ex = block_excl_sum<kBatchWaves>(c[0] + c[1] + c[2] + c[3], scratch, all);
+        s_pre[tid] = ex;
+        s_sg[tid] = sg;
+        s_cum[tid][0] = c[0];
+        s_cum[tid][1] = c[0] + c[1];
+        s_cum[tid][2] = c[0] + c[1] + c[2];
+        s_cum[tid][3] = c[0] + c[1] + c[2] + c[3];
+        __syncthreads();
+        const uint32_t nrun = min((uint32_t)kBatchBlock, nseg - c0);
+        for (uint32_t p = tid; p < all; p += kBatchBlock) {
+            // the last segment of the run with pre <= p holds p (an empty
+            // segment shares its pre with the next one)
+            uint32_t lo = 0, hi = nrun;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (s_pre[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t j = p - s_pre[lo];
+            const uint32_t q = j < s_cum[lo][0] ? 0u : j < s_cum[lo][1] ? 1u : j < s_cum[lo][2] ? 2u : 3u;
+            const PolyRec r = kept[s_sg[lo] * kSeg + j];
+            const uint32_t o = done + p + q + 1;
+            out_xy[2 * o] = r.x;
+            out_xy[2 * o + 1] = r.y;
+            out_idx[o] = r.idx;
+        }
+        done += all;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int q = 0; q < 4; ++q) host_hdr->fin_w2[q] = s_reg[q];
+        host_hdr->gat_count = npoly;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // SPA in subsets (Section 2.2.2; the limitation of Section 4.3): the
 // divide-and-conquer variant that the paper implements, kept for the
 // discard-effectiveness experiments (the path itself runs the exact rule).
@@ -2308,7 +2415,8 @@ namespace {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-constexpr size_t kHostChainDefault = 1u << 20;  // pinned chain records
+constexpr size_t kHostChainDefault = 1u << 20;  // pinned chain records at first
+constexpr size_t kHostChainMax = 1u << 24;      // the most it grows to
 
 struct Workspace {
     std::mutex mu;
@@ -2333,9 +2441,15 @@ struct Workspace {
     PolyRec* h_chain = nullptr;     // pinned, device-visible
     PolyRec* h_chain_dev = nullptr; // its device address
     size_t h_chain_cap = 0;
+    size_t h_chain_want = kHostChainDefault;  // raised by a call whose chain spilled
     int32_t* h_out = nullptr;       // pinned, device-visible: count, then indices
     int32_t* h_out_dev = nullptr;   // its device address
     size_t h_out_cap = 0;
+    int32_t* h_pxy = nullptr;       // pinned, device-visible: k_gather's polygon,
+    int32_t* h_pidx = nullptr;      // (x, y) pairs and indices
+    int32_t* h_pxy_dev = nullptr;
+    int32_t* h_pidx_dev = nullptr;
+    size_t h_poly_cap = 0;          // vertices
     std::vector<int32_t> xy, idx;   // finish input
     std::vector<PolyRec> spill;     // chain records beyond the pinned buffer
     PolyRec* dev_spill = nullptr;   // device: chain records beyond the pinned buffer
@@ -2476,20 +2590,27 @@ int ensure_device(Workspace& w, size_t n)
     return CH_OK;
 }
 
-int ensure_host(Workspace& w, size_t out)
+// Pinned buffers: the header, the result (out vertices) and, for the host
+// polygon of chainhull_polygon (chain), the chain records and segment counts.
+int ensure_host(Workspace& w, size_t out, bool chain)
 {
     if (!w.h_hdr) {
         CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_hdr), sizeof(DevHeader), hipHostMallocMapped));
         CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_hdr_dev), w.h_hdr, 0));
     }
-    if (!w.h_chain) {
-        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_chain), sizeof(PolyRec) * kHostChainDefault,
+    if (chain && w.h_chain && w.h_chain_cap < w.h_chain_want) {  // no kernel of this workspace runs here
+        CH_TRY(hipHostFree(w.h_chain));
+        w.h_chain = nullptr;
+        w.h_chain_cap = 0;
+    }
+    if (chain && !w.h_chain) {
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_chain), sizeof(PolyRec) * w.h_chain_want,
                              hipHostMallocMapped));
         CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_chain_dev), w.h_chain, 0));
-        w.h_chain_cap = kHostChainDefault;
+        w.h_chain_cap = w.h_chain_want;
     }
     const size_t nseg = w.cap / kSeg + 1;
-    if (w.h_segcnt_cap < nseg) {
+    if (chain && w.h_segcnt_cap < nseg) {
         if (w.h_segcnt) CH_TRY(hipHostFree(w.h_segcnt));
         w.h_segcnt = nullptr;
         CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_segcnt), sizeof(uint32_t) * 4 * nseg, hipHostMallocMapped));
@@ -2534,6 +2655,8 @@ void free_workspace(Workspace* w)
     if (w->h_chain) (void)hipHostFree(w->h_chain);
     if (w->h_out) (void)hipHostFree(w->h_out);
     if (w->h_segcnt) (void)hipHostFree(w->h_segcnt);
+    if (w->h_pxy) (void)hipHostFree(w->h_pxy);
+    if (w->h_pidx) (void)hipHostFree(w->h_pidx);
     if (w->b_offsets) (void)hipFree(w->b_offsets);
     if (w->b_order) (void)hipFree(w->b_order);
     if (w->h_b_offsets) (void)hipHostFree(w->h_b_offsets);
@@ -2556,10 +2679,11 @@ int record(Workspace& w, int k)
     return hip_status(hipEventRecord(w.ev[k], w.stream));
 }
 
-// Steps 1-6 on the device; the chains end in w.h_chain (and w.spill), the
-// counts in w.h_hdr.  With fin_idx, k_finish then finishes the hull on the
-// device into fin_idx / fin_count when the polygon fits its workgroup
-// (h_hdr->fin_done).  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
+// Steps 1-6 on the device; the counts end in w.h_hdr.  Without fin_idx the
+// chains end in w.h_chain (and w.spill).  With fin_idx, k_finish then
+// finishes the hull on the device into fin_idx / fin_count when the polygon
+// fits its workgroup (h_hdr->fin_done); otherwise gather_polygon fetches the
+// polygon for the host finish.  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
 // 2 | k_cand (+ k_count_regions) | 3 | sort | 4 | SPA + chains | 5 |
 // k_finish | 6.
 int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
@@ -2589,9 +2713,12 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32
     CH_TRY(record(w, 4));
     CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1], w.val[1],
                                  w.hdr, w.bk, w.dev_chain));
+    // hull2d (fin_idx) leaves the host chain buffer alone: its host finish
+    // reads k_gather's polygon
     CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kChainGrid), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
-                                 w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill, w.h_segcnt_dev, w.h_hdr_dev,
-                                 stats ? 0 : 1, w.dev_kept, w.dev_segcnt));
+                                 fin_idx ? nullptr : w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill,
+                                 fin_idx ? nullptr : w.h_segcnt_dev, w.h_hdr_dev, stats ? 0 : 1, w.dev_kept,
+                                 w.dev_segcnt));
     CH_TRY(record(w, 5));
     if (fin_idx) {
         CH_LAUNCH(hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBatchBlock), 0, s, w.hdr, w.dev_segcnt, w.dev_kept,
@@ -2601,13 +2728,17 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32
     CH_TRY(hipStreamSynchronize(s));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
-    if (fin_idx && w.h_hdr->fin_done) return CH_OK;  // the hull is written
+    if (fin_idx) return CH_OK;  // the hull is written, or k_gather's turn
     // kept chain points sit below the chain length
     const size_t m = w.h_hdr->chain;
     w.spill.clear();
     if (m > w.h_chain_cap) {
         w.spill.resize(m - w.h_chain_cap);
         CH_TRY(hipMemcpy(w.spill.data(), w.dev_spill, sizeof(PolyRec) * w.spill.size(), hipMemcpyDeviceToHost));
+        // the next call's chain of this size lands in pinned memory whole
+        size_t want = w.h_chain_cap;
+        while (want < m && want < kHostChainMax) want *= 2;
+        w.h_chain_want = want;
     }
     return CH_OK;
 }
@@ -2682,12 +2813,47 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
     st->polygon = w.w2[0] + w.w2[1] + w.w2[2] + w.w2[3] + 4;
     if (g_timing && w.events) {
         // stage slots: 0 sample + staircases, 1 k_stream, 2 k_cand, 3 sort,
-        // 4 SPA + chains, 5 device finish (6 is unused, 7 the host finish)
+        // 4 SPA + chains, 5 device finish (6 and 7, the host finish, are
+        // wall-clock times set by the caller)
         for (int k = 0; k < 6; ++k) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
         }
     }
+}
+
+// After run_preprocess with fin_idx left the finish to the host: the
+// polygon, gathered on the device into pinned memory (w.h_pxy, w.h_pidx;
+// its size returned in *m), and the per-region counts for the statistics.
+int gather_polygon(Workspace& w, size_t* m)
+{
+    const size_t need = (size_t)w.h_hdr->chain + 4;  // at least the polygon
+    if (w.h_poly_cap < need) {
+        if (w.h_pxy) CH_TRY(hipHostFree(w.h_pxy));
+        if (w.h_pidx) CH_TRY(hipHostFree(w.h_pidx));
+        w.h_pxy = w.h_pidx = nullptr;
+        w.h_poly_cap = 0;
+        size_t cap = 4096;
+        while (cap < need) cap *= 2;
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_pxy), sizeof(int32_t) * 2 * cap, hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_pxy_dev), w.h_pxy, 0));
+        CH_TRY(hipHostMalloc(reinterpret_cast<void**>(&w.h_pidx), sizeof(int32_t) * cap, hipHostMallocMapped));
+        CH_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.h_pidx_dev), w.h_pidx, 0));
+        w.h_poly_cap = cap;
+    }
+    const uint32_t cap32 = (uint32_t)std::min<size_t>(w.h_poly_cap, UINT32_MAX);
+    CH_LAUNCH(hipLaunchKernelGGL(k_gather, dim3(1), dim3(kBatchBlock), 0, w.stream, w.hdr, w.dev_segcnt,
+                                 w.dev_kept, w.h_pxy_dev, w.h_pidx_dev, cap32, w.h_hdr_dev));
+    CH_TRY(hipStreamSynchronize(w.stream));
+    const DevHeader& h = *w.h_hdr;
+    if (h.gat_count < 4 || h.gat_count > w.h_poly_cap) return CH_EHIP;
+    for (int q = 0; q < 4; ++q) {
+        w.w2[q] = h.fin_w2[q];
+        w.s2[q] = h.s2[q];
+    }
+    w.chain = h.chain;
+    *m = h.gat_count;
+    return CH_OK;
 }
 
 int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, hipStream_t stream)
@@ -2707,7 +2873,7 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
         return CH_OK;
     }
     CH_TRY(ensure_device(*w, (size_t)n));
-    CH_TRY(ensure_host(*w, 0));  // after the device part: sized by its capacity
+    CH_TRY(ensure_host(*w, 0, false));
     rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
     if (rc == CH_OK && w->h_hdr->fin_done) {
         // finished on the device: the hull is in out_idx / out_count
@@ -2724,16 +2890,19 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     int64_t h = 0;
     if (rc == CH_OK) {
         const auto t0 = std::chrono::steady_clock::now();
-        build_polygon(*w);
-        fill_stats(*w, n, &st, false);
-        rc = ensure_host(*w, w->idx.size());
-        if (rc == CH_OK) {
-            rc = melkman_finish(w->xy.data(), w->idx.data(), (int64_t)w->idx.size(), w->h_out + 1, &h) == 0
-                     ? CH_OK
-                     : CH_EHIP;
-        }
+        size_t m = 0;
+        rc = gather_polygon(*w, &m);
         const auto t1 = std::chrono::steady_clock::now();
-        st.ms[7] = std::chrono::duration<float, std::milli>(t1 - t0).count();
+        if (rc == CH_OK) {
+            fill_stats(*w, n, &st, false);
+            rc = ensure_host(*w, m, false);
+        }
+        if (rc == CH_OK) {
+            rc = melkman_finish(w->h_pxy, w->h_pidx, (int64_t)m, w->h_out + 1, &h) == 0 ? CH_OK : CH_EHIP;
+        }
+        const auto t2 = std::chrono::steady_clock::now();
+        st.ms[6] = std::chrono::duration<float, std::milli>(t1 - t0).count();
+        st.ms[7] = std::chrono::duration<float, std::milli>(t2 - t1).count();
         st.hull = h;
     }
     if (rc != CH_OK) {
@@ -2899,7 +3068,7 @@ int chainhull_polygon(const float* points, int64_t n, int32_t* poly_idx, int64_t
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
     CH_TRY(ensure_device(*w, (size_t)n));
-    CH_TRY(ensure_host(*w, 0));  // after the device part: sized by its capacity
+    CH_TRY(ensure_host(*w, 0, true));  // after the device part: sized by its capacity
     rc = run_preprocess(*w, points, (uint32_t)n, true);
     if (rc != CH_OK) return rc;
     build_polygon(*w);
