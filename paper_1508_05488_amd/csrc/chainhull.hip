@@ -664,18 +664,27 @@ __device__ inline void reduce_quad(const ExtPartial* __restrict__ part, int npar
 {
     ExtAcc r;
     ext_init(r);
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-        const ExtPartial p = part[b];
-        ExtAcc o;
-        for (int e = 0; e < 2; ++e) {
-            o.kmin[e] = p.kmin[e];
-            o.kmax[e] = p.kmax[e];
-            o.imin[e] = p.imin[e];
-            o.imax[e] = p.imax[e];
+    constexpr int kU = 4;  // partials loaded together per thread
+    for (int b0 = threadIdx.x; b0 < nparts; b0 += kU * kBlock) {
+        ExtPartial p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (b0 + u * kBlock < nparts) p[u] = part[b0 + u * kBlock];
         }
-        o.bad = p.err != 0;
-        o.hi = 0;
-        ext_combine(r, o);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (b0 + u * kBlock >= nparts) continue;
+            ExtAcc o;
+            for (int e = 0; e < 2; ++e) {
+                o.kmin[e] = p[u].kmin[e];
+                o.kmax[e] = p[u].kmax[e];
+                o.imin[e] = p[u].imin[e];
+                o.imax[e] = p[u].imax[e];
+            }
+            o.bad = p[u].err != 0;
+            o.hi = 0;
+            ext_combine(r, o);
+        }
     }
     ext_block_reduce(r, sh);
     __shared__ Quad sq;
@@ -930,6 +939,13 @@ __global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restric
 // thread owns kBuckets / kBlock consecutive buckets.  Returns the total.
 constexpr int kPerThreadBuckets = kBuckets / kBlock;  // 32
 
+// LDS position of bucket b in a per-bucket array that threads read with
+// the ownership above (thread t: buckets 32t .. 32t+31): one pad word per
+// 32 puts the lanes of one read step in distinct banks.  The arrays are
+// filled from global memory with lane-consecutive (coalesced) loads first.
+__device__ inline uint32_t bpad(uint32_t b) { return b + (b >> 5); }
+constexpr int kBucketsPadded = kBuckets + kBuckets / 32;
+
 __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ in_key,
                                                    const u64* __restrict__ in_val, uint32_t in_region,
                                                    const uint32_t* __restrict__ candcount, int nlists,
@@ -937,9 +953,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
                                                    DevHeader* __restrict__ hdr, Buckets bk)
 {
     static_assert(kBuckets % kBlock == 0 && (kBuckets / 4) % kPerThreadBuckets == 0, "bucket ownership");
-    __shared__ uint32_t soff[kBuckets];   // first position of each bucket
-    __shared__ uint32_t sthr[kBuckets];   // threshold entering each bucket
-    __shared__ uint32_t lcnt[kBuckets];   // this chunk's records per bucket, then their base
+    __shared__ uint32_t soff[kBucketsPadded];  // first position of each bucket (at bpad)
+    __shared__ uint32_t sthr[kBucketsPadded];  // threshold entering each bucket (at bpad)
+    __shared__ uint32_t lcnt[kBuckets];        // this chunk's records per bucket, then their base
     __shared__ uint32_t scratch[kWaves];
     const uint32_t tid = threadIdx.x;
     if (hdr->err) return;
@@ -947,40 +963,60 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
     // bucket offsets and thresholds: thread t owns kPerThreadBuckets
     // consecutive buckets, so a region's buckets are one wave's
     {
-        uint32_t c[kPerThreadBuckets], sum = 0;
-        u64 mk[kPerThreadBuckets];
+        // staged: counts in soff, smallest k2 in sthr (all loads in flight
+        // together)
+        {
+            uint32_t vc[kPerThreadBuckets];
+            u64 vm[kPerThreadBuckets];
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) {
+                vc[k] = bk.cnt[k * kBlock + tid];
+                vm[k] = bk.kmin[k * kBlock + tid];
+            }
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) {
+                const uint32_t b = k * kBlock + tid;
+                soff[bpad(b)] = vc[k];
+                sthr[bpad(b)] = (uint32_t)(vm[k] >> 23);
+                lcnt[b] = 0;
+            }
+        }
+        __syncthreads();
+        uint32_t c[kPerThreadBuckets], mk[kPerThreadBuckets], sum = 0, lo = ~0u;
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
-            c[k] = bk.cnt[tid * kPerThreadBuckets + k];
-            mk[k] = bk.kmin[tid * kPerThreadBuckets + k];
+            const uint32_t b = bpad(tid * kPerThreadBuckets + k);
+            c[k] = soff[b];
+            mk[k] = sthr[b];
             sum += c[k];
+            lo = min(lo, mk[k]);
         }
         uint32_t total;
-        uint32_t run = block_excl_sum(sum, scratch, total);
+        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow every read above)
         const uint32_t q = tid / 64;
-        uint32_t lo = ~0u;
-#pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) lo = min(lo, (uint32_t)(mk[k] >> 23));
         const uint32_t incl = wave_incl_min(lo);
         uint32_t before = __shfl_up(incl, 1);
         if (lane_id() == 0) before = ~0u;
         before = min(before, hdr->sigma[q]);
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
-            const uint32_t b = tid * kPerThreadBuckets + k;
+            const uint32_t b = bpad(tid * kPerThreadBuckets + k);
             soff[b] = run;
             sthr[b] = before;
-            lcnt[b] = 0;
-            if (blockIdx.x == 0) {
-                bk.off[b] = run;
-                bk.thr[b] = before;
-            }
             run += c[k];
-            before = min(before, (uint32_t)(mk[k] >> 23));
+            before = min(before, mk[k]);
         }
         if (blockIdx.x == 0 && tid == 0) hdr->cand = total;
     }
     __syncthreads();
+    if (blockIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            const uint32_t b = k * kBlock + tid;
+            bk.off[b] = soff[bpad(b)];
+            bk.thr[b] = sthr[bpad(b)];
+        }
+    }
 
     // Place this workgroup's records (k_cand workgroup blockIdx.x), a chunk
     // at a time: local ranks by LDS atomics, one global reservation per
@@ -1013,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
             if (b[k] != ~0u) {
                 const uint32_t k1 = kk[k] & kM, k2 = (uint32_t)(vv[k] >> 32);
                 const u64 me = ((u64)k2 << 23) | k1;
-                if (k2 >= sthr[b[k]] || (bm[k] < me && (uint32_t)(bm[k] & kM) <= k1)) {
+                if (k2 >= sthr[bpad(b[k])] || (bm[k] < me && (uint32_t)(bm[k] & kM) <= k1)) {
                     b[k] = ~0u;
                 } else {
                     r[k] = atomicAdd(&lcnt[b[k]], 1u);
@@ -1024,7 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ 
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            if ((own >> k) & 1u) lcnt[b[k]] = soff[b[k]] + atomicAdd(&bk.cur[b[k]], lcnt[b[k]]);
+            if ((own >> k) & 1u) lcnt[b[k]] = soff[bpad(b[k])] + atomicAdd(&bk.cur[b[k]], lcnt[b[k]]);
         }
         __syncthreads();
 #pragma unroll
@@ -1206,7 +1242,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                                                   DevHeader* __restrict__ host_hdr, int prehull,
                                                   PolyRec* __restrict__ dev_kept, uint32_t* __restrict__ dev_segcnt)
 {
-    __shared__ uint32_t pre[kBuckets];  // chain points before each bucket
+    __shared__ uint32_t pre[kBucketsPadded];  // chain points before each bucket (at bpad)
     __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
     __shared__ uint16_t lst[kSeg];
     __shared__ uint8_t reg[kSeg], alive[kSeg];
@@ -1228,23 +1264,31 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
 
     uint32_t total;
     {
+        {
+            uint32_t v[kPerThreadBuckets];  // staged, all loads in flight together
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) v[k] = bk.surv[k * kBlock + tid];
+#pragma unroll
+            for (int k = 0; k < kPerThreadBuckets; ++k) pre[bpad(k * kBlock + tid)] = v[k];
+        }
+        __syncthreads();
         uint32_t c[kPerThreadBuckets], sum = 0;
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
-            c[k] = bk.surv[tid * kPerThreadBuckets + k];
+            c[k] = pre[bpad(tid * kPerThreadBuckets + k)];
             sum += c[k];
         }
-        uint32_t run = block_excl_sum(sum, scratch, total);
+        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow every read above)
 #pragma unroll
         for (int k = 0; k < kPerThreadBuckets; ++k) {
-            pre[tid * kPerThreadBuckets + k] = run;
+            pre[bpad(tid * kPerThreadBuckets + k)] = run;
             run += c[k];
         }
     }
     __syncthreads();
     if (blockIdx.x == 0 && tid < 4) {
-        const uint32_t first = pre[tid << kBucketBits];
-        const uint32_t last = tid == 3 ? total : pre[(tid + 1) << kBucketBits];
+        const uint32_t first = pre[bpad(tid << kBucketBits)];
+        const uint32_t last = tid == 3 ? total : pre[bpad((tid + 1) << kBucketBits)];
         hdr->s2[tid] = last - first;
         if (tid == 0) hdr->chain = total;
     }
@@ -1264,7 +1308,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
             uint32_t lo = 0, hi = kBuckets - 1;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi + 1) / 2;
-                if (pre[mid] <= g) lo = mid;
+                if (pre[bpad(mid)] <= g) lo = mid;
                 else hi = mid - 1;
             }
             bb[k] = lo;
@@ -1276,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         for (int k = 0; k < kPerThreadSeg; ++k) {
             if (k >= kmax) continue;
             const uint32_t i = k * kBlock + tid, g = base + min(i, len - 1);
-            aa[k] += g - pre[bb[k]];
+            aa[k] += g - pre[bpad(bb[k])];
             rr[k] = dev_chain[aa[k]];
         }
 #pragma unroll
