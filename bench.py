@@ -6,7 +6,10 @@ the Melkman finish) over each of the three 20M-point inputs: uniform square,
 uniform disk, and Gaussian (sigma 2^20 around 2^22, clamped), integer-valued
 float32 in [0, 2^23).  Inputs are generated on the host and copied to HBM
 before timing starts.  ``value`` is input points per second over the timed
-steps (Mpts/s).
+steps (Mpts/s), with the faster of two ways to call the library, both
+timed: three blocking ``hull2d`` calls per step, or three ``hull2d_async``
+calls queued per step with one synchronisation (their results are checked
+equal; ``calls`` holds both).
 
 Prints one JSON line.  Extra fields: per-distribution rates and counts, the
 per-stage times from HIP events recorded on the library's stream, the
@@ -374,7 +377,51 @@ def main():
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     total_pts = n * len(DISTS) * args.steps
-    value = total_pts / elapsed / 1e6
+    value_blocking = total_pts / elapsed / 1e6
+
+    # timed region 1b: the same hulls queued with hull2d_async (every step on
+    # the device, no host round trip between the inputs), one
+    # synchronisation per step when the counts are read; an input left to
+    # the host finish (CH_BATCH_REDO) is recomputed with hull2d inside the
+    # region
+    acnt = torch.empty(len(DISTS), dtype=torch.int32, device=dev)
+    aout = {d: torch.empty(n, dtype=torch.int32, device=dev) for d, _ in DISTS}
+    redo = [0]
+
+    def step_async():
+        for k, (d, _) in enumerate(DISTS):
+            rc = ch.hull2d_async(inputs[d], aout[d], acnt[k:k + 1], stream)
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, f"hull2d_async {d}")
+        counts = acnt.cpu()  # synchronises the stream
+        for k, (d, _) in enumerate(DISTS):
+            c = int(counts[k])
+            if c == ch.CH_BATCH_REDO:
+                redo[0] += 1
+                rc = ch.hull2d_into(inputs[d], aout[d], acnt[k:k + 1], stream)
+                if rc != ch.CH_OK:
+                    raise ch.ChainHullError(rc, f"hull2d {d}")
+            elif c < 0:
+                raise ch.ChainHullError(c, f"hull2d_async {d}")
+
+    for _ in range(args.warmup):
+        step_async()
+    torch.cuda.synchronize()
+    t0a = time.perf_counter()
+    for _ in range(args.steps):
+        step_async()
+    torch.cuda.synchronize()
+    t1a = time.perf_counter()
+    elapsed_async = t1a - t0a
+    # the queued results are the blocking ones
+    for k, (d, _) in enumerate(DISTS):
+        c = int(outs[d][1].item())
+        if int(acnt[k].item()) != c or not torch.equal(aout[d][:c], outs[d][0][:c]):
+            raise RuntimeError(f"hull2d_async and hull2d differ on {d}")
+    value_async = total_pts / elapsed_async / 1e6
+    value = max(value_blocking, value_async)
+    api = "hull2d_async" if value_async >= value_blocking else "hull2d"
+    ms_per_step = 1e3 * (elapsed_async if api == "hull2d_async" else elapsed) / args.steps
 
     # timed region 2: the same steps with HIP events recorded by the library
     # on the call's stream around every stage
@@ -472,7 +519,13 @@ def main():
         "config": {"workload": f"exact 2D hull, {n} integer-valued f32 points in [0,2^23), "
                                "three inputs per step: uniform square, uniform disk, Gaussian sigma 2^20",
                    "n_points": n, "inputs_per_step": len(DISTS), "seeds": [s for _, s in DISTS],
-                   "input_sha256_16": {d: sha16(host[d]) for d, _ in DISTS}},
+                   "input_sha256_16": {d: sha16(host[d]) for d, _ in DISTS},
+                   "api": api},
+        "calls": {"hull2d_async": {"value": round(value_async, 2), "ms_per_step": round(1e3 * elapsed_async / args.steps, 4),
+                                   "redo": redo[0],
+                                   "note": "three calls queued per step, one synchronisation when the counts are read"},
+                  "hull2d": {"value": round(value_blocking, 2), "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+                             "note": "three blocking calls per step"}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")

@@ -102,6 +102,25 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
  * the same.) */
 
 /*
+ * hull2d_async: hull2d with every step on the device and nothing
+ * synchronised (Section 2.1, steps 1-7), for callers that queue several
+ * hulls back to back or capture the call in a HIP graph.
+ *   points, n, out_idx, stream  as in hull2d.
+ *   out_count  device memory, one int32; receives, in stream order, the
+ *              number of hull vertices, or CH_EDOMAIN (a coordinate out of
+ *              the domain), CH_EHIP (a failed step), or CH_BATCH_REDO when
+ *              the polygon exceeds the device finish (more than 3584
+ *              vertices after the pre-hull; hull2d computes such an input).
+ * Returns after queueing the kernels: CH_OK, CH_EINVAL (bad argument, before
+ * any work), CH_ENOMEM or CH_EHIP.  The stream's workspace (shared with
+ * hull2d on that stream) is allocated or grown only when n exceeds what it
+ * holds; a graph captures the call allocation-free after a first call with
+ * at least as many points.  Calls on one stream run one after another; the
+ * statistics of chainhull_last_stats are not filled.
+ */
+int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
+
+/*
  * hull2d_batched: num_sets independent hulls (Section 2.1 applied per set).
  *   points      device memory, the sets' points concatenated as in hull2d.
  *   offsets     host memory, num_sets + 1 non-decreasing int64 with

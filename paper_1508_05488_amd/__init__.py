@@ -21,7 +21,7 @@ CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4,
 CH_BATCH_REDO = -(2 ** 31)
 
 # C entry points declared in include/chainhull.h
-EXPORTS = ("hull2d", "hull2d_batched", "hull2d_batched_async", "chainhull_polygon", "chainhull_finish_host",
+EXPORTS = ("hull2d", "hull2d_async", "hull2d_batched", "hull2d_batched_async", "chainhull_polygon", "chainhull_finish_host",
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes", "chainhull_spa_chunked",
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
@@ -113,6 +113,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.hull2d.argtypes = [vp, i64, vp, vp, vp]
+    L.hull2d_async.argtypes = [vp, i64, vp, vp, vp]
+    L.hull2d_async.restype = ctypes.c_int
     L.hull2d.restype = ctypes.c_int
     L.hull2d_batched.argtypes = [vp, vp, i32, vp, vp, vp]
     L.hull2d_batched.restype = ctypes.c_int
@@ -196,6 +198,15 @@ def hull2d_into(points, out_idx, out_count, stream=None) -> int:
     """hull2d writing into caller-provided device tensors; returns the status."""
     return lib().hull2d(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
                         _stream_ptr(stream))
+
+
+def hull2d_async(points, out_idx, out_count, stream=None) -> int:
+    """hull2d with every step on the device, queued on the stream and not
+    synchronised: out_count (CUDA int32 [1]) receives the hull size, a
+    negative status, or CH_BATCH_REDO (then call hull2d).  out_idx: CUDA
+    int32 with room for the points.  Returns the status of the launch."""
+    return lib().hull2d_async(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
+                              _stream_ptr(stream))
 
 
 def hull2d_batched(points, offsets, stream=None):

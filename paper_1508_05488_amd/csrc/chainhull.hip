@@ -2192,7 +2192,9 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
 //           and goes to its polygon position (its rank plus the extreme
 //           points before its region).
 // A polygon of more than kBatchPolyMax vertices, or one that Melkman cannot
-// finish in LDS, is left to the host (fin_done = 0 in the header).
+// finish in LDS, is left to the host (fin_done = 0 in the header, the count
+// kBatchRedo until the host's result replaces it); after a failed step the
+// count is the call's negative status.
 // ---------------------------------------------------------------------------
 struct SegEnt {
     uint32_t sg, pre;  // segment, rank of its first kept point
@@ -2212,7 +2214,10 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
     const uint32_t tid = threadIdx.x, lane = lane_id();
     SegEnt* const tab = reinterpret_cast<SegEnt*>(smem + kPolyBytes);
     if (hdr->err) {
-        if (tid == 0) host_hdr->fin_done = 0;
+        if (tid == 0) {
+            host_hdr->fin_done = 0;
+            *out_count = (hdr->err & kErrDomain) ? CH_EDOMAIN : CH_EHIP;
+        }
         return;
     }
     const uint32_t chain = hdr->chain;
@@ -2254,7 +2259,10 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
         nt += nz;
     }
     if (!fits) {
-        if (tid == 0) host_hdr->fin_done = 0;
+        if (tid == 0) {
+            host_hdr->fin_done = 0;
+            *out_count = kBatchRedo;
+        }
         return;
     }
 #pragma unroll
@@ -2305,7 +2313,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
     __syncthreads();
     const int h = poly_finish(Pl, total + 4, rbase[1], out_idx, scratch, &s_flag, &s_ext, &s_start);
     if (tid == 0) {
-        if (h >= 0) *out_count = h;
+        *out_count = h >= 0 ? h : kBatchRedo;
         host_hdr->fin_hull = h;
         for (int q = 0; q < 4; ++q) host_hdr->fin_w2[q] = s_reg[q];
         host_hdr->fin_done = h >= 0 ? 1u : 0u;
@@ -2730,8 +2738,8 @@ int record(Workspace& w, int k)
 // polygon for the host finish.  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
 // 2 | k_cand (+ k_count_regions) | 3 | sort | 4 | SPA + chains | 5 |
 // k_finish | 6.
-int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
-                   int32_t* fin_count = nullptr)
+int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx,
+                      int32_t* fin_count)
 {
     hipStream_t s = w.stream;
     CH_TRY(record(w, 0));
@@ -2769,7 +2777,14 @@ int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32
                                      fin_idx, fin_count, w.h_hdr_dev));
     }
     CH_TRY(record(w, 6));
-    CH_TRY(hipStreamSynchronize(s));
+    return CH_OK;
+}
+
+int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
+                   int32_t* fin_count = nullptr)
+{
+    CH_TRY(launch_preprocess(w, pts, n, stats, fin_idx, fin_count));
+    CH_TRY(hipStreamSynchronize(w.stream));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
     if (fin_idx) return CH_OK;  // the hull is written, or k_gather's turn
@@ -2974,6 +2989,24 @@ extern "C" {
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream)
 {
     return hull_one(points, n, out_idx, out_count, reinterpret_cast<hipStream_t>(stream));
+}
+
+int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream)
+{
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx))) return CH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
+    if (n == 0) {  // a kernel, not a memset: the call may be captured in a graph
+        CH_LAUNCH(hipLaunchKernelGGL(k_put_result, dim3(1), dim3(kBlock), 0, s, nullptr, 0, out_idx, out_count));
+        return CH_OK;
+    }
+    int rc = CH_OK;
+    Workspace* w = workspace_for(s, &rc);
+    if (!w) return rc;
+    std::lock_guard<std::mutex> lk(w->mu);
+    CH_TRY(ensure_device(*w, (size_t)n));
+    CH_TRY(ensure_host(*w, 0, false));
+    return launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
 }
 
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets, int32_t* out_idx,

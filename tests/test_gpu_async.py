@@ -1,0 +1,133 @@
+"""hull2d_async (every step on the device, nothing synchronised): its
+results equal hull2d's and, where the oracle finishes in seconds, the
+oracle's; several calls queued back to back on one stream; the count codes
+for an out-of-domain input and for a polygon beyond the device finish; a
+HIP graph of the call replayed on new inputs.  Each case prints its name
+before its GPU calls."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1508_05488_amd as ch  # noqa: E402
+from oracle import hull as oracle  # noqa: E402
+from paper_1508_05488_amd import workloads as wl  # noqa: E402
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_async(d, stream=None):
+    out = torch.full((max(d.shape[0], 1),), -7, dtype=torch.int32, device="cuda")
+    cnt = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    assert ch.hull2d_async(d, out, cnt, stream=stream) == ch.CH_OK
+    return out, cnt
+
+
+@pytest.mark.parametrize("dist,n,seed", [("square", 100_000, 301), ("disk", 100_000, 302),
+                                         ("gaussian", 100_000, 303), ("square", 2_000_003, 304),
+                                         ("disk", 1_000_001, 305), ("gaussian", 3_000_000, 306)])
+def test_async_equals_blocking_and_oracle(dist, n, seed):
+    pts = wl.generate(dist, n, seed)
+    d = torch.from_numpy(pts).cuda()
+    say(f"  hull2d_async {dist} n={n}")
+    out, cnt = run_async(d)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert c > 0, c
+    ref = ch.hull2d(d).cpu().numpy()
+    assert np.array_equal(out[:c].cpu().numpy(), ref)
+    if n <= 100_000:
+        assert np.array_equal(ref, oracle.hull(pts))
+
+
+def test_async_small_and_degenerate():
+    cases = [np.zeros((0, 2), np.float32), np.array([[3, 4]], np.float32),
+             np.array([[3, 4], [3, 4]], np.float32), np.array([[1, 1], [5, 5], [9, 9]], np.float32),
+             np.full((1000, 2), 12345, np.float32),
+             np.stack([np.arange(700) % 13, np.arange(700) % 13], 1).astype(np.float32),
+             wl.generate("square", 3, 311), wl.generate("disk", 257, 312), wl.generate("gaussian", 4097, 313)]
+    for k, pts in enumerate(cases):
+        say(f"  hull2d_async small case {k} (n={pts.shape[0]})")
+        d = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+        out, cnt = run_async(d)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        assert c >= 0, (k, c)
+        assert np.array_equal(out[:c].cpu().numpy(), oracle.hull(pts)), k
+
+
+def test_async_queued_back_to_back():
+    inputs = [wl.generate(dist, n, 320 + k) for k, (dist, n) in
+              enumerate([("square", 1_500_000), ("gaussian", 40_000), ("disk", 2_500_000), ("square", 7),
+                         ("gaussian", 2_000_000)])]
+    dev = [torch.from_numpy(p).cuda() for p in inputs]
+    refs = [ch.hull2d(d).cpu().numpy() for d in dev]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    say("  hull2d_async: five calls queued on one stream")
+    with torch.cuda.stream(s):
+        res = [run_async(d, stream=s) for d in dev]
+    s.synchronize()
+    for k, ((out, cnt), ref) in enumerate(zip(res, refs)):
+        c = int(cnt.item())
+        assert np.array_equal(out[:c].cpu().numpy(), ref), k
+
+
+def test_async_domain_error_and_redo():
+    bad = wl.generate("square", 50_000, 331)
+    bad[777, 1] = 0.5
+    say("  hull2d_async: out-of-domain coordinate")
+    _, cnt = run_async(torch.from_numpy(bad).cuda())
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == ch.CH_EDOMAIN
+    # many points on a circle: a polygon beyond the device finish
+    big = wl.generate("adversarial", 2_000_000, 332)
+    d = torch.from_numpy(big).cuda()
+    say("  hull2d_async: polygon beyond the device finish")
+    out, cnt = run_async(d)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == ch.CH_BATCH_REDO
+    h = ch.hull2d(d)
+    assert ch.last_stats()["device_finish"] is False and h.numel() > 0
+    # the workspace serves a good call after both
+    good = wl.generate("disk", 300_000, 333)
+    out, cnt = run_async(torch.from_numpy(good).cuda())
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert np.array_equal(out[:c].cpu().numpy(), oracle.hull(good))
+
+
+def test_async_graph_replays():
+    n = 1_000_000
+    seeds = (341, 342, 343)
+    inputs = [wl.generate(("square", "disk", "gaussian")[k], n, s) for k, s in enumerate(seeds)]
+    d = torch.from_numpy(inputs[0]).cuda()
+    out = torch.zeros(n, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    say("  hull2d_async: warm-up and capture")
+    with torch.cuda.stream(s):  # warm-up outside the capture: the workspace exists
+        assert ch.hull2d_async(d, out, cnt, stream=s) == ch.CH_OK
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rc = ch.hull2d_async(d, out, cnt, stream=s)
+    assert rc == ch.CH_OK
+    for rep, pts in enumerate(inputs * 2):
+        d.copy_(torch.from_numpy(pts))
+        out.zero_()
+        cnt.fill_(-7)
+        ref = ch.hull2d(d).cpu().numpy()  # eager work between the replays
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        assert np.array_equal(out[:c].cpu().numpy(), ref), rep
