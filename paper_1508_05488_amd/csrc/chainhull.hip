@@ -66,6 +66,7 @@ namespace chainhull {
 
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64;
 typedef long long i64;
 
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
                                                    uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount)
 {
-    __shared__ uint32_t sst[4 * kStairSlots];
+    __shared__ __align__(16) uint32_t sst[4 * kStairSlots];
     __shared__ uint32_t lidx[kWaves][kWaveList];
     __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
@@ -483,7 +484,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     // round of kBlock*kStreamUnroll at a time.  Every lane runs the same
     // number of rounds (the list append is wave-wide); lanes past the range
     // reread the last float4, which changes nothing and lists nothing.  The
-    // first round's loads are issued before the staircase is staged.
+    // staircase loads go first and the first round's point loads right after
+    // them, so that the wait for the staircase (loads complete in issue
+    // order) leaves the point loads in flight while it is staged.
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
     constexpr uint32_t kRound = kBlock * kStreamUnroll;
@@ -494,10 +497,22 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         for (int u = 0; u < kStreamUnroll; ++u)
             v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
     };
+    constexpr int kStairPer = 4 * kStairSlots / 4 / kBlock;  // uint4 loads per thread
+    static_assert(kStairPer * 4 * kBlock == 4 * kStairSlots, "staircase staging");
+    v4u sv[kStairPer];
+#pragma unroll
+    for (int k = 0; k < kStairPer; ++k) sv[k] = reinterpret_cast<const v4u*>(stair)[k * kBlock + tid];
     v4f va[kStreamUnroll];
-    if (rounds) load_round(0, va);
-
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock) sst[e] = stair[e];
+    {
+        // unconditional, so that no branch joins before the staircase wait (a
+        // workgroup without points reads the staircase's first bytes instead)
+        const v4f* src = rounds ? p4 : reinterpret_cast<const v4f*>(stair);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            va[u] = __builtin_nontemporal_load(src + (rounds ? min(lo + u * kBlock + tid, n4 - 1) : 0u));
+    }
+#pragma unroll
+    for (int k = 0; k < kStairPer; ++k) reinterpret_cast<v4u*>(sst)[k * kBlock + tid] = sv[k];
     if (tid == 0) s_fill = 0;
     __syncthreads();
     uint32_t* const my_idx = open_idx + (size_t)blockIdx.x * region;
@@ -747,8 +762,13 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
     reduce_quad(part, nparts, hdr, Q, sh);
     if (blockIdx.x == 0) {
         // the number of open points, for the call's counts
+        static_assert(kStreamGrid % kBlock == 0, "open-point counts per thread");
         uint32_t c = 0;
-        for (int b = tid; b < nparts; b += kBlock) c += wgcount[b];
+#pragma unroll
+        for (int k = 0; k < kStreamGrid / kBlock; ++k) {  // all loads in flight together
+            const int b = k * kBlock + (int)tid;
+            c += b < nparts ? wgcount[b] : 0u;
+        }
         uint32_t total;
         (void)block_excl_sum(c, scratch, total);
         if (tid == 0) hdr->open = total;
