@@ -6,10 +6,12 @@ the Melkman finish) over each of the three 20M-point inputs: uniform square,
 uniform disk, and Gaussian (sigma 2^20 around 2^22, clamped), integer-valued
 float32 in [0, 2^23).  Inputs are generated on the host and copied to HBM
 before timing starts.  ``value`` is input points per second over the timed
-steps (Mpts/s), with the faster of two ways to call the library, both
-timed: three blocking ``hull2d`` calls per step, or three ``hull2d_async``
-calls queued per step with one synchronisation (their results are checked
-equal; ``calls`` holds both).
+steps (Mpts/s), with the fastest of four ways to call the library, all
+timed: three blocking ``hull2d`` calls per step; three ``hull2d_async``
+calls queued on one stream with one synchronisation; one ``hull2d_async``
+call per input on three streams; that three-stream step captured in a HIP
+graph and replayed.  Their results are checked equal; ``calls`` holds all
+four.
 
 Prints one JSON line.  Extra fields: per-distribution rates and counts, the
 per-stage times from HIP events recorded on the library's stream, the
@@ -419,9 +421,109 @@ def main():
         if int(acnt[k].item()) != c or not torch.equal(aout[d][:c], outs[d][0][:c]):
             raise RuntimeError(f"hull2d_async and hull2d differ on {d}")
     value_async = total_pts / elapsed_async / 1e6
-    value = max(value_blocking, value_async)
-    api = "hull2d_async" if value_async >= value_blocking else "hull2d"
-    ms_per_step = 1e3 * (elapsed_async if api == "hull2d_async" else elapsed) / args.steps
+
+    # timed region 1c: the three inputs on three streams (one library
+    # workspace each), so that one hull's short latency-bound kernels overlap
+    # another's pass over its points; one synchronisation per step
+    streams = [torch.cuda.Stream() for _ in DISTS]
+    mcnt = torch.empty(len(DISTS), dtype=torch.int32, device=dev)
+    mout = {d: torch.empty(n, dtype=torch.int32, device=dev) for d, _ in DISTS}
+    cur = torch.cuda.current_stream()
+
+    def step_streams():
+        for k, (d, _) in enumerate(DISTS):
+            streams[k].wait_stream(cur)  # the inputs and the count buffer are ready
+            rc = ch.hull2d_async(inputs[d], mout[d], mcnt[k:k + 1], streams[k])
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, f"hull2d_async {d}")
+        for st in streams:
+            cur.wait_stream(st)
+        counts = mcnt.cpu()  # synchronises the current stream, which waited on all three
+        for k, (d, _) in enumerate(DISTS):
+            c = int(counts[k])
+            if c == ch.CH_BATCH_REDO:
+                redo[0] += 1
+                rc = ch.hull2d_into(inputs[d], mout[d], mcnt[k:k + 1], cur)
+                if rc != ch.CH_OK:
+                    raise ch.ChainHullError(rc, f"hull2d {d}")
+            elif c < 0:
+                raise ch.ChainHullError(c, f"hull2d_async {d}")
+
+    for _ in range(args.warmup):
+        step_streams()
+    torch.cuda.synchronize()
+    t0m = time.perf_counter()
+    for _ in range(args.steps):
+        step_streams()
+    torch.cuda.synchronize()
+    t1m = time.perf_counter()
+    elapsed_streams = t1m - t0m
+    for k, (d, _) in enumerate(DISTS):
+        c = int(outs[d][1].item())
+        if int(mcnt[k].item()) != c or not torch.equal(mout[d][:c], outs[d][0][:c]):
+            raise RuntimeError(f"hull2d_async on three streams and hull2d differ on {d}")
+    value_streams = total_pts / elapsed_streams / 1e6
+
+    # timed region 1d: the three-stream step captured once in a HIP graph
+    # (the workspaces exist after the steps above, so the capture allocates
+    # nothing) and replayed, one launch and one synchronisation per step; the
+    # graph ends with a copy of the counts into pinned host memory
+    hcnt = torch.empty(len(DISTS), dtype=torch.int32, pin_memory=True)
+    gcap = torch.cuda.Stream()
+    gcap.wait_stream(cur)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gcap):
+        gs = torch.cuda.current_stream()
+        for k, (d, _) in enumerate(DISTS):
+            streams[k].wait_stream(gs)
+            rc = ch.hull2d_async(inputs[d], mout[d], mcnt[k:k + 1], streams[k])
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, f"hull2d_async {d} (capture)")
+        for st in streams:
+            gs.wait_stream(st)
+        hcnt.copy_(mcnt, non_blocking=True)
+
+    def step_graph():
+        graph.replay()
+        cur.synchronize()
+        counts = hcnt.numpy()
+        for k, (d, _) in enumerate(DISTS):
+            c = int(counts[k])
+            if c == ch.CH_BATCH_REDO:
+                redo[0] += 1
+                rc = ch.hull2d_into(inputs[d], mout[d], mcnt[k:k + 1], cur)
+                if rc != ch.CH_OK:
+                    raise ch.ChainHullError(rc, f"hull2d {d}")
+            elif c < 0:
+                raise ch.ChainHullError(c, f"hull2d_async {d}")
+
+    for _ in range(args.warmup):
+        step_graph()
+    torch.cuda.synchronize()
+    t0g = time.perf_counter()
+    for _ in range(args.steps):
+        step_graph()
+    torch.cuda.synchronize()
+    t1g = time.perf_counter()
+    elapsed_graph = t1g - t0g
+    for k, (d, _) in enumerate(DISTS):
+        c = int(outs[d][1].item())
+        if int(mcnt[k].item()) != c or not torch.equal(mout[d][:c], outs[d][0][:c]):
+            raise RuntimeError(f"the graph of three hull2d_async streams and hull2d differ on {d}")
+    value_graph = total_pts / elapsed_graph / 1e6
+    del graph
+    torch.cuda.synchronize()
+    for st in streams:
+        ch.release_stream(st)
+    del mout
+
+    ways = {"hull2d": (value_blocking, elapsed), "hull2d_async": (value_async, elapsed_async),
+            "hull2d_async_3_streams": (value_streams, elapsed_streams),
+            "hull2d_async_3_streams_graph": (value_graph, elapsed_graph)}
+    api = max(ways, key=lambda k: ways[k][0])
+    value = ways[api][0]
+    ms_per_step = 1e3 * ways[api][1] / args.steps
 
     # timed region 2: the same steps with HIP events recorded by the library
     # on the call's stream around every stage
@@ -525,7 +627,15 @@ def main():
                                    "redo": redo[0],
                                    "note": "three calls queued per step, one synchronisation when the counts are read"},
                   "hull2d": {"value": round(value_blocking, 2), "ms_per_step": round(1e3 * elapsed / args.steps, 4),
-                             "note": "three blocking calls per step"}},
+                             "note": "three blocking calls per step"},
+                  "hull2d_async_3_streams": {"value": round(value_streams, 2),
+                                             "ms_per_step": round(1e3 * elapsed_streams / args.steps, 4),
+                                             "note": "one hull2d_async call per input, each on its own stream "
+                                                     "(and library workspace), one synchronisation per step"},
+                  "hull2d_async_3_streams_graph": {"value": round(value_graph, 2),
+                                                   "ms_per_step": round(1e3 * elapsed_graph / args.steps, 4),
+                                                   "note": "the three-stream step captured once in a HIP graph and "
+                                                           "replayed: one launch and one synchronisation per step"}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")

@@ -293,6 +293,11 @@ def release() -> None:
     lib().chainhull_release()
 
 
+def release_stream(stream) -> None:
+    """Free the library workspace of one stream (no call on it may be running)."""
+    _check(lib().chainhull_release_stream(_stream_ptr(stream)), "chainhull_release_stream")
+
+
 def workspace_bytes(n: int) -> int:
     return int(lib().chainhull_workspace_bytes(int(n)))
 

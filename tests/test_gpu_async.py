@@ -131,3 +131,50 @@ def test_async_graph_replays():
         torch.cuda.synchronize()
         c = int(cnt.item())
         assert np.array_equal(out[:c].cpu().numpy(), ref), rep
+
+
+def test_async_three_stream_graph_replays():
+    # one call per input on its own stream, the fork and join captured in one
+    # graph, as the benchmark replays it
+    n = 1_000_000
+    kinds = ("square", "disk", "gaussian")
+    d = [torch.from_numpy(wl.generate(kinds[k], n, 351 + k)).cuda() for k in range(3)]
+    outs = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    cnt = torch.zeros(3, dtype=torch.int32, device="cuda")
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    cur = torch.cuda.current_stream()
+    say("  hull2d_async on three streams: warm-up and capture")
+
+    def fork_join(base):
+        for k in range(3):
+            streams[k].wait_stream(base)
+            assert ch.hull2d_async(d[k], outs[k], cnt[k:k + 1], streams[k]) == ch.CH_OK
+        for st in streams:
+            base.wait_stream(st)
+
+    fork_join(cur)  # warm-up: the workspaces exist before the capture
+    torch.cuda.synchronize()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(cur)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        fork_join(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(4):
+        pts = [wl.generate(kinds[(k + rep) % 3], n, 360 + 3 * rep + k) for k in range(3)]
+        for k in range(3):
+            d[k].copy_(torch.from_numpy(pts[k]))
+            outs[k].zero_()
+        cnt.fill_(-7)
+        refs = [ch.hull2d(x).cpu().numpy() for x in d]  # eager work between the replays
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        c = cnt.cpu().numpy()
+        for k in range(3):
+            assert np.array_equal(outs[k][:c[k]].cpu().numpy(), refs[k]), (rep, k)
+    del g
+    torch.cuda.synchronize()
+    for st in streams:
+        ch.release_stream(st)
