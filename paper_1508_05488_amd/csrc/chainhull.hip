@@ -674,32 +674,38 @@ __device__ inline void make_quad(ExtAcc r, Quad& Q)
 
 // Every workgroup reduces the per-workgroup extreme partials itself (a few
 // tens of KB) and derives the quadrilateral; workgroup 0 publishes it.
-__device__ inline void reduce_quad(const ExtPartial* __restrict__ part, int nparts, DevHeader* __restrict__ hdr,
+// Thread t holds partials t, t + kBlock, ... (nparts <= kStreamGrid); the
+// loads are issued first (load_partials) so that other set-up can run while
+// they are in flight.
+constexpr int kPartPer = kStreamGrid / kBlock;
+
+__device__ inline void load_partials(const ExtPartial* __restrict__ part, int nparts, ExtPartial (&p)[kPartPer])
+{
+#pragma unroll
+    for (int u = 0; u < kPartPer; ++u) {
+        const int b = u * kBlock + (int)threadIdx.x;
+        if (b < nparts) p[u] = part[b];
+    }
+}
+
+__device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, DevHeader* __restrict__ hdr,
                                    Quad& Q, ExtAcc* sh)
 {
     ExtAcc r;
     ext_init(r);
-    constexpr int kU = 4;  // partials loaded together per thread
-    for (int b0 = threadIdx.x; b0 < nparts; b0 += kU * kBlock) {
-        ExtPartial p[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (b0 + u * kBlock < nparts) p[u] = part[b0 + u * kBlock];
+    for (int u = 0; u < kPartPer; ++u) {
+        if (u * kBlock + (int)threadIdx.x >= nparts) continue;
+        ExtAcc o;
+        for (int e = 0; e < 2; ++e) {
+            o.kmin[e] = p[u].kmin[e];
+            o.kmax[e] = p[u].kmax[e];
+            o.imin[e] = p[u].imin[e];
+            o.imax[e] = p[u].imax[e];
         }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (b0 + u * kBlock >= nparts) continue;
-            ExtAcc o;
-            for (int e = 0; e < 2; ++e) {
-                o.kmin[e] = p[u].kmin[e];
-                o.kmax[e] = p[u].kmax[e];
-                o.imin[e] = p[u].imin[e];
-                o.imax[e] = p[u].imax[e];
-            }
-            o.bad = p[u].err != 0;
-            o.hi = 0;
-            ext_combine(r, o);
-        }
+        o.bad = p[u].err != 0;
+        o.hi = 0;
+        ext_combine(r, o);
     }
     ext_block_reduce(r, sh);
     __shared__ Quad sq;
@@ -753,13 +759,15 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
     __shared__ uint32_t scratch[kWaves];
     __shared__ uint32_t lcnt[kBuckets];  // per sort bucket, this chunk
     __shared__ u64 lmin[kBuckets];
+    ExtPartial pp[kPartPer];
+    load_partials(part, nparts, pp);  // in flight during the LDS set-up
     for (int b = threadIdx.x; b < kBuckets; b += kBlock) {
         lcnt[b] = 0;
         lmin[b] = ~0ull;
     }
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     Quad Q;
-    reduce_quad(part, nparts, hdr, Q, sh);
+    reduce_quad(pp, nparts, hdr, Q, sh);
     if (blockIdx.x == 0) {
         // the number of open points, for the call's counts
         static_assert(kStreamGrid % kBlock == 0, "open-point counts per thread");
@@ -1135,7 +1143,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
     {
         // one wave per bucket of at most kWaveBucket records
         const uint32_t b = blockIdx.x * kBucketsPerSpa + wave;
-        const uint32_t m = bk.cur[b];
+        const uint32_t m = __builtin_amdgcn_readfirstlane(bk.cur[b]);  // the same in every lane
         if (lane == 0) s_fill[wave] = m;
         if (m <= kWaveBucket) {
             const uint32_t off = bk.off[b], thr = bk.thr[b];
@@ -1147,15 +1155,18 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
                 idx = (uint32_t)v;
             }
             bool kept = lane < m && k2 < thr;
+            // j is the same in every lane: lane j's values by readlane (no LDS
+            // round trip, unlike a general shuffle)
             for (uint32_t j = 0; j < m; ++j) {
-                const uint32_t a1 = __shfl(k1, j), a2 = __shfl(k2, j), ai = __shfl(idx, j);
+                const uint32_t a1 = __builtin_amdgcn_readlane(k1, j), a2 = __builtin_amdgcn_readlane(k2, j),
+                               ai = __builtin_amdgcn_readlane(idx, j);
                 const bool prec = a1 < k1 || (a1 == k1 && (a2 < k2 || (a2 == k2 && ai < idx)));
                 if (prec && a2 <= k2) kept = false;
             }
             const u64 kb = __ballot(kept);
             uint32_t rank = 0;
             for (uint32_t j = 0; j < m; ++j) {
-                const uint32_t a1 = __shfl(k1, j);
+                const uint32_t a1 = __builtin_amdgcn_readlane(k1, j);
                 if (((kb >> j) & 1ull) && a1 < k1) ++rank;
             }
             if (kept) dev_chain[off + rank] = chain_rec(b >> kBucketBits, k1, k2, idx);
