@@ -38,6 +38,20 @@ def test_strerror_and_workspace_bound():
     assert ch.workspace_bytes(10) > 0
 
 
+def test_single_hull_entry_points_reject_bad_arguments():
+    # checked on the host before any device call (no GPU is touched)
+    L = ch.lib()
+    buf = ctypes.create_string_buffer(64)
+    base = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
+    for fn in (L.hull2d, L.hull2d_async):
+        assert fn(base, -1, base, base, None) == ch.CH_EINVAL          # n < 0
+        assert fn(base, 1 << 31, base, base, None) == ch.CH_EINVAL     # n > 2^31 - 1
+        assert fn(base, 5, base, None, None) == ch.CH_EINVAL           # no count
+        assert fn(None, 5, base, base, None) == ch.CH_EINVAL           # no points
+        assert fn(base, 5, None, base, None) == ch.CH_EINVAL           # no output
+        assert fn(base + 4, 5, base, base, None) == ch.CH_EINVAL       # points not 8-byte aligned
+
+
 def _finish_via_library(pts):
     res = steps.cudachain(pts)
     X, Y = steps.to_int(pts)
