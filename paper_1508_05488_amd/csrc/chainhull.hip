@@ -1919,6 +1919,10 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     if (rounds > 0) load_round(0, va);
     if (rounds > 1) load_round(1, vb);
     bool full = false;  // the same in every thread
+    // (uniform) the fill at the last check, counting the two points the head
+    // and tail visits may have listed before it; rounds since; the wcnt
+    // buffer of the next check
+    uint32_t known = 2, since = 0, par = 0;
     for (uint32_t r = 0; r < rounds; ++r) {
         if (r + 2 < rounds) load_round(r + 2, vc);
 #pragma unroll
@@ -1936,19 +1940,31 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             list_point(X0, Y0, i0, valid, sx0, sy0);
             list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
         }
-        // the list's fill after this round, the same in every thread: each
-        // wave posts its own count (double-buffered: a wave that runs ahead
-        // writes the other buffer)
-        if (lane == 0) wcnt[r & 1][wave] = wtot;
-        __syncthreads();
-        uint32_t fill = 0;
+        // The list holds at most known + since * kBatchRound points now and
+        // the next round adds at most kBatchRound: only when that bound
+        // could pass the list's room is the fill taken (a workgroup
+        // barrier), the same in every thread: each wave posts its own count
+        // (double-buffered: a wave that runs ahead to the next check writes
+        // the other buffer).
+        ++since;
+        if (known + (since + 1) * kBatchRound > (uint32_t)kBatchList) {
+            if (lane == 0) wcnt[par][wave] = wtot;
+            __syncthreads();
+            uint32_t fill = 0;
 #pragma unroll
-        for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[r & 1][w];
-        // a list still too full after the compaction: the set has too many
-        // open points for the workgroup
-        if (fill > (uint32_t)kBatchList - kBatchRound && compact() > (uint32_t)kBatchList - kBatchRound) {
-            full = true;
-            break;
+            for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[par][w];
+            par ^= 1u;
+            if (fill > (uint32_t)kBatchList - kBatchRound) {
+                fill = compact();
+                // a list still too full after the compaction: the set has
+                // too many open points for the workgroup
+                if (fill > (uint32_t)kBatchList - kBatchRound) {
+                    full = true;
+                    break;
+                }
+            }
+            known = fill;
+            since = 0;
         }
 #pragma unroll
         for (int u = 0; u < kBatchUnroll; ++u) {
@@ -1956,6 +1972,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             vb[u] = vc[u];
         }
     }
+    __syncthreads();  // every append of the stream is in the list
     if (full) {
         if (tid == 0) out_counts[set] = kBatchRedo;
         return;
