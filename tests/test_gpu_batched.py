@@ -105,3 +105,21 @@ def test_batched_repeat_is_deterministic():
     assert torch.equal(ca, cb)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+@pytest.mark.timeout(300)
+def test_benchmark_workload_sampled_sets():
+    # the 4096-set workload the benchmark times (594M points, one call), the
+    # hull of a seeded sample of 256 sets against the oracle, every count
+    # a hull size (no set handed back)
+    pts, offs, dists = wl.batched_sets(4096, 1_000, 1_000_000, seed=7)
+    say(f"  hull2d_batched: 4096 sets, {offs[-1]} points")
+    hulls, counts = ch.hull2d_batched(torch.from_numpy(pts).cuda(), offs)
+    c = counts.cpu().numpy()
+    assert np.all(c > 0)
+    st = ch.last_batch_stats()
+    assert st["redo_sets"] == 0 and st["device_sets"] == 4096, st
+    rng = np.random.default_rng(4096)
+    for s in sorted(rng.choice(4096, size=256, replace=False)):
+        want = oracle.hull(pts[offs[s]:offs[s + 1]])
+        assert np.array_equal(hulls[s].cpu().numpy(), want), (s, dists[s], int(offs[s + 1] - offs[s]))
