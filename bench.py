@@ -13,9 +13,16 @@ call per input on three streams; that three-stream step captured in a HIP
 graph and replayed.  Their results are checked equal; ``calls`` holds all
 four.
 
-Prints one JSON line.  Extra fields: per-distribution rates and counts, the
-per-stage times from HIP events recorded on the library's stream, the
-roofline of the dominant kernel, and the CPU oracle timed on the host.
+``per_config`` times every single-hull configuration on its own, cold: a
+1 GiB write precedes each repetition so that no input is served from the
+256 MB last-level cache.  For each it gives the preprocessing time t_pre
+(one HIP event pair around steps 1-6 on the library's stream), the
+end-to-end time of one ``hull2d_async`` call (host clock, until the count
+is read), the B_alg roofline fraction of t_pre and the per-stage split.
+
+Prints one JSON line.  Further fields: the roofline of the dominant kernel,
+the CPU oracle timed on the host, the batched workload against the plain
+path, and the serving loop at several arrival rates against the plain path.
 """
 from __future__ import annotations
 
@@ -36,8 +43,28 @@ DISTS = (("square", 2), ("disk", 3), ("gaussian", 4))
 N_POINTS = 20_000_000
 BATCH_SETS, BATCH_LO, BATCH_HI, BATCH_SEED = 4096, 1_000, 1_000_000, 7
 SERVE_LO, SERVE_HI, SERVE_POOL, SERVE_SEED = 10_000, 20_000_000, 48, 8
+FLUSH_BYTES = 1 << 30
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1508_05488_amd", "csrc", "chainhull.hip")
+# single-hull configurations timed one by one: name -> (distribution, n, seed, cold repetitions)
+PER_CONFIG = (
+    ("square_100k", "square", 100_000, 1, 21),
+    ("square_20m", "square", 20_000_000, 2, 20),
+    ("disk_20m", "disk", 20_000_000, 3, 20),
+    ("gaussian_20m", "gaussian", 20_000_000, 4, 20),
+    ("adversarial_20m", "adversarial", 20_000_000, 5, 20),
+    ("adversarial_100m", "adversarial", 100_000_000, 6, 20),
+)
+# the paper's own figures, quoted as context only (other hardware)
+PAPER_CONTEXT = {
+    "claim": "5x-6x speedup over Qhull at 20M points (abstract, introduction, conclusion)",
+    "hardware": "GTX 660M (Table 2) and GT 640 (Table 4), Kepler, 384 CUDA cores each, CUDA 5.5, "
+                "with Intel i7-3610QM / i5-3470 hosts",
+    "caveat": "the 20M random-square rows of Tables 2 and 4 give 4.01x and 4.07x; the 5x-6x come from the "
+              "projected mesh sets (Tables 3 and 5)",
+    "paper_20m_square_gpu_mpts_per_s": {"gtx660m": 34.4, "gt640": 36.9},
+    "paper_20m_square_total_ms": {"gtx660m": 587.4, "gt640": 544.4},
+}
 
 
 def parse():
@@ -51,9 +78,11 @@ def parse():
     ap.add_argument("--batch-sets", type=int, default=BATCH_SETS)
     ap.add_argument("--batch-calls", type=int, default=30)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--no-other", action="store_true", help="skip the 100K and adversarial single-hull configurations")
-    ap.add_argument("--serve-rate", type=float, default=10_000.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--no-per-config", action="store_true", help="skip the per-configuration single-hull table")
+    ap.add_argument("--configs", default="", help="comma-separated subset of the per-configuration names")
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.75,1.0,1.2",
+                    help="arrival rates as fractions of the server's measured capacity")
+    ap.add_argument("--serve-requests", type=int, default=1500)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-set comparison of the batched measurement")
@@ -104,36 +133,115 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def measure_other_configs(ch, wl, torch, dev):
-    """The other single-hull configurations: 100K uniform points (latency:
-    median of 21 blocking calls) and 20M adversarial points (10 % on a
-    circle; median of 3 blocking calls, end to end, its finish on the host)."""
+def b_alg(n, s1, s2) -> float:
+    """Algorithmic bytes of steps 1-6: two passes over the points, each
+    round-1 survivor record written and read once, each SPA survivor written."""
+    return 16.0 * n + 24.0 * s1 + 12.0 * s2
+
+
+def moved_bytes(n, st) -> float:
+    """Bytes the path's kernels must move at least, from the call's counts:
+    the points once; the open points written by the pass and read back; the
+    sort records written, re-read and read by the per-bucket pass; the chain
+    points written and read."""
+    return 8.0 * n + 24.0 * st["open"] + 36.0 * st["candidates"] + 24.0 * float(sum(st["s2"]))
+
+
+class Flusher:
+    """Writes 1 GiB of device memory: the 256 MB last-level cache then holds
+    none of an input, so the next repetition reads it from HBM."""
+
+    def __init__(self, torch, dev):
+        self.buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+        self.k = 0
+
+    def __call__(self):
+        self.k += 1
+        self.buf.fill_(float(self.k))
+
+
+def measure_per_config(ch, wl, torch, dev, args, flush, names):
+    """Each single-hull configuration alone, cold (see the module docstring)."""
     out = {}
-    for name, dist, n, seed, reps in (("square_100k", "square", 100_000, 1, 21),
-                                      ("adversarial_20m", "adversarial", 20_000_000, 5, 3)):
+    stream = torch.cuda.current_stream()
+    for name, dist, n, seed, reps in PER_CONFIG:
+        if names and name not in names:
+            continue
+        print(f"bench: per-config {name}", file=sys.stderr, flush=True)
         pts = wl.generate(dist, n, seed)
         d = torch.from_numpy(pts).to(dev)
-        for _ in range(2):
-            ch.hull2d(d)
+        o_b = torch.empty(n, dtype=torch.int32, device=dev)
+        c_b = torch.zeros(1, dtype=torch.int32, device=dev)
+        o_a = torch.empty(n, dtype=torch.int32, device=dev)
+        c_a = torch.zeros(1, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            ch.hull2d_into(d, o_b, c_b, stream)
+            ch.hull2d_async(d, o_a, c_a, stream)
         torch.cuda.synchronize()
-        t = []
+        # t_pre: one event pair around steps 1-6 (and one around the finish)
+        ch.set_timing(2)
+        t_pre, t_fin = [], []
         for _ in range(reps):
-            a = time.perf_counter()
-            h = ch.hull2d(d)
-            torch.cuda.synchronize()
-            t.append(time.perf_counter() - a)
-        ch.set_timing(True)
-        ch.hull2d(d)
+            flush()
+            rc = ch.hull2d_into(d, o_b, c_b, stream)
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, f"hull2d {name}")
+            st = ch.last_stats()
+            t_pre.append(st["ms_pre"])
+            t_fin.append(st["ms_finish"])
+        ch.set_timing(0)
         torch.cuda.synchronize()
-        ch.set_timing(False)
-        st = ch.last_stats()
-        ms = float(np.median(t)) * 1e3
-        out[name] = {"n": n, "seed": seed, "input_sha256_16": sha16(pts), "ms_median": round(ms, 4),
-                     "mpts_per_s": round(n / ms / 1e3, 1), "hull": int(h.numel()), "polygon": st["polygon"],
-                     "device_finish": st["device_finish"],
-                     "stages_ms": {k: round(v, 4) for k, v in st["ms"].items() if not k.startswith("unused")}}
-        del d
-    torch.cuda.empty_cache()
+        # t_e2e: one hull2d_async call, until its count is on the host
+        t_e2e, redo = [], 0
+        for _ in range(reps):
+            flush()
+            c_a.fill_(-7)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            rc = ch.hull2d_async(d, o_a, c_a, stream)
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, f"hull2d_async {name}")
+            c = int(c_a.item())
+            if c == ch.CH_BATCH_REDO:
+                redo += 1
+                rc = ch.hull2d_into(d, o_a, c_a, stream)
+                if rc != ch.CH_OK:
+                    raise ch.ChainHullError(rc, f"hull2d {name}")
+                c = int(c_a.item())
+            t_e2e.append(time.perf_counter() - a)
+        cb = int(c_b.item())
+        same = int(c_a.item()) == cb and torch.equal(o_a[:cb], o_b[:cb])
+        # the stage split (every stage bracketed by events), cold
+        flush()
+        ch.set_timing(1)
+        ch.hull2d_into(d, o_b, c_b, stream)
+        st1 = ch.last_stats()
+        ch.set_timing(0)
+        # exact round-1 and SPA counts (outside the timed calls)
+        _, pst = ch.polygon(d)
+        torch.cuda.synchronize()
+        tp = float(np.median(t_pre))
+        te = float(np.median(t_e2e)) * 1e3
+        s1, s2 = int(sum(pst["s1"])), int(sum(pst["s2"]))
+        ba = b_alg(n, s1, s2)
+        mv = moved_bytes(n, st1)
+        out[name] = {
+            "n": n, "seed": seed, "input_sha256_16": sha16(pts), "reps": reps,
+            "t_pre_us": round(tp * 1e3, 2), "t_pre_us_p10_p90": [round(float(np.percentile(t_pre, q)) * 1e3, 2)
+                                                                for q in (10, 90)],
+            "t_finish_us": round(float(np.median(t_fin)) * 1e3, 2),
+            "t_e2e_us": round(te * 1e3, 2),
+            "mpts_per_s_e2e": round(n / te / 1e3, 1),
+            "mpts_per_s_pre": round(n / tp / 1e3, 1),
+            "b_alg_bytes": ba, "b_alg_frac": round(ba / (tp * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "moved_bytes": mv, "moved_frac": round(mv / (tp * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "hull": cb, "polygon": st1["polygon"], "open": st1["open"], "candidates": st1["candidates"],
+            "s1": s1, "s2": s2, "device_finish": st1["device_finish"], "async_redo": redo,
+            "async_equals_blocking": bool(same),
+            "stages_us": {k: round(v * 1e3, 2) for k, v in st1["ms"].items()},
+        }
+        del d, o_a, o_b
+        torch.cuda.empty_cache()
     return out
 
 
@@ -235,30 +343,45 @@ def measure_batched(ch, wl, torch, dev, args):
 
 
 def measure_serving(ch, wl, torch, dev, args):
-    """Hull requests arriving as a Poisson stream at a fixed rate, sizes
-    log-uniform in [1e4, 2e7], each uniform square, disk or Gaussian (a pool
-    of 48 seeded requests resident in HBM, submitted in turn), served by the
-    continuous-batching server with a 288 GB budget.  Latency is from
-    submission to completion.  The same arrival stream is then served by
-    the plain path, one blocking hull2d call at a time in arrival order."""
+    """Hull requests arriving as a Poisson stream, sizes log-uniform in
+    [1e4, 2e7], each uniform square, disk or Gaussian, served by the
+    continuous-batching server with a 288 GB budget.  The requests cycle
+    through a pool of 48 seeded inputs resident in HBM (about 1 GB, four
+    times the last-level cache, so a request's points are not cached from
+    its previous turn).  First the server's closed-loop capacity (all
+    requests submitted at once); then, at each arrival rate of a sweep
+    (fractions of that capacity), the server and the plain path (one
+    blocking hull2d at a time, in arrival order) on the same arrival
+    times.  Latency is from arrival to completion."""
     import threading
     rng = np.random.default_rng(SERVE_SEED)
     names = ("square", "disk", "gaussian")
     sizes = np.floor(np.exp(rng.uniform(np.log(SERVE_LO), np.log(SERVE_HI), size=SERVE_POOL))).astype(np.int64)
     pool = [torch.from_numpy(wl.generate(names[k % 3], int(n), SERVE_SEED * 1000 + k)).to(dev)
             for k, n in enumerate(sizes)]
+    pool_bytes = int(8 * sizes.sum())
     nreq = args.serve_requests
     order = np.arange(nreq) % SERVE_POOL
-    gaps = rng.exponential(1.0 / args.serve_rate, size=nreq)
+    unit_gaps = rng.exponential(1.0, size=nreq)
     pts_total = int(sum(int(sizes[k]) for k in order))
 
-    def run_server():
+    # closed-loop capacity: the same requests all submitted at once
+    with ch.Server(workers=args.serve_workers, mem_budget=288 << 30) as srv:
+        for p in pool[:8]:
+            srv.wait(srv.submit(p))
+        t0 = time.perf_counter()
+        tk = [srv.submit(pool[order[k]]) for k in range(min(nreq, 8 * SERVE_POOL))]
+        for t in tk:
+            srv.wait(t)
+        cap = len(tk) / (time.perf_counter() - t0)
+
+    def run_server(rate):
+        gaps = unit_gaps / rate
         lat = []
         with ch.Server(workers=args.serve_workers, mem_budget=288 << 30) as srv:
             for p in pool[:8]:  # warm the workers' workspaces
                 srv.wait(srv.submit(p))
             tickets = []
-            done = threading.Event()
 
             def waiter():
                 k = 0
@@ -268,7 +391,6 @@ def measure_serving(ch, wl, torch, dev, args):
                         k += 1
                     else:
                         time.sleep(0)
-                done.set()
 
             th = threading.Thread(target=waiter)
             th.start()
@@ -284,55 +406,57 @@ def measure_serving(ch, wl, torch, dev, args):
             st = srv.stats()
         return np.array(lat), elapsed, st
 
-    lat, elapsed, st = run_server()
-    # closed-loop capacity: the same requests all submitted at once
-    with ch.Server(workers=args.serve_workers, mem_budget=288 << 30) as srv:
-        for p in pool[:8]:
-            srv.wait(srv.submit(p))
-        t0 = time.perf_counter()
-        tk = [srv.submit(pool[order[k]]) for k in range(min(nreq, 4 * SERVE_POOL))]
-        for t in tk:
-            srv.wait(t)
-        cap = len(tk) / (time.perf_counter() - t0)
-    # the plain path on the same arrivals: one hull2d at a time
     out = torch.empty(int(sizes.max()), dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     lib = ch.lib()
-    torch.cuda.synchronize()
-    plat = []
-    t0 = time.perf_counter()
-    arrive = t0
-    for k in range(nreq):
-        arrive += gaps[k]
-        while time.perf_counter() < arrive:
-            pass
-        p = pool[order[k]]
-        rc = lib.hull2d(p.data_ptr(), p.shape[0], out.data_ptr(), cnt.data_ptr(), stream.cuda_stream)
-        if rc != ch.CH_OK:
-            raise ch.ChainHullError(rc, "hull2d")
-        stream.synchronize()
-        plat.append(time.perf_counter() - arrive)
-    pel = time.perf_counter() - t0
-    plat = np.array(plat) * 1e3
+
+    def run_plain(rate):
+        gaps = unit_gaps / rate
+        torch.cuda.synchronize()
+        plat = []
+        t0 = time.perf_counter()
+        arrive = t0
+        for k in range(nreq):
+            arrive += gaps[k]
+            while time.perf_counter() < arrive:
+                pass
+            p = pool[order[k]]
+            rc = lib.hull2d(p.data_ptr(), p.shape[0], out.data_ptr(), cnt.data_ptr(), stream.cuda_stream)
+            if rc != ch.CH_OK:
+                raise ch.ChainHullError(rc, "hull2d")
+            stream.synchronize()
+            plat.append(time.perf_counter() - arrive)
+        return np.array(plat) * 1e3, time.perf_counter() - t0
+
+    sweep = []
+    for frac in [float(x) for x in args.serve_rates.split(",") if x]:
+        rate = frac * cap
+        print(f"bench: serving at {rate:.0f} requests/s", file=sys.stderr, flush=True)
+        lat, elapsed, st = run_server(rate)
+        plat, pel = run_plain(rate)
+        sweep.append({
+            "rate_fraction_of_capacity": frac, "arrival_rate": round(rate, 1),
+            "server": {"hulls_per_s": round(nreq / elapsed, 1), "mpts_per_s": round(pts_total / elapsed / 1e6, 1),
+                       "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                       "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+                       "batches": st["batches"], "batched_requests": st["batched_requests"],
+                       "single_requests": st["single_requests"], "max_inflight": st["max_inflight"]},
+            "plain_path": {"hulls_per_s": round(nreq / pel, 1),
+                           "latency_ms_p50": round(float(np.percentile(plat, 50)), 4),
+                           "latency_ms_p99": round(float(np.percentile(plat, 99)), 4)},
+        })
     del pool, out
     torch.cuda.empty_cache()
     return {
-        "workload": f"Poisson arrivals at {args.serve_rate:.0f} requests/s, sizes log-uniform in [{SERVE_LO}, "
-                    f"{SERVE_HI}], uniform square, disk or Gaussian (a pool of {SERVE_POOL} seeded requests in HBM, "
-                    f"submitted in turn); {args.serve_workers} worker streams; 288 GB admission budget",
-        "requests": nreq,
-        "points": pts_total,
-        "hulls_per_s": round(nreq / elapsed, 1),
-        "mpts_per_s": round(pts_total / elapsed / 1e6, 1),
-        "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
-        "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+        "workload": f"Poisson arrivals, sizes log-uniform in [{SERVE_LO}, {SERVE_HI}], uniform square, disk or "
+                    f"Gaussian (a pool of {SERVE_POOL} seeded requests in HBM, {pool_bytes / 1e9:.2f} GB, cycled); "
+                    f"{args.serve_workers} worker streams; 288 GB admission budget; {nreq} requests per rate",
+        "requests_per_rate": nreq,
+        "points_per_rate": pts_total,
         "capacity_hulls_per_s": round(cap, 1),
-        "server_stats": st,
-        "plain_path": {"hulls_per_s": round(nreq / pel, 1),
-                       "latency_ms_p50": round(float(np.percentile(plat, 50)), 4),
-                       "latency_ms_p99": round(float(np.percentile(plat, 99)), 4),
-                       "note": "same arrivals, one blocking hull2d call at a time in arrival order"},
+        "sweep": sweep,
+        "note": "plain path: one blocking hull2d call at a time in arrival order, same arrival times",
     }
 
 
@@ -358,6 +482,7 @@ def main():
     outs = {d: (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
             for d, _ in DISTS}
     stream = torch.cuda.current_stream()
+    print("bench: headline steps", file=sys.stderr, flush=True)
 
     def step(collect=None):
         for d, _ in DISTS:
@@ -377,7 +502,6 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
     total_pts = n * len(DISTS) * args.steps
     value_blocking = total_pts / elapsed / 1e6
 
@@ -409,6 +533,9 @@ def main():
     for _ in range(args.warmup):
         step_async()
     torch.cuda.synchronize()
+    acnt.fill_(-7)
+    for d, _ in DISTS:
+        aout[d].fill_(-7)
     t0a = time.perf_counter()
     for _ in range(args.steps):
         step_async()
@@ -449,19 +576,28 @@ def main():
             elif c < 0:
                 raise ch.ChainHullError(c, f"hull2d_async {d}")
 
+    def clear_multi():
+        mcnt.fill_(-7)
+        for d, _ in DISTS:
+            mout[d].fill_(-7)
+        torch.cuda.synchronize()
+
+    def check_multi(what):
+        for k, (d, _) in enumerate(DISTS):
+            c = int(outs[d][1].item())
+            if int(mcnt[k].item()) != c or not torch.equal(mout[d][:c], outs[d][0][:c]):
+                raise RuntimeError(f"{what} and hull2d differ on {d}")
+
     for _ in range(args.warmup):
         step_streams()
-    torch.cuda.synchronize()
+    clear_multi()
     t0m = time.perf_counter()
     for _ in range(args.steps):
         step_streams()
     torch.cuda.synchronize()
     t1m = time.perf_counter()
     elapsed_streams = t1m - t0m
-    for k, (d, _) in enumerate(DISTS):
-        c = int(outs[d][1].item())
-        if int(mcnt[k].item()) != c or not torch.equal(mout[d][:c], outs[d][0][:c]):
-            raise RuntimeError(f"hull2d_async on three streams and hull2d differ on {d}")
+    check_multi("hull2d_async on three streams")
     value_streams = total_pts / elapsed_streams / 1e6
 
     # timed region 1d: the three-stream step captured once in a HIP graph
@@ -501,16 +637,15 @@ def main():
     for _ in range(args.warmup):
         step_graph()
     torch.cuda.synchronize()
+    # the replays below must write every result again: clear them first
+    clear_multi()
     t0g = time.perf_counter()
     for _ in range(args.steps):
         step_graph()
     torch.cuda.synchronize()
     t1g = time.perf_counter()
     elapsed_graph = t1g - t0g
-    for k, (d, _) in enumerate(DISTS):
-        c = int(outs[d][1].item())
-        if int(mcnt[k].item()) != c or not torch.equal(mout[d][:c], outs[d][0][:c]):
-            raise RuntimeError(f"the graph of three hull2d_async streams and hull2d differ on {d}")
+    check_multi("the graph of three hull2d_async streams")
     value_graph = total_pts / elapsed_graph / 1e6
     del graph
     torch.cuda.synchronize()
@@ -530,32 +665,13 @@ def main():
     ch.set_timing(True)
     stats = {d: [] for d, _ in DISTS}
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
     for _ in range(args.steps):
         step(stats)
     torch.cuda.synchronize()
-    t3 = time.perf_counter()
     ch.set_timing(False)
-
     stage_ms = {}
     for key in ch.STAGES:
         stage_ms[key] = float(np.mean([s["ms"][key] for d, _ in DISTS for s in stats[d]]))
-    per_dist = {}
-    for d, _ in DISTS:
-        s = stats[d][-1]
-        per_dist[d] = {
-            "hull": s["hull"], "s1": int(sum(s["s1"])), "open": s["open"], "candidates": s["candidates"],
-            "s2": int(sum(s["s2"])),
-        }
-        for key in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish"):
-            per_dist[d][key + "_ms"] = float(np.mean([x["ms"][key] for x in stats[d]]))
-
-    # counts of the discard rounds (the stats mode of the library counts the
-    # round-1 survivors; outside the timed regions)
-    for d, _ in DISTS:
-        _, pst = ch.polygon(inputs[d])
-        per_dist[d].update({"s1": int(sum(pst["s1"])), "s2": int(sum(pst["s2"]))})
-    torch.cuda.synchronize()
 
     # roofline of the dominant kernel, the one pass over the points: it reads
     # 8 bytes per point and writes 12 bytes per listed (open) point; its
@@ -569,29 +685,37 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms}
 
-    # whole-preprocessing accounting with B_alg = 16n + 24*s1 + 12*s2
-    b_alg = [16.0 * n + 24.0 * per_dist[d]["s1"] + 12.0 * per_dist[d]["s2"] for d, _ in DISTS]
-    t_pre = sum(stage_ms[k] for k in ("sample", "stream", "cand", "sort", "spa"))
-    pre_frac = float(np.mean(b_alg)) / (t_pre * 1e-3) / (HBM_PEAK_GBS * 1e9) if t_pre > 0 else 0.0
-
     cpu = None
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         from oracle import hull as oracle
-        tc = 0.0
+        per = []
         for d, _ in DISTS:
-            a = time.perf_counter()
-            oracle.hull(host[d])
-            tc += time.perf_counter() - a
+            t = []
+            for _ in range(3):
+                a = time.perf_counter()
+                oracle.hull(host[d])
+                t.append(time.perf_counter() - a)
+            per.append(float(np.median(t)))
+        tc = float(sum(per))
         cpu = {"value": round(n * len(DISTS) / tc / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-               "sample": f"one single-threaded oracle run on each of the three {n}-point inputs ({tc:.1f} s); "
-                         f"host CPU {cpu_model()}, {os.cpu_count()} logical CPUs"}
+               "sample": f"the single-threaded C oracle on each of the three {n}-point inputs, median of 3 runs "
+                         f"each ({tc:.1f} s for the three medians); host CPU {cpu_model()}, "
+                         f"{os.cpu_count()} logical CPUs"}
+    del inputs, outs, aout
+    torch.cuda.empty_cache()
 
-    other = None if args.no_other else measure_other_configs(ch, wl, torch, dev)
+    flush = Flusher(torch, dev)
+    per_config = None
+    if not args.no_per_config:
+        names = [x for x in args.configs.split(",") if x]
+        per_config = measure_per_config(ch, wl, torch, dev, args, flush, names)
+    del flush
+    torch.cuda.empty_cache()
 
     batched = None
     if not args.no_batched:
-        del inputs, outs
-        torch.cuda.empty_cache()
+        print("bench: batched", file=sys.stderr, flush=True)
         batched = measure_batched(ch, wl, torch, dev, args)
 
     serving = None
@@ -625,7 +749,8 @@ def main():
                    "api": api},
         "calls": {"hull2d_async": {"value": round(value_async, 2), "ms_per_step": round(1e3 * elapsed_async / args.steps, 4),
                                    "redo": redo[0],
-                                   "note": "three calls queued per step, one synchronisation when the counts are read"},
+                                   "note": "three calls queued on one stream per step, one synchronisation when "
+                                           "the counts are read"},
                   "hull2d": {"value": round(value_blocking, 2), "ms_per_step": round(1e3 * elapsed / args.steps, 4),
                              "note": "three blocking calls per step"},
                   "hull2d_async_3_streams": {"value": round(value_streams, 2),
@@ -638,12 +763,9 @@ def main():
                                                            "replayed: one launch and one synchronisation per step"}},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "stages_ms": {k: round(v, 4) for k in ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")
-                      for v in [stage_ms[k]]},
-        "ms_per_step_with_events": round(1e3 * (t3 - t2) / args.steps, 4),
-        "preprocess_b_alg_frac": round(pre_frac, 4),
-        "per_distribution": per_dist,
-        "other_configs": other,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "per_config": per_config,
+        "paper_context": PAPER_CONTEXT,
         "batched": batched,
         "serving": serving,
     }

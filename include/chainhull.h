@@ -47,7 +47,7 @@ typedef enum {
     CH_EDOMAIN = -2, /* a coordinate is not an integer in [0, 2^23) */
     CH_ENOMEM = -3,  /* device or pinned host allocation failed */
     CH_EHIP = -4,    /* a HIP runtime call failed */
-    CH_EADMIT = -5   /* reserved for admission control in a serving loop */
+    CH_EADMIT = -5   /* a serving request that alone exceeds the server's memory budget */
 } ch_status;
 
 /* Counts and timings of the most recent call on the calling thread. */
@@ -78,6 +78,9 @@ typedef struct {
     float ms[8];
     int32_t device_finish;  /* 1 when hull2d finished step 7 on the device */
     int32_t reserved;
+    float ms_pre;         /* steps 1-6 on the device (stages 0-4) as one HIP event
+                             span, when timing is on */
+    float ms_finish;      /* the device finish (stage 5) as one span */
 } ch_stats;
 
 /*
@@ -221,8 +224,10 @@ int chainhull_finish_host(const int32_t* poly_xy, const int32_t* poly_idx, int64
  * call into *out.  Returns CH_OK, or CH_EINVAL for a null pointer. */
 int chainhull_last_stats(ch_stats* out);
 
-/* Turn per-stage HIP event timing on (nonzero) or off (0) for later calls.
- * Timing adds event records to the stream; it does not change results. */
+/* HIP event timing of later calls: 0 off, 1 every stage (ms[0..5]), 2 only
+ * steps 1-6 and the device finish as two spans (ms_pre, ms_finish: fewer
+ * event records in the stream); any other nonzero value means 1.  Timing
+ * adds event records to the stream; it does not change results. */
 void chainhull_set_timing(int enable);
 
 /* A static description of a ch_status value. */

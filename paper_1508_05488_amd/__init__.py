@@ -51,6 +51,8 @@ class ChStats(ctypes.Structure):
         ("ms", ctypes.c_float * 8),
         ("device_finish", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("ms_pre", ctypes.c_float),
+        ("ms_finish", ctypes.c_float),
     ]
 
     def as_dict(self) -> dict:
@@ -66,6 +68,8 @@ class ChStats(ctypes.Structure):
             "hull": self.hull,
             "ms": dict(zip(STAGES, list(self.ms))),
             "device_finish": bool(self.device_finish),
+            "ms_pre": self.ms_pre,
+            "ms_finish": self.ms_finish,
         }
 
 
@@ -285,8 +289,10 @@ def last_batch_stats() -> dict:
     return st.as_dict()
 
 
-def set_timing(enable: bool) -> None:
-    lib().chainhull_set_timing(1 if enable else 0)
+def set_timing(enable) -> None:
+    """0/False: off; 1/True: every stage; 2: steps 1-6 and the finish as
+    two spans only (ms_pre, ms_finish)."""
+    lib().chainhull_set_timing(2 if enable == 2 else (1 if enable else 0))
 
 
 def release() -> None:

@@ -2590,36 +2590,61 @@ StreamShape stream_shape(size_t n, uint32_t head)
     return sh;
 }
 
-// Records the per-workgroup regions need for any call with up to cap points
-// (k_cand's regions, 4 lists each, fit in the same room since kStreamGrid
-// is a multiple of 4).
+// Records the per-workgroup regions need for any call with up to cap
+// points: k_stream's lists take grid regions, k_cand's take
+// ceil(grid / 4) regions of four lists; grid never exceeds G(cap) and a
+// region never exceeds 2 P(cap) + 2 points (per is rounded up to a whole
+// round of float4s, and is one round below 2^20 float4s).
 size_t region_cap(size_t cap)
 {
-    static_assert(kStreamGrid % kListsPerCand == 0, "k_cand regions");
-    return (size_t)kStreamGrid * stream_shape(cap, 0).region;
+    const size_t round = (size_t)kBlock * kStreamUnroll;
+    const size_t n4 = cap / 2;
+    const size_t g = std::max<size_t>(1, std::min<size_t>(kStreamGrid, (n4 + round - 1) / round));
+    const size_t per = std::max(round, ((n4 + kStreamGrid - 1) / kStreamGrid + round - 1) / round * round);
+    return (g + kListsPerCand) * (2 * per + 2);
 }
 
-size_t device_bytes(size_t cap)
+// The device workspace for calls with up to cap points: its size, and, when
+// w is given, every array's place in it from base.
+size_t layout(Workspace* w, char* base, size_t cap)
 {
     const size_t rc = region_cap(cap);
-    size_t b = 0;
-    b += align_up(sizeof(DevHeader), 256);
-    b += align_up(sizeof(ExtPartial) * kStreamGrid, 256);
-    b += 5 * align_up(sizeof(uint32_t) * kBuckets, 256) + align_up(sizeof(u64) * kBuckets, 256);
-    b += align_up(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks, 256);
-    b += align_up(sizeof(uint32_t) * 4 * kStairSlots, 256);
-    b += 2 * align_up(sizeof(uint32_t) * kStreamGrid, 256);
-    b += align_up(sizeof(uint32_t) * rc, 256) + align_up(sizeof(u64) * rc, 256);
-    b += 2 * align_up(sizeof(uint32_t) * rc, 256);
-    b += 2 * align_up(sizeof(u64) * rc, 256);
-    b += 3 * align_up(sizeof(PolyRec) * cap, 256);
-    b += align_up(sizeof(uint32_t) * 4 * (cap / kSeg + 1), 256);
-    return b;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* r = base ? base + o : nullptr;
+        o += align_up(bytes, 256);
+        return r;
+    };
+    Workspace tmp;
+    Workspace& W = w ? *w : tmp;
+    W.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
+    W.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
+    W.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.kmin = reinterpret_cast<u64*>(take(sizeof(u64) * kBuckets));
+    W.bk.cur = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.thr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.surv = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
+    W.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
+    W.wgcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
+    W.candcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
+    W.open_idx = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
+    W.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
+    for (int i = 0; i < 2; ++i) W.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
+    for (int i = 0; i < 2; ++i) W.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
+    W.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    W.dev_spill = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    W.dev_kept = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
+    W.dev_segcnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * (cap / kSeg + 1)));
+    return o;
 }
+
+size_t device_bytes(size_t cap) { return layout(nullptr, nullptr, cap); }
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
-std::atomic<bool> g_timing{false};
+std::atomic<int> g_timing{0};  // 0 off, 1 every stage, 2 steps 1-6 and the finish only
 thread_local ch_stats t_stats;
 thread_local ch_batch_stats t_bstats;
 
@@ -2660,33 +2685,7 @@ int ensure_device(Workspace& w, size_t n)
     CH_TRY(hipMalloc(&p, device_bytes(cap)));
     w.dbuf = p;
     w.cap = cap;
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        char* r = p + o;
-        o += align_up(bytes, 256);
-        return r;
-    };
-    w.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
-    w.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
-    w.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.bk.kmin = reinterpret_cast<u64*>(take(sizeof(u64) * kBuckets));
-    w.bk.cur = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.bk.thr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.bk.surv = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    w.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
-    w.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
-    const size_t rc = region_cap(cap);
-    w.wgcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
-    w.candcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
-    w.open_idx = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
-    w.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
-    for (int i = 0; i < 2; ++i) w.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
-    for (int i = 0; i < 2; ++i) w.val[i] = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
-    w.dev_chain = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
-    w.dev_spill = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
-    w.dev_kept = reinterpret_cast<PolyRec*>(take(sizeof(PolyRec) * cap));
-    w.dev_segcnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * (cap / kSeg + 1)));
+    layout(&w, p, cap);
     return CH_OK;
 }
 
@@ -2771,7 +2770,9 @@ void free_workspace(Workspace* w)
 
 int record(Workspace& w, int k)
 {
-    if (!g_timing) return CH_OK;
+    const int mode = g_timing;
+    if (!mode) return CH_OK;
+    if (mode == 2 && k != 0 && k != 5 && k != 6) return CH_OK;
     if (!w.events) {
         for (auto& e : w.ev) CH_TRY(hipEventCreate(&e));
         w.events = true;
@@ -2921,11 +2922,17 @@ void fill_stats(const Workspace& w, int64_t n, ch_stats* st, bool stats)
     if (g_timing && w.events) {
         // stage slots: 0 sample + staircases, 1 k_stream, 2 k_cand, 3 sort,
         // 4 SPA + chains, 5 device finish (6 and 7, the host finish, are
-        // wall-clock times set by the caller)
-        for (int k = 0; k < 6; ++k) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
+        // wall-clock times set by the caller); steps 1-6 and the finish as
+        // single spans in either mode
+        if (g_timing == 1) {
+            for (int k = 0; k < 6; ++k) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) st->ms[k] = ms;
+            }
         }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, w.ev[0], w.ev[5]) == hipSuccess) st->ms_pre = ms;
+        if (hipEventElapsedTime(&ms, w.ev[5], w.ev[6]) == hipSuccess) st->ms_finish = ms;
     }
 }
 
@@ -3226,7 +3233,7 @@ int chainhull_last_stats(ch_stats* out)
     return CH_OK;
 }
 
-void chainhull_set_timing(int enable) { g_timing = enable != 0; }
+void chainhull_set_timing(int enable) { g_timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0); }
 
 const char* chainhull_strerror(int status)
 {
