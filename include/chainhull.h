@@ -47,7 +47,8 @@ typedef enum {
     CH_EDOMAIN = -2, /* a coordinate is not an integer in [0, 2^23) */
     CH_ENOMEM = -3,  /* device or pinned host allocation failed */
     CH_EHIP = -4,    /* a HIP runtime call failed */
-    CH_EADMIT = -5   /* a serving request that alone exceeds the server's memory budget */
+    CH_EADMIT = -5,  /* a serving request that alone exceeds the server's memory budget */
+    CH_ECAPACITY = -6 /* hull2d_noalloc: more points than its fixed device buffer holds */
 } ch_status;
 
 /* Counts and timings of the most recent call on the calling thread. */
@@ -122,6 +123,35 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
  * statistics of chainhull_last_stats are not filled.
  */
 int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
+
+/* The fixed device buffer of hull2d_noalloc: its size, and the most points a
+ * call may have. */
+#define CH_NOALLOC_MAX_POINTS 1048576
+#define CH_NOALLOC_SCRATCH_BYTES (96u << 20)
+
+/*
+ * hull2d_noalloc: hull2d_async for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and result as hull2d_async, with
+ * every intermediate array in one fixed buffer of CH_NOALLOC_SCRATCH_BYTES
+ * of device memory that the library holds per device (a static device
+ * array, present from the library's load on a device until the process
+ * ends) instead of a per-stream workspace.  Nothing is allocated, on the
+ * device or in pinned host memory, and no timing events are recorded.
+ *   points, out_idx, out_count, stream  as in hull2d_async; out_count
+ *              receives, in stream order, the hull size, CH_EDOMAIN,
+ *              CH_EHIP or CH_BATCH_REDO as there.
+ *   n          0 <= n <= CH_NOALLOC_MAX_POINTS; a larger n returns
+ *              CH_ECAPACITY before any device work.
+ * Every call on a device uses that device's one buffer: calls that overlap
+ * on one device (on different streams, or from different threads) race and
+ * corrupt each other's results; the caller serialises them.  The buffer
+ * keeps the last call's contents; each call clears what it needs first.
+ * The first call on a device looks up the buffer's device address (no
+ * allocation).  Returns after queueing the kernels: CH_OK, CH_EINVAL (bad
+ * argument), CH_ECAPACITY or CH_EHIP.
+ */
+int hull2d_noalloc(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
 
 /*
  * hull2d_batched: num_sets independent hulls (Section 2.1 applied per set).

@@ -17,11 +17,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libchainhull.so")
 
-CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT = 0, -1, -2, -3, -4, -5
+CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM, CH_EHIP, CH_EADMIT, CH_ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_MAX_POINTS = 1 << 20      # CH_NOALLOC_MAX_POINTS
+NOALLOC_SCRATCH_BYTES = 96 << 20  # CH_NOALLOC_SCRATCH_BYTES
 CH_BATCH_REDO = -(2 ** 31)
 
 # C entry points declared in include/chainhull.h
-EXPORTS = ("hull2d", "hull2d_async", "hull2d_batched", "hull2d_batched_async", "chainhull_polygon", "chainhull_finish_host",
+EXPORTS = ("hull2d", "hull2d_async", "hull2d_noalloc", "hull2d_batched", "hull2d_batched_async", "chainhull_polygon", "chainhull_finish_host",
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes", "chainhull_spa_chunked",
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
@@ -119,6 +121,8 @@ def lib():
     L.hull2d.argtypes = [vp, i64, vp, vp, vp]
     L.hull2d_async.argtypes = [vp, i64, vp, vp, vp]
     L.hull2d_async.restype = ctypes.c_int
+    L.hull2d_noalloc.argtypes = [vp, i64, vp, vp, vp]
+    L.hull2d_noalloc.restype = ctypes.c_int
     L.hull2d.restype = ctypes.c_int
     L.hull2d_batched.argtypes = [vp, vp, i32, vp, vp, vp]
     L.hull2d_batched.restype = ctypes.c_int
@@ -211,6 +215,14 @@ def hull2d_async(points, out_idx, out_count, stream=None) -> int:
     int32 with room for the points.  Returns the status of the launch."""
     return lib().hull2d_async(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
                               _stream_ptr(stream))
+
+
+def hull2d_noalloc(points, out_idx, out_count, stream=None) -> int:
+    """hull2d_async on the library's fixed per-device buffer: allocates
+    nothing (at most NOALLOC_MAX_POINTS points, else CH_ECAPACITY).  Calls
+    that overlap on one device race.  Returns the status of the launch."""
+    return lib().hull2d_noalloc(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
+                                _stream_ptr(stream))
 
 
 def hull2d_batched(points, offsets, stream=None):

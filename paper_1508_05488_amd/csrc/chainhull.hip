@@ -62,6 +62,12 @@
 #include "chainhull.h"
 #include "finish.h"
 
+// The fixed device buffer of hull2d_noalloc (callers that cannot allocate):
+// one copy per device, held from the code object's load until the process
+// ends.  Host code never uses this name as an address: it takes the
+// device's address from hipGetSymbolAddress (noalloc_base).
+static __device__ __align__(256) unsigned char scratch[CH_NOALLOC_SCRATCH_BYTES];
+
 namespace chainhull {
 
 typedef float v2f __attribute__((ext_vector_type(2)));
@@ -2568,6 +2574,7 @@ struct Workspace {
     int32_t* h_b_counts = nullptr;
     hipEvent_t ev[8] = {};
     bool events = false;
+    bool no_events = false;  // hull2d_noalloc's view: never creates or records events
 };
 
 // Launch shape of k_stream for n points whose first `head` (0 or 1) points
@@ -2771,7 +2778,7 @@ void free_workspace(Workspace* w)
 int record(Workspace& w, int k)
 {
     const int mode = g_timing;
-    if (!mode) return CH_OK;
+    if (!mode || w.no_events) return CH_OK;
     if (mode == 2 && k != 0 && k != 5 && k != 6) return CH_OK;
     if (!w.events) {
         for (auto& e : w.ev) CH_TRY(hipEventCreate(&e));
@@ -3034,6 +3041,32 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     return CH_OK;
 }
 
+
+// hull2d_noalloc: the device address of the fixed buffer, looked up once per
+// device with that device current.
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_base[kNoAllocDevices] = {};
+
+int noalloc_base(int dev, char** base)
+{
+    if (dev < 0 || dev >= kNoAllocDevices) return CH_EHIP;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_base[dev]) {
+        void* p = nullptr;
+        CH_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch)));
+        if (!p) return CH_EHIP;
+        g_noalloc_base[dev] = static_cast<char*>(p);
+    }
+    *base = g_noalloc_base[dev];
+    return CH_OK;
+}
+
+// What hull2d_noalloc needs of the buffer for n points: the workspace
+// layout for n, then a device-side stand-in for the pinned header (k_chain
+// and k_finish write it; nobody reads it).
+size_t noalloc_bytes(size_t n) { return device_bytes(n) + align_up(sizeof(DevHeader), 256); }
+
 }  // namespace
 }  // namespace chainhull
 
@@ -3062,6 +3095,34 @@ int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0, false));
     return launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
+}
+
+int hull2d_noalloc(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream)
+{
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx))) return CH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
+    if (n > (int64_t)CH_NOALLOC_MAX_POINTS) return CH_ECAPACITY;
+    if (n == 0) {
+        CH_LAUNCH(hipLaunchKernelGGL(k_put_result, dim3(1), dim3(kBlock), 0, s, nullptr, 0, out_idx, out_count));
+        return CH_OK;
+    }
+    // the whole layout for the largest call must fit the buffer
+    if (noalloc_bytes(CH_NOALLOC_MAX_POINTS) > CH_NOALLOC_SCRATCH_BYTES) return CH_EHIP;
+    int dev = 0;
+    CH_TRY(hipGetDevice(&dev));
+    char* base = nullptr;
+    CH_TRY(noalloc_base(dev, &base));
+    // a view of the buffer (no allocation): the layout for n points, the
+    // header stand-in after it
+    Workspace w;
+    w.device = dev;
+    w.stream = s;
+    w.no_events = true;
+    w.cap = (size_t)n;
+    const size_t used = layout(&w, base, (size_t)n);
+    w.h_hdr_dev = reinterpret_cast<DevHeader*>(base + used);
+    return launch_preprocess(w, points, (uint32_t)n, false, out_idx, out_count);
 }
 
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets, int32_t* out_idx,
@@ -3244,6 +3305,7 @@ const char* chainhull_strerror(int status)
     case CH_ENOMEM: return "out of memory";
     case CH_EHIP: return "HIP runtime error";
     case CH_EADMIT: return "request not admitted";
+    case CH_ECAPACITY: return "more points than the fixed buffer of hull2d_noalloc holds";
     default: return "unknown status";
     }
 }

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_and_workspace_bound():
-    for code in (ch.CH_OK, ch.CH_EINVAL, ch.CH_EDOMAIN, ch.CH_ENOMEM, ch.CH_EHIP, ch.CH_EADMIT):
+    for code in (ch.CH_OK, ch.CH_EINVAL, ch.CH_EDOMAIN, ch.CH_ENOMEM, ch.CH_EHIP, ch.CH_EADMIT, ch.CH_ECAPACITY):
         assert ch.strerror(code)
     assert ch.strerror(123) == "unknown status"
     assert ch.workspace_bytes(20_000_000) >= 20_000_000 * 24
@@ -43,13 +43,24 @@ def test_single_hull_entry_points_reject_bad_arguments():
     L = ch.lib()
     buf = ctypes.create_string_buffer(64)
     base = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
-    for fn in (L.hull2d, L.hull2d_async):
+    for fn in (L.hull2d, L.hull2d_async, L.hull2d_noalloc):
         assert fn(base, -1, base, base, None) == ch.CH_EINVAL          # n < 0
         assert fn(base, 1 << 31, base, base, None) == ch.CH_EINVAL     # n > 2^31 - 1
         assert fn(base, 5, base, None, None) == ch.CH_EINVAL           # no count
         assert fn(None, 5, base, base, None) == ch.CH_EINVAL           # no points
         assert fn(base, 5, None, base, None) == ch.CH_EINVAL           # no output
         assert fn(base + 4, 5, base, base, None) == ch.CH_EINVAL       # points not 8-byte aligned
+    # beyond the fixed buffer of hull2d_noalloc
+    assert L.hull2d_noalloc(base, ch.NOALLOC_MAX_POINTS + 1, base, base, None) == ch.CH_ECAPACITY
+
+
+def test_noalloc_buffer_holds_the_largest_call():
+    # the workspace layout for the most points hull2d_noalloc takes, plus
+    # its header stand-in, fits the fixed device buffer declared in the header
+    assert ch.workspace_bytes(ch.NOALLOC_MAX_POINTS) + 256 <= ch.NOALLOC_SCRATCH_BYTES
+    hdr = open(os.path.join(ROOT, "include", "chainhull.h")).read()
+    assert f"#define CH_NOALLOC_MAX_POINTS {ch.NOALLOC_MAX_POINTS}" in hdr
+    assert "#define CH_NOALLOC_SCRATCH_BYTES (96u << 20)" in hdr and ch.NOALLOC_SCRATCH_BYTES == 96 << 20
 
 
 def _finish_via_library(pts):
