@@ -68,14 +68,16 @@ typedef struct {
     int64_t hull;         /* hull vertices */
     /* Milliseconds per stage when timing is on (chainhull_set_timing), from
      * HIP events on the call's stream: 0 sampled staircases, 1 the pass over
-     * the points (validation, staircase test), 2 extreme points reduced,
-     * quadrilateral discard + region distribution + chunk dominance filter
-     * (and, in chainhull_polygon, the round-1 counts), 3 region sort, first
-     * level (records placed by bucket), 4 region sort, second level + SPA +
-     * chain concatenation (+ pre-hull in hull2d), 5 the device finish of
-     * hull2d; the host finish of hull2d in wall-clock time, 0 when the
-     * device finished: 6 the polygon gathered on the device into pinned
-     * memory (one workgroup) and waited for, 7 Melkman's algorithm on it. */
+     * the points (validation, staircase test, extreme points reduced),
+     * 2 quadrilateral discard + region distribution + chunk dominance filter
+     * + each workgroup's records sorted by bucket (and, in chainhull_polygon,
+     * the round-1 counts), 3 the bucket table's columns (bucket sizes,
+     * starts, thresholds), 4 region sort, second level + SPA + chain
+     * concatenation (+ pre-hull in hull2d), 5 the device finish of hull2d
+     * (one workgroup, or many for a large polygon); the host finish of
+     * hull2d in wall-clock time, 0 when the device finished (it runs only if
+     * the device finish gives up): 6 the polygon gathered on the device into
+     * pinned memory and waited for, 7 Melkman's algorithm on it. */
     float ms[8];
     int32_t device_finish;  /* 1 when hull2d finished step 7 on the device */
     int32_t reserved;
@@ -101,9 +103,11 @@ typedef struct {
  * Returns CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM or CH_EHIP.
  */
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
-/* (Step 7 runs on the device when the polygon left by steps 1-6 and the
- * pre-hull has at most 3584 vertices, on the host otherwise; the result is
- * the same.) */
+/* (Step 7 runs on the device: in one workgroup when the polygon left by
+ * steps 1-6 and the pre-hull has at most 3584 vertices, across many
+ * workgroups otherwise.  Melkman on the host remains as a fallback for a
+ * polygon the device finish gives up on, which is not expected; the result
+ * is the same.) */
 
 /*
  * hull2d_async: hull2d with every step on the device and nothing
@@ -113,14 +117,19 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
  *   out_count  device memory, one int32; receives, in stream order, the
  *              number of hull vertices, or CH_EDOMAIN (a coordinate out of
  *              the domain), CH_EHIP (a failed step), or CH_BATCH_REDO when
- *              the polygon exceeds the device finish (more than 3584
- *              vertices after the pre-hull; hull2d computes such an input).
+ *              the device finish gave up on the polygon (not expected;
+ *              hull2d computes such an input on the host).
  * Returns after queueing the kernels: CH_OK, CH_EINVAL (bad argument, before
  * any work), CH_ENOMEM or CH_EHIP.  The stream's workspace (shared with
  * hull2d on that stream) is allocated or grown only when n exceeds what it
  * holds; a graph captures the call allocation-free after a first call with
- * at least as many points.  Calls on one stream run one after another; the
- * statistics of chainhull_last_stats are not filled.
+ * at least as many points (under capture, a call that would allocate
+ * returns CH_EINVAL).  A captured graph keeps using the workspace's
+ * addresses: from the capture on, a call on that stream that would grow the
+ * workspace returns CH_EINVAL, until chainhull_release_stream (or
+ * chainhull_release) frees it; the graph must not be replayed after that.
+ * Calls on one stream run one after another; the statistics of
+ * chainhull_last_stats are not filled.
  */
 int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
 
@@ -286,9 +295,48 @@ int chainhull_spa_chunked(const uint32_t* k2_sorted, int64_t m, uint32_t sigma, 
                           void* stream);
 
 /* Free the cached workspace of one stream on the current device (device and
- * pinned host memory).  No call on that stream may be running.  Returns
- * CH_OK (also when the stream has no workspace). */
+ * pinned host memory).  No call on that stream may be running, and no graph
+ * that captured a call on it may be replayed afterwards (this also lifts
+ * the capture's hold on the workspace's size).  Returns CH_OK (also when
+ * the stream has no workspace). */
 int chainhull_release_stream(void* stream);
+
+/*
+ * Launch shapes (the autotuner's knobs).  The paper fixes its block size by
+ * the GPU generation and leaves the best work per thread open (Sections
+ * 2.2.2, 4.3); here every shape that no LDS layout fixes is a run-time
+ * choice, picked per size class by the project's autotuner
+ * (paper_1508_05488_amd/autotune.py), which times the candidates on the
+ * device, checks that each gives the same hulls, and stores the fastest.
+ * Every field must hold one of the values listed; results never depend on
+ * the shape.
+ */
+typedef struct {
+    int32_t stream_grid;     /* k_stream workgroups at most: 128, 256, 512 or 1024 */
+    int32_t stream_unroll;   /* float4 loads in flight per k_stream thread: 2 or 4 */
+    int32_t cand_per_row;    /* open points per k_cand workgroup (one row of the bucket
+                                table each, at most 256): 1024 .. 2^20; the count of
+                                open points is known on the device only, so the rows
+                                follow it there */
+    int32_t chain_grid;      /* k_chain workgroups at most: 64 .. 4096 */
+    int32_t wide_grid;       /* k_finish_wide workgroups: 64 .. 4096 */
+    int32_t batch_unroll;    /* float4 loads per thread and round in the batched kernel: 1 or 2 */
+    int32_t batch_order;     /* batched launch order: 0 larger sets first, 1 as given */
+    int32_t serve_batch_max; /* serving: requests of at most this many points are
+                                batched (0 .. 2^22); read when a server is created */
+} ch_tuning;
+
+/* Use *t for calls whose point count (for hull2d_batched: total points) is
+ * at most n_max.  The table holds up to 16 such classes; a call takes the
+ * class with the smallest n_max >= its n, else the defaults.  n_max < 0
+ * clears the table (t may then be NULL).  Must not run while another call
+ * is being set up.  Returns CH_OK or CH_EINVAL (a field out of range, or the
+ * table is full). */
+int chainhull_set_tuning(int64_t n_max, const ch_tuning* t);
+
+/* The shapes a call with n points would use; n < 0: the defaults.  Returns
+ * CH_OK or CH_EINVAL for a null pointer. */
+int chainhull_get_tuning(int64_t n, ch_tuning* out);
 
 /* Upper bound on the device workspace bytes a call with n points needs. */
 size_t chainhull_workspace_bytes(int64_t n);
@@ -300,8 +348,9 @@ size_t chainhull_workspace_bytes(int64_t n);
  * alone, whatever else is in flight).
  *
  * Worker threads, each with its own stream, take the oldest pending work
- * when free: a request of more than 2^18 points alone through the
- * single-hull path, or every pending smaller request together (gathered
+ * when free: a request of more than serve_batch_max points (the tuned launch
+ * shape in force when the server is created; 2^18 by default) alone through
+ * the single-hull path, or every pending smaller request together (gathered
  * into the worker's staging buffer and computed by one hull2d_batched
  * launch).  Requests that arrive while others run join the next batch; the
  * workers' streams overlap on the device.
@@ -309,7 +358,10 @@ size_t chainhull_workspace_bytes(int64_t n);
  * Admission: a request holds part of mem_budget from submission until it
  * completes (12 bytes per point when it is batched, the single-hull
  * workspace bound otherwise); requests are admitted first come, first
- * served, as budget frees up.
+ * served, as budget frees up.  The device memory a worker keeps between
+ * requests (its stream's workspace, its staging buffers) counts against
+ * the same budget: a worker releases it after a request when the requests
+ * in flight and the workers' memory would otherwise exceed the budget.
  */
 typedef struct ch_server ch_server;
 
@@ -331,7 +383,9 @@ typedef struct {
 int chainhull_server_create(int32_t workers, size_t mem_budget, ch_server** out);
 
 /* Submit one request.  points: device memory, n float32 (x, y) pairs as in
- * hull2d, 8-byte aligned, unchanged until the request completes; out_idx
+ * hull2d, 8-byte aligned, written completely before the call (the workers'
+ * streams are not ordered after any stream of the caller's) and unchanged
+ * until the request completes; out_idx
  * (room for n int32) and out_count (one int32): device memory that receives
  * the hull as hull2d writes it.  *ticket receives the request's ticket.
  * Returns at once: CH_OK, CH_EINVAL (bad argument, or the server is being

@@ -27,7 +27,7 @@ EXPORTS = ("hull2d", "hull2d_async", "hull2d_noalloc", "hull2d_batched", "hull2d
            "chainhull_last_stats", "chainhull_last_batch_stats", "chainhull_set_timing", "chainhull_strerror",
            "chainhull_release", "chainhull_release_stream", "chainhull_workspace_bytes", "chainhull_spa_chunked",
            "chainhull_server_create", "chainhull_server_submit", "chainhull_server_wait",
-           "chainhull_server_stats", "chainhull_server_destroy")
+           "chainhull_server_stats", "chainhull_server_destroy", "chainhull_set_tuning", "chainhull_get_tuning")
 
 STAGES = ("sample", "stream", "cand", "sort", "spa", "finish_dev", "gather", "finish")
 
@@ -106,7 +106,28 @@ class ChServerStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved0"}
 
 
+class ChTuning(ctypes.Structure):
+    """Launch shapes (include/chainhull.h, ch_tuning)."""
+    _fields_ = [
+        ("stream_grid", ctypes.c_int32),
+        ("stream_unroll", ctypes.c_int32),
+        ("cand_per_row", ctypes.c_int32),
+        ("chain_grid", ctypes.c_int32),
+        ("wide_grid", ctypes.c_int32),
+        ("batch_unroll", ctypes.c_int32),
+        ("batch_order", ctypes.c_int32),
+        ("serve_batch_max", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+TUNING_FIELDS = tuple(k for k, _ in ChTuning._fields_)
+TUNING_DIR = os.path.join(_PKG, "tuning")
+
 _lib = None
+_tuning_loaded = None
 
 
 def lib():
@@ -158,8 +179,79 @@ def lib():
     L.chainhull_server_destroy.restype = ctypes.c_int
     L.chainhull_workspace_bytes.argtypes = [i64]
     L.chainhull_workspace_bytes.restype = ctypes.c_size_t
+    L.chainhull_set_tuning.argtypes = [i64, ctypes.POINTER(ChTuning)]
+    L.chainhull_set_tuning.restype = ctypes.c_int
+    L.chainhull_get_tuning.argtypes = [i64, ctypes.POINTER(ChTuning)]
+    L.chainhull_get_tuning.restype = ctypes.c_int
     _lib = L
+    load_tuning()
     return L
+
+
+def get_tuning(n: int = -1) -> dict:
+    """The launch shapes a call with n points uses (n < 0: the defaults)."""
+    t = ChTuning()
+    _check(lib().chainhull_get_tuning(int(n), ctypes.byref(t)), "chainhull_get_tuning")
+    return t.as_dict()
+
+
+def set_tuning(n_max: int, tuning: dict) -> None:
+    """Use these shapes for calls of at most n_max points."""
+    t = ChTuning(**{k: int(tuning[k]) for k in TUNING_FIELDS})
+    _check(lib().chainhull_set_tuning(int(n_max), ctypes.byref(t)), "chainhull_set_tuning")
+
+
+def clear_tuning() -> None:
+    """Back to the default shapes for every call."""
+    lib().chainhull_set_tuning(-1, None)
+
+
+def device_key() -> str:
+    """The current GPU's name and architecture, the key of its tuning file."""
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "gpu").split(":")[0]
+    name = "".join(c if c.isalnum() else "_" for c in p.name).strip("_")
+    return f"{arch}_{name}"
+
+
+def tuning_path(key: str | None = None) -> str:
+    return os.path.join(TUNING_DIR, f"{key or device_key()}.json")
+
+
+def load_tuning(path: str | None = None):
+    """Apply the autotuner's saved shapes for the current GPU (a JSON file
+    under tuning/, written by autotune.py), when one exists.  Returns the
+    path applied, or None (defaults).  Without a GPU nothing is read."""
+    global _tuning_loaded
+    import json
+    if path is None:
+        try:
+            import torch
+            if not torch.cuda.is_available():
+                return None
+            path = tuning_path()
+        except Exception:
+            return None
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    L = _lib
+    L.chainhull_set_tuning(-1, None)
+    for c in doc.get("classes", []):
+        t = ChTuning(**{k: int(c["tuning"][k]) for k in TUNING_FIELDS})
+        rc = L.chainhull_set_tuning(int(c["n_max"]), ctypes.byref(t))
+        if rc != CH_OK:
+            raise ChainHullError(rc, f"tuning file {path}")
+    _tuning_loaded = path
+    return path
+
+
+def tuning_source():
+    """The tuning file applied when the library was loaded, or None."""
+    lib()
+    return _tuning_loaded
 
 
 def strerror(status: int) -> str:
@@ -363,6 +455,10 @@ class Server:
             out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
         if out_count is None:
             out_count = torch.zeros(1, dtype=torch.int32, device=pts.device)
+        # the workers' streams are not ordered after the caller's: the points
+        # (and the count's zero fill) must be complete before a worker reads
+        # them
+        torch.cuda.current_stream(pts.device).synchronize()
         t = ctypes.c_uint64(0)
         rc = lib().chainhull_server_submit(self._h, pts.data_ptr(), n, out_idx.data_ptr(), out_count.data_ptr(),
                                            ctypes.byref(t))

@@ -1,37 +1,46 @@
-// chainhull: the CudaChain preprocessing path (Section 2.1, steps 1-6) as
-// hand-written gfx950 kernels, the pipeline around them and the C ABI.
+// chainhull: the CudaChain hot path (Section 2.1, steps 1-7) as hand-written
+// gfx950 kernels, the pipeline around them and the C ABI.
 //
 // Kernels of one hull (all on the caller's stream):
-//   k_sample        a strided sample of the points: per-frame slot minima
-//   k_stair         the sampled staircases (prefix minima); clears counters
+//   k_sample        a sample of the points: per-frame slot minima; its last
+//                   workgroup builds the sampled staircases (prefix minima)
+//                   and clears the call's counters
 //   k_stream        the one full pass over the points: the domain check and
 //                   the sampled-staircase dominance test; lists the points
-//                   that pass it (the extreme points are among them)
-//   k_cand          step 1's reduction (the quadrilateral), step 2's exact
-//                   region test on the listed points, a chunk staircase;
-//                   writes the records and counts them per sort bucket
-//   k_bucket        steps 3-4, level 1: records placed by bucket (region,
-//                   top k1 bits), after a bucket-staircase filter
-//   k_bucket_spa    steps 3-5, level 2: each bucket ordered by its low k1
-//                   bits and filtered by SPA
+//                   that pass it (the extreme points are among them); its
+//                   last workgroup reduces the extreme points (step 1) and
+//                   publishes the quadrilateral
+//   k_cand          step 2's exact region test on the listed points, a chunk
+//                   staircase; each workgroup sorts its records by sort
+//                   bucket (region, top k1 bits) in its own part and writes
+//                   its row of the bucket table
+//   k_scan          the bucket table's columns: bucket sizes, where each
+//                   bucket starts, the SPA threshold entering it
+//   k_bucket_spa    steps 3-5: each bucket gathered from the rows' parts,
+//                   ordered by its low k1 bits and filtered by SPA
 //   k_chain         step 6: the chains concatenated, shortened by a
-//                   pre-hull, written to pinned host memory with the header
-// then Melkman on the host (step 7), and the result copied into the
-// caller's device buffers by k_put_result.
+//                   pre-hull per segment
+//   k_finish        step 7 in one workgroup for polygons that fit it
+//   k_finish_wide   step 7 across workgroups for larger polygons
+// (hull2d falls back to Melkman on the host only if the device finish gives
+// up; chainhull_polygon stops after k_chain and returns the polygon.)
 //
 // Data layout in HBM (one workspace per device and stream):
 //   points           caller's n x float32[2], read once in full (k_stream)
-//   samp, stair      sampled slot minima, staircases (4 x 1024 u32 each)
+//   DevHeader        extreme points, quadrilateral edges, frames, counters;
+//                    with the look-back states and arrival counters it is
+//                    zeroed when the workspace is allocated
+//   samp, stair      sampled slot minima per sample workgroup, staircases
 //   ExtPartial[G]    per-workgroup extreme keys
 //   open lists       per k_stream workgroup: index; x | y << 23 | mask << 46
-//   DevHeader        extreme points, quadrilateral edges, frames, counters
-//   key[2], val[2]   records: u32 q << 23 | k1, u64 k2 << 32 | index; [0]
-//                    holds k_cand's per-workgroup regions, [1] the records
-//                    in bucket order
-//   bucket arrays    counts, minima, cursors, offsets, thresholds, survivors
-//                    (8192 buckets each)
-//   chain, spill     SPA survivors (index, x, y) at their bucket's place;
-//                    kept chain points beyond the pinned host buffer
+//   key[2], val[2]   records: u32 q << 23 | k1, u64 k2 << 32 | index; per
+//                    k_cand workgroup a part in each: [0] in chunk order,
+//                    [1] by bucket
+//   rowoff, rowmin   the bucket table: per k_cand workgroup and bucket the
+//                    first position in its part, the smallest k2
+//   bucket arrays    sizes, starts, thresholds, survivors (8192 buckets)
+//   chain, kept      SPA survivors (index, x, y) at their bucket's place;
+//                    the pre-hull's kept points per 1024-point segment
 //
 // Regions follow the paper (R1 lower left, R2 lower right, R3 upper right,
 // R4 upper left); q = r - 1 is the region code in the sort key, so ascending
@@ -105,7 +114,11 @@ struct DevHeader {
     int32_t fin_hull;    // its size
     uint32_t fin_w2[4];  // polygon vertices per region it finished from
     uint32_t gat_count;  // polygon vertices k_gather wrote for the host finish
-    uint32_t pad[8];
+    uint32_t wide;       // 1 when k_finish left the polygon to k_finish_wide
+    uint32_t epoch;      // calls on this workspace so far (tags the look-back states)
+    uint32_t wide_ticket;  // k_finish_wide's next item
+    uint32_t fin_fail;   // 1 when k_finish_wide gave up (the host finishes)
+    uint32_t pad[4];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -121,14 +134,18 @@ struct PolyRec {
     int32_t idx, x, y;
 };
 
-// Per-bucket arrays of one call (device memory unless noted).
+// Per-bucket arrays of one call (device memory).
 struct Buckets {
-    uint32_t* cnt;    // records per bucket (k_cand)
-    u64* kmin;        // smallest (k2 << 23 | k1) per bucket (k_cand)
-    uint32_t* cur;    // fill cursors (k_bucket)
-    uint32_t* off;    // first record of each bucket (k_bucket)
-    uint32_t* thr;    // smallest k2 over the region's earlier buckets and first point
-    uint32_t* surv;   // SPA survivors per bucket (k_bucket_spa)
+    uint32_t* cnt;     // records per bucket (k_scan)
+    uint32_t* off;     // first record of each bucket in bucket order (k_bucket_spa)
+    uint32_t* surv;    // SPA survivors per bucket (k_bucket_spa)
+    uint32_t* lstart;  // first record of the bucket among its k_scan workgroup's buckets
+    uint32_t* lthr;    // smallest k2 over the earlier buckets of its k_scan workgroup
+    uint32_t* wtot;    // per k_scan workgroup: records
+    uint32_t* wmin;    // per k_scan workgroup: smallest k2
+    uint32_t* wgbase;  // per k_scan workgroup: the first record of its buckets
+    uint32_t* wgthr;   // per k_scan workgroup: the threshold entering its buckets
+    uint32_t* ctr;     // k_scan's arrival counter (zero between calls)
 };
 
 // ---------------------------------------------------------------------------
@@ -136,6 +153,29 @@ struct Buckets {
 // ---------------------------------------------------------------------------
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Cross-workgroup hand-offs inside one kernel.  The last workgroup to
+// arrive reads what the others wrote: they store it with device-scope
+// stores (written through to where every XCD sees it, instead of a
+// device-scope release fence, which would write back the whole L2 of the
+// XCD), wait until those stores have completed, and only then count their
+// arrival; the last arrival reads with device-scope loads.
+__device__ inline void st_dev(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_dev(u64* p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline uint32_t ld_dev(const uint32_t* p)
+{
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline u64 ld_dev(const u64* p) { return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void stores_done()
+{
+    // (a workgroup-scope release orders the compiler but waits for nothing:
+    // the explicit wait makes the device-scope stores complete first)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+// Arrival counter: returns the count before this arrival.
+__device__ inline uint32_t arrive(uint32_t* ctr) { return __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 __device__ inline void take_min(u64& k, uint32_t& i, u64 ok, uint32_t oi)
 {
@@ -342,11 +382,11 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // the region sort and SPA unchanged, so any filter that only drops dominated
 // points may run before them.
 //
-// Sampled staircases.  k_sample takes a sample of kSamplePts points (64 evenly
-// spaced runs of consecutive points)
-// and records, in each of the four region frames, the smallest k2 per slot of
-// 2^kStairShift k1 values, over all sample points (not only the region's);
-// k_stair turns them into exclusive prefix minima over the slots.  A sample
+// Sampled staircases.  k_sample takes a sample of kSamplePts points
+// (kSampleBlocks evenly spaced runs of consecutive points) and records, in
+// each of the four region frames, the smallest k2 per slot of 2^kStairShift
+// k1 values, over all sample points (not only the region's), then turns them
+// into exclusive prefix minima over the slots.  A sample
 // point p' with smaller k1 and k2 <= k2 of p in the frame of p's region lies
 // in that region as well (moving towards the corner never re-enters the
 // quadrilateral), so it dominates p there.  A point whose k2 is not below
@@ -362,8 +402,8 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // staircase is empty up to its slot), and likewise every point with the
 // smallest y (R2), the largest x (R3) and the largest y (R4); so the
 // lexicographic extremes of the open points, ties to the smallest index,
-// are those of all points.  k_cand then reduces the extreme points, runs the exact
-// region test on the open points only (a point counts for its region only if
+// are those of all points.  The last k_stream workgroup reduces them; k_cand
+// runs the exact region test on the open points only (a point counts for its region only if
 // it passed that region's frame), and filters again with a staircase over
 // chunks of 1024 records: per region and k1-slot of 2^14 values the smallest
 // (k2, k1) in LDS; a record is dropped when the region's first point or a
@@ -371,14 +411,13 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // record precedes it with k1 <= its k1.  The rest become sort records.
 // ---------------------------------------------------------------------------
 
-constexpr int kSampleBlocks = 64;
-constexpr int kSamplePerThread = 8;
+constexpr int kSampleBlocks = 16;
+constexpr int kSamplePerThread = 32;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
 constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
-constexpr int kStreamGrid = 1024;   // persistent workgroups of k_stream
-constexpr int kStreamUnroll = 4;    // float4 loads in flight per thread
+constexpr int kStreamGrid = 1024;   // k_stream workgroups at most (the partials' room)
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
 constexpr int kCandChunk = 1024;    // records filtered together
 
@@ -388,83 +427,204 @@ __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
     return (u64)X | ((u64)Y << 23) | ((u64)mask << 46);
 }
 
+// k_sample: workgroup b reads a run of kBlock * kSamplePerThread consecutive
+// points (coalesced), the runs evenly spaced (a smaller input is sampled with
+// repeats at evenly spaced indices), and writes its per-frame slot minima to
+// its row of samp.  The workgroup that finishes last (a counter, cleared
+// again by it) takes the minimum over the rows and builds the staircases:
+// per frame the exclusive prefix minimum over the slots.  Layout:
+// stair[2s], stair[2s+1] = R1 at x-slot s, R3 at its own slot of the same x;
+// stair[2S + 2s], stair[2S + 2s + 1] = R2 at y-slot s, R4 at its own slot of
+// the same y (S = kStairSlots), so that one 64-bit LDS read per coordinate
+// serves two frames.  It also clears the call's counters in the header.
 __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts, uint32_t n,
-                                                   uint32_t* __restrict__ samp)
+                                                   uint32_t* __restrict__ samp, uint32_t* __restrict__ stair,
+                                                   DevHeader* __restrict__ hdr, uint32_t* __restrict__ ctr)
 {
-    __shared__ uint32_t st[4 * kStairSlots];
-    const uint32_t tid = threadIdx.x;
+    __shared__ __align__(16) uint32_t st[4 * kStairSlots];
+    __shared__ uint32_t s_last;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
     __syncthreads();
-    uint32_t X[kSamplePerThread], Y[kSamplePerThread];
-    // workgroup b reads a run of kBlock * kSamplePerThread consecutive points
-    // (coalesced), the runs evenly spaced; a smaller input is sampled with
-    // repeats at evenly spaced indices
     constexpr uint32_t kRun = kBlock * kSamplePerThread;
     const bool runs = n >= kSamplePts;
     const uint32_t start = runs ? (uint32_t)(((u64)blockIdx.x * (n - kRun)) / (kSampleBlocks - 1)) : 0u;
+    constexpr int kBatch = 8;  // points loaded together per thread
+    for (int k0 = 0; k0 < kSamplePerThread; k0 += kBatch) {
+        uint32_t X[kBatch], Y[kBatch];
 #pragma unroll
-    for (int k = 0; k < kSamplePerThread; ++k) {
-        const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
-        const uint32_t i = runs ? start + k * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
-        const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
-        // out-of-domain values only need to stay in range here: such a call
-        // fails with a domain error
-        X[k] = coord_u32(p.x) & kM;
-        Y[k] = coord_u32(p.y) & kM;
-    }
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k0 + k;
+            const uint32_t i = runs ? start + (k0 + k) * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
+            const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
+            // out-of-domain values only need to stay in range here: such a
+            // call fails with a domain error
+            X[k] = coord_u32(p.x) & kM;
+            Y[k] = coord_u32(p.y) & kM;
+        }
 #pragma unroll
-    for (int k = 0; k < kSamplePerThread; ++k) {
-        const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
-        atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
-        atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
-        atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
-        atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
-    }
-    __syncthreads();
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock) samp[blockIdx.x * 4 * kStairSlots + e] = st[e];
-}
-
-// Workgroup q (of 4, kStairSlots threads each) builds frame q's staircase.
-// Layout: stair[2s], stair[2s+1] = R1 at x-slot s, R3 at its own slot of
-// the same x; stair[2S + 2s], stair[2S + 2s + 1] = R2 at y-slot s, R4 at its
-// own slot of the same y (S = kStairSlots), so that one 64-bit LDS read per
-// coordinate serves two frames.  The workgroups also clear the call's
-// counters and bucket arrays.
-__global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restrict__ samp,
-                                                       uint32_t* __restrict__ stair, DevHeader* __restrict__ hdr,
-                                                       Buckets bk)
-{
-    constexpr int kW = kStairSlots / 64;
-    __shared__ uint32_t wmin[kW];
-    const uint32_t q = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = t / 64;
-    uint32_t v[kSampleBlocks];
-#pragma unroll
-    for (int b = 0; b < kSampleBlocks; ++b) v[b] = samp[b * 4 * kStairSlots + q * kStairSlots + t];
-    uint32_t m = ~0u;
-#pragma unroll
-    for (int b = 0; b < kSampleBlocks; ++b) m = min(m, v[b]);
-    const uint32_t incl = wave_incl_min(m);
-    uint32_t excl = __shfl_up(incl, 1);
-    if (lane == 0) excl = ~0u;
-    if (lane == 63) wmin[wave] = incl;
-    __syncthreads();
-    for (uint32_t w = 0; w < wave; ++w) excl = min(excl, wmin[w]);
-    const uint32_t S = kStairSlots;
-    const uint32_t at = q == 0 ? 2 * t : q == 1 ? 2 * S + 2 * t : q == 2 ? 2 * (S - 1 - t) + 1 : 2 * S + 2 * (S - 1 - t) + 1;
-    stair[at] = excl;
-    for (uint32_t b = q * kStairSlots + t; b < (uint32_t)kBuckets; b += 4 * kStairSlots) {
-        bk.cnt[b] = 0;
-        bk.kmin[b] = ~0ull;
-        bk.cur[b] = 0;
-    }
-    if (q == 0) {
-        if (t < 4) hdr->s1[t] = 0;
-        if (t == 0) {
-            hdr->open = 0;
-            hdr->cand = 0;
-            hdr->err = 0;
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
+            atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
+            atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
+            atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
+            atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
         }
     }
+    __syncthreads();
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock) st_dev(samp + blockIdx.x * 4 * kStairSlots + e, st[e]);
+    stores_done();
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t a = arrive(ctr);
+        s_last = a == (uint32_t)gridDim.x - 1 ? 1u : 0u;
+        if (s_last) st_dev(ctr, 0u);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // thread t: slots 16t .. 16t+15 of all frames, so wave f owns frame f
+    constexpr int kPer = 4 * kStairSlots / kBlock;  // 16
+    static_assert(kPer * 64 == kStairSlots && kPer % 4 == 0, "one wave per frame");
+    uint32_t m[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) m[k] = ~0u;
+    for (int b = 0; b < kSampleBlocks; ++b) {
+        const u64* row = reinterpret_cast<const u64*>(samp + b * 4 * kStairSlots + tid * kPer);
+#pragma unroll
+        for (int k = 0; k < kPer / 2; ++k) {
+            const u64 v = ld_dev(row + k);
+            m[2 * k] = min(m[2 * k], (uint32_t)v);
+            m[2 * k + 1] = min(m[2 * k + 1], (uint32_t)(v >> 32));
+        }
+    }
+    uint32_t lo = ~0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) lo = min(lo, m[k]);
+    const uint32_t incl = wave_incl_min(lo);
+    uint32_t excl = __shfl_up(incl, 1);
+    if (lane == 0) excl = ~0u;
+    const uint32_t q = tid / 64, S = kStairSlots;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t sl = lane * kPer + k;
+        const uint32_t at = q == 0 ? 2 * sl : q == 1 ? 2 * S + 2 * sl : q == 2 ? 2 * (S - 1 - sl) + 1 : 2 * S + 2 * (S - 1 - sl) + 1;
+        stair[at] = excl;
+        excl = min(excl, m[k]);
+    }
+    if (tid < 4) hdr->s1[tid] = 0;
+    if (tid == 0) {
+        hdr->open = 0;
+        hdr->cand = 0;
+        hdr->err = 0;
+        hdr->wide = 0;
+        hdr->wide_ticket = 0;
+        hdr->fin_fail = 0;
+        hdr->epoch = hdr->epoch + 1;
+    }
+}
+
+// The quadrilateral: extreme points, edges and frames, from the reduced
+// extreme keys.
+struct Quad {
+    uint32_t X[4], Y[4], idx[4];  // P_minx, P_miny, P_maxx, P_maxy
+    int32_t ex[4], ey[4];         // edge q runs from E_q to E_{q+1}
+    double ec[4];                 // ex*E_q.y - ey*E_q.x
+    uint32_t sigma[4];            // k2 of each region's first point
+    uint32_t err;
+};
+
+// The edges and the regions' first keys from the extreme points Q.X, Q.Y.
+__device__ inline void quad_edges(Quad& Q)
+{
+    // region q lies strictly right of edge q: ex*(y - E_q.y) - ey*(x - E_q.x) < 0
+    for (int q = 0; q < 4; ++q) {
+        const int s = (q + 1) & 3;
+        Q.ex[q] = (int32_t)Q.X[s] - (int32_t)Q.X[q];
+        Q.ey[q] = (int32_t)Q.Y[s] - (int32_t)Q.Y[q];
+        Q.ec[q] = (double)Q.ex[q] * (double)Q.Y[q] - (double)Q.ey[q] * (double)Q.X[q];
+    }
+    Q.sigma[0] = Q.Y[0];        // R1 starts at P_minx
+    Q.sigma[1] = Q.X[1] ^ kM;   // R2 starts at P_miny
+    Q.sigma[2] = Q.Y[2] ^ kM;   // R3 starts at P_maxx
+    Q.sigma[3] = Q.X[3];        // R4 starts at P_maxy
+}
+
+__device__ inline void make_quad(ExtAcc r, Quad& Q)
+{
+    for (int e = 0; e < 2; ++e) {
+        if (r.imax[e] == ~0u) {  // every key is 0: the minimum is the answer
+            r.kmax[e] = r.kmin[e];
+            r.imax[e] = r.imin[e];
+        }
+    }
+    // masked so that a rejected input still gives in-range values
+    const u64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
+    Q.idx[0] = r.imin[0];
+    Q.idx[1] = r.imin[1];
+    Q.idx[2] = r.imax[0];
+    Q.idx[3] = r.imax[1];
+    Q.X[0] = (uint32_t)(key[0] >> 32) & kM; Q.Y[0] = ((uint32_t)key[0] & kM) ^ kM;
+    Q.Y[1] = (uint32_t)(key[1] >> 32) & kM; Q.X[1] = (uint32_t)key[1] & kM;
+    Q.X[2] = (uint32_t)(key[2] >> 32) & kM; Q.Y[2] = ((uint32_t)key[2] & kM) ^ kM;
+    Q.Y[3] = (uint32_t)(key[3] >> 32) & kM; Q.X[3] = (uint32_t)key[3] & kM;
+    quad_edges(Q);
+    Q.err = r.bad ? kErrDomain : 0u;
+}
+
+// The last k_stream workgroup to finish reduces the per-workgroup extreme
+// partials (a few tens of KB) and publishes the quadrilateral in the header.
+// Thread t holds partials t, t + kBlock, ... (nparts <= kStreamGrid); the
+// loads are issued first (load_partials) so that other set-up can run while
+// they are in flight.
+constexpr int kPartPer = kStreamGrid / kBlock;
+
+__device__ inline void load_partials(const ExtPartial* __restrict__ part, int nparts, ExtPartial (&p)[kPartPer])
+{
+#pragma unroll
+    for (int u = 0; u < kPartPer; ++u) {
+        const int b = u * kBlock + (int)threadIdx.x;
+        if (b < nparts) p[u] = part[b];
+    }
+}
+
+__device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, DevHeader* __restrict__ hdr,
+                                   Quad& Q, ExtAcc* sh, bool publish)
+{
+    ExtAcc r;
+    ext_init(r);
+#pragma unroll
+    for (int u = 0; u < kPartPer; ++u) {
+        if (u * kBlock + (int)threadIdx.x >= nparts) continue;
+        ExtAcc o;
+        for (int e = 0; e < 2; ++e) {
+            o.kmin[e] = p[u].kmin[e];
+            o.kmax[e] = p[u].kmax[e];
+            o.imin[e] = p[u].imin[e];
+            o.imax[e] = p[u].imax[e];
+        }
+        o.bad = p[u].err != 0;
+        o.hi = 0;
+        ext_combine(r, o);
+    }
+    ext_block_reduce(r, sh);
+    __shared__ Quad sq;
+    if (threadIdx.x == 0) {
+        make_quad(r, sq);
+        if (publish) {
+            for (int e = 0; e < 4; ++e) {
+                hdr->ext_x[e] = sq.X[e];
+                hdr->ext_y[e] = sq.Y[e];
+                hdr->ext_idx[e] = sq.idx[e];
+                hdr->ex[e] = sq.ex[e];
+                hdr->ey[e] = sq.ey[e];
+                hdr->ec[e] = sq.ec[e];
+                hdr->sigma[e] = sq.sigma[e];
+            }
+            if (sq.err) atomicOr(&hdr->err, sq.err);
+        }
+    }
+    __syncthreads();
+    Q = sq;
 }
 
 // `head` leading points (0 or 1) are visited singly so that the rest of the
@@ -472,17 +632,20 @@ __global__ __launch_bounds__(kStairSlots) void k_stair(const uint32_t* __restric
 // Workgroup b writes its open points to its own region [b*region, ...) of
 // the open arrays and their number to wgcount[b]: no two workgroups share a
 // counter (same-address atomics from many workgroups serialise).  `per`
-// float4s per workgroup, a multiple of kBlock*kStreamUnroll.
+// float4s per workgroup, a multiple of kBlock*kStreamUnroll (the float4
+// loads in flight per thread).
+template <int kStreamUnroll>
 __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
                                                    const uint32_t* __restrict__ stair, ExtPartial* __restrict__ part,
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
-                                                   uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount)
+                                                   uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount,
+                                                   DevHeader* __restrict__ hdr, uint32_t* __restrict__ sctr)
 {
     __shared__ __align__(16) uint32_t sst[4 * kStairSlots];
     __shared__ uint32_t lidx[kWaves][kWaveList];
     __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
-    __shared__ uint32_t s_fill;
+    __shared__ uint32_t s_fill, s_last;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     const u64 lt = (1ull << lane) - 1ull;
 
@@ -626,112 +789,50 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             p.imax[e] = a.imax[e];
         }
         p.err = (a.bad || a.hi > kM) ? 1u : 0u;
-        part[blockIdx.x] = p;
-    }
-}
-
-// The quadrilateral: extreme points, edges and frames, from the reduced
-// extreme keys.
-struct Quad {
-    uint32_t X[4], Y[4], idx[4];  // P_minx, P_miny, P_maxx, P_maxy
-    int32_t ex[4], ey[4];         // edge q runs from E_q to E_{q+1}
-    double ec[4];                 // ex*E_q.y - ey*E_q.x
-    uint32_t sigma[4];            // k2 of each region's first point
-    uint32_t err;
-};
-
-// The edges and the regions' first keys from the extreme points Q.X, Q.Y.
-__device__ inline void quad_edges(Quad& Q)
-{
-    // region q lies strictly right of edge q: ex*(y - E_q.y) - ey*(x - E_q.x) < 0
-    for (int q = 0; q < 4; ++q) {
-        const int s = (q + 1) & 3;
-        Q.ex[q] = (int32_t)Q.X[s] - (int32_t)Q.X[q];
-        Q.ey[q] = (int32_t)Q.Y[s] - (int32_t)Q.Y[q];
-        Q.ec[q] = (double)Q.ex[q] * (double)Q.Y[q] - (double)Q.ey[q] * (double)Q.X[q];
-    }
-    Q.sigma[0] = Q.Y[0];        // R1 starts at P_minx
-    Q.sigma[1] = Q.X[1] ^ kM;   // R2 starts at P_miny
-    Q.sigma[2] = Q.Y[2] ^ kM;   // R3 starts at P_maxx
-    Q.sigma[3] = Q.X[3];        // R4 starts at P_maxy
-}
-
-__device__ inline void make_quad(ExtAcc r, Quad& Q)
-{
-    for (int e = 0; e < 2; ++e) {
-        if (r.imax[e] == ~0u) {  // every key is 0: the minimum is the answer
-            r.kmax[e] = r.kmin[e];
-            r.imax[e] = r.imin[e];
-        }
-    }
-    // masked so that a rejected input still gives in-range values
-    const u64 key[4] = {r.kmin[0], r.kmin[1], r.kmax[0], r.kmax[1]};
-    Q.idx[0] = r.imin[0];
-    Q.idx[1] = r.imin[1];
-    Q.idx[2] = r.imax[0];
-    Q.idx[3] = r.imax[1];
-    Q.X[0] = (uint32_t)(key[0] >> 32) & kM; Q.Y[0] = ((uint32_t)key[0] & kM) ^ kM;
-    Q.Y[1] = (uint32_t)(key[1] >> 32) & kM; Q.X[1] = (uint32_t)key[1] & kM;
-    Q.X[2] = (uint32_t)(key[2] >> 32) & kM; Q.Y[2] = ((uint32_t)key[2] & kM) ^ kM;
-    Q.Y[3] = (uint32_t)(key[3] >> 32) & kM; Q.X[3] = (uint32_t)key[3] & kM;
-    quad_edges(Q);
-    Q.err = r.bad ? kErrDomain : 0u;
-}
-
-// Every workgroup reduces the per-workgroup extreme partials itself (a few
-// tens of KB) and derives the quadrilateral; workgroup 0 publishes it.
-// Thread t holds partials t, t + kBlock, ... (nparts <= kStreamGrid); the
-// loads are issued first (load_partials) so that other set-up can run while
-// they are in flight.
-constexpr int kPartPer = kStreamGrid / kBlock;
-
-__device__ inline void load_partials(const ExtPartial* __restrict__ part, int nparts, ExtPartial (&p)[kPartPer])
-{
-#pragma unroll
-    for (int u = 0; u < kPartPer; ++u) {
-        const int b = u * kBlock + (int)threadIdx.x;
-        if (b < nparts) p[u] = part[b];
-    }
-}
-
-__device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, DevHeader* __restrict__ hdr,
-                                   Quad& Q, ExtAcc* sh)
-{
-    ExtAcc r;
-    ext_init(r);
-#pragma unroll
-    for (int u = 0; u < kPartPer; ++u) {
-        if (u * kBlock + (int)threadIdx.x >= nparts) continue;
-        ExtAcc o;
-        for (int e = 0; e < 2; ++e) {
-            o.kmin[e] = p[u].kmin[e];
-            o.kmax[e] = p[u].kmax[e];
-            o.imin[e] = p[u].imin[e];
-            o.imax[e] = p[u].imax[e];
-        }
-        o.bad = p[u].err != 0;
-        o.hi = 0;
-        ext_combine(r, o);
-    }
-    ext_block_reduce(r, sh);
-    __shared__ Quad sq;
-    if (threadIdx.x == 0) {
-        make_quad(r, sq);
-        if (blockIdx.x == 0) {
-            for (int e = 0; e < 4; ++e) {
-                hdr->ext_x[e] = sq.X[e];
-                hdr->ext_y[e] = sq.Y[e];
-                hdr->ext_idx[e] = sq.idx[e];
-                hdr->ex[e] = sq.ex[e];
-                hdr->ey[e] = sq.ey[e];
-                hdr->ec[e] = sq.ec[e];
-                hdr->sigma[e] = sq.sigma[e];
+        // (device-scope stores: the last workgroup reads them)
+        st_dev(wgcount + blockIdx.x, s_fill);
+        u64* const pw = reinterpret_cast<u64*>(part + blockIdx.x);
+        static_assert(sizeof(ExtPartial) == 8 * sizeof(u64), "ExtPartial is eight words");
+        const u64* const pv = reinterpret_cast<const u64*>(&p);
+        for (int k = 0; k < 8; ++k) st_dev(pw + k, pv[k]);
+        stores_done();
+        // arrival: counters per group of 32 workgroups, then one over the
+        // groups (same-address atomics from many workgroups serialise); the
+        // last arrival of a group clears its counter, the last overall the top
+        const uint32_t g = blockIdx.x / 32, gsize = min(32u, gridDim.x - g * 32);
+        bool last = false;
+        if (arrive(&sctr[1 + g]) == gsize - 1) {
+            st_dev(&sctr[1 + g], 0u);
+            if (arrive(&sctr[0]) == (gridDim.x + 31) / 32 - 1) {
+                st_dev(&sctr[0], 0u);
+                last = true;
             }
-            if (sq.err) atomicOr(&hdr->err, sq.err);
         }
+        s_last = last ? 1u : 0u;
     }
     __syncthreads();
-    Q = sq;
+    if (!s_last) return;
+    // the last workgroup: the quadrilateral and the number of open points
+    ExtPartial pp[kPartPer];
+#pragma unroll
+    for (int u = 0; u < kPartPer; ++u) {
+        const int b = u * kBlock + (int)tid;
+        if (b < (int)gridDim.x) {
+            const u64* const pr = reinterpret_cast<const u64*>(part + b);
+            u64* const pd = reinterpret_cast<u64*>(&pp[u]);
+            for (int k = 0; k < 8; ++k) pd[k] = ld_dev(pr + k);
+        }
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kStreamGrid / kBlock; ++k) {
+        const uint32_t b = k * kBlock + tid;
+        c += b < gridDim.x ? ld_dev(wgcount + b) : 0u;
+    }
+    Quad Q;
+    reduce_quad(pp, (int)gridDim.x, hdr, Q, sh, true);
+    c = wave_sum(c);
+    if (lane == 0 && c) atomicAdd(&hdr->open, c);
 }
 
 // Region (0..3, or 4 for none) of a point by the exact test: every product is
@@ -746,65 +847,116 @@ __device__ inline uint32_t region_of(const Quad& Q, uint32_t X, uint32_t Y)
     return t0 ? 0u : t1 ? 1u : t2 ? 2u : t3 ? 3u : 4u;
 }
 
-// Workgroup j takes the open lists of k_stream workgroups 4j .. 4j+3 and
-// writes its records to its own region [j*4*region, ...) of the record
-// arrays, their number to candcount[j], and adds its records' number and
-// smallest k2 per sort bucket to the global bucket arrays.
-constexpr int kListsPerCand = 4;
+// Frame coordinates (k1, k2) of a point (X, Y) in region q's frame.
+__device__ inline void to_frame(uint32_t q, uint32_t X, uint32_t Y, uint32_t& k1, uint32_t& k2)
+{
+    const uint32_t a = (q & 1u) ? Y : X;
+    const uint32_t b = (q & 1u) ? X : Y;
+    k1 = (q & 2u) ? a ^ kM : a;
+    k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+}
 
-__global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ part, int nparts,
+// Bucket arrays that threads read with the ownership "thread t: buckets
+// kPerThreadBuckets*t .. kPerThreadBuckets*(t+1)-1" sit in LDS at bpad(b):
+// one pad word per 32 puts the lanes of one read step in distinct banks.
+constexpr int kPerThreadBuckets = kBuckets / kBlock;  // 32
+__device__ inline uint32_t bpad(uint32_t b) { return b + (b >> 5); }
+constexpr int kBucketsPadded = kBuckets + kBuckets / 32;
+
+// k_cand: workgroup j takes the open lists of k_stream workgroups
+// L*j .. L*(j+1)-1 (L = lists, a launch shape).  It runs the exact region test
+// and the chunk filter on them, then sorts its records by sort bucket
+// (region q and the top kBucketBits bits of k1) inside its own part of the
+// record arrays: a counting sort with its histogram in LDS, so no two
+// workgroups share a counter.  Its row of the bucket table receives, per
+// bucket, the first position of the bucket's records in its part (and the
+// total at the end) and their smallest k2.
+//   pass 1  the records, in chunk order, to part A (key[0], val[0]); LDS
+//           counts and smallest k2 per bucket;
+//   pass 2  the counts' exclusive prefix sum: the row;
+//   pass 3  the records again from part A, each to part B (key[1], val[1])
+//           at its bucket's next position.
+constexpr int kCandMaxRows = 256;  // rows of the bucket table (k_cand workgroups) at most
+
+// Rows of the bucket table for a call: one per cand_per_row open points (a
+// launch shape), at least one, at most kCandMaxRows and the k_stream grid;
+// row r takes lists [r*lists, min((r+1)*lists, grid)), so the rows' parts
+// tile the open lists' regions.  The open count comes from k_stream, so
+// k_cand, k_scan and k_bucket_spa all derive the same rows from it.
+__device__ inline uint32_t cand_rows(uint32_t open, uint32_t grid, uint32_t per_row, uint32_t& lists)
+{
+    uint32_t r = (open + per_row - 1) / per_row;
+    r = max(1u, min(r, min((uint32_t)kCandMaxRows, grid)));
+    lists = (grid + r - 1) / r;
+    return (grid + lists - 1) / lists;
+}
+
+// The quadrilateral from the header (published by k_stream).
+__device__ inline void quad_from_header(const DevHeader* __restrict__ hdr, Quad& Q)
+{
+    for (int q = 0; q < 4; ++q) {
+        Q.ex[q] = hdr->ex[q];
+        Q.ey[q] = hdr->ey[q];
+        Q.ec[q] = hdr->ec[q];
+        Q.sigma[q] = hdr->sigma[q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ hdr,
                                                  const uint32_t* __restrict__ open_idx,
                                                  const u64* __restrict__ open_xym, uint32_t region,
-                                                 const uint32_t* __restrict__ wgcount, DevHeader* __restrict__ hdr,
-                                                 uint32_t* __restrict__ out_key, u64* __restrict__ out_val,
-                                                 uint32_t* __restrict__ candcount, Buckets bk)
+                                                 const uint32_t* __restrict__ wgcount, uint32_t grid,
+                                                 uint32_t per_row, uint32_t* __restrict__ key_a, u64* __restrict__ val_a,
+                                                 uint32_t* __restrict__ key_b, u64* __restrict__ val_b,
+                                                 uint32_t* __restrict__ rowoff, uint32_t* __restrict__ rowmin)
 {
-    __shared__ ExtAcc sh[kWaves];
     __shared__ u64 smin[4 * kSlots];
     __shared__ uint32_t sexc[4 * kSlots];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t lcnt[kBuckets];  // per sort bucket, this chunk
-    __shared__ u64 lmin[kBuckets];
-    ExtPartial pp[kPartPer];
-    load_partials(part, nparts, pp);  // in flight during the LDS set-up
-    for (int b = threadIdx.x; b < kBuckets; b += kBlock) {
-        lcnt[b] = 0;
-        lmin[b] = ~0ull;
-    }
+    __shared__ uint32_t lcnt[kBucketsPadded];  // per bucket (at bpad): counts, then next positions
+    __shared__ uint32_t lmin[kBuckets];        // smallest k2 per bucket
+    __shared__ uint32_t s_start[kStreamGrid + 1];  // the lists' first positions in the concatenation
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
+    if (hdr->err) return;
+    uint32_t lists;
+    const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
+    if (blockIdx.x >= rows) return;
     Quad Q;
-    reduce_quad(pp, nparts, hdr, Q, sh);
-    if (blockIdx.x == 0) {
-        // the number of open points, for the call's counts
-        static_assert(kStreamGrid % kBlock == 0, "open-point counts per thread");
-        uint32_t c = 0;
+    quad_from_header(hdr, Q);
+    for (int b = tid; b < kBuckets; b += kBlock) {
+        lcnt[bpad(b)] = 0;
+        lmin[b] = ~0u;
+    }
+    // the workgroup's lists, concatenated (thread t: lists 4t .. 4t+3)
+    const uint32_t first = blockIdx.x * lists, nl = min(lists, grid - first);
+    {
+        uint32_t c[4], sum = 0;
 #pragma unroll
-        for (int k = 0; k < kStreamGrid / kBlock; ++k) {  // all loads in flight together
-            const int b = k * kBlock + (int)tid;
-            c += b < nparts ? wgcount[b] : 0u;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t l = 4 * tid + k;
+            c[k] = l < nl ? wgcount[first + l] : 0u;
+            sum += c[k];
         }
         uint32_t total;
-        (void)block_excl_sum(c, scratch, total);
-        if (tid == 0) hdr->open = total;
-    }
-    if (Q.err) {
-        if (tid == 0) candcount[blockIdx.x] = 0;
-        return;
-    }
-    // the workgroup's lists, concatenated
-    uint32_t start[kListsPerCand + 1];
-    start[0] = 0;
+        uint32_t run = block_excl_sum(sum, scratch, total);
 #pragma unroll
-    for (int l = 0; l < kListsPerCand; ++l) {
-        const int b = (int)blockIdx.x * kListsPerCand + l;
-        start[l + 1] = start[l] + (b < nparts ? wgcount[b] : 0u);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t l = 4 * tid + k;
+            if (l < nl) s_start[l] = run;
+            run += c[k];
+        }
+        if (tid == 0) s_start[nl] = total;
     }
-    const uint32_t count = start[kListsPerCand];
-    uint32_t* const my_key = out_key + (size_t)blockIdx.x * kListsPerCand * region;
-    u64* const my_val = out_val + (size_t)blockIdx.x * kListsPerCand * region;
+    static_assert(4 * kBlock >= kStreamGrid, "four lists per thread");
+    __syncthreads();
+    const uint32_t count = s_start[nl];
+    const size_t part = (size_t)first * region;
+    uint32_t* const my_ka = key_a + part;
+    u64* const my_va = val_a + part;
     uint32_t written = 0;
     constexpr int kPer = kCandChunk / kBlock;
 
+    // ---- pass 1 ----
     for (uint32_t c0 = 0; c0 < count; c0 += kCandChunk) {
         for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
         __syncthreads();
@@ -814,23 +966,17 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
             const uint32_t e = c0 + k * kBlock + tid;
             addrs[k] = ~0u;
             if (e < count) {
-                uint32_t l = 0, sl = 0;
-#pragma unroll
-                for (int m = 1; m < kListsPerCand; ++m) {
-                    if (e >= start[m]) {
-                        l = m;
-                        sl = start[m];
-                    }
-                }
-                const size_t at = (size_t)(blockIdx.x * kListsPerCand + l) * region + (e - sl);
+                // the list holding e: the last with start <= e
+                uint32_t l = 0;
+                for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1)
+                    if (l + st < nl && s_start[l + st] <= e) l += st;
+                const size_t at = ((size_t)first + l) * region + (e - s_start[l]);
                 const u64 r = open_xym[at];
                 const uint32_t X = (uint32_t)r & kM, Y = (uint32_t)(r >> 23) & kM, mask = (uint32_t)(r >> 46);
                 const uint32_t q = region_of(Q, X, Y);
                 if (q < 4 && ((mask >> q) & 1u)) {
-                    const uint32_t a = (q & 1u) ? Y : X;
-                    const uint32_t b = (q & 1u) ? X : Y;
-                    const uint32_t k1 = (q & 2u) ? a ^ kM : a;
-                    const uint32_t k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
+                    uint32_t k1, k2;
+                    to_frame(q, X, Y, k1, k2);
                     k1s[k] = k1;
                     k2s[k] = k2;
                     idxs[k] = open_idx[at];
@@ -878,35 +1024,69 @@ __global__ __launch_bounds__(kBlock) void k_cand(const ExtPartial* __restrict__ 
         }
         uint32_t total;
         uint32_t pos = written + block_excl_sum(__popc(keep), scratch, total);
-        uint32_t own = 0;  // records whose bucket this thread publishes
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             if ((keep >> k) & 1u) {
                 const uint32_t q = addrs[k] >> kSlotBits;
-                my_key[pos] = (q << 23) | k1s[k];
-                my_val[pos] = ((u64)k2s[k] << 32) | idxs[k];
+                my_ka[pos] = (q << 23) | k1s[k];
+                my_va[pos] = ((u64)k2s[k] << 32) | idxs[k];
                 ++pos;
                 const uint32_t b = (q << kBucketBits) | (k1s[k] >> kLowBits);
-                if (atomicAdd(&lcnt[b], 1u) == 0) own |= 1u << k;
-                atomicMin(&lmin[b], ((u64)k2s[k] << 23) | k1s[k]);
+                atomicAdd(&lcnt[bpad(b)], 1u);
+                atomicMin(&lmin[b], k2s[k]);
             }
         }
         written += total;
         __syncthreads();
-        // the chunk's records and smallest k2 per bucket, one atomic each
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if ((own >> k) & 1u) {
-                const uint32_t b = ((addrs[k] >> kSlotBits) << kBucketBits) | (k1s[k] >> kLowBits);
-                atomicAdd(&bk.cnt[b], lcnt[b]);
-                atomicMin(&bk.kmin[b], lmin[b]);
-                lcnt[b] = 0;
-                lmin[b] = ~0ull;
-            }
-        }
-        __syncthreads();
     }
-    if (tid == 0) candcount[blockIdx.x] = written;
+
+    // ---- pass 2: the row (thread t owns buckets 32t .. 32t+31) ----
+    __syncthreads();  // (the counts' set-up, when there was no chunk)
+    uint32_t* const my_off = rowoff + (size_t)blockIdx.x * (kBuckets + 1);
+    {
+        uint32_t c[kPerThreadBuckets], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            c[k] = lcnt[bpad(tid * kPerThreadBuckets + k)];
+            sum += c[k];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow every read above)
+#pragma unroll
+        for (int k = 0; k < kPerThreadBuckets; ++k) {
+            lcnt[bpad(tid * kPerThreadBuckets + k)] = run;
+            run += c[k];
+        }
+        if (tid == 0) my_off[kBuckets] = total;
+    }
+    __syncthreads();
+    for (int b = tid; b < kBuckets; b += kBlock) {
+        my_off[b] = lcnt[bpad(b)];
+        rowmin[(size_t)blockIdx.x * kBuckets + b] = lmin[b];
+    }
+
+    // ---- pass 3: part A -> part B by bucket ----
+    __syncthreads();  // (a workgroup-scope fence and barrier: part A's stores, before other threads read them)
+    uint32_t* const my_kb = key_b + part;
+    u64* const my_vb = val_b + part;
+    for (uint32_t i0 = 0; i0 < written; i0 += 4 * kBlock) {
+        uint32_t kk[4];
+        u64 vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + u * kBlock + tid;
+            kk[u] = i < written ? my_ka[i] : ~0u;
+            vv[u] = i < written ? my_va[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (kk[u] == ~0u) continue;
+            const uint32_t b = ((kk[u] >> 23) << kBucketBits) | ((kk[u] & kM) >> kLowBits);
+            const uint32_t p = atomicAdd(&lcnt[bpad(b)], 1u);
+            my_kb[p] = kk[u];
+            my_vb[p] = vv[u];
+        }
+    }
 }
 
 // Round-1 survivor counts per region (Section 2.1.1), for chainhull_polygon:
@@ -946,182 +1126,141 @@ __global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restric
 // Steps 3-6 (Section 2.1; Table 1; Figure 2): the region sort, SPA and the
 // chain order, as a two-level sort fused with SPA.
 //
-// Level 1 (k_bucket): the records are placed by bucket, the region code and
-// the top kBucketBits bits of k1 (a counting sort: k_cand counted the
-// buckets).  Buckets in ascending order list the regions in Table 1's order
-// and each region by ascending k1.
+// Level 1: the records are grouped by bucket, the region code and the top
+// kBucketBits bits of k1 (a counting sort): k_cand sorts each workgroup's
+// records by bucket in its own part of the record arrays and writes its
+// row of the bucket table (first position per bucket, smallest k2 per
+// bucket); k_scan sums the rows per bucket (bucket sizes, where each
+// bucket's records start in the concatenated order) and takes, per region,
+// the exclusive prefix minimum of the buckets' smallest k2 seeded with the
+// region's first point (the threshold entering each bucket).  Buckets in
+// ascending order list the regions in Table 1's order and each region by
+// ascending k1.
 //
-// Level 2 (k_bucket_spa, one workgroup per bucket): inside a bucket the low
-// kLowBits bits of k1 address an LDS table directly, and a 64-bit atomic
-// minimum of (k2 << 32 | index) per entry leaves each group of equal k1 with
-// its smallest (k2, index): the order Table 1 asks for, restricted to what
-// SPA can keep.  SPA keeps a record iff its k2 is below the k2 of every
-// earlier record of its region and of the region's first point (Figure 2's
-// threshold t is exactly that running minimum, since a discarded record
-// never lowers it); within an equal-k1 group only the group's smallest
-// (k2, index) can qualify.  The running minimum entering a bucket is the
-// minimum over the region's earlier buckets (their smallest k2, counted by
-// k_cand) and the region's first point; inside the bucket it is an
-// exclusive prefix minimum over the table.  Survivors are written, in k1
+// Level 2 (k_bucket_spa): a bucket's records are gathered from the rows'
+// parts; inside a bucket the low kLowBits bits of k1 address an LDS table
+// directly, and a 64-bit atomic minimum of (k2 << 32 | index) per entry
+// leaves each group of equal k1 with its smallest (k2, index): the order
+// Table 1 asks for, restricted to what SPA can keep.  SPA keeps a record iff
+// its k2 is below the k2 of every earlier record of its region and of the
+// region's first point (Figure 2's threshold t is exactly that running
+// minimum, since a discarded record never lowers it); within an equal-k1
+// group only the group's smallest (k2, index) can qualify.  The running
+// minimum entering a bucket is the threshold above; inside the bucket it is
+// an exclusive prefix minimum over the table.  Survivors are written, in k1
 // order, as (index, x, y) at the bucket's first record position of the
-// chain buffer (pinned host memory while it fits); the number per bucket
-// goes to host memory, and the host concatenates the buckets.
+// chain buffer; their number per bucket goes to bk.surv.
 // ---------------------------------------------------------------------------
 
-// Exclusive prefix sum (counts) and, per region, exclusive prefix minimum
-// seeded with the region's first point (thresholds) over all buckets; every
-// thread owns kBuckets / kBlock consecutive buckets.  Returns the total.
-constexpr int kPerThreadBuckets = kBuckets / kBlock;  // 32
+// k_scan: workgroup j owns buckets [64j, 64j+64) (within one region, since
+// a region has 2048 buckets); wave w sums rows w, w+4, ... of them, one
+// bucket per lane.  Per bucket: its size and smallest k2 over the rows;
+// then, inside the workgroup, the exclusive prefix sum of the sizes
+// (lstart) and exclusive prefix minimum of the smallest k2 (lthr).  The
+// workgroup that finishes last (a counter, cleared again by it) combines the
+// workgroups' totals: the first record of workgroup j's buckets (wgbase) and
+// the threshold entering them (wgthr, seeded with the region's first
+// point).  A bucket's first record is then lstart + wgbase, its threshold
+// min(lthr, wgthr).
+constexpr int kScanBuckets = 64;                    // buckets per k_scan workgroup
+constexpr int kScanGrid = kBuckets / kScanBuckets;  // 128
+constexpr int kScanPerRegion = kScanGrid / 4;       // 32
+static_assert(kScanGrid <= 2 * 64 && kScanPerRegion == 32, "the last workgroup's combine: two waves, half a wave per region");
 
-// LDS position of bucket b in a per-bucket array that threads read with
-// the ownership above (thread t: buckets 32t .. 32t+31): one pad word per
-// 32 puts the lanes of one read step in distinct banks.  The arrays are
-// filled from global memory with lane-consecutive (coalesced) loads first.
-__device__ inline uint32_t bpad(uint32_t b) { return b + (b >> 5); }
-constexpr int kBucketsPadded = kBuckets + kBuckets / 32;
-
-__global__ __launch_bounds__(kBlock) void k_bucket(const uint32_t* __restrict__ in_key,
-                                                   const u64* __restrict__ in_val, uint32_t in_region,
-                                                   const uint32_t* __restrict__ candcount, int nlists,
-                                                   uint32_t* __restrict__ key, u64* __restrict__ val,
-                                                   DevHeader* __restrict__ hdr, Buckets bk)
+__global__ __launch_bounds__(kBlock) void k_scan(DevHeader* __restrict__ hdr, const uint32_t* __restrict__ rowoff,
+                                                 const uint32_t* __restrict__ rowmin, uint32_t grid,
+                                                 uint32_t per_row, Buckets bk)
 {
-    static_assert(kBuckets % kBlock == 0 && (kBuckets / 4) % kPerThreadBuckets == 0, "bucket ownership");
-    __shared__ uint32_t soff[kBucketsPadded];  // first position of each bucket (at bpad)
-    __shared__ uint32_t sthr[kBucketsPadded];  // threshold entering each bucket (at bpad)
-    __shared__ uint32_t lcnt[kBuckets];        // this chunk's records per bucket, then their base
+    __shared__ uint32_t s_c[kWaves][64], s_m[kWaves][64];
     __shared__ uint32_t scratch[kWaves];
-    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_last;
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     if (hdr->err) return;
-
-    // bucket offsets and thresholds: thread t owns kPerThreadBuckets
-    // consecutive buckets, so a region's buckets are one wave's
-    {
-        // staged: counts in soff, smallest k2 in sthr (all loads in flight
-        // together)
-        {
-            uint32_t vc[kPerThreadBuckets];
-            u64 vm[kPerThreadBuckets];
+    uint32_t lists;
+    const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
+    const uint32_t b = blockIdx.x * kScanBuckets + lane;
+    uint32_t c = 0, m = ~0u;
+    constexpr int kBatch = 8;  // rows loaded together per wave
+    for (uint32_t r0 = wave; r0 < rows; r0 += kWaves * kBatch) {
+        uint32_t lo[kBatch], hi[kBatch], mn[kBatch];
 #pragma unroll
-            for (int k = 0; k < kPerThreadBuckets; ++k) {
-                vc[k] = bk.cnt[k * kBlock + tid];
-                vm[k] = bk.kmin[k * kBlock + tid];
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t r = min(r0 + k * kWaves, rows - 1);
+            lo[k] = rowoff[(size_t)r * (kBuckets + 1) + b];
+            hi[k] = rowoff[(size_t)r * (kBuckets + 1) + b + 1];
+            mn[k] = rowmin[(size_t)r * kBuckets + b];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            if (r0 + k * kWaves < rows) {
+                c += hi[k] - lo[k];
+                m = min(m, mn[k]);
             }
-#pragma unroll
-            for (int k = 0; k < kPerThreadBuckets; ++k) {
-                const uint32_t b = k * kBlock + tid;
-                soff[bpad(b)] = vc[k];
-                sthr[bpad(b)] = (uint32_t)(vm[k] >> 23);
-                lcnt[b] = 0;
-            }
         }
-        __syncthreads();
-        uint32_t c[kPerThreadBuckets], mk[kPerThreadBuckets], sum = 0, lo = ~0u;
+    }
+    s_c[wave][lane] = c;
+    s_m[wave][lane] = m;
+    __syncthreads();
+    if (wave == 0) {
+        c = 0;
+        m = ~0u;
 #pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) {
-            const uint32_t b = bpad(tid * kPerThreadBuckets + k);
-            c[k] = soff[b];
-            mk[k] = sthr[b];
-            sum += c[k];
-            lo = min(lo, mk[k]);
+        for (int w = 0; w < kWaves; ++w) {
+            c += s_c[w][lane];
+            m = min(m, s_m[w][lane]);
         }
-        uint32_t total;
-        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow every read above)
-        const uint32_t q = tid / 64;
-        const uint32_t incl = wave_incl_min(lo);
-        uint32_t before = __shfl_up(incl, 1);
-        if (lane_id() == 0) before = ~0u;
-        before = min(before, hdr->sigma[q]);
-#pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) {
-            const uint32_t b = bpad(tid * kPerThreadBuckets + k);
-            soff[b] = run;
-            sthr[b] = before;
-            run += c[k];
-            before = min(before, mk[k]);
+        bk.cnt[b] = c;
+        const uint32_t incl = wave_incl_sum(c);
+        bk.lstart[b] = incl - c;
+        const uint32_t mincl = wave_incl_min(m);
+        uint32_t mexcl = __shfl_up(mincl, 1);
+        if (lane == 0) mexcl = ~0u;
+        bk.lthr[b] = mexcl;
+        const uint32_t tot = __shfl(incl, 63), mtot = __shfl(mincl, 63);
+        if (lane == 0) {
+            // the workgroup's totals, then its arrival
+            st_dev(bk.wtot + blockIdx.x, tot);
+            st_dev(bk.wmin + blockIdx.x, mtot);
+            stores_done();
+            const uint32_t a = arrive(bk.ctr);
+            s_last = a == (uint32_t)gridDim.x - 1 ? 1u : 0u;
+            if (s_last) st_dev(bk.ctr, 0u);
         }
-        if (blockIdx.x == 0 && tid == 0) hdr->cand = total;
     }
     __syncthreads();
-    if (blockIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) {
-            const uint32_t b = k * kBlock + tid;
-            bk.off[b] = soff[bpad(b)];
-            bk.thr[b] = sthr[bpad(b)];
-        }
+    if (!s_last) return;
+    // the last workgroup: thread j < kScanGrid combines workgroup j
+    const uint32_t j = tid;
+    const uint32_t t = j < (uint32_t)kScanGrid ? ld_dev(bk.wtot + j) : 0u;
+    const uint32_t mj = j < (uint32_t)kScanGrid ? ld_dev(bk.wmin + j) : ~0u;
+    uint32_t total;
+    const uint32_t base = block_excl_sum(t, scratch, total);
+    // exclusive prefix minimum over the earlier workgroups of the region
+    // (32 workgroups: half a wave), seeded with the region's first point
+    const uint32_t half = lane & 32u, q = (j / kScanPerRegion) & 3u;
+    uint32_t before = hdr->sigma[q];
+    for (uint32_t k = 0; k < 32; ++k) {  // (uniform: every lane takes part in the shuffle)
+        const uint32_t v = (uint32_t)__shfl(mj, (int)(half + k));
+        if (k < (lane & 31u)) before = min(before, v);
     }
-
-    // Place this workgroup's records (k_cand workgroup blockIdx.x), a chunk
-    // at a time: local ranks by LDS atomics, one global reservation per
-    // bucket and chunk.  A record is dropped first when the threshold
-    // entering its bucket is <= its k2 (a record of an earlier bucket, or the
-    // region's first point, dominates it) or when its bucket's smallest
-    // record precedes it with k1 <= its k1; the sort and SPA would drop it.
-    const uint32_t count = (int)blockIdx.x < nlists ? candcount[blockIdx.x] : 0u;
-    const uint32_t* const src_k = in_key + (size_t)blockIdx.x * in_region;
-    const u64* const src_v = in_val + (size_t)blockIdx.x * in_region;
-    constexpr int kPer = 4;
-    for (uint32_t c0 = 0; c0 < count; c0 += kPer * kBlock) {
-        uint32_t kk[kPer], b[kPer], r[kPer];
-        u64 vv[kPer], bm[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t i = c0 + k * kBlock + tid;
-            b[k] = ~0u;
-            if (i < count) {
-                kk[k] = src_k[i];
-                vv[k] = src_v[i];
-                b[k] = ((kk[k] >> 23) << kBucketBits) | ((kk[k] & kM) >> kLowBits);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) bm[k] = b[k] != ~0u ? bk.kmin[b[k]] : ~0ull;
-        uint32_t own = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (b[k] != ~0u) {
-                const uint32_t k1 = kk[k] & kM, k2 = (uint32_t)(vv[k] >> 32);
-                const u64 me = ((u64)k2 << 23) | k1;
-                if (k2 >= sthr[bpad(b[k])] || (bm[k] < me && (uint32_t)(bm[k] & kM) <= k1)) {
-                    b[k] = ~0u;
-                } else {
-                    r[k] = atomicAdd(&lcnt[b[k]], 1u);
-                    if (r[k] == 0) own |= 1u << k;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if ((own >> k) & 1u) lcnt[b[k]] = soff[bpad(b[k])] + atomicAdd(&bk.cur[b[k]], lcnt[b[k]]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (b[k] != ~0u) {
-                const uint32_t pos = lcnt[b[k]] + r[k];
-                key[pos] = kk[k];
-                val[pos] = vv[k];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if ((own >> k) & 1u) lcnt[b[k]] = 0;
-        }
-        __syncthreads();
+    if (j < (uint32_t)kScanGrid) {
+        bk.wgbase[j] = base;
+        bk.wgthr[j] = before;
     }
+    if (j == 0) hdr->cand = total;
 }
 
-// Workgroup g takes buckets 4g .. 4g+3.  A bucket of at most 64 records is
+// Workgroup g takes buckets 4g .. 4g+3.  A bucket's records are gathered
+// from the rows' parts (row w: part B of k_cand workgroup w, positions
+// [rowoff[w][b], rowoff[w][b+1]); each lane holds up to four rows).  A bucket of at most 64 records is
 // resolved by one wave without the table: lane l holds record l, which SPA
 // keeps iff its k2 is below the threshold and no record of the bucket
 // precedes it in (k1, k2, index) order with k2 <= its k2; its rank in the
 // chain is the number of kept records with a smaller k1 (kept records have
 // distinct k1).  Larger buckets use the table, the whole workgroup on one
 // bucket at a time.  Survivors go, as (index, x, y), to dev_chain at the
-// bucket's first record position; their number to bk.surv.
+// bucket's first record position (also written to bk.off); their number to
+// bk.surv.
 constexpr int kPerThreadLow = kLowSize / kBlock;  // 16
 constexpr int kBucketsPerSpa = kWaves;
 constexpr uint32_t kWaveBucket = 64;
@@ -1137,26 +1276,68 @@ __device__ inline PolyRec chain_rec(uint32_t q, uint32_t k1, uint32_t k2, uint32
 }
 
 __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restrict__ key,
-                                                       const u64* __restrict__ val,
+                                                       const u64* __restrict__ val, uint32_t region, uint32_t grid,
+                                                       uint32_t per_row, const uint32_t* __restrict__ rowoff,
                                                        const DevHeader* __restrict__ hdr, Buckets bk,
                                                        PolyRec* __restrict__ dev_chain)
 {
+    constexpr int kRowsPerLane = kCandMaxRows / 64;
     __shared__ u64 tab[kLowSize];
     __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_fill[kBucketsPerSpa];
+    __shared__ uint32_t s_m[kBucketsPerSpa], s_off[kBucketsPerSpa], s_thr[kBucketsPerSpa];
+    // per bucket and row: first position in the row's part, records before the row
+    __shared__ uint32_t s_seg[kBucketsPerSpa][kCandMaxRows], s_pre[kBucketsPerSpa][kCandMaxRows];
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     if (hdr->err) return;
+    uint32_t lists;
+    const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
+    const size_t part = (size_t)lists * region;  // records in one row's part
+    // the row holding record i of bucket kb: the last row with pre <= i
+    auto row_of = [&](uint32_t kb, uint32_t i) {
+        uint32_t r = 0;
+        for (uint32_t st = kCandMaxRows / 2; st > 0; st >>= 1)
+            if (r + st < rows && s_pre[kb][r + st] <= i) r += st;
+        return r;
+    };
     {
-        // one wave per bucket of at most kWaveBucket records
+        // wave w: bucket 4g + w.  Its segments (rows lane, lane + 64, ...),
+        // where it starts, its threshold
         const uint32_t b = blockIdx.x * kBucketsPerSpa + wave;
-        const uint32_t m = __builtin_amdgcn_readfirstlane(bk.cur[b]);  // the same in every lane
-        if (lane == 0) s_fill[wave] = m;
+        uint32_t lo[kRowsPerLane], n[kRowsPerLane];
+#pragma unroll
+        for (int k = 0; k < kRowsPerLane; ++k) {
+            const uint32_t r = lane + 64 * k;
+            lo[k] = 0;
+            n[k] = 0;
+            if (r < rows) {
+                lo[k] = rowoff[(size_t)r * (kBuckets + 1) + b];
+                n[k] = rowoff[(size_t)r * (kBuckets + 1) + b + 1] - lo[k];
+            }
+        }
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < kRowsPerLane; ++k) {
+            const uint32_t incl = wave_incl_sum(n[k]);
+            s_seg[wave][lane + 64 * k] = lo[k];
+            s_pre[wave][lane + 64 * k] = m + incl - n[k];
+            m += __shfl(incl, 63);
+        }
+        const uint32_t off = bk.lstart[b] + bk.wgbase[b / kScanBuckets];
+        const uint32_t thr = min(bk.lthr[b], bk.wgthr[b / kScanBuckets]);
+        if (lane == 0) {
+            s_m[wave] = m;
+            s_off[wave] = off;
+            s_thr[wave] = thr;
+            bk.off[b] = off;
+        }
+        __builtin_amdgcn_wave_barrier();
         if (m <= kWaveBucket) {
-            const uint32_t off = bk.off[b], thr = bk.thr[b];
             uint32_t k1 = ~0u, k2 = ~0u, idx = ~0u;
             if (lane < m) {
-                k1 = key[off + lane] & kM;
-                const u64 v = val[off + lane];
+                const uint32_t r = row_of(wave, lane);
+                const size_t at = (size_t)r * part + s_seg[wave][r] + (lane - s_pre[wave][r]);
+                k1 = key[at] & kM;
+                const u64 v = val[at];
                 k2 = (uint32_t)(v >> 32);
                 idx = (uint32_t)v;
             }
@@ -1181,9 +1362,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
     }
     __syncthreads();
     for (int kb = 0; kb < kBucketsPerSpa; ++kb) {
-        const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = s_fill[kb];
+        const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = s_m[kb];
         if (m <= kWaveBucket) continue;
-        const uint32_t off = bk.off[b], thr = bk.thr[b];
+        const uint32_t off = s_off[kb], thr = s_thr[kb];
         for (int e = tid; e < kLowSize; e += kBlock) tab[e] = ~0ull;
         __syncthreads();
         constexpr int kBatch = 8;  // records loaded together per thread
@@ -1193,8 +1374,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const uint32_t i = i0 + u * kBlock + tid;
-                k1[u] = i < m ? key[off + i] : 0u;
-                v[u] = i < m ? val[off + i] : ~0ull;
+                k1[u] = 0u;
+                v[u] = ~0ull;
+                if (i < m) {
+                    const uint32_t r = row_of(kb, i);
+                    const size_t at = (size_t)r * part + s_seg[kb][r] + (i - s_pre[kb][r]);
+                    k1[u] = key[at];
+                    v[u] = val[at];
+                }
             }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u)
@@ -1254,16 +1441,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
 // ---------------------------------------------------------------------------
 constexpr int kSeg = 1024;
 constexpr int kPerThreadSeg = kSeg / kBlock;  // 4
-constexpr int kChainGrid = 256;
 constexpr int kPrehullRounds = 16;
-
-__device__ inline void to_frame(uint32_t q, uint32_t X, uint32_t Y, uint32_t& k1, uint32_t& k2)
-{
-    const uint32_t a = (q & 1u) ? Y : X;
-    const uint32_t b = (q & 1u) ? X : Y;
-    k1 = (q & 2u) ? a ^ kM : a;
-    k2 = ((q ^ (q >> 1)) & 1u) ? b ^ kM : b;
-}
 
 // Frame cross product (o, a, b): > 0 for a left turn.
 __device__ inline i64 frame_turn(uint32_t o1, uint32_t o2, uint32_t a1, uint32_t a2, uint32_t b1, uint32_t b2)
@@ -1298,6 +1476,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         publish_header();
         return;
     }
+    // the chain is at most the sort records long: workgroups past its last
+    // segment have nothing to do (workgroup 0 still publishes the header)
+    if (blockIdx.x > 0 && blockIdx.x >= (hdr->cand + kSeg - 1) / kSeg) return;
 
     uint32_t total;
     {
@@ -1484,8 +1665,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
 constexpr int kBatchBlock = 512;                                   // two workgroups per CU
 constexpr int kBatchWaves = kBatchBlock / 64;
 constexpr int kBatchWavesPerSimd = 4;                              // 128 VGPRs: two workgroups fit
-constexpr int kBatchUnroll = 2;                                    // float4 loads per thread and round
-constexpr uint32_t kBatchRound = 2u * kBatchUnroll * kBatchBlock;  // points per round
+constexpr int kBatchUnrollMax = 2;                                 // float4 loads per thread and round, at most
+constexpr uint32_t kBatchRoundMax = 2u * kBatchUnrollMax * kBatchBlock;  // points per round, at most
 constexpr int kBatchList = 8192;                                   // listed points per set
 constexpr int kBatchPerList = kBatchList / kBatchBlock;
 constexpr int kBatchCand = 4096;                                   // sort records per set
@@ -1498,7 +1679,7 @@ constexpr int kBatchChunks = 64, kBatchChunk = 128;                // the first 
 constexpr int kBatchRounds = 32;                                   // pre-hull rounds at most
 constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger sets: single-hull path
 constexpr int32_t kBatchRedo = INT32_MIN;
-static_assert(kBatchList >= 2 * (int)kBatchRound, "a round must fit beside a compacted list");
+static_assert(kBatchList >= 2 * (int)kBatchRoundMax, "a round must fit beside a compacted list");
 static_assert(kBatchCand / kBatchBlock <= 8 && kBatchPolyMax % kBatchBlock == 0, "per-thread shares");
 // LDS: [staircase u32 x 4S][raw slot minima u32 x 4S] [list u32 x
 // kBatchList].  Once the stream is done the region slot minima (u64 x
@@ -1751,6 +1932,7 @@ __device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, 
     return (int)*s_start;
 }
 
+template <int kBatchUnroll>
 __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(const float* __restrict__ pts,
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ order,
@@ -1803,7 +1985,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         atomicMin(&raw[2 * S + ((x ^ kM) >> kStairShift)], y ^ kM);  // R3: (M-x, M-y)
         atomicMin(&raw[3 * S + ((y ^ kM) >> kStairShift)], x);  // R4: (M-y, x)
     };
-    if (m > kBatchRound) {
+    if (m > (2u * kBatchUnroll * kBatchBlock)) {
         constexpr uint32_t kThreads = kBatchBlock / kBatchChunks, kPer = kBatchChunk / kThreads;
         const uint32_t c = tid / kThreads, sub = tid % kThreads;
         const uint32_t start = (uint32_t)(((u64)c * (m - kBatchChunk)) / (kBatchChunks - 1));
@@ -1946,25 +2128,25 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             list_point(X0, Y0, i0, valid, sx0, sy0);
             list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
         }
-        // The list holds at most known + since * kBatchRound points now and
-        // the next round adds at most kBatchRound: only when that bound
+        // The list holds at most known + since * (2u * kBatchUnroll * kBatchBlock) points now and
+        // the next round adds at most (2u * kBatchUnroll * kBatchBlock): only when that bound
         // could pass the list's room is the fill taken (a workgroup
         // barrier), the same in every thread: each wave posts its own count
         // (double-buffered: a wave that runs ahead to the next check writes
         // the other buffer).
         ++since;
-        if (known + (since + 1) * kBatchRound > (uint32_t)kBatchList) {
+        if (known + (since + 1) * (2u * kBatchUnroll * kBatchBlock) > (uint32_t)kBatchList) {
             if (lane == 0) wcnt[par][wave] = wtot;
             __syncthreads();
             uint32_t fill = 0;
 #pragma unroll
             for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[par][w];
             par ^= 1u;
-            if (fill > (uint32_t)kBatchList - kBatchRound) {
+            if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
                 fill = compact();
                 // a list still too full after the compaction: the set has
                 // too many open points for the workgroup
-                if (fill > (uint32_t)kBatchList - kBatchRound) {
+                if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
                     full = true;
                     break;
                 }
@@ -2245,10 +2427,11 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
 //   pass 2  each kept point finds its segment by binary search in the table
 //           and goes to its polygon position (its rank plus the extreme
 //           points before its region).
-// A polygon of more than kBatchPolyMax vertices, or one that Melkman cannot
-// finish in LDS, is left to the host (fin_done = 0 in the header, the count
-// kBatchRedo until the host's result replaces it); after a failed step the
-// count is the call's negative status.
+// A polygon of more than kBatchPolyMax vertices goes to k_finish_wide (the
+// header's wide flag); one that Melkman cannot finish in LDS is left to the
+// host (fin_done = 0 in the header, the count kBatchRedo until the host's
+// result replaces it); after a failed step the count is the call's negative
+// status.
 // ---------------------------------------------------------------------------
 struct SegEnt {
     uint32_t sg, pre;  // segment, rank of its first kept point
@@ -2256,7 +2439,7 @@ struct SegEnt {
 };
 constexpr size_t kFinishLds = kPolyBytes + sizeof(SegEnt) * (size_t)kBatchPolyMax;
 
-__global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(const DevHeader* __restrict__ hdr,
+__global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(DevHeader* __restrict__ hdr,
                                                         const uint32_t* __restrict__ segcnt,
                                                         const PolyRec* __restrict__ kept,
                                                         int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count,
@@ -2313,9 +2496,12 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
         nt += nz;
     }
     if (!fits) {
+        // too large for one workgroup: k_finish_wide takes it (the count
+        // stays kBatchRedo until it has written the hull)
         if (tid == 0) {
             host_hdr->fin_done = 0;
             *out_count = kBatchRedo;
+            hdr->wide = 1;
         }
         return;
     }
@@ -2371,6 +2557,503 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(cons
         host_hdr->fin_hull = h;
         for (int q = 0; q < 4; ++q) host_hdr->fin_w2[q] = s_reg[q];
         host_hdr->fin_done = h >= 0 ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 7 on the device for polygons beyond one workgroup (Section 2.1.3's
+// hull, computed without Melkman's sequential deque).
+//
+// Every hull vertex of region q lies on the lower hull, in q's frame, of the
+// region's kept points and its two extreme points E_q (start) and E_{q+1}
+// (end): a point v is a strict hull vertex iff some line through v has every
+// other of these points strictly on its inner side (larger k2); the points
+// of the other regions and of the quadrilateral are then on that side too
+// (the region's corner triangle holds everything below such a line).
+//
+// k_chain cut the region chain into segments; within a segment the kept
+// points of one region form a piece P (ascending k1, descending k2).  Let H
+// be P's lower hull (P itself when the pre-hull converged).  For a line
+// touching H from below with slope s, a point a left of H is strictly above
+// it iff s > slope of the lower tangent from a to H, and a point b right of
+// H iff s < slope of the tangent from H to b.  With
+//   sigma_L = max over the region's points left of P and E_q of the tangent
+//             slope from a to H,
+//   sigma_R = min over the points right of P and E_{q+1} of the tangent
+//             slope from H to b,
+// a vertex v of H with incoming and outgoing edge slopes s_in < s_out (minus
+// and plus infinity at H's ends) is a strict hull vertex iff
+//   max(s_in, sigma_L) < min(s_out, sigma_R).
+// Tangents are binary searches over H in LDS.  A piece whose bounding box
+// lies strictly above the line found from the neighbouring segments cannot
+// raise sigma_L (or lower sigma_R) and is skipped.
+//
+// The output is written in the order E_1, R2, E_2, R3, E_3, R4, E_0, R1 (the
+// hull from P_miny counter-clockwise): items (the extreme points and the
+// pieces) are taken in that order by ticket, and each item's first output
+// position is an exclusive prefix sum over the earlier items' vertex counts
+// by decoupled look-back: an item publishes its count, then sums its
+// predecessors' counts back to the nearest one that has published its
+// inclusive prefix.  An item waits only on items with smaller tickets, which
+// running workgroups hold and complete without waiting on later ones, so the
+// look-back always ends.
+// ---------------------------------------------------------------------------
+constexpr int kWideBlock = 256;
+constexpr int kWideWaves = kWideBlock / 64;
+constexpr int kWideNear = 2;                // neighbouring segments searched before the pruning pass
+constexpr int kWideList = 1024;             // segments left after pruning, processed per pass
+constexpr uint32_t kWideSpinMax = 1u << 20; // safety bound of one look-back wait (never reached)
+constexpr u64 kLookAgg = 1ull << 62, kLookIncl = 2ull << 62;
+
+// A slope dy/dx with dx >= 0; dx == 0 stands for minus infinity (dy < 0) or
+// plus infinity (dy > 0).  Every product is below 2^46.
+struct Slope {
+    i64 dy, dx;
+};
+
+__device__ inline bool slope_less(Slope a, Slope b)
+{
+    if (a.dx == 0 && b.dx == 0) return a.dy < 0 && b.dy > 0;
+    if (a.dx == 0) return a.dy < 0;
+    if (b.dx == 0) return b.dy > 0;
+    return a.dy * b.dx < b.dy * a.dx;
+}
+
+// A line through two points of the region, from (a1, a2) to (b1, b2) with
+// a1 <= b1 (frame coordinates): a tangent candidate.
+struct Line {
+    uint32_t a1, a2, b1, b2;
+    uint32_t ok;
+};
+
+__device__ inline Slope line_slope(const Line& l) { return Slope{(i64)l.b2 - (i64)l.a2, (i64)l.b1 - (i64)l.a1}; }
+
+// The better of two candidates: the larger slope (want_max) or the smaller.
+__device__ inline Line line_better(const Line& x, const Line& y, bool want_max)
+{
+    if (!y.ok) return x;
+    if (!x.ok) return y;
+    const bool y_less = slope_less(line_slope(y), line_slope(x));
+    const bool x_less = slope_less(line_slope(x), line_slope(y));
+    return (want_max ? x_less : y_less) ? y : x;
+}
+
+// Workgroup reduction of one candidate per thread; every thread gets the
+// result.  sh: kWideWaves Lines of LDS.
+__device__ inline Line line_reduce(Line v, bool want_max, Line* sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Line o;
+        o.a1 = __shfl_xor(v.a1, off);
+        o.a2 = __shfl_xor(v.a2, off);
+        o.b1 = __shfl_xor(v.b1, off);
+        o.b2 = __shfl_xor(v.b2, off);
+        o.ok = __shfl_xor(v.ok, off);
+        v = line_better(v, o, want_max);
+    }
+    if (lane_id() == 0) sh[threadIdx.x / 64] = v;
+    __syncthreads();
+    Line r = sh[0];
+    for (int w = 1; w < kWideWaves; ++w) r = line_better(r, sh[w], want_max);
+    __syncthreads();
+    return r;
+}
+
+// The lower tangent from a point a left of the hull H[0 .. h) (ascending k1,
+// strictly convex): the first k with H[k+1] not strictly below the line from
+// a through H[k] (the predicate holds for a prefix of k).
+__device__ inline uint32_t tangent_from_left(const uint32_t* hk1, const uint32_t* hk2, uint32_t h, uint32_t a1,
+                                             uint32_t a2)
+{
+    uint32_t lo = 0, hi = h - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (frame_turn(a1, a2, hk1[mid], hk2[mid], hk1[mid + 1], hk2[mid + 1]) < 0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The lower tangent from the hull to a point b right of it: the first k with
+// H[k+1] not strictly below the line from H[k] to b.
+__device__ inline uint32_t tangent_to_right(const uint32_t* hk1, const uint32_t* hk2, uint32_t h, uint32_t b1,
+                                            uint32_t b2)
+{
+    uint32_t lo = 0, hi = h - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (frame_turn(hk1[mid], hk2[mid], b1, b2, hk1[mid + 1], hk2[mid + 1]) < 0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Decoupled look-back by wave 0: publishes the item's count, sums the counts
+// of the items before it back to the nearest published inclusive prefix,
+// publishes its own inclusive prefix and returns the exclusive one (the same
+// in every lane of wave 0).  state: flag (2 bits) | epoch (30 bits) | value.
+__device__ inline uint32_t look_back(u64* states, uint32_t t, uint32_t epoch, uint32_t count, bool& fail)
+{
+    const uint32_t lane = lane_id();
+    const u64 ep = (u64)(epoch & 0x3FFFFFFFu) << 32;
+    if (lane == 0) __hip_atomic_store(states + t, kLookAgg | ep | count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0, spins = 0;
+    int j = (int)t - 1;
+    while (j >= 0) {
+        const int at = j - (int)lane;
+        u64 v = kLookIncl | ep;  // before the first item: an inclusive prefix of 0
+        if (at >= 0) v = __hip_atomic_load(states + at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ready = (v & 0x3FFFFFFF00000000ull) == ep && (v >> 62) != 0;
+        const bool incl = ready && (v >> 62) == 2;
+        const u64 im = __ballot(incl), rm = __ballot(ready);
+        const uint32_t last = im ? (uint32_t)__builtin_ctzll(im) : 63u;
+        const u64 need = last == 63 ? ~0ull : ((2ull << last) - 1ull);
+        if ((rm & need) == need) {
+            excl += wave_sum(lane <= last ? (uint32_t)v : 0u);
+            if (im) break;
+            j -= 64;
+        } else {
+            if (++spins > kWideSpinMax) {
+                fail = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    if (lane == 0 && !fail)
+        __hip_atomic_store(states + t, kLookIncl | ep | (u64)(excl + count), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// Region layout of the chain for the wide finish: region q's SPA survivors
+// occupy chain positions [rs, rs + s2[q]), so its pieces lie in segments
+// first .. first + nseg - 1.
+struct WideRegion {
+    uint32_t first, nseg;
+};
+
+// Segment s's kept points of region q: offset inside the segment and count.
+__device__ inline void piece_of(const uint32_t* __restrict__ segcnt, uint32_t s, uint32_t q, uint32_t& off,
+                                uint32_t& cnt)
+{
+    const v4u c = reinterpret_cast<const v4u*>(segcnt)[s];
+    const uint32_t c4[4] = {c.x, c.y, c.z, c.w};
+    off = 0;
+    for (uint32_t k = 0; k < q; ++k) off += c4[k];
+    cnt = c4[q];
+}
+
+__global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restrict__ hdr,
+                                                            const uint32_t* __restrict__ segcnt,
+                                                            const PolyRec* __restrict__ kept,
+                                                            u64* __restrict__ states,
+                                                            int32_t* __restrict__ out_idx,
+                                                            int32_t* __restrict__ out_count,
+                                                            DevHeader* __restrict__ host_hdr)
+{
+    __shared__ uint32_t hk1[kSeg], hk2[kSeg];
+    __shared__ int32_t hidx[kSeg];
+    __shared__ uint16_t hrank[kSeg];  // 1 + output rank of a strict vertex, 0 otherwise
+    __shared__ uint32_t slist[kWideList], s_lo[kWideList], s_pre[kWideList];  // listed segments: id, offset, prefix
+    __shared__ Line sh_line[kWideWaves];
+    __shared__ uint32_t scratch[kWideWaves];
+    __shared__ uint32_t s_t, s_h, s_nl, s_bad, s_base, s_fail;
+    const uint32_t tid = threadIdx.x;
+    if (!hdr->wide || hdr->err) return;
+    const uint32_t epoch = hdr->epoch;
+    // the region layout, in LDS (indexed by region)
+    __shared__ WideRegion R[4];
+    if (tid == 0) {
+        uint32_t rs = 0;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t m = hdr->s2[q];
+            R[q].first = rs / kSeg;
+            R[q].nseg = m ? (rs + m - 1) / kSeg - rs / kSeg + 1 : 0u;
+            rs += m;
+        }
+    }
+    __syncthreads();
+    uint32_t nitems = 4;
+    for (int q = 0; q < 4; ++q) nitems += R[q].nseg;
+    bool fail = false;
+
+    for (;;) {
+        if (tid == 0) s_t = __hip_atomic_fetch_add(&hdr->wide_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t t = s_t;
+        __syncthreads();
+        if (t >= nitems) break;
+        // the item: extreme point E_q, or region q's piece in segment s
+        uint32_t q = 0, s = 0, rest = t;
+        bool is_ext = false;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t qq = (uint32_t)(k + 1) & 3u;  // E_1, R2, E_2, R3, E_3, R4, E_0, R1
+            if (rest == 0) {
+                q = qq;
+                is_ext = true;
+                break;
+            }
+            rest -= 1;
+            if (rest < R[qq].nseg) {
+                q = qq;
+                s = R[qq].first + rest;
+                break;
+            }
+            rest -= R[qq].nseg;
+        }
+        uint32_t count = 0, h = 0;
+        if (is_ext) {
+            // a coincident earlier extreme point (in the order E_1, E_2, E_3,
+            // E_0) has been written already
+            auto same = [&](uint32_t a, uint32_t b) {
+                return hdr->ext_x[a] == hdr->ext_x[b] && hdr->ext_y[a] == hdr->ext_y[b];
+            };
+            const bool dup = q == 2 ? same(2, 1) : q == 3 ? same(3, 2) : q == 0 ? (same(0, 3) || same(0, 1)) : false;
+            count = dup ? 0u : 1u;
+        } else {
+            uint32_t off, cnt;
+            piece_of(segcnt, s, q, off, cnt);
+            // the piece in frame coordinates
+            for (uint32_t j = tid; j < cnt; j += kWideBlock) {
+                const PolyRec r = kept[(size_t)s * kSeg + off + j];
+                uint32_t k1, k2;
+                to_frame(q, (uint32_t)r.x, (uint32_t)r.y, k1, k2);
+                hk1[j] = k1;
+                hk2[j] = k2;
+                hidx[j] = r.idx;
+            }
+            if (tid == 0) s_bad = 0;
+            __syncthreads();
+            for (uint32_t j = tid + 1; j + 1 < cnt; j += kWideBlock)
+                if (frame_turn(hk1[j - 1], hk2[j - 1], hk1[j], hk2[j], hk1[j + 1], hk2[j + 1]) <= 0) s_bad = 1;
+            __syncthreads();
+            if (s_bad) {
+                // not convex (the pre-hull stopped early): its lower hull, in place
+                if (tid == 0) {
+                    uint32_t m = 0;
+                    for (uint32_t j = 0; j < cnt; ++j) {
+                        const uint32_t k1 = hk1[j], k2 = hk2[j];
+                        const int32_t ix = hidx[j];
+                        while (m >= 2 && frame_turn(hk1[m - 2], hk2[m - 2], hk1[m - 1], hk2[m - 1], k1, k2) <= 0) --m;
+                        hk1[m] = k1;
+                        hk2[m] = k2;
+                        hidx[m] = ix;
+                        ++m;
+                    }
+                    s_h = m;
+                }
+            } else if (tid == 0) {
+                s_h = cnt;
+            }
+            __syncthreads();
+            h = s_h;
+            if (h) {
+                const uint32_t qn = (q + 1) & 3;
+                uint32_t e1, e2, f1, f2;
+                to_frame(q, hdr->ext_x[q], hdr->ext_y[q], e1, e2);    // E_q: left of every point
+                to_frame(q, hdr->ext_x[qn], hdr->ext_y[qn], f1, f2);  // E_{q+1}: right of every point
+                const uint32_t lo_seg = R[q].first, hi_seg = R[q].first + R[q].nseg;  // [lo_seg, hi_seg)
+                Line best[2];
+                // the listed segments' points (slist[0 .. nl)) as candidates,
+                // all at once: per segment its place and count, their prefix
+                // sum, then every point by one thread, four loads in flight
+                auto eval_list = [&](uint32_t nl, bool left) -> Line {
+                    for (uint32_t e = tid; e < nl; e += kWideBlock) {
+                        uint32_t o, c;
+                        piece_of(segcnt, slist[e], q, o, c);
+                        s_lo[e] = o;
+                        s_pre[e] = c;
+                    }
+                    __syncthreads();
+                    uint32_t total;
+                    {
+                        constexpr int kPer = kWideList / kWideBlock;
+                        uint32_t c[kPer], sum = 0;
+#pragma unroll
+                        for (int k = 0; k < kPer; ++k) {
+                            const uint32_t e = tid * kPer + k;
+                            c[k] = e < nl ? s_pre[e] : 0u;
+                            sum += c[k];
+                        }
+                        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow the reads above)
+#pragma unroll
+                        for (int k = 0; k < kPer; ++k) {
+                            const uint32_t e = tid * kPer + k;
+                            if (e < nl) s_pre[e] = run;
+                            run += c[k];
+                        }
+                    }
+                    __syncthreads();
+                    Line acc = Line{0, 0, 0, 0, 0u};
+                    constexpr int kLoads = 4;
+                    for (uint32_t i0 = 0; i0 < total; i0 += kLoads * kWideBlock) {
+                        PolyRec r[kLoads];
+#pragma unroll
+                        for (int u = 0; u < kLoads; ++u) {
+                            const uint32_t i = i0 + u * kWideBlock + tid;
+                            if (i < total) {
+                                uint32_t e = 0;  // the last listed segment with pre <= i
+                                for (uint32_t st = kWideList / 2; st > 0; st >>= 1)
+                                    if (e + st < nl && s_pre[e + st] <= i) e += st;
+                                r[u] = kept[(size_t)slist[e] * kSeg + s_lo[e] + (i - s_pre[e])];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < kLoads; ++u) {
+                            if (i0 + u * kWideBlock + tid < total) {
+                                uint32_t k1, k2;
+                                to_frame(q, (uint32_t)r[u].x, (uint32_t)r[u].y, k1, k2);
+                                Line l;
+                                if (left) {
+                                    const uint32_t k = tangent_from_left(hk1, hk2, h, k1, k2);
+                                    l = Line{k1, k2, hk1[k], hk2[k], 1u};
+                                } else {
+                                    const uint32_t k = tangent_to_right(hk1, hk2, h, k1, k2);
+                                    l = Line{hk1[k], hk2[k], k1, k2, 1u};
+                                }
+                                acc = line_better(acc, l, left);
+                            }
+                        }
+                    }
+                    return line_reduce(acc, left, sh_line);
+                };
+                // side 0: points left of the piece (E_q and earlier segments),
+                // the largest tangent slope; side 1: points right of it (later
+                // segments and E_{q+1}), the smallest
+                for (int side = 0; side < 2; ++side) {
+                    const bool left = side == 0;
+                    // the extreme point and the neighbouring segments first
+                    if (tid == 0) {
+                        uint32_t nn = 0;
+                        for (int d = 1; d <= kWideNear; ++d) {
+                            const int64_t sg = left ? (int64_t)s - d : (int64_t)s + d;
+                            if (sg >= (int64_t)lo_seg && sg < (int64_t)hi_seg) slist[nn++] = (uint32_t)sg;
+                        }
+                        s_nl = nn;
+                    }
+                    __syncthreads();
+                    Line cur = eval_list(s_nl, left);
+                    {
+                        Line ext;
+                        if (left) {
+                            const uint32_t k = tangent_from_left(hk1, hk2, h, e1, e2);
+                            ext = Line{e1, e2, hk1[k], hk2[k], 1u};
+                        } else {
+                            const uint32_t k = tangent_to_right(hk1, hk2, h, f1, f2);
+                            ext = Line{hk1[k], hk2[k], f1, f2, 1u};
+                        }
+                        cur = line_better(cur, ext, left);
+                    }
+                    // the other segments: those whose bounding box is not
+                    // strictly above the current line, in passes of at most
+                    // kWideList segments
+                    const uint32_t a0 = left ? lo_seg : (uint32_t)(s + kWideNear + 1);
+                    const uint32_t a1 = left ? (s > lo_seg + kWideNear ? s - kWideNear : lo_seg) : hi_seg;
+                    for (uint32_t p0 = a0; p0 < a1; p0 += kWideList) {
+                        if (tid == 0) s_nl = 0;
+                        __syncthreads();
+                        const uint32_t p1 = min(a1, p0 + (uint32_t)kWideList);
+                        const bool vertical = cur.b1 == cur.a1;  // (only E_q above the first point: nothing to prune)
+                        for (uint32_t sg = p0 + tid; sg < p1; sg += kWideBlock) {
+                            uint32_t o, c;
+                            piece_of(segcnt, sg, q, o, c);
+                            if (!c) continue;
+                            bool keep = true;
+                            if (!vertical) {
+                                const PolyRec r0 = kept[(size_t)sg * kSeg + o];
+                                const PolyRec r1 = kept[(size_t)sg * kSeg + o + c - 1];
+                                uint32_t x1, x2, y1, y2;
+                                to_frame(q, (uint32_t)r0.x, (uint32_t)r0.y, x1, x2);  // largest k2
+                                to_frame(q, (uint32_t)r1.x, (uint32_t)r1.y, y1, y2);  // largest k1, smallest k2
+                                // the box [x1, y1] x [y2, x2] is strictly above the
+                                // line when its two lower corners are
+                                keep = !(frame_turn(cur.a1, cur.a2, cur.b1, cur.b2, x1, y2) > 0 &&
+                                         frame_turn(cur.a1, cur.a2, cur.b1, cur.b2, y1, y2) > 0);
+                            }
+                            if (keep) slist[atomicAdd(&s_nl, 1u)] = sg;
+                        }
+                        __syncthreads();
+                        const uint32_t nl = s_nl;
+                        if (nl) cur = line_better(cur, eval_list(nl, left), left);
+                        __syncthreads();
+                    }
+                    if (left) best[0] = cur;
+                    else best[1] = cur;
+                }
+                // strict vertices of the piece's hull, in order
+                const Slope sl = best[0].ok ? line_slope(best[0]) : Slope{-1, 0};
+                const Slope sr = best[1].ok ? line_slope(best[1]) : Slope{1, 0};
+                for (uint32_t k0 = 0; k0 < h; k0 += kWideBlock) {
+                    const uint32_t k = k0 + tid;
+                    bool strict = false;
+                    if (k < h) {
+                        const Slope sin = k > 0 ? Slope{(i64)hk2[k] - (i64)hk2[k - 1], (i64)hk1[k] - (i64)hk1[k - 1]}
+                                                : Slope{-1, 0};
+                        const Slope sout = k + 1 < h ? Slope{(i64)hk2[k + 1] - (i64)hk2[k], (i64)hk1[k + 1] - (i64)hk1[k]}
+                                                     : Slope{1, 0};
+                        const Slope lo = slope_less(sin, sl) ? sl : sin;
+                        const Slope hi = slope_less(sr, sout) ? sr : sout;
+                        strict = slope_less(lo, hi);
+                    }
+                    uint32_t tot;
+                    const uint32_t r = block_excl_sum(strict ? 1u : 0u, scratch, tot);
+                    // (1 + rank in the piece; the output position needs the
+                    // item's base from the look-back)
+                    if (k < h) hrank[k] = (uint16_t)(strict ? count + r + 1 : 0u);
+                    count += tot;
+                    __syncthreads();
+                }
+            }
+        }
+        // the item's first output position
+        if (tid < 64) {
+            bool f = false;
+            const uint32_t base = look_back(states, t, epoch, count, f);
+            if (tid == 0) {
+                s_base = base;
+                s_fail = f ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        const uint32_t base = s_base;
+        fail = s_fail != 0;
+        if (is_ext) {
+            if (tid == 0 && count) out_idx[base] = (int32_t)hdr->ext_idx[q];
+        } else {
+            for (uint32_t k = tid; k < h; k += kWideBlock) {
+                const uint32_t r = hrank[k];
+                if (r) out_idx[base + r - 1] = hidx[k];
+            }
+        }
+        if (t == nitems - 1 && tid == 0) {
+            // the last item: the hull size and the counts for the host
+            const int32_t total = (int32_t)(base + count);
+            if (!fail) atomicCAS(out_count, kBatchRedo, total);
+            host_hdr->fin_hull = total;
+            for (int k = 0; k < 4; ++k) {
+                uint32_t w = 0;
+                const uint32_t first = R[k].first, ns = R[k].nseg;
+                for (uint32_t sg = first; sg < first + ns; ++sg) {
+                    uint32_t o, c;
+                    piece_of(segcnt, sg, k, o, c);
+                    w += c;
+                }
+                host_hdr->fin_w2[k] = w;
+            }
+            if (!fail) host_hdr->fin_done = 1u;
+        }
+        if (fail) {
+            // a look-back wait ran out (not expected): the call reports an
+            // error instead of a wrong hull, and hull2d finishes on the host
+            if (tid == 0) {
+                atomicExch(out_count, (int32_t)CH_EHIP);
+                host_hdr->fin_fail = 1u;
+            }
+            break;
+        }
+        __syncthreads();
     }
 }
 
@@ -2537,8 +3220,10 @@ struct Workspace {
     uint32_t* open_idx = nullptr;   // k_stream's per-workgroup lists
     u64* open_xym = nullptr;
     uint32_t* wgcount = nullptr;
-    uint32_t* candcount = nullptr;
-    uint32_t* key[2] = {nullptr, nullptr};  // k_cand's regions; the bucketed records
+    uint32_t* sctr = nullptr;       // k_stream's arrival counters (zero between calls)
+    uint32_t* rowoff = nullptr;     // k_cand's rows of the bucket table: first position per bucket
+    uint32_t* rowmin = nullptr;     // and smallest k2 per bucket
+    uint32_t* key[2] = {nullptr, nullptr};  // k_cand's parts: records in chunk order, by bucket
     u64* val[2] = {nullptr, nullptr};
     Buckets bk = {};
     PolyRec* dev_chain = nullptr;
@@ -2561,6 +3246,7 @@ struct Workspace {
     PolyRec* dev_spill = nullptr;   // device: chain records beyond the pinned buffer
     PolyRec* dev_kept = nullptr;    // device copies of the kept chain points and
     uint32_t* dev_segcnt = nullptr; // their per-segment counts (the device finish)
+    u64* states = nullptr;          // k_finish_wide's look-back states (zeroed at allocation)
     uint32_t* h_segcnt = nullptr;   // pinned, device-visible: kept points per segment and region
     uint32_t* h_segcnt_dev = nullptr;
     size_t h_segcnt_cap = 0;        // segments
@@ -2575,6 +3261,7 @@ struct Workspace {
     hipEvent_t ev[8] = {};
     bool events = false;
     bool no_events = false;  // hull2d_noalloc's view: never creates or records events
+    bool captured = false;   // a HIP graph captured a call on this workspace: it must not move
 };
 
 // Launch shape of k_stream for n points whose first `head` (0 or 1) points
@@ -2584,12 +3271,43 @@ struct StreamShape {
     uint32_t n4, grid, per, region;
 };
 
-StreamShape stream_shape(size_t n, uint32_t head)
+// ---- launch shapes (ch_tuning), per size class ----
+constexpr ch_tuning kDefaultTuning = {1024, 4, 8192, 1024, 1024, 2, 0, 1 << 18};
+constexpr int kTuningClasses = 16;
+std::mutex g_tune_mu;
+int g_tune_count = 0;
+int64_t g_tune_nmax[kTuningClasses];
+ch_tuning g_tune[kTuningClasses];
+
+bool tuning_valid(const ch_tuning& t)
+{
+    const bool grid = t.stream_grid == 128 || t.stream_grid == 256 || t.stream_grid == 512 || t.stream_grid == 1024;
+    return grid && (t.stream_unroll == 2 || t.stream_unroll == 4) && t.cand_per_row >= 1024 &&
+           t.cand_per_row <= (1 << 20) && t.chain_grid >= 64 && t.chain_grid <= 4096 &&
+           t.wide_grid >= 64 && t.wide_grid <= 4096 && (t.batch_unroll == 1 || t.batch_unroll == 2) &&
+           (t.batch_order == 0 || t.batch_order == 1) && t.serve_batch_max >= 0 && t.serve_batch_max <= (1 << 22);
+}
+
+// The shapes of a call with n points: the class with the smallest n_max >= n.
+ch_tuning tuning_for(int64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int best = -1;
+    for (int k = 0; k < g_tune_count; ++k)
+        if (n >= 0 && g_tune_nmax[k] >= n && (best < 0 || g_tune_nmax[k] < g_tune_nmax[best])) best = k;
+    return best >= 0 ? g_tune[best] : kDefaultTuning;
+}
+
+// k_stream's shape for n points whose first `head` (0 or 1) points precede
+// the 16-byte aligned part: grid (at most grid_max), and the float4s one
+// workgroup streams (a whole number of rounds of kBlock * unroll) and the
+// points it can visit (its region in the open lists).
+StreamShape stream_shape(size_t n, uint32_t head, uint32_t grid_max, uint32_t unroll)
 {
     StreamShape sh;
     sh.n4 = (uint32_t)((n - head) / 2);
-    const size_t round = (size_t)kBlock * kStreamUnroll;
-    sh.grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(kStreamGrid, (sh.n4 + round - 1) / round));
+    const size_t round = (size_t)kBlock * unroll;
+    sh.grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(grid_max, (sh.n4 + round - 1) / round));
     const size_t per = std::max<size_t>(1, (sh.n4 + sh.grid - 1) / sh.grid);
     sh.per = (uint32_t)((per + round - 1) / round * round);
     sh.grid = (uint32_t)std::max<size_t>(1, (sh.n4 + sh.per - 1) / sh.per);  // no empty workgroup
@@ -2598,17 +3316,19 @@ StreamShape stream_shape(size_t n, uint32_t head)
 }
 
 // Records the per-workgroup regions need for any call with up to cap
-// points: k_stream's lists take grid regions, k_cand's take
-// ceil(grid / 4) regions of four lists; grid never exceeds G(cap) and a
-// region never exceeds 2 P(cap) + 2 points (per is rounded up to a whole
-// round of float4s, and is one round below 2^20 float4s).
+// points, whatever its launch shape: k_stream's lists take grid regions,
+// and k_cand's parts tile the same regions; both grid and the region grow
+// with n, so the largest call of each shape bounds the rest.
 size_t region_cap(size_t cap)
 {
-    const size_t round = (size_t)kBlock * kStreamUnroll;
-    const size_t n4 = cap / 2;
-    const size_t g = std::max<size_t>(1, std::min<size_t>(kStreamGrid, (n4 + round - 1) / round));
-    const size_t per = std::max(round, ((n4 + kStreamGrid - 1) / kStreamGrid + round - 1) / round * round);
-    return (g + kListsPerCand) * (2 * per + 2);
+    size_t best = 0;
+    for (uint32_t g : {128u, 256u, 512u, 1024u})
+        for (uint32_t u : {2u, 4u})
+            for (uint32_t head : {0u, 1u}) {
+                const StreamShape sh = stream_shape(std::max<size_t>(cap, 2), head, g, u);
+                best = std::max(best, (size_t)sh.grid * sh.region);
+            }
+    return best;
 }
 
 // The device workspace for calls with up to cap points: its size, and, when
@@ -2624,18 +3344,26 @@ size_t layout(Workspace* w, char* base, size_t cap)
     };
     Workspace tmp;
     Workspace& W = w ? *w : tmp;
+    // zeroed at allocation: the header, the look-back states, the counters
     W.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
+    W.states = reinterpret_cast<u64*>(take(sizeof(u64) * (cap / kSeg + 16)));
+    W.sctr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (2 + kStreamGrid / 32)));  // [last]: k_sample's
+    W.bk.ctr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     W.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
     W.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    W.bk.kmin = reinterpret_cast<u64*>(take(sizeof(u64) * kBuckets));
-    W.bk.cur = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
-    W.bk.thr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.surv = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.lstart = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.lthr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.wtot = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
+    W.bk.wmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
+    W.bk.wgbase = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
+    W.bk.wgthr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
+    W.rowoff = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kCandMaxRows * (kBuckets + 1)));
+    W.rowmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kCandMaxRows * kBuckets));
     W.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
     W.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
     W.wgcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
-    W.candcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
     W.open_idx = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
     W.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
     for (int i = 0; i < 2; ++i) W.key[i] = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
@@ -2680,6 +3408,9 @@ inline int hip_status(int rc) { return rc; }  // already a ch_status
 int ensure_device(Workspace& w, size_t n)
 {
     if (w.dbuf && w.cap >= n) return CH_OK;
+    // a captured graph holds the workspace's addresses: it stays until the
+    // caller releases the stream
+    if (w.captured) return CH_EINVAL;
     size_t cap = std::max<size_t>(n, 1u << 16);
     if (w.cap) cap = std::max(cap, w.cap + w.cap / 2);
     if (w.dbuf) {
@@ -2693,6 +3424,9 @@ int ensure_device(Workspace& w, size_t n)
     w.dbuf = p;
     w.cap = cap;
     layout(&w, p, cap);
+    // the header's call counter, the look-back states and the arrival
+    // counters start at zero (they sit together at the start of the layout)
+    CH_TRY(hipMemsetAsync(w.hdr, 0, reinterpret_cast<char*>(w.bk.ctr + 64) - reinterpret_cast<char*>(w.hdr), w.stream));
     return CH_OK;
 }
 
@@ -2788,42 +3522,54 @@ int record(Workspace& w, int k)
 }
 
 // Steps 1-6 on the device; the counts end in w.h_hdr.  Without fin_idx the
-// chains end in w.h_chain (and w.spill).  With fin_idx, k_finish then
-// finishes the hull on the device into fin_idx / fin_count when the polygon
-// fits its workgroup (h_hdr->fin_done); otherwise gather_polygon fetches the
-// polygon for the host finish.  Timing events: 0 | k_sample, k_stair | 1 | k_stream |
-// 2 | k_cand (+ k_count_regions) | 3 | sort | 4 | SPA + chains | 5 |
-// k_finish | 6.
+// chains end in w.h_chain (and w.spill).  With fin_idx, k_finish and
+// k_finish_wide then finish the hull on the device into fin_idx / fin_count
+// (h_hdr->fin_done); only if they gave up does gather_polygon fetch the
+// polygon for the host finish.  Timing events: 0 | k_sample | 1 | k_stream |
+// 2 | k_cand (+ k_count_regions) | 3 | k_scan | 4 | k_bucket_spa, k_chain |
+// 5 | k_finish, k_finish_wide | 6.
 int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx,
                       int32_t* fin_count)
 {
     hipStream_t s = w.stream;
+    const ch_tuning tu = tuning_for(n);
     CH_TRY(record(w, 0));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.samp));
-    CH_LAUNCH(hipLaunchKernelGGL(k_stair, dim3(4), dim3(kStairSlots), 0, s, w.samp, w.stair, w.hdr, w.bk));
+    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.samp, w.stair, w.hdr,
+                                 w.sctr + 1 + kStreamGrid / 32));
     CH_TRY(record(w, 1));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
-    const StreamShape sh = stream_shape(n, head);
-    CH_LAUNCH(hipLaunchKernelGGL(k_stream, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
-                                 w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount));
+    const StreamShape sh = stream_shape(n, head, (uint32_t)tu.stream_grid, (uint32_t)tu.stream_unroll);
+    if (tu.stream_unroll == 2) {
+        CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
+                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, w.hdr, w.sctr));
+    } else {
+        CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
+                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, w.hdr, w.sctr));
+    }
     CH_TRY(record(w, 2));
-    const uint32_t gc = (sh.grid + kListsPerCand - 1) / kListsPerCand;
-    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kBlock), 0, s, w.part, (int)sh.grid, w.open_idx, w.open_xym,
-                                 sh.region, w.wgcount, w.hdr, w.key[0], w.val[0], w.candcount, w.bk));
+    // the rows of the bucket table follow the open count (k_stream's, on the
+    // device): up to one k_cand workgroup per cand_per_row open points
+    const uint32_t gc = std::min<uint32_t>(kCandMaxRows, sh.grid);
+    const uint32_t per_row = (uint32_t)tu.cand_per_row;
+    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kBlock), 0, s, w.hdr, w.open_idx, w.open_xym, sh.region,
+                                 w.wgcount, sh.grid, per_row, w.key[0], w.val[0], w.key[1], w.val[1], w.rowoff,
+                                 w.rowmin));
     if (stats) {
         const uint32_t gr = std::max<uint32_t>(1u, std::min<uint32_t>(256u, (n + kBlock * 8 - 1) / (kBlock * 8)));
         CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gr), dim3(kBlock), 0, s, pts, n, w.hdr));
     }
     CH_TRY(record(w, 3));
-    // k_cand's regions (key[0]) -> by bucket (key[1]) -> SPA per bucket
-    CH_LAUNCH(hipLaunchKernelGGL(k_bucket, dim3(gc), dim3(kBlock), 0, s, w.key[0], w.val[0],
-                                 kListsPerCand * sh.region, w.candcount, (int)gc, w.key[1], w.val[1], w.hdr, w.bk));
+    // the bucket table's columns -> bucket sizes, starts and thresholds;
+    // then SPA per bucket, its records gathered from the rows' parts
+    CH_LAUNCH(hipLaunchKernelGGL(k_scan, dim3(kScanGrid), dim3(kBlock), 0, s, w.hdr, w.rowoff, w.rowmin, sh.grid,
+                                 per_row, w.bk));
     CH_TRY(record(w, 4));
-    CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1], w.val[1],
-                                 w.hdr, w.bk, w.dev_chain));
+    CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1],
+                                 w.val[1], sh.region, sh.grid, per_row, w.rowoff, w.hdr, w.bk, w.dev_chain));
     // hull2d (fin_idx) leaves the host chain buffer alone: its host finish
     // reads k_gather's polygon
-    CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(kChainGrid), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
+    const uint32_t gch = (uint32_t)std::min<size_t>((size_t)tu.chain_grid, (n + kSeg - 1) / kSeg);
+    CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(gch), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
                                  fin_idx ? nullptr : w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill,
                                  fin_idx ? nullptr : w.h_segcnt_dev, w.h_hdr_dev, stats ? 0 : 1, w.dev_kept,
                                  w.dev_segcnt));
@@ -2831,6 +3577,9 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
     if (fin_idx) {
         CH_LAUNCH(hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBatchBlock), 0, s, w.hdr, w.dev_segcnt, w.dev_kept,
                                      fin_idx, fin_count, w.h_hdr_dev));
+        // (returns at once unless k_finish left the polygon to it)
+        CH_LAUNCH(hipLaunchKernelGGL(k_finish_wide, dim3((uint32_t)tu.wide_grid), dim3(kWideBlock), 0, s, w.hdr, w.dev_segcnt,
+                                     w.dev_kept, w.states, fin_idx, fin_count, w.h_hdr_dev));
     }
     CH_TRY(record(w, 6));
     return CH_OK;
@@ -2996,7 +3745,7 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0, false));
     rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
-    if (rc == CH_OK && w->h_hdr->fin_done) {
+    if (rc == CH_OK && w->h_hdr->fin_done && !w->h_hdr->fin_fail) {
         // finished on the device: the hull is in out_idx / out_count
         for (int q = 0; q < 4; ++q) {
             w->w2[q] = w->h_hdr->fin_w2[q];
@@ -3092,8 +3841,12 @@ int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_
     Workspace* w = workspace_for(s, &rc);
     if (!w) return rc;
     std::lock_guard<std::mutex> lk(w->mu);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CH_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone && (!w->dbuf || w->cap < (size_t)n)) return CH_EINVAL;  // no allocation under capture
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0, false));
+    if (cs == hipStreamCaptureStatusActive) w->captured = true;
     return launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
 }
 
@@ -3113,14 +3866,16 @@ int hull2d_noalloc(const float* points, int64_t n, int32_t* out_idx, int32_t* ou
     CH_TRY(hipGetDevice(&dev));
     char* base = nullptr;
     CH_TRY(noalloc_base(dev, &base));
-    // a view of the buffer (no allocation): the layout for n points, the
+    // a view of the buffer (no allocation): the workspace layout, the
     // header stand-in after it
     Workspace w;
     w.device = dev;
     w.stream = s;
     w.no_events = true;
-    w.cap = (size_t)n;
-    const size_t used = layout(&w, base, (size_t)n);
+    w.cap = (size_t)CH_NOALLOC_MAX_POINTS;
+    // (the layout of the largest call, so that every array, the look-back
+    // states among them, sits at the same place in every call)
+    const size_t used = layout(&w, base, (size_t)CH_NOALLOC_MAX_POINTS);
     w.h_hdr_dev = reinterpret_cast<DevHeader*>(base + used);
     return launch_preprocess(w, points, (uint32_t)n, false, out_idx, out_count);
 }
@@ -3181,9 +3936,12 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
         for (int32_t s = 0; s < num_sets; ++s) {
             if (offsets[s + 1] - offsets[s] <= kBatchMaxSet) w->h_b_order[nk++] = s;
         }
-        std::stable_sort(w->h_b_order, w->h_b_order + nk, [&](int32_t a, int32_t b) {
-            return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
-        });
+        const ch_tuning tu = tuning_for(offsets[num_sets]);
+        if (tu.batch_order == 0) {
+            std::stable_sort(w->h_b_order, w->h_b_order + nk, [&](int32_t a, int32_t b) {
+                return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+            });
+        }
         bs.device_sets = nk;
         if (nk > 0) {
             CH_TRY(hipMemcpyAsync(w->b_offsets, w->h_b_offsets, sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice,
@@ -3191,7 +3949,8 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
             CH_TRY(hipMemcpyAsync(w->b_order, w->h_b_order, sizeof(int32_t) * (size_t)nk, hipMemcpyHostToDevice, st));
             CH_TRY(record(*w, 0));
             const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
-            CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
+            auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
+            CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
                                          w->b_offsets, w->b_order, out_idx, out_counts, pts_odd, num_sets));
             CH_TRY(record(*w, 1));
             CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
@@ -3237,7 +3996,9 @@ int hull2d_batched_async(const float* points, const int64_t* offsets, const int3
     if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
     if (num_sets == 0) return CH_OK;
     const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
-    CH_LAUNCH(hipLaunchKernelGGL(k_batch_hull, dim3((uint32_t)num_sets), dim3(kBatchBlock), 0,
+    const ch_tuning tu = tuning_for(INT64_MAX);
+    auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
+    CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)num_sets), dim3(kBatchBlock), 0,
                                  reinterpret_cast<hipStream_t>(stream), points, offsets, order, out_idx, out_counts,
                                  pts_odd, num_sets));
     return CH_OK;
@@ -3342,6 +4103,34 @@ int chainhull_release_stream(void* stream)
         free_workspace(it->second);
         g_ws.erase(it);
     }
+    return CH_OK;
+}
+
+int chainhull_set_tuning(int64_t n_max, const ch_tuning* t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (n_max < 0) {
+        g_tune_count = 0;
+        return CH_OK;
+    }
+    if (!t || !tuning_valid(*t)) return CH_EINVAL;
+    for (int k = 0; k < g_tune_count; ++k) {
+        if (g_tune_nmax[k] == n_max) {
+            g_tune[k] = *t;
+            return CH_OK;
+        }
+    }
+    if (g_tune_count >= kTuningClasses) return CH_EINVAL;
+    g_tune_nmax[g_tune_count] = n_max;
+    g_tune[g_tune_count] = *t;
+    ++g_tune_count;
+    return CH_OK;
+}
+
+int chainhull_get_tuning(int64_t n, ch_tuning* out)
+{
+    if (!out) return CH_EINVAL;
+    *out = n < 0 ? kDefaultTuning : tuning_for(n);
     return CH_OK;
 }
 

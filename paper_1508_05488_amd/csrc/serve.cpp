@@ -5,7 +5,8 @@
 // server admits it against a memory budget and queues it.  Worker threads,
 // each with its own HIP stream (and so its own library workspace), take the
 // oldest pending work whenever they are free:
-//   * a large request (more than kServeBatchMax points) alone, through the
+//   * a large request (more points than the tuned serve_batch_max, 2^18 by
+//     default) alone, through the
 //     single-hull path (`hull2d`), which uses the whole device;
 //   * otherwise every pending small request (up to kServeBatchSets sets and
 //     kServeBatchPoints points): their points are gathered into the
@@ -20,6 +21,12 @@
 // completion (12 bytes per point for a batched request's staging, the
 // single-hull workspace bound for a large one).  Admission is first come,
 // first served; a request that could never fit is refused with CH_EADMIT.
+// The memory a worker keeps between requests (its stream's workspace and
+// its staging buffers) counts against the budget too: when it would take
+// the requests in flight and the workers' memory past the budget, the
+// worker gives its memory back after its request.  The server's device
+// memory then stays within the budget plus what the running requests
+// allocate beyond their share.
 
 #include <hip/hip_runtime.h>
 
@@ -38,7 +45,6 @@
 namespace chainhull {
 namespace {
 
-constexpr int64_t kServeBatchMax = 1 << 18;         // points of a request that is batched
 constexpr int32_t kServeBatchSets = 4096;           // requests per batched launch
 constexpr int64_t kServeBatchPoints = 64ll << 20;   // points per batched launch
 constexpr int32_t kServeMaxWorkers = 16;
@@ -67,16 +73,45 @@ struct Worker {
     int32_t* h_cnt = nullptr;    // pinned copy of the counts
     int64_t stage_cap = 0;       // points
     int32_t sets_cap = 0;
+    int64_t ws_n = 0;            // the most points one call on its stream has had (its workspace)
+    size_t retained = 0;         // device bytes it keeps between requests (workspace and staging)
+    bool busy = false;           // running a request (under the server's lock)
     std::thread th;
 };
+
+// Device memory a worker keeps: its stream's workspace and its staging.
+size_t retained_bytes(const Worker& w)
+{
+    return (w.ws_n ? chainhull_workspace_bytes(w.ws_n) : 0) + (size_t)w.stage_cap * 12 + (size_t)w.sets_cap * 4;
+}
+
+// Give a worker's memory back: its stream's workspace and its staging.
+void release_worker(Worker& w)
+{
+    (void)hipStreamSynchronize(w.stream);
+    (void)chainhull_release_stream(w.stream);
+    if (w.stage_pts) (void)hipFree(w.stage_pts);
+    if (w.stage_out) (void)hipFree(w.stage_out);
+    if (w.stage_cnt) (void)hipFree(w.stage_cnt);
+    if (w.h_cnt) (void)hipHostFree(w.h_cnt);
+    w.stage_pts = nullptr;
+    w.stage_out = nullptr;
+    w.stage_cnt = nullptr;
+    w.h_cnt = nullptr;
+    w.stage_cap = 0;
+    w.sets_cap = 0;
+    w.ws_n = 0;
+}
 
 }  // namespace
 }  // namespace chainhull
 
 struct ch_server {
     int device = 0;
+    int64_t batch_max = 0;  // requests of at most this many points are batched (the tuned shape)
     size_t budget = 0;
     size_t reserved = 0;
+    size_t retained = 0;  // device bytes the workers keep between requests
     bool stop = false;
     uint64_t next_ticket = 1;
     std::mutex mu;
@@ -94,22 +129,34 @@ struct ch_server {
 namespace chainhull {
 namespace {
 
-size_t need_of(int64_t n)
+size_t need_of(const ch_server* s, int64_t n)
 {
-    if (n <= kServeBatchMax) return (size_t)n * 12 + 64;
+    if (n <= s->batch_max) return (size_t)n * 12 + 64;
     return chainhull_workspace_bytes(n);
 }
 
-// Admit from the head of the admission queue while the budget allows.
-// Caller holds s->mu.
+// Admit from the head of the admission queue while the budget allows: the
+// requests in flight, the memory the workers keep and the head's need must
+// fit.  When only the memory of idle workers stands in the way, they give
+// it back first.  Caller holds s->mu.
 void admit_locked(ch_server* s)
 {
     bool any = false;
-    while (!s->admission.empty() && s->reserved + s->admission.front()->need <= s->budget) {
+    while (!s->admission.empty()) {
+        const size_t need = s->admission.front()->need;
+        if (s->reserved + s->retained + need > s->budget) {
+            for (auto& w : s->workers) {
+                if (w.busy || !w.retained) continue;
+                release_worker(w);
+                s->retained -= w.retained;
+                w.retained = 0;
+            }
+            if (s->reserved + s->retained + need > s->budget) break;
+        }
         Request* r = s->admission.front();
         s->admission.pop_front();
         s->reserved += r->need;
-        (r->n <= kServeBatchMax ? s->small : s->large).push_back(r);
+        (r->n <= s->batch_max ? s->small : s->large).push_back(r);
         any = true;
     }
     if (any) s->cv_work.notify_all();
@@ -160,7 +207,10 @@ int grow(Worker& w, int64_t pts, int32_t sets)
 void run_batch(Worker& w, std::vector<Request*>& batch)
 {
     int64_t total = 0;
-    for (Request* r : batch) total += r->n;
+    for (Request* r : batch) {
+        total += r->n;
+        w.ws_n = std::max(w.ws_n, r->n);  // (a set the kernel hands back runs alone on this stream)
+    }
     int rc = grow(w, total, (int32_t)batch.size());
     std::vector<int64_t> offs(batch.size() + 1, 0);
     for (size_t k = 0; k < batch.size(); ++k) offs[k + 1] = offs[k] + batch[k]->n;
@@ -190,7 +240,11 @@ void run_batch(Worker& w, std::vector<Request*>& batch)
         const int32_t c = w.h_cnt[k];
         r->status = c < 0 ? c : CH_OK;
         r->hull = c < 0 ? 0 : c;
-        bool ok = hipMemcpyAsync(r->out_count, w.stage_cnt + k, 4, hipMemcpyDeviceToDevice, w.stream) == hipSuccess;
+        // a failed request's count is 0, as hull2d leaves it; its status is
+        // the ticket's
+        bool ok = c < 0 ? hipMemsetAsync(r->out_count, 0, 4, w.stream) == hipSuccess
+                        : hipMemcpyAsync(r->out_count, w.stage_cnt + k, 4, hipMemcpyDeviceToDevice, w.stream) ==
+                              hipSuccess;
         if (c > 0)
             ok = ok && hipMemcpyAsync(r->out_idx, w.stage_out + offs[k], (size_t)c * 4, hipMemcpyDeviceToDevice,
                                       w.stream) == hipSuccess;
@@ -203,6 +257,7 @@ void run_batch(Worker& w, std::vector<Request*>& batch)
 
 void run_single(Worker& w, Request* r)
 {
+    w.ws_n = std::max(w.ws_n, r->n);
     int rc = hull2d(r->pts, r->n, r->out_idx, r->out_count, w.stream);
     int32_t h = 0;
     if (rc == CH_OK) {
@@ -243,6 +298,7 @@ void worker_loop(ch_server* s, Worker* w)
                 s->batches += 1;
                 s->batched_requests += (int64_t)batch.size();
             }
+            w->busy = true;
             s->inflight += single ? 1 : (int32_t)batch.size();
             s->max_inflight = std::max(s->max_inflight, s->inflight);
         }
@@ -258,7 +314,17 @@ void worker_loop(ch_server* s, Worker* w)
             } else {
                 for (Request* r : batch) finish_locked(s, r, r->status, r->hull);
             }
-            admit_locked(s);
+            // the memory this worker keeps counts against the budget with the
+            // requests in flight; beyond it, the worker gives its memory back
+            w->busy = false;
+            s->retained -= w->retained;
+            w->retained = retained_bytes(*w);
+            if (s->reserved + s->retained + w->retained > s->budget) {
+                release_worker(*w);
+                w->retained = 0;
+            }
+            s->retained += w->retained;
+            admit_locked(s);  // (may release idle workers' memory for the next request)
         }
         s->cv_done.notify_all();
     }
@@ -281,6 +347,9 @@ int chainhull_server_create(int32_t workers, size_t mem_budget, ch_server** out)
         return CH_EHIP;
     }
     s->budget = mem_budget;
+    ch_tuning tu;
+    (void)chainhull_get_tuning(INT64_MAX, &tu);
+    s->batch_max = tu.serve_batch_max;
     s->workers.resize((size_t)workers);
     for (auto& w : s->workers) {
         if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) {
@@ -300,7 +369,7 @@ int chainhull_server_submit(ch_server* s, const float* points, int64_t n, int32_
 {
     if (!s || !ticket || !out_count || n < 0 || n > INT32_MAX || (n > 0 && (!points || !out_idx))) return CH_EINVAL;
     if (reinterpret_cast<uintptr_t>(points) & 7u) return CH_EINVAL;
-    const size_t need = need_of(n);
+    const size_t need = need_of(s, n);
     if (need > s->budget) return CH_EADMIT;
     Request* r = new Request();
     r->pts = points;

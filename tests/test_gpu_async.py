@@ -1,8 +1,9 @@
 """hull2d_async (every step on the device, nothing synchronised): its
 results equal hull2d's and, where the oracle finishes in seconds, the
-oracle's; several calls queued back to back on one stream; the count codes
-for an out-of-domain input and for a polygon beyond the device finish; a
-HIP graph of the call replayed on new inputs.  Each case prints its name
+oracle's; several calls queued back to back on one stream; the count code
+for an out-of-domain input; polygons beyond one workgroup (points on a
+circle, up to the 20M adversarial input) finished by the wide device
+finish; a HIP graph of the call replayed on new inputs.  Each case prints its name
 before its GPU calls."""
 import sys
 
@@ -79,22 +80,24 @@ def test_async_queued_back_to_back():
         assert np.array_equal(out[:c].cpu().numpy(), ref), k
 
 
-def test_async_domain_error_and_redo():
+def test_async_domain_error_and_wide_finish():
     bad = wl.generate("square", 50_000, 331)
     bad[777, 1] = 0.5
     say("  hull2d_async: out-of-domain coordinate")
     _, cnt = run_async(torch.from_numpy(bad).cuda())
     torch.cuda.synchronize()
     assert int(cnt.item()) == ch.CH_EDOMAIN
-    # many points on a circle: a polygon beyond the device finish
-    big = wl.generate("adversarial", 2_000_000, 332)
-    d = torch.from_numpy(big).cuda()
-    say("  hull2d_async: polygon beyond the device finish")
-    out, cnt = run_async(d)
-    torch.cuda.synchronize()
-    assert int(cnt.item()) == ch.CH_BATCH_REDO
-    h = ch.hull2d(d)
-    assert ch.last_stats()["device_finish"] is False and h.numel() > 0
+    # many points on a circle: a polygon beyond one workgroup, finished by
+    # the wide device finish
+    for n, seed in ((2_000_000, 332), (700_001, 334)):
+        big = wl.generate("adversarial", n, seed)
+        d = torch.from_numpy(big).cuda()
+        say(f"  hull2d_async: adversarial n={n} (wide finish)")
+        out, cnt = run_async(d)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        assert c > 0, c
+        assert np.array_equal(out[:c].cpu().numpy(), oracle.hull(big))
     # the workspace serves a good call after both
     good = wl.generate("disk", 300_000, 333)
     out, cnt = run_async(torch.from_numpy(good).cuda())
@@ -103,10 +106,24 @@ def test_async_domain_error_and_redo():
     assert np.array_equal(out[:c].cpu().numpy(), oracle.hull(good))
 
 
+@pytest.mark.timeout(300)
+def test_async_adversarial_20m_against_oracle():
+    pts = wl.workload("adversarial_20m")
+    d = torch.from_numpy(pts).cuda()
+    say("  hull2d_async adversarial_20m")
+    out, cnt = run_async(d)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert c > 0, c
+    got = out[:c].cpu().numpy()
+    say("  oracle adversarial_20m")
+    assert np.array_equal(got, oracle.hull(pts))
+
+
 def test_async_graph_replays():
     n = 1_000_000
-    seeds = (341, 342, 343)
-    inputs = [wl.generate(("square", "disk", "gaussian")[k], n, s) for k, s in enumerate(seeds)]
+    seeds = (341, 342, 343, 344)
+    inputs = [wl.generate(("square", "disk", "gaussian", "adversarial")[k], n, s) for k, s in enumerate(seeds)]
     d = torch.from_numpy(inputs[0]).cuda()
     out = torch.zeros(n, dtype=torch.int32, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -178,3 +195,45 @@ def test_async_three_stream_graph_replays():
     torch.cuda.synchronize()
     for st in streams:
         ch.release_stream(st)
+
+
+def test_captured_workspace_does_not_move():
+    # a graph holds the stream's workspace addresses: from the capture on, a
+    # call that would grow the workspace is refused until the stream is
+    # released; under capture a call that would allocate is refused
+    small = torch.from_numpy(wl.generate("disk", 200_000, 371)).cuda()
+    big = torch.from_numpy(wl.generate("disk", 3_000_000, 372)).cuda()
+    out = torch.zeros(3_000_000, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ch.release_stream(s)  # (torch reuses streams: no workspace of an earlier test)
+    say("  hull2d_async: under capture, a call on a stream without a workspace is refused")
+    g0 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g0, stream=s):
+        cnt.fill_(-3)  # (a kernel, so that the graph is not empty)
+        rc = ch.hull2d_async(small, out, cnt, stream=s)
+    assert rc == ch.CH_EINVAL
+    del g0
+    say("  hull2d_async: warm-up, capture, then a larger call")
+    assert ch.hull2d_async(small, out, cnt, stream=s) == ch.CH_OK
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        assert ch.hull2d_async(small, out, cnt, stream=s) == ch.CH_OK
+    assert ch.hull2d_async(big, out, cnt, stream=s) == ch.CH_EINVAL
+    cnt.fill_(-7)
+    g.replay()
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert np.array_equal(out[:c].cpu().numpy(), ch.hull2d(small).cpu().numpy())
+    del g
+    torch.cuda.synchronize()
+    ch.release_stream(s)
+    say("  hull2d_async: after the release the larger call runs")
+    assert ch.hull2d_async(big, out, cnt, stream=s) == ch.CH_OK
+    s.synchronize()
+    c = int(cnt.item())
+    assert np.array_equal(out[:c].cpu().numpy(), ch.hull2d(big).cpu().numpy())
+    ch.release_stream(s)

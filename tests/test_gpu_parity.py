@@ -234,17 +234,19 @@ def test_bucket_paths(m):
     stage_parity(pts, f"bucket m={m}")
 
 
-def test_device_and_host_finish():
-    # a short polygon is finished on the device; the rounded circle leaves
-    # more than the device finish holds, so the host finishes it
+def test_device_finish_one_and_many_workgroups():
+    # a short polygon is finished by one workgroup; the rounded circle leaves
+    # more than one workgroup holds, and the wide finish (tangents to the
+    # pieces' hulls, many workgroups) takes it
     sq = wl.generate("square", 1_000_000, 81)
-    print("  hull2d square 1M (device finish)", file=sys.stderr, flush=True)
+    print("  hull2d square 1M (one-workgroup finish)", file=sys.stderr, flush=True)
     got = ch.hull2d(torch.from_numpy(sq).cuda()).cpu().numpy()
     assert ch.last_stats()["device_finish"]
     assert np.array_equal(got, oracle.hull(sq))
-    adv = wl.generate("adversarial", 2_000_000, 82)
-    print("  hull2d adversarial 2M (host finish)", file=sys.stderr, flush=True)
-    got = ch.hull2d(torch.from_numpy(adv).cuda()).cpu().numpy()
-    st = ch.last_stats()
-    assert not st["device_finish"] and st["polygon"] > 4096
-    assert np.array_equal(got, oracle.hull(adv))
+    for n, seed in ((2_000_000, 82), (5_000_001, 83)):
+        adv = wl.generate("adversarial", n, seed)
+        print(f"  hull2d adversarial n={n} (wide finish)", file=sys.stderr, flush=True)
+        got = ch.hull2d(torch.from_numpy(adv).cuda()).cpu().numpy()
+        st = ch.last_stats()
+        assert st["device_finish"] and st["polygon"] > 3584
+        assert np.array_equal(got, oracle.hull(adv))

@@ -100,10 +100,45 @@ def test_domain_error_stays_in_its_request():
         t_big = srv.submit(torch.from_numpy(big_bad).cuda())
         for p, t in zip(good, t_good):
             assert np.array_equal(srv.wait(t)[0].cpu().numpy(), oracle.hull(p))
+        outs = {}
         for t in (t_bad, t_big):
+            outs[t] = srv._live[t][2]
             with pytest.raises(ch.ChainHullError) as e:
                 srv.wait(t)
             assert e.value.status == ch.CH_EDOMAIN
+    # a failed request's count is 0 whichever path served it, as hull2d
+    # leaves it
+    torch.cuda.synchronize()
+    for t, cnt in outs.items():
+        assert int(cnt.item()) == 0, t
+
+
+def test_server_memory_stays_within_budget():
+    # large requests (each alone on a worker's stream, with its own
+    # workspace) on four workers under a budget of about two workspaces: the
+    # memory the workers keep between requests counts against the budget
+    n = 1_000_000
+    reqs = [torch.from_numpy(wl.generate(("square", "disk")[k % 2], n, 91 + k)).cuda() for k in range(12)]
+    outs = [(torch.empty(n, dtype=torch.int32, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda"))
+            for _ in reqs]
+    alone = [ch.hull2d(p).cpu().numpy() for p in reqs]
+    ch.release()  # no workspace of this process's own calls stays behind
+    budget = int(2.5 * ch.workspace_bytes(n))
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    say(f"  server: 12 requests of {n} points, budget {budget >> 20} MiB")
+    low = free0
+    with ch.Server(workers=4, mem_budget=budget) as srv:
+        tickets = [srv.submit(p, o, c) for p, (o, c) in zip(reqs, outs)]
+        got = []
+        for t in tickets:
+            got.append(srv.wait(t)[0].cpu().numpy())
+            low = min(low, torch.cuda.mem_get_info()[0])
+    used = free0 - low
+    say(f"  server: most device memory in use {used >> 20} MiB")
+    assert used <= budget + (64 << 20), (used, budget)
+    for g, a in zip(got, alone):
+        assert np.array_equal(g, a)
 
 
 def test_poisson_arrivals():

@@ -105,3 +105,30 @@ def test_host_finish_degenerate_inputs():
     assert ch.finish_host([[0, 0], [1, 1], [2, 2], [3, 3], [2, 2]], [0, 1, 2, 3, 4]).tolist() == [0, 3]
     with pytest.raises(ch.ChainHullError):
         ch.finish_host([[0, 0], [1 << 23, 0], [0, 1]], [0, 1, 2])
+
+
+def test_tuning_table_on_the_host():
+    # the launch-shape table is host state: set, looked up by size class,
+    # validated, cleared (no GPU is touched)
+    base = ch.get_tuning(-1)
+    assert base == {"stream_grid": 1024, "stream_unroll": 4, "cand_per_row": 8192, "chain_grid": 1024,
+                    "wide_grid": 1024, "batch_unroll": 2, "batch_order": 0, "serve_batch_max": 1 << 18}
+    try:
+        ch.set_tuning(1000, dict(base, stream_grid=256, cand_per_row=2048))
+        ch.set_tuning(10**6, dict(base, stream_unroll=2))
+        assert ch.get_tuning(10)["stream_grid"] == 256
+        assert ch.get_tuning(1000)["cand_per_row"] == 2048
+        assert ch.get_tuning(1001)["stream_unroll"] == 2 and ch.get_tuning(1001)["stream_grid"] == 1024
+        assert ch.get_tuning(10**6 + 1) == base
+        for bad in (dict(stream_grid=300), dict(stream_unroll=3), dict(cand_per_row=512),
+                    dict(chain_grid=10), dict(wide_grid=5000), dict(batch_unroll=4), dict(batch_order=2),
+                    dict(serve_batch_max=-1)):
+            with pytest.raises(ch.ChainHullError):
+                ch.set_tuning(5, dict(base, **bad))
+        for k in range(14):
+            ch.set_tuning(2 * 10**6 + k, base)
+        with pytest.raises(ch.ChainHullError):  # 16 classes at most
+            ch.set_tuning(3 * 10**6, base)
+    finally:
+        ch.clear_tuning()
+    assert ch.get_tuning(10) == base
