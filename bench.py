@@ -660,6 +660,25 @@ def main():
     value = ways[api][0]
     ms_per_step = 1e3 * ways[api][1] / args.steps
 
+    # the autotuner's launch shapes (a file under tuning/ for this GPU, applied
+    # when the library loaded) against the built-in defaults, on the queued
+    # path: the same steps again with the defaults
+    tuning = {"source": os.path.relpath(ch.tuning_source(), ROOT) if ch.tuning_source() else None,
+              "shapes_20m": ch.get_tuning(n), "default_shapes": ch.get_tuning(-1)}
+    if ch.tuning_source():
+        ch.clear_tuning()
+        for _ in range(args.warmup):
+            step_async()
+        torch.cuda.synchronize()
+        t0d = time.perf_counter()
+        for _ in range(args.steps):
+            step_async()
+        torch.cuda.synchronize()
+        t1d = time.perf_counter()
+        ch.load_tuning(ch.tuning_source())
+        tuning["hull2d_async_tuned_mpts_per_s"] = round(value_async, 2)
+        tuning["hull2d_async_default_mpts_per_s"] = round(total_pts / (t1d - t0d) / 1e6, 2)
+
     # timed region 2: the same steps with HIP events recorded by the library
     # on the call's stream around every stage
     ch.set_timing(True)
@@ -763,6 +782,7 @@ def main():
                                                            "replayed: one launch and one synchronisation per step"}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tuning": tuning,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "per_config": per_config,
         "paper_context": PAPER_CONTEXT,

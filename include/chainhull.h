@@ -73,8 +73,8 @@ typedef struct {
      * + each workgroup's records sorted by bucket (and, in chainhull_polygon,
      * the round-1 counts), 3 the bucket table's columns (bucket sizes,
      * starts, thresholds), 4 region sort, second level + SPA + chain
-     * concatenation (+ pre-hull in hull2d), 5 the device finish of hull2d
-     * (one workgroup, or many for a large polygon); the host finish of
+     * concatenation (+ pre-hull in hull2d), 5 the device finish of hull2d;
+     * the host finish of
      * hull2d in wall-clock time, 0 when the device finished (it runs only if
      * the device finish gives up): 6 the polygon gathered on the device into
      * pinned memory and waited for, 7 Melkman's algorithm on it. */
@@ -103,11 +103,10 @@ typedef struct {
  * Returns CH_OK, CH_EINVAL, CH_EDOMAIN, CH_ENOMEM or CH_EHIP.
  */
 int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream);
-/* (Step 7 runs on the device: in one workgroup when the polygon left by
- * steps 1-6 and the pre-hull has at most 3584 vertices, across many
- * workgroups otherwise.  Melkman on the host remains as a fallback for a
- * polygon the device finish gives up on, which is not expected; the result
- * is the same.) */
+/* (Step 7 runs on the device, across workgroups, for every polygon that
+ * steps 1-6 and the pre-hull leave.  Melkman on the host remains as a
+ * fallback for a polygon the device finish gives up on, which is not
+ * expected; the result is the same.) */
 
 /*
  * hull2d_async: hull2d with every step on the device and nothing

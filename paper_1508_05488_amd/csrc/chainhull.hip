@@ -20,8 +20,8 @@
 //                   ordered by its low k1 bits and filtered by SPA
 //   k_chain         step 6: the chains concatenated, shortened by a
 //                   pre-hull per segment
-//   k_finish        step 7 in one workgroup for polygons that fit it
-//   k_finish_wide   step 7 across workgroups for larger polygons
+//   k_finish_wide   step 7 across workgroups: every kept point tested
+//                   against tangents to its neighbours' hulls
 // (hull2d falls back to Melkman on the host only if the device finish gives
 // up; chainhull_polygon stops after k_chain and returns the polygon.)
 //
@@ -114,7 +114,7 @@ struct DevHeader {
     int32_t fin_hull;    // its size
     uint32_t fin_w2[4];  // polygon vertices per region it finished from
     uint32_t gat_count;  // polygon vertices k_gather wrote for the host finish
-    uint32_t wide;       // 1 when k_finish left the polygon to k_finish_wide
+    uint32_t unused0;
     uint32_t epoch;      // calls on this workspace so far (tags the look-back states)
     uint32_t wide_ticket;  // k_finish_wide's next item
     uint32_t fin_fail;   // 1 when k_finish_wide gave up (the host finishes)
@@ -159,14 +159,9 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 // stores (written through to where every XCD sees it, instead of a
 // device-scope release fence, which would write back the whole L2 of the
 // XCD), wait until those stores have completed, and only then count their
-// arrival; the last arrival reads with device-scope loads.
+// arrival; the last arrival takes a device-scope acquire and reads.
 __device__ inline void st_dev(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline void st_dev(u64* p, u64 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ inline uint32_t ld_dev(const uint32_t* p)
-{
-    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline u64 ld_dev(const u64* p) { return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline void stores_done()
 {
     // (a workgroup-scope release orders the compiler but waits for nothing:
@@ -174,6 +169,10 @@ __device__ inline void stores_done()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
+// The last arrival, before it reads what the others stored: a device-scope
+// acquire (drops stale cache lines once; the reads are plain loads, issued
+// together).
+__device__ inline void last_arrival_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 // Arrival counter: returns the count before this arrival.
 __device__ inline uint32_t arrive(uint32_t* ctr) { return __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -405,7 +404,7 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // are those of all points.  The last k_stream workgroup reduces them; k_cand
 // runs the exact region test on the open points only (a point counts for its region only if
 // it passed that region's frame), and filters again with a staircase over
-// chunks of 1024 records: per region and k1-slot of 2^14 values the smallest
+// chunks of kCandChunk records: per region and k1-slot of 2^14 values the smallest
 // (k2, k1) in LDS; a record is dropped when the region's first point or a
 // record of an earlier slot has k2 <= its k2, or when its slot's smallest
 // record precedes it with k1 <= its k1.  The rest become sort records.
@@ -419,7 +418,7 @@ constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
 constexpr int kStreamGrid = 1024;   // k_stream workgroups at most (the partials' room)
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
-constexpr int kCandChunk = 1024;    // records filtered together
+constexpr int kCandChunk = 2048;    // records filtered together
 
 // Open-point record: X | Y << 23 | frame mask << 46.
 __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
@@ -488,13 +487,17 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
     uint32_t m[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) m[k] = ~0u;
+    last_arrival_acquire();
+#pragma unroll 4
     for (int b = 0; b < kSampleBlocks; ++b) {
-        const u64* row = reinterpret_cast<const u64*>(samp + b * 4 * kStairSlots + tid * kPer);
+        const v4u* row = reinterpret_cast<const v4u*>(samp + b * 4 * kStairSlots + tid * kPer);
 #pragma unroll
-        for (int k = 0; k < kPer / 2; ++k) {
-            const u64 v = ld_dev(row + k);
-            m[2 * k] = min(m[2 * k], (uint32_t)v);
-            m[2 * k + 1] = min(m[2 * k + 1], (uint32_t)(v >> 32));
+        for (int k = 0; k < kPer / 4; ++k) {
+            const v4u v = row[k];
+            m[4 * k] = min(m[4 * k], v.x);
+            m[4 * k + 1] = min(m[4 * k + 1], v.y);
+            m[4 * k + 2] = min(m[4 * k + 2], v.z);
+            m[4 * k + 3] = min(m[4 * k + 3], v.w);
         }
     }
     uint32_t lo = ~0u;
@@ -516,7 +519,6 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
         hdr->open = 0;
         hdr->cand = 0;
         hdr->err = 0;
-        hdr->wide = 0;
         hdr->wide_ticket = 0;
         hdr->fin_fail = 0;
         hdr->epoch = hdr->epoch + 1;
@@ -581,10 +583,7 @@ constexpr int kPartPer = kStreamGrid / kBlock;
 __device__ inline void load_partials(const ExtPartial* __restrict__ part, int nparts, ExtPartial (&p)[kPartPer])
 {
 #pragma unroll
-    for (int u = 0; u < kPartPer; ++u) {
-        const int b = u * kBlock + (int)threadIdx.x;
-        if (b < nparts) p[u] = part[b];
-    }
+    for (int u = 0; u < kPartPer; ++u) p[u] = part[min(u * kBlock + (int)threadIdx.x, nparts - 1)];  // (reduce_quad skips the repeats)
 }
 
 __device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, DevHeader* __restrict__ hdr,
@@ -813,21 +812,15 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     __syncthreads();
     if (!s_last) return;
     // the last workgroup: the quadrilateral and the number of open points
+    last_arrival_acquire();
     ExtPartial pp[kPartPer];
-#pragma unroll
-    for (int u = 0; u < kPartPer; ++u) {
-        const int b = u * kBlock + (int)tid;
-        if (b < (int)gridDim.x) {
-            const u64* const pr = reinterpret_cast<const u64*>(part + b);
-            u64* const pd = reinterpret_cast<u64*>(&pp[u]);
-            for (int k = 0; k < 8; ++k) pd[k] = ld_dev(pr + k);
-        }
-    }
+    load_partials(part, (int)gridDim.x, pp);
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < kStreamGrid / kBlock; ++k) {
-        const uint32_t b = k * kBlock + tid;
-        c += b < gridDim.x ? ld_dev(wgcount + b) : 0u;
+        const uint32_t b = min(k * kBlock + tid, gridDim.x - 1);  // (all loads issued together)
+        const uint32_t v = wgcount[b];
+        c += k * kBlock + tid < gridDim.x ? v : 0u;
     }
     Quad Q;
     reduce_quad(pp, (int)gridDim.x, hdr, Q, sh, true);
@@ -972,6 +965,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
                     if (l + st < nl && s_start[l + st] <= e) l += st;
                 const size_t at = ((size_t)first + l) * region + (e - s_start[l]);
                 const u64 r = open_xym[at];
+                const uint32_t ix = open_idx[at];  // (with the record, not after the test: one round trip)
                 const uint32_t X = (uint32_t)r & kM, Y = (uint32_t)(r >> 23) & kM, mask = (uint32_t)(r >> 46);
                 const uint32_t q = region_of(Q, X, Y);
                 if (q < 4 && ((mask >> q) & 1u)) {
@@ -979,7 +973,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
                     to_frame(q, X, Y, k1, k2);
                     k1s[k] = k1;
                     k2s[k] = k2;
-                    idxs[k] = open_idx[at];
+                    idxs[k] = ix;
                     addrs[k] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
                     atomicMin(&smin[addrs[k]], ((u64)k2 << 23) | k1);
                 }
@@ -1230,9 +1224,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevHeader* __restrict__ hdr, co
     __syncthreads();
     if (!s_last) return;
     // the last workgroup: thread j < kScanGrid combines workgroup j
+    last_arrival_acquire();
     const uint32_t j = tid;
-    const uint32_t t = j < (uint32_t)kScanGrid ? ld_dev(bk.wtot + j) : 0u;
-    const uint32_t mj = j < (uint32_t)kScanGrid ? ld_dev(bk.wmin + j) : ~0u;
+    const uint32_t t = j < (uint32_t)kScanGrid ? bk.wtot[j] : 0u;
+    const uint32_t mj = j < (uint32_t)kScanGrid ? bk.wmin[j] : ~0u;
     uint32_t total;
     const uint32_t base = block_excl_sum(t, scratch, total);
     // exclusive prefix minimum over the earlier workgroups of the region
@@ -1557,7 +1552,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         }
         if (tid < 4) s_cnt[tid] = 0;
         __syncthreads();
-        // alive points in order: thread t owns positions [16t, 16t+16)
+        // alive points in order: thread t owns positions [4t, 4t+4)
         auto compact = [&]() -> uint32_t {
             uint32_t mine = 0;
 #pragma unroll
@@ -1577,7 +1572,70 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         };
         // Pre-hull rounds: every alive point that makes no left turn with
         // its alive neighbours of the same region goes at once; repeat
-        // until none does (at most kPrehullRounds times).
+        // until none does (at most kPrehullRounds times).  First inside
+        // each wave's window of 256 positions (lane l: 4l .. 4l+3; the
+        // alive flags stay in registers, the neighbours come from wave
+        // scans, no workgroup barrier), then over the whole segment.
+        if (prehull) {
+            const uint32_t p0 = tid * kPerThreadSeg;
+            const uint32_t lane = lane_id();
+            bool al[kPerThreadSeg];
+#pragma unroll
+            for (int k = 0; k < kPerThreadSeg; ++k) al[k] = p0 + k < len;
+            for (int round = 0; round < kPrehullRounds; ++round) {
+                // the nearest alive positions before and after this lane's
+                int last = -1, first = 1 << 30;
+#pragma unroll
+                for (int k = kPerThreadSeg - 1; k >= 0; --k)
+                    if (al[k]) first = (int)(p0 + k);
+#pragma unroll
+                for (int k = 0; k < kPerThreadSeg; ++k)
+                    if (al[k]) last = (int)(p0 + k);
+                int before = last, after = first;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int b = __shfl_up(before, off), a = __shfl_down(after, off);
+                    if (lane >= (uint32_t)off) before = max(before, b);
+                    if (lane + off < 64) after = min(after, a);
+                }
+                int prev = __shfl_up(before, 1), next = __shfl_down(after, 1);
+                if (lane == 0) prev = -1;
+                if (lane == 63) next = 1 << 30;
+                bool gone[kPerThreadSeg];
+                // prev: the last alive before position k; then the next
+                // alive after it, scanning from the lane's end
+                int pv[kPerThreadSeg], nx[kPerThreadSeg];
+#pragma unroll
+                for (int k = 0; k < kPerThreadSeg; ++k) {
+                    pv[k] = prev;
+                    if (al[k]) prev = (int)(p0 + k);
+                }
+#pragma unroll
+                for (int k = kPerThreadSeg - 1; k >= 0; --k) {
+                    nx[k] = next;
+                    if (al[k]) next = (int)(p0 + k);
+                }
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < kPerThreadSeg; ++k) {
+                    gone[k] = false;
+                    if (al[k] && pv[k] >= 0 && nx[k] < (int)len) {
+                        const uint32_t i = p0 + k, a = (uint32_t)pv[k], c = (uint32_t)nx[k];
+                        if (reg[a] == reg[i] && reg[c] == reg[i] &&
+                            frame_turn(ka[a], kb[a], ka[i], kb[i], ka[c], kb[c]) <= 0) {
+                            gone[k] = true;
+                            any = true;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kPerThreadSeg; ++k) al[k] = al[k] && !gone[k];
+                if (!__ballot(any)) break;
+            }
+#pragma unroll
+            for (int k = 0; k < kPerThreadSeg; ++k)
+                if (p0 + k < len) alive[p0 + k] = al[k] ? 1 : 0;
+        }
         if (tid < 2) s_removed[tid] = 0;
         uint32_t n_alive = compact();
         for (int round = 0; prehull && round < kPrehullRounds; ++round) {
@@ -1606,7 +1664,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                 if (o < host_cap) host_chain[o] = r;
                 else spill[o - host_cap] = r;
             }
-            dev_kept[o] = r;  // k_finish and k_gather read these
+            dev_kept[o] = r;  // k_finish_wide and k_gather read these
             atomicAdd(&s_cnt[reg[i]], 1u);
         }
         __syncthreads();
@@ -1714,8 +1772,7 @@ struct BatchPoly {  // polygon view of the LDS
 
 // The polygon view of LDS at b: x, y, idx (int32), the pre-hull list
 // (u16), Melkman's deque (u16, 2 * kBatchPolyMax + 8), region and alive
-// flags (u8); kPolyBytes in all.
-constexpr size_t kPolyBytes = 16 * (size_t)kBatchPolyMax + 2 * (2 * (size_t)kBatchPolyMax + 8);
+// flags (u8).
 __device__ inline BatchPoly poly_view(unsigned char* b)
 {
     BatchPoly Pl;
@@ -2415,154 +2472,8 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
 }
 
 // ---------------------------------------------------------------------------
-// Step 7 on the device for the single-hull path (Section 2.1.3): one
-// workgroup assembles the polygon [P_minx, R1, P_miny, R2, P_maxx, R3,
-// P_maxy, R4] from k_chain's device copy of its output (per 1024-position
-// segment and region, the kept points at the segment's start) and finishes
-// it as the batched
-// kernel does (poly_finish), writing the hull into the caller's buffers.
-//   pass 1  a scan over the segments' counts: a table of the non-empty
-//           segments (segment, first polygon rank, cumulative region counts)
-//           and the points per region;
-//   pass 2  each kept point finds its segment by binary search in the table
-//           and goes to its polygon position (its rank plus the extreme
-//           points before its region).
-// A polygon of more than kBatchPolyMax vertices goes to k_finish_wide (the
-// header's wide flag); one that Melkman cannot finish in LDS is left to the
-// host (fin_done = 0 in the header, the count kBatchRedo until the host's
-// result replaces it); after a failed step the count is the call's negative
-// status.
-// ---------------------------------------------------------------------------
-struct SegEnt {
-    uint32_t sg, pre;  // segment, rank of its first kept point
-    uint16_t cum[4];   // kept points in regions <= q inside the segment
-};
-constexpr size_t kFinishLds = kPolyBytes + sizeof(SegEnt) * (size_t)kBatchPolyMax;
-
-__global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_finish(DevHeader* __restrict__ hdr,
-                                                        const uint32_t* __restrict__ segcnt,
-                                                        const PolyRec* __restrict__ kept,
-                                                        int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count,
-                                                        DevHeader* __restrict__ host_hdr)
-{
-    __shared__ __align__(16) unsigned char smem[kFinishLds];
-    __shared__ uint32_t scratch[kBatchWaves];
-    __shared__ uint32_t s_flag, s_ext, s_start, s_reg[4];
-    const uint32_t tid = threadIdx.x, lane = lane_id();
-    SegEnt* const tab = reinterpret_cast<SegEnt*>(smem + kPolyBytes);
-    if (hdr->err) {
-        if (tid == 0) {
-            host_hdr->fin_done = 0;
-            *out_count = (hdr->err & kErrDomain) ? CH_EDOMAIN : CH_EHIP;
-        }
-        return;
-    }
-    const uint32_t chain = hdr->chain;
-    const uint32_t nseg = (chain + kSeg - 1) / kSeg;
-    if (tid < 4) s_reg[tid] = 0;
-    __syncthreads();
-
-    // ---- pass 1: the non-empty segments ----
-    uint32_t total = 0, nt = 0, reg[4] = {0, 0, 0, 0};
-    bool fits = true;
-    for (uint32_t c0 = 0; c0 < nseg; c0 += kBatchBlock) {
-        const uint32_t sg = c0 + tid;
-        uint32_t c[4] = {0, 0, 0, 0};
-        if (sg < nseg) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = segcnt[4 * sg + q];
-        }
-        const uint32_t tot = c[0] + c[1] + c[2] + c[3];
-        uint32_t all, nz;
-        const uint32_t ex = block_excl_sum<kBatchWaves>(tot, scratch, all);
-        const uint32_t at = block_excl_sum<kBatchWaves>(tot ? 1u : 0u, scratch, nz);
-        if (total + all + 4 > (uint32_t)kBatchPolyMax) {  // the same in every thread
-            fits = false;
-            break;
-        }
-        if (tot) {
-            SegEnt e;
-            e.sg = sg;
-            e.pre = total + ex;
-            e.cum[0] = (uint16_t)c[0];
-            e.cum[1] = (uint16_t)(c[0] + c[1]);
-            e.cum[2] = (uint16_t)(c[0] + c[1] + c[2]);
-            e.cum[3] = (uint16_t)tot;
-            tab[nt + at] = e;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) reg[q] += c[q];
-        total += all;
-        nt += nz;
-    }
-    if (!fits) {
-        // too large for one workgroup: k_finish_wide takes it (the count
-        // stays kBatchRedo until it has written the hull)
-        if (tid == 0) {
-            host_hdr->fin_done = 0;
-            *out_count = kBatchRedo;
-            hdr->wide = 1;
-        }
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t v = wave_sum(reg[q]);
-        if (lane == 0 && v) atomicAdd(&s_reg[q], v);
-    }
-    __syncthreads();
-
-    // ---- pass 2: the polygon ----
-    BatchPoly Pl = poly_view(smem);
-    uint32_t rbase[4];  // polygon position of E_q
-    {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            rbase[q] = acc;
-            acc += 1 + s_reg[q];
-        }
-    }
-    if (tid < 4) {
-        const uint32_t q = tid, o = q == 0 ? rbase[0] : q == 1 ? rbase[1] : q == 2 ? rbase[2] : rbase[3];
-        Pl.x[o] = (int32_t)hdr->ext_x[q];
-        Pl.y[o] = (int32_t)hdr->ext_y[q];
-        Pl.idx[o] = (int32_t)hdr->ext_idx[q];
-        Pl.reg[o] = 4;
-        Pl.alive[o] = 1;
-    }
-    for (uint32_t p = tid; p < total; p += kBatchBlock) {
-        uint32_t lo = 0, hi = nt;  // the last entry with pre <= p
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (tab[mid].pre <= p) lo = mid;
-            else hi = mid;
-        }
-        const SegEnt e = tab[lo];
-        const uint32_t j = p - e.pre;
-        const uint32_t q = j < e.cum[0] ? 0u : j < e.cum[1] ? 1u : j < e.cum[2] ? 2u : 3u;
-        const uint32_t at = e.sg * kSeg + j;
-        const PolyRec r = kept[at];
-        const uint32_t o = p + q + 1;
-        Pl.x[o] = r.x;
-        Pl.y[o] = r.y;
-        Pl.idx[o] = r.idx;
-        Pl.reg[o] = (uint8_t)q;
-        Pl.alive[o] = 1;
-    }
-    __syncthreads();
-    const int h = poly_finish(Pl, total + 4, rbase[1], out_idx, scratch, &s_flag, &s_ext, &s_start);
-    if (tid == 0) {
-        *out_count = h >= 0 ? h : kBatchRedo;
-        host_hdr->fin_hull = h;
-        for (int q = 0; q < 4; ++q) host_hdr->fin_w2[q] = s_reg[q];
-        host_hdr->fin_done = h >= 0 ? 1u : 0u;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Step 7 on the device for polygons beyond one workgroup (Section 2.1.3's
-// hull, computed without Melkman's sequential deque).
+// Step 7 on the device (Section 2.1.3's hull, computed without Melkman's
+// sequential deque), across workgroups.
 //
 // Every hull vertex of region q lies on the lower hull, in q's frame, of the
 // region's kept points and its two extreme points E_q (start) and E_{q+1}
@@ -2761,7 +2672,14 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
     __shared__ uint32_t scratch[kWideWaves];
     __shared__ uint32_t s_t, s_h, s_nl, s_bad, s_base, s_fail;
     const uint32_t tid = threadIdx.x;
-    if (!hdr->wide || hdr->err) return;
+    if (hdr->err) {
+        // a failed step: the count is the call's status
+        if (blockIdx.x == 0 && tid == 0) {
+            host_hdr->fin_done = 0;
+            *out_count = (hdr->err & kErrDomain) ? CH_EDOMAIN : CH_EHIP;
+        }
+        return;
+    }
     const uint32_t epoch = hdr->epoch;
     // the region layout, in LDS (indexed by region)
     __shared__ WideRegion R[4];
@@ -2777,6 +2695,7 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
     __syncthreads();
     uint32_t nitems = 4;
     for (int q = 0; q < 4; ++q) nitems += R[q].nseg;
+    if (blockIdx.x >= nitems) return;  // (no ticket could be left for it)
     bool fail = false;
 
     for (;;) {
@@ -3007,7 +2926,13 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
                 }
             }
         }
-        // the item's first output position
+        // the item's first output position (the first item's workgroup
+        // first sets the count to a sentinel that only the last item's
+        // total replaces, so that a failed item can never be overwritten)
+        if (t == 0 && tid == 0) {
+            st_dev(reinterpret_cast<uint32_t*>(out_count), (uint32_t)kBatchRedo);
+            stores_done();
+        }
         if (tid < 64) {
             bool f = false;
             const uint32_t base = look_back(states, t, epoch, count, f);
@@ -3058,7 +2983,7 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
 }
 
 // ---------------------------------------------------------------------------
-// The host finish's input when k_finish leaves the polygon to the host: one
+// The host finish's input when the device finish gave up (not expected): one
 // workgroup gathers the polygon [P_minx, R1, P_miny, R2, P_maxx, R3, P_maxy,
 // R4] from k_chain's device copy (per segment and region, the kept points at
 // the segment's start) into pinned host memory, densely, as (x, y) pairs and
@@ -3272,7 +3197,7 @@ struct StreamShape {
 };
 
 // ---- launch shapes (ch_tuning), per size class ----
-constexpr ch_tuning kDefaultTuning = {1024, 4, 8192, 1024, 1024, 2, 0, 1 << 18};
+constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18};
 constexpr int kTuningClasses = 16;
 std::mutex g_tune_mu;
 int g_tune_count = 0;
@@ -3522,12 +3447,12 @@ int record(Workspace& w, int k)
 }
 
 // Steps 1-6 on the device; the counts end in w.h_hdr.  Without fin_idx the
-// chains end in w.h_chain (and w.spill).  With fin_idx, k_finish and
-// k_finish_wide then finish the hull on the device into fin_idx / fin_count
+// chains end in w.h_chain (and w.spill).  With fin_idx, k_finish_wide then
+// finishes the hull on the device into fin_idx / fin_count
 // (h_hdr->fin_done); only if they gave up does gather_polygon fetch the
 // polygon for the host finish.  Timing events: 0 | k_sample | 1 | k_stream |
 // 2 | k_cand (+ k_count_regions) | 3 | k_scan | 4 | k_bucket_spa, k_chain |
-// 5 | k_finish, k_finish_wide | 6.
+// 5 | k_finish_wide | 6.
 int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx,
                       int32_t* fin_count)
 {
@@ -3575,10 +3500,8 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
                                  w.dev_segcnt));
     CH_TRY(record(w, 5));
     if (fin_idx) {
-        CH_LAUNCH(hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBatchBlock), 0, s, w.hdr, w.dev_segcnt, w.dev_kept,
-                                     fin_idx, fin_count, w.h_hdr_dev));
-        // (returns at once unless k_finish left the polygon to it)
-        CH_LAUNCH(hipLaunchKernelGGL(k_finish_wide, dim3((uint32_t)tu.wide_grid), dim3(kWideBlock), 0, s, w.hdr, w.dev_segcnt,
+        CH_LAUNCH(hipLaunchKernelGGL(k_finish_wide, dim3((uint32_t)tu.wide_grid), dim3(kWideBlock), 0, s, w.hdr,
+                                     w.dev_segcnt,
                                      w.dev_kept, w.states, fin_idx, fin_count, w.h_hdr_dev));
     }
     CH_TRY(record(w, 6));

@@ -111,7 +111,7 @@ def test_tuning_table_on_the_host():
     # the launch-shape table is host state: set, looked up by size class,
     # validated, cleared (no GPU is touched)
     base = ch.get_tuning(-1)
-    assert base == {"stream_grid": 1024, "stream_unroll": 4, "cand_per_row": 8192, "chain_grid": 1024,
+    assert base == {"stream_grid": 1024, "stream_unroll": 4, "cand_per_row": 2048, "chain_grid": 1024,
                     "wide_grid": 1024, "batch_unroll": 2, "batch_order": 0, "serve_batch_max": 1 << 18}
     try:
         ch.set_tuning(1000, dict(base, stream_grid=256, cand_per_row=2048))
