@@ -80,7 +80,9 @@ typedef struct {
      * pinned memory and waited for, 7 Melkman's algorithm on it. */
     float ms[8];
     int32_t device_finish;  /* 1 when hull2d finished step 7 on the device */
-    int32_t reserved;
+    int32_t fused;          /* 1 when the small-input path (one workgroup of the
+                               batched kernel) computed the hull: the stage counts
+                               are then -1 and ms_pre spans that kernel */
     float ms_pre;         /* steps 1-6 on the device (stages 0-4) as one HIP event
                              span, when timing is on */
     float ms_finish;      /* the device finish (stage 5) as one span */
@@ -115,9 +117,10 @@ int hull2d(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count,
  *   points, n, out_idx, stream  as in hull2d.
  *   out_count  device memory, one int32; receives, in stream order, the
  *              number of hull vertices, or CH_EDOMAIN (a coordinate out of
- *              the domain), CH_EHIP (a failed step), or CH_BATCH_REDO when
- *              the device finish gave up on the polygon (not expected;
- *              hull2d computes such an input on the host).
+ *              the domain), or CH_EHIP (a failed step, or a device finish
+ *              that gave up on the polygon: not expected, and hull2d
+ *              computes such an input on the host).  CH_BATCH_REDO stands
+ *              there only while the finish runs.
  * Returns after queueing the kernels: CH_OK, CH_EINVAL (bad argument, before
  * any work), CH_ENOMEM or CH_EHIP.  The stream's workspace (shared with
  * hull2d on that stream) is allocated or grown only when n exceeds what it
@@ -147,8 +150,8 @@ int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_
  * ends) instead of a per-stream workspace.  Nothing is allocated, on the
  * device or in pinned host memory, and no timing events are recorded.
  *   points, out_idx, out_count, stream  as in hull2d_async; out_count
- *              receives, in stream order, the hull size, CH_EDOMAIN,
- *              CH_EHIP or CH_BATCH_REDO as there.
+ *              receives, in stream order, the hull size, CH_EDOMAIN or
+ *              CH_EHIP as there.
  *   n          0 <= n <= CH_NOALLOC_MAX_POINTS; a larger n returns
  *              CH_ECAPACITY before any device work.
  * Every call on a device uses that device's one buffer: calls that overlap
@@ -323,6 +326,12 @@ typedef struct {
     int32_t batch_order;     /* batched launch order: 0 larger sets first, 1 as given */
     int32_t serve_batch_max; /* serving: requests of at most this many points are
                                 batched (0 .. 2^22); read when a server is created */
+    int32_t fused_max;       /* hull2d, hull2d_async, hull2d_noalloc: inputs of at
+                                most this many points run every step in one
+                                workgroup of the batched kernel first (0 .. 2^22;
+                                0: never); the single-hull kernels then run only
+                                for an input it leaves (queued behind it and
+                                returning at once otherwise) */
 } ch_tuning;
 
 /* Use *t for calls whose point count (for hull2d_batched: total points) is

@@ -52,7 +52,7 @@ class ChStats(ctypes.Structure):
         ("hull", ctypes.c_int64),
         ("ms", ctypes.c_float * 8),
         ("device_finish", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
         ("ms_pre", ctypes.c_float),
         ("ms_finish", ctypes.c_float),
     ]
@@ -70,6 +70,7 @@ class ChStats(ctypes.Structure):
             "hull": self.hull,
             "ms": dict(zip(STAGES, list(self.ms))),
             "device_finish": bool(self.device_finish),
+            "fused": bool(self.fused),
             "ms_pre": self.ms_pre,
             "ms_finish": self.ms_finish,
         }
@@ -117,6 +118,7 @@ class ChTuning(ctypes.Structure):
         ("batch_unroll", ctypes.c_int32),
         ("batch_order", ctypes.c_int32),
         ("serve_batch_max", ctypes.c_int32),
+        ("fused_max", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -302,8 +304,9 @@ def hull2d_into(points, out_idx, out_count, stream=None) -> int:
 
 def hull2d_async(points, out_idx, out_count, stream=None) -> int:
     """hull2d with every step on the device, queued on the stream and not
-    synchronised: out_count (CUDA int32 [1]) receives the hull size, a
-    negative status, or CH_BATCH_REDO (then call hull2d).  out_idx: CUDA
+    synchronised: out_count (CUDA int32 [1]) receives the hull size or a
+    negative status (CH_EHIP if the device finish gave up: then call
+    hull2d, which finishes on the host).  out_idx: CUDA
     int32 with room for the points.  Returns the status of the launch."""
     return lib().hull2d_async(points.data_ptr(), points.shape[0], out_idx.data_ptr(), out_count.data_ptr(),
                               _stream_ptr(stream))

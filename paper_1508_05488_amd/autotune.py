@@ -8,8 +8,12 @@ shape of the single-hull path (k_stream grid and loads in flight, open
 points per k_cand workgroup, k_chain and k_finish_wide grids) on seeded
 inputs of each distribution, checks that every candidate gives exactly the
 default shape's hulls (a shape never changes a result), and keeps the
-fastest; then the batched kernel's loads in flight and launch order on a
-batch of sets; then the serving threshold (the largest request for which
+fastest (with the small-input path off, so that the single-hull kernels
+themselves are timed); then the batched kernel's loads in flight and launch
+order on a batch of sets; then two thresholds from one sweep of sizes: the
+small-input path's (the largest size up to which the batched kernel's one
+workgroup, with the single-hull kernels gated behind it, is not slower than
+the single-hull kernels) and the serving one (the largest request for which
 one workgroup of the batched kernel is at most ``SERVE_RATIO`` times slower
 than the whole device).  The result is a JSON file under ``tuning/``, keyed
 by the GPU, that the binding applies when the library loads.
@@ -45,11 +49,11 @@ def candidates(quick: bool = False):
     """Every single-hull shape the autotuner tries (the defaults among them)."""
     grids = (256, 512, 1024)
     unrolls = (2, 4)
-    per_row = (2048, 8192, 32768)
+    per_row = (1024, 2048, 4096, 8192)
     chain = (256, 1024)
     wide = (512, 1024, 2048)
     if quick:
-        grids, per_row, wide = (512, 1024), (8192, 32768), (1024,)
+        grids, unrolls, per_row, chain, wide = (512, 1024), (4,), (2048, 4096), (1024,), (1024,)
     return [{"stream_grid": g, "stream_unroll": u, "cand_per_row": r, "chain_grid": c, "wide_grid": w}
             for g, u, r, c, w in itertools.product(grids, unrolls, per_row, chain, wide)]
 
@@ -97,6 +101,7 @@ def tune_single(torch, dev, timer, quick: bool, log) -> list:
         cnt = torch.empty(1, dtype=torch.int32, device=dev)
         # the default shape's hulls: every candidate must reproduce them
         ch.clear_tuning()
+        ch.set_tuning(2**40, shape(default, fused_max=0))
         ref = {}
         for d, x in inputs.items():
             assert ch.hull2d_async(x, out, cnt) == ch.CH_OK
@@ -108,7 +113,7 @@ def tune_single(torch, dev, timer, quick: bool, log) -> list:
         flush = n * 8 < 512 << 20
         rows = []
         for cand in candidates(quick):
-            t = shape(default, **cand)
+            t = shape(default, **cand, fused_max=0)  # (the single-hull kernels themselves)
             ch.clear_tuning()
             ch.set_tuning(n_max, t)
             ms, ok = {}, True
@@ -159,24 +164,42 @@ def tune_batched(torch, dev, timer, log, sets: int = 1024) -> dict:
 
 
 def tune_serving(torch, dev, timer, log) -> dict:
-    """Largest request size for which the batched kernel (one workgroup per
-    set) is at most SERVE_RATIO times slower than the single-hull path."""
+    """Per size n on the uniform disk: the single-hull kernels alone
+    (fused_max 0), the small-input path (the batched kernel's one workgroup
+    with the single-hull kernels gated behind it) and the batched kernel
+    alone on the one set.  fused_max: the largest n for which the
+    small-input path is not slower than the single-hull kernels;
+    serve_batch_max: the largest n for which the batched kernel is at most
+    SERVE_RATIO times slower than them."""
     sizes = [int(2 ** k) for k in np.arange(12, 22.5, 0.5)]
-    rows, best = [], 4096
-    for m in sizes:
-        pts = wl.generate("disk", m, 700 + m % 997)
-        d = torch.from_numpy(pts).to(dev)
-        out = torch.empty(m, dtype=torch.int32, device=dev)
-        cnt = torch.empty(1, dtype=torch.int32, device=dev)
-        offs_d = torch.tensor([0, m], dtype=torch.int64, device=dev)
-        cnts = torch.empty(1, dtype=torch.int32, device=dev)
-        t_one = timer.time(lambda: ch.hull2d_async(d, out, cnt), 7, False)
-        t_bat = timer.time(lambda: ch.hull2d_batched_async(d, offs_d, None, out, cnts), 7, False)
-        rows.append({"n": m, "single_ms": t_one, "batched_ms": t_bat})
-        log(f"autotune serving: n={m} single {t_one:.4f} ms batched {t_bat:.4f} ms")
-        if t_bat <= SERVE_RATIO * t_one:
-            best = m
-    return {"serve_batch_max": int(min(best, 1 << 22)), "ratio": SERVE_RATIO, "sizes": rows}
+    rows, best_serve, best_fused = [], 4096, 0
+    base = ch.get_tuning(-1)
+    try:
+        for m in sizes:
+            pts = wl.generate("disk", m, 700 + m % 997)
+            d = torch.from_numpy(pts).to(dev)
+            out = torch.empty(m, dtype=torch.int32, device=dev)
+            cnt = torch.empty(1, dtype=torch.int32, device=dev)
+            offs_d = torch.tensor([0, m], dtype=torch.int64, device=dev)
+            cnts = torch.empty(1, dtype=torch.int32, device=dev)
+            ch.clear_tuning()
+            ch.set_tuning(2**40, shape(base, fused_max=0))
+            t_one = timer.time(lambda: ch.hull2d_async(d, out, cnt), 7, False)
+            ch.clear_tuning()
+            ch.set_tuning(2**40, shape(base, fused_max=1 << 22))
+            t_fus = timer.time(lambda: ch.hull2d_async(d, out, cnt), 7, False)
+            ch.clear_tuning()
+            t_bat = timer.time(lambda: ch.hull2d_batched_async(d, offs_d, None, out, cnts), 7, False)
+            rows.append({"n": m, "single_ms": t_one, "fused_ms": t_fus, "batched_ms": t_bat})
+            log(f"autotune serving: n={m} single {t_one:.4f} ms fused {t_fus:.4f} ms batched {t_bat:.4f} ms")
+            if t_bat <= SERVE_RATIO * t_one:
+                best_serve = m
+            if t_fus <= t_one and (len(rows) == 1 or best_fused == rows[-2]["n"]):
+                best_fused = m  # (the sizes up to m all gain)
+    finally:
+        ch.clear_tuning()
+    return {"serve_batch_max": int(min(best_serve, 1 << 22)), "fused_max": int(min(best_fused, 1 << 22)),
+            "ratio": SERVE_RATIO, "sizes": rows}
 
 
 def run(out_path: str | None = None, quick: bool = False, log=print) -> dict:
@@ -194,6 +217,7 @@ def run(out_path: str | None = None, quick: bool = False, log=print) -> dict:
         c["tuning"]["batch_unroll"] = bat["batch_unroll"]
         c["tuning"]["batch_order"] = bat["batch_order"]
         c["tuning"]["serve_batch_max"] = srv["serve_batch_max"]
+        c["tuning"]["fused_max"] = srv["fused_max"]
     doc = {"device": ch.device_key(), "generated_unix": int(time.time()), "seconds": round(time.time() - t0, 1),
            "classes": classes, "batched": bat, "serving": srv}
     path = out_path or ch.tuning_path()

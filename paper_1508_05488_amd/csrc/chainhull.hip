@@ -2,18 +2,19 @@
 // gfx950 kernels, the pipeline around them and the C ABI.
 //
 // Kernels of one hull (all on the caller's stream):
-//   k_sample        a sample of the points: per-frame slot minima; its last
-//                   workgroup builds the sampled staircases (prefix minima)
-//                   and clears the call's counters
-//   k_stream        the one full pass over the points: the domain check and
-//                   the sampled-staircase dominance test; lists the points
-//                   that pass it (the extreme points are among them); its
-//                   last workgroup reduces the extreme points (step 1) and
-//                   publishes the quadrilateral
-//   k_cand          step 2's exact region test on the listed points, a chunk
-//                   staircase; each workgroup sorts its records by sort
-//                   bucket (region, top k1 bits) in its own part and writes
-//                   its row of the bucket table
+//   k_sample        a sample of the points: per-frame slot minima, merged
+//                   into the call's table by atomic maxima of complements
+//   k_stream        the one full pass over the points: each workgroup turns
+//                   the table into the sampled staircases (prefix minima),
+//                   then the domain check and the staircase dominance test;
+//                   lists the points that pass it (the extreme points are
+//                   among them) and its extreme keys
+//   k_cand          step 1's reduction of the extreme keys (every
+//                   workgroup; the first publishes the quadrilateral and
+//                   starts the call's header), step 2's exact region test on
+//                   the listed points, a chunk staircase; each workgroup
+//                   sorts its records by sort bucket (region, top k1 bits) in
+//                   its own part and writes its row of the bucket table
 //   k_scan          the bucket table's columns: bucket sizes, where each
 //                   bucket starts, the SPA threshold entering it
 //   k_bucket_spa    steps 3-5: each bucket gathered from the rows' parts,
@@ -28,9 +29,10 @@
 // Data layout in HBM (one workspace per device and stream):
 //   points           caller's n x float32[2], read once in full (k_stream)
 //   DevHeader        extreme points, quadrilateral edges, frames, counters;
-//                    with the look-back states and arrival counters it is
+//                    with the look-back states and the sample table it is
 //                    zeroed when the workspace is allocated
-//   samp, stair      sampled slot minima per sample workgroup, staircases
+//   stab             the sample's slot minima, complemented (4 x 1024 words;
+//                    zero again after every call)
 //   ExtPartial[G]    per-workgroup extreme keys
 //   open lists       per k_stream workgroup: index; x | y << 23 | mask << 46
 //   key[2], val[2]   records: u32 q << 23 | k1, u64 k2 << 32 | index; per
@@ -88,8 +90,19 @@ typedef long long i64;
 constexpr uint32_t kM = (1u << 23) - 1;
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kSlotBits = 9;
-constexpr int kSlots = 1 << kSlotBits;            // k1 slots per region (chunk filter)
+// Chunk-filter slots of region q, by u = k1 minus the k1 of the region's
+// first point: kFineSlots slots of 2^kFineShift values at the region's start
+// (where the sampled staircase knows nothing, and where open points crowd
+// on inputs that fill their bounding box), then slots of 2^kCoarseShift.
+constexpr int kFineSlots = 128;
+constexpr int kFineShift = 7;
+constexpr int kCoarseShift = 14;
+constexpr int kSlots = kFineSlots + (1 << (23 - kCoarseShift));  // 640 per region
+__device__ inline uint32_t chunk_slot(uint32_t u)
+{
+    constexpr uint32_t kFineEnd = (uint32_t)kFineSlots << kFineShift;
+    return u < kFineEnd ? (u >> kFineShift) : kFineSlots + ((u - kFineEnd) >> kCoarseShift);
+}
 // Buckets of the region sort: region q and the top kBucketBits bits of k1;
 // inside a bucket, k1's low kLowBits bits address an LDS table directly.
 constexpr int kBucketBits = 11;
@@ -98,6 +111,12 @@ constexpr int kBuckets = 4 << kBucketBits;        // 8192
 constexpr int kLowSize = 1 << kLowBits;           // 4096
 
 constexpr uint32_t kErrDomain = 1;   // a coordinate is outside the domain
+constexpr int32_t kBatchRedo = INT32_MIN;  // a count: the batched kernel left the set to the single-hull path
+
+// The small-input path runs the batched kernel on the one set first and the
+// single-hull kernels after it gated on its count (gate): they do their work
+// only if it left kBatchRedo, and return at once otherwise.
+__device__ inline bool gated_off(const int32_t* gate) { return gate && *gate != kBatchRedo; }
 
 struct DevHeader {
     double ec[4];        // ex*E_q.y - ey*E_q.x for the edge E_q -> E_{q+1}
@@ -141,11 +160,9 @@ struct Buckets {
     uint32_t* surv;    // SPA survivors per bucket (k_bucket_spa)
     uint32_t* lstart;  // first record of the bucket among its k_scan workgroup's buckets
     uint32_t* lthr;    // smallest k2 over the earlier buckets of its k_scan workgroup
+    uint32_t* bmin;    // smallest k2 of the bucket's records (k_scan)
     uint32_t* wtot;    // per k_scan workgroup: records
     uint32_t* wmin;    // per k_scan workgroup: smallest k2
-    uint32_t* wgbase;  // per k_scan workgroup: the first record of its buckets
-    uint32_t* wgthr;   // per k_scan workgroup: the threshold entering its buckets
-    uint32_t* ctr;     // k_scan's arrival counter (zero between calls)
 };
 
 // ---------------------------------------------------------------------------
@@ -199,6 +216,13 @@ __device__ inline uint32_t wave_sum(uint32_t v)
     return v;
 }
 
+__device__ inline uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off));
+    return v;
+}
+
 __device__ inline uint32_t wave_incl_sum(uint32_t v)
 {
     const uint32_t lane = lane_id();
@@ -219,6 +243,40 @@ __device__ inline uint32_t wave_incl_min(uint32_t v)
         if (lane >= (uint32_t)off) v = min(v, o);
     }
     return v;
+}
+
+// Inclusive and exclusive minimum scans over the wave without the LDS
+// crossbar: DPP row shifts inside each row of 16 lanes, then the rows'
+// totals by readlane.  (DPP row_shr:n, control 0x110 + n; a lane whose
+// source lies outside its row keeps the identity.)
+__device__ inline uint32_t dpp_row_shr(uint32_t v, int ctrl_n)
+{
+    switch (ctrl_n) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x111, 0xf, 0xf, false);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x112, 0xf, 0xf, false);
+    case 4: return (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x114, 0xf, 0xf, false);
+    default: return (uint32_t)__builtin_amdgcn_update_dpp((int)~0u, (int)v, 0x118, 0xf, 0xf, false);
+    }
+}
+
+__device__ inline void wave_min_scan(uint32_t v, uint32_t& incl, uint32_t& excl, uint32_t& total)
+{
+    const uint32_t lane = lane_id();
+    v = min(v, dpp_row_shr(v, 1));
+    v = min(v, dpp_row_shr(v, 2));
+    v = min(v, dpp_row_shr(v, 4));
+    v = min(v, dpp_row_shr(v, 8));
+    // v: inclusive minimum inside the row; the rows' totals
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = min(r0, (uint32_t)__builtin_amdgcn_readlane((int)v, 31));
+    const uint32_t r2 = min(r1, (uint32_t)__builtin_amdgcn_readlane((int)v, 47));
+    const uint32_t before = lane < 16 ? ~0u : lane < 32 ? r0 : lane < 48 ? r1 : r2;
+    incl = min(v, before);
+    total = min(r2, (uint32_t)__builtin_amdgcn_readlane((int)v, 63));
+    // exclusive: the row's shifted inclusive value, the earlier rows' total
+    // at a row's first lane
+    const uint32_t sh = dpp_row_shr(v, 1);
+    excl = (lane & 15u) == 0 ? before : min(sh, before);
 }
 
 // Exclusive workgroup sum of one value per thread (W waves); `total` gets
@@ -359,14 +417,15 @@ __device__ inline void ext_wave_reduce(ExtAcc& a)
     }
 }
 
-// Reduce over the workgroup; thread 0 gets the result.
+// Reduce over the workgroup (W waves); thread 0 gets the result.
+template <int W = kWaves>
 __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 {
     ext_wave_reduce(a);
     if (lane_id() == 0) sh[threadIdx.x / 64] = a;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kWaves; ++w) ext_combine(a, sh[w]);
+        for (int w = 1; w < W; ++w) ext_combine(a, sh[w]);
     }
 }
 
@@ -404,13 +463,13 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // are those of all points.  The last k_stream workgroup reduces them; k_cand
 // runs the exact region test on the open points only (a point counts for its region only if
 // it passed that region's frame), and filters again with a staircase over
-// chunks of kCandChunk records: per region and k1-slot of 2^14 values the smallest
+// chunks of kCandChunk records: per region and k1-slot (chunk_slot) the smallest
 // (k2, k1) in LDS; a record is dropped when the region's first point or a
 // record of an earlier slot has k2 <= its k2, or when its slot's smallest
 // record precedes it with k1 <= its k1.  The rest become sort records.
 // ---------------------------------------------------------------------------
 
-constexpr int kSampleBlocks = 16;
+constexpr int kSampleBlocks = 64;
 constexpr int kSamplePerThread = 32;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
 constexpr int kStairBits = 10;
@@ -418,7 +477,6 @@ constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
 constexpr int kStreamGrid = 1024;   // k_stream workgroups at most (the partials' room)
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
-constexpr int kCandChunk = 2048;    // records filtered together
 
 // Open-point record: X | Y << 23 | frame mask << 46.
 __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
@@ -428,101 +486,45 @@ __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
 
 // k_sample: workgroup b reads a run of kBlock * kSamplePerThread consecutive
 // points (coalesced), the runs evenly spaced (a smaller input is sampled with
-// repeats at evenly spaced indices), and writes its per-frame slot minima to
-// its row of samp.  The workgroup that finishes last (a counter, cleared
-// again by it) takes the minimum over the rows and builds the staircases:
-// per frame the exclusive prefix minimum over the slots.  Layout:
-// stair[2s], stair[2s+1] = R1 at x-slot s, R3 at its own slot of the same x;
-// stair[2S + 2s], stair[2S + 2s + 1] = R2 at y-slot s, R4 at its own slot of
-// the same y (S = kStairSlots), so that one 64-bit LDS read per coordinate
-// serves two frames.  It also clears the call's counters in the header.
+// repeats at evenly spaced indices), takes its per-frame slot minima in LDS
+// and merges them into the call's table stab by atomic maxima of their
+// complements (so that zero, the cleared state, stands for an empty slot).
+// Table layout: frame f's slots at [f*S, (f+1)*S), S = kStairSlots; R1 by
+// x-slot, R2 by y-slot, R3 by (M-x)-slot, R4 by (M-y)-slot.  k_cand clears
+// the table again once k_stream has read it.
 __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts, uint32_t n,
-                                                   uint32_t* __restrict__ samp, uint32_t* __restrict__ stair,
-                                                   DevHeader* __restrict__ hdr, uint32_t* __restrict__ ctr)
+                                                   uint32_t* __restrict__ stab, const int32_t* __restrict__ gate)
 {
     __shared__ __align__(16) uint32_t st[4 * kStairSlots];
-    __shared__ uint32_t s_last;
-    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t tid = threadIdx.x;
+    if (gated_off(gate)) return;
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
     __syncthreads();
     constexpr uint32_t kRun = kBlock * kSamplePerThread;
     const bool runs = n >= kSamplePts;
     const uint32_t start = runs ? (uint32_t)(((u64)blockIdx.x * (n - kRun)) / (kSampleBlocks - 1)) : 0u;
-    constexpr int kBatch = 8;  // points loaded together per thread
-    for (int k0 = 0; k0 < kSamplePerThread; k0 += kBatch) {
-        uint32_t X[kBatch], Y[kBatch];
+    uint32_t X[kSamplePerThread], Y[kSamplePerThread];  // every point load of a thread in flight together
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k0 + k;
-            const uint32_t i = runs ? start + (k0 + k) * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
-            const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
-            // out-of-domain values only need to stay in range here: such a
-            // call fails with a domain error
-            X[k] = coord_u32(p.x) & kM;
-            Y[k] = coord_u32(p.y) & kM;
-        }
+    for (int k = 0; k < kSamplePerThread; ++k) {
+        const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
+        const uint32_t i = runs ? start + k * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
+        const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
+        // out-of-domain values only need to stay in range here: such a call
+        // fails with a domain error
+        X[k] = coord_u32(p.x) & kM;
+        Y[k] = coord_u32(p.y) & kM;
+    }
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
-            atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
-            atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
-            atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
-            atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
-        }
+    for (int k = 0; k < kSamplePerThread; ++k) {
+        const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
+        atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
+        atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
+        atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
+        atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
     }
     __syncthreads();
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock) st_dev(samp + blockIdx.x * 4 * kStairSlots + e, st[e]);
-    stores_done();
-    __syncthreads();
-    if (tid == 0) {
-        const uint32_t a = arrive(ctr);
-        s_last = a == (uint32_t)gridDim.x - 1 ? 1u : 0u;
-        if (s_last) st_dev(ctr, 0u);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    // thread t: slots 16t .. 16t+15 of all frames, so wave f owns frame f
-    constexpr int kPer = 4 * kStairSlots / kBlock;  // 16
-    static_assert(kPer * 64 == kStairSlots && kPer % 4 == 0, "one wave per frame");
-    uint32_t m[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) m[k] = ~0u;
-    last_arrival_acquire();
-#pragma unroll 4
-    for (int b = 0; b < kSampleBlocks; ++b) {
-        const v4u* row = reinterpret_cast<const v4u*>(samp + b * 4 * kStairSlots + tid * kPer);
-#pragma unroll
-        for (int k = 0; k < kPer / 4; ++k) {
-            const v4u v = row[k];
-            m[4 * k] = min(m[4 * k], v.x);
-            m[4 * k + 1] = min(m[4 * k + 1], v.y);
-            m[4 * k + 2] = min(m[4 * k + 2], v.z);
-            m[4 * k + 3] = min(m[4 * k + 3], v.w);
-        }
-    }
-    uint32_t lo = ~0u;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) lo = min(lo, m[k]);
-    const uint32_t incl = wave_incl_min(lo);
-    uint32_t excl = __shfl_up(incl, 1);
-    if (lane == 0) excl = ~0u;
-    const uint32_t q = tid / 64, S = kStairSlots;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const uint32_t sl = lane * kPer + k;
-        const uint32_t at = q == 0 ? 2 * sl : q == 1 ? 2 * S + 2 * sl : q == 2 ? 2 * (S - 1 - sl) + 1 : 2 * S + 2 * (S - 1 - sl) + 1;
-        stair[at] = excl;
-        excl = min(excl, m[k]);
-    }
-    if (tid < 4) hdr->s1[tid] = 0;
-    if (tid == 0) {
-        hdr->open = 0;
-        hdr->cand = 0;
-        hdr->err = 0;
-        hdr->wide_ticket = 0;
-        hdr->fin_fail = 0;
-        hdr->epoch = hdr->epoch + 1;
-    }
+    for (int e = tid; e < 4 * kStairSlots; e += kBlock)
+        if (st[e] != ~0u) atomicMax(stab + e, ~st[e]);
 }
 
 // The quadrilateral: extreme points, edges and frames, from the reduced
@@ -573,57 +575,29 @@ __device__ inline void make_quad(ExtAcc r, Quad& Q)
     Q.err = r.bad ? kErrDomain : 0u;
 }
 
-// The last k_stream workgroup to finish reduces the per-workgroup extreme
-// partials (a few tens of KB) and publishes the quadrilateral in the header.
-// Thread t holds partials t, t + kBlock, ... (nparts <= kStreamGrid); the
-// loads are issued first (load_partials) so that other set-up can run while
-// they are in flight.
-constexpr int kPartPer = kStreamGrid / kBlock;
-
-__device__ inline void load_partials(const ExtPartial* __restrict__ part, int nparts, ExtPartial (&p)[kPartPer])
-{
-#pragma unroll
-    for (int u = 0; u < kPartPer; ++u) p[u] = part[min(u * kBlock + (int)threadIdx.x, nparts - 1)];  // (reduce_quad skips the repeats)
-}
-
-__device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, DevHeader* __restrict__ hdr,
-                                   Quad& Q, ExtAcc* sh, bool publish)
+// The quadrilateral from k_stream's per-workgroup extreme partials (a few
+// tens of KB): thread t of a workgroup of W waves takes partial t (nparts
+// <= 64 W); every thread returns with it in *sq.
+template <int W>
+__device__ inline void quad_from_partials(const ExtPartial* __restrict__ part, uint32_t nparts, ExtAcc* sh,
+                                          Quad* sq)
 {
     ExtAcc r;
     ext_init(r);
+    if (threadIdx.x < nparts) {
+        const ExtPartial p = part[threadIdx.x];
 #pragma unroll
-    for (int u = 0; u < kPartPer; ++u) {
-        if (u * kBlock + (int)threadIdx.x >= nparts) continue;
-        ExtAcc o;
         for (int e = 0; e < 2; ++e) {
-            o.kmin[e] = p[u].kmin[e];
-            o.kmax[e] = p[u].kmax[e];
-            o.imin[e] = p[u].imin[e];
-            o.imax[e] = p[u].imax[e];
+            r.kmin[e] = p.kmin[e];
+            r.kmax[e] = p.kmax[e];
+            r.imin[e] = p.imin[e];
+            r.imax[e] = p.imax[e];
         }
-        o.bad = p[u].err != 0;
-        o.hi = 0;
-        ext_combine(r, o);
+        r.bad = p.err != 0;
     }
-    ext_block_reduce(r, sh);
-    __shared__ Quad sq;
-    if (threadIdx.x == 0) {
-        make_quad(r, sq);
-        if (publish) {
-            for (int e = 0; e < 4; ++e) {
-                hdr->ext_x[e] = sq.X[e];
-                hdr->ext_y[e] = sq.Y[e];
-                hdr->ext_idx[e] = sq.idx[e];
-                hdr->ex[e] = sq.ex[e];
-                hdr->ey[e] = sq.ey[e];
-                hdr->ec[e] = sq.ec[e];
-                hdr->sigma[e] = sq.sigma[e];
-            }
-            if (sq.err) atomicOr(&hdr->err, sq.err);
-        }
-    }
+    ext_block_reduce<W>(r, sh);
+    if (threadIdx.x == 0) make_quad(r, *sq);
     __syncthreads();
-    Q = sq;
 }
 
 // `head` leading points (0 or 1) are visited singly so that the rest of the
@@ -635,16 +609,17 @@ __device__ inline void reduce_quad(const ExtPartial (&p)[kPartPer], int nparts, 
 // loads in flight per thread).
 template <int kStreamUnroll>
 __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
-                                                   const uint32_t* __restrict__ stair, ExtPartial* __restrict__ part,
+                                                   const uint32_t* __restrict__ stab, ExtPartial* __restrict__ part,
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
                                                    uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount,
-                                                   DevHeader* __restrict__ hdr, uint32_t* __restrict__ sctr)
+                                                   const int32_t* __restrict__ gate)
 {
+    if (gated_off(gate)) return;
     __shared__ __align__(16) uint32_t sst[4 * kStairSlots];
     __shared__ uint32_t lidx[kWaves][kWaveList];
     __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
-    __shared__ uint32_t s_fill, s_last;
+    __shared__ uint32_t s_fill;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     const u64 lt = (1ull << lane) - 1ull;
 
@@ -652,9 +627,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     // round of kBlock*kStreamUnroll at a time.  Every lane runs the same
     // number of rounds (the list append is wave-wide); lanes past the range
     // reread the last float4, which changes nothing and lists nothing.  The
-    // staircase loads go first and the first round's point loads right after
-    // them, so that the wait for the staircase (loads complete in issue
-    // order) leaves the point loads in flight while it is staged.
+    // sample table's loads go first and the first round's point loads right
+    // after them, so that the wait for the table (loads complete in issue
+    // order) leaves the point loads in flight while the staircases are built.
     const v4f* p4 = reinterpret_cast<const v4f*>(pts + 2 * head);
     const uint32_t n4 = (n - head) / 2;
     constexpr uint32_t kRound = kBlock * kStreamUnroll;
@@ -665,22 +640,42 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         for (int u = 0; u < kStreamUnroll; ++u)
             v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
     };
-    constexpr int kStairPer = 4 * kStairSlots / 4 / kBlock;  // uint4 loads per thread
-    static_assert(kStairPer * 4 * kBlock == 4 * kStairSlots, "staircase staging");
-    v4u sv[kStairPer];
+    // wave f holds frame f, lane l its slots l, l + 64, ..., l + 960
+    // (coalesced loads; consecutive lanes write neighbouring LDS words)
+    constexpr int kPer = kStairSlots / 64;  // 16
+    static_assert(4 * 64 == kBlock, "one wave per frame");
+    uint32_t sv[kPer];
 #pragma unroll
-    for (int k = 0; k < kStairPer; ++k) sv[k] = reinterpret_cast<const v4u*>(stair)[k * kBlock + tid];
+    for (int k = 0; k < kPer; ++k) sv[k] = stab[wave * kStairSlots + k * 64 + lane];
     v4f va[kStreamUnroll];
     {
-        // unconditional, so that no branch joins before the staircase wait (a
-        // workgroup without points reads the staircase's first bytes instead)
-        const v4f* src = rounds ? p4 : reinterpret_cast<const v4f*>(stair);
+        // unconditional, so that no branch joins before the table wait (a
+        // workgroup without points reads the table's first bytes instead)
+        const v4f* src = rounds ? p4 : reinterpret_cast<const v4f*>(stab);
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u)
             va[u] = __builtin_nontemporal_load(src + (rounds ? min(lo + u * kBlock + tid, n4 - 1) : 0u));
     }
+    {
+        // The staircases: per frame the exclusive prefix minimum of the slot
+        // minima (the table holds their complements; zero: no sample).  LDS
+        // layout: sst[2s], sst[2s+1] = R1 at x-slot s, R3 at its own slot of
+        // the same x; sst[2S + 2s], sst[2S + 2s + 1] = R2 at y-slot s, R4 at
+        // its own slot of the same y (S = kStairSlots), so that one 64-bit
+        // LDS read per coordinate serves two frames.
+        const uint32_t q = wave, S = kStairSlots;
+        uint32_t carry = ~0u;  // over the earlier rows of 64 slots
 #pragma unroll
-    for (int k = 0; k < kStairPer; ++k) reinterpret_cast<v4u*>(sst)[k * kBlock + tid] = sv[k];
+        for (int k = 0; k < kPer; ++k) {
+            uint32_t incl, excl, tot;
+            wave_min_scan(~sv[k], incl, excl, tot);
+            excl = min(excl, carry);
+            carry = min(carry, tot);
+            const uint32_t sl = k * 64 + lane;
+            const uint32_t at = q == 0 ? 2 * sl : q == 1 ? 2 * S + 2 * sl : q == 2 ? 2 * (S - 1 - sl) + 1 : 2 * S + 2 * (S - 1 - sl) + 1;
+            sst[at] = excl;
+        }
+    }
     if (tid == 0) s_fill = 0;
     __syncthreads();
     uint32_t* const my_idx = open_idx + (size_t)blockIdx.x * region;
@@ -695,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     auto flush = [&]() {
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(&s_fill, wcount);
-        base = __shfl(base, 0);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);  // (every lane is active here)
         __builtin_amdgcn_wave_barrier();
         for (uint32_t e = lane; e < wcount; e += 64) {
             const uint32_t i = lidx[wave][e];
@@ -788,44 +783,8 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             p.imax[e] = a.imax[e];
         }
         p.err = (a.bad || a.hi > kM) ? 1u : 0u;
-        // (device-scope stores: the last workgroup reads them)
-        st_dev(wgcount + blockIdx.x, s_fill);
-        u64* const pw = reinterpret_cast<u64*>(part + blockIdx.x);
-        static_assert(sizeof(ExtPartial) == 8 * sizeof(u64), "ExtPartial is eight words");
-        const u64* const pv = reinterpret_cast<const u64*>(&p);
-        for (int k = 0; k < 8; ++k) st_dev(pw + k, pv[k]);
-        stores_done();
-        // arrival: counters per group of 32 workgroups, then one over the
-        // groups (same-address atomics from many workgroups serialise); the
-        // last arrival of a group clears its counter, the last overall the top
-        const uint32_t g = blockIdx.x / 32, gsize = min(32u, gridDim.x - g * 32);
-        bool last = false;
-        if (arrive(&sctr[1 + g]) == gsize - 1) {
-            st_dev(&sctr[1 + g], 0u);
-            if (arrive(&sctr[0]) == (gridDim.x + 31) / 32 - 1) {
-                st_dev(&sctr[0], 0u);
-                last = true;
-            }
-        }
-        s_last = last ? 1u : 0u;
+        part[blockIdx.x] = p;  // (k_cand reduces the partials)
     }
-    __syncthreads();
-    if (!s_last) return;
-    // the last workgroup: the quadrilateral and the number of open points
-    last_arrival_acquire();
-    ExtPartial pp[kPartPer];
-    load_partials(part, (int)gridDim.x, pp);
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kStreamGrid / kBlock; ++k) {
-        const uint32_t b = min(k * kBlock + tid, gridDim.x - 1);  // (all loads issued together)
-        const uint32_t v = wgcount[b];
-        c += k * kBlock + tid < gridDim.x ? v : 0u;
-    }
-    Quad Q;
-    reduce_quad(pp, (int)gridDim.x, hdr, Q, sh, true);
-    c = wave_sum(c);
-    if (lane == 0 && c) atomicAdd(&hdr->open, c);
 }
 
 // Region (0..3, or 4 for none) of a point by the exact test: every product is
@@ -869,6 +828,20 @@ constexpr int kBucketsPadded = kBuckets + kBuckets / 32;
 //   pass 2  the counts' exclusive prefix sum: the row;
 //   pass 3  the records again from part A, each to part B (key[1], val[1])
 //           at its bucket's next position.
+// One workgroup of 16 waves per CU (its LDS holds the histogram, the slot
+// minima and the list starts): four waves per SIMD to hide the latency of
+// the record loads and the region test.
+constexpr int kCandBlock = 1024;
+constexpr int kCandWaves = kCandBlock / 64;
+constexpr int kCandChunk = 4096;                              // records filtered together
+constexpr int kCandPer = kCandChunk / kCandBlock;             // 4 per thread
+constexpr int kCandBucketsPer = kBuckets / kCandBlock;        // buckets per thread in pass 2
+static_assert(kCandBlock >= kStreamGrid, "one list per thread");
+// LDS position of bucket b in the histogram: thread t reads buckets
+// 8t .. 8t+7 in pass 2, so one pad word per 8 puts a read step's lanes in
+// distinct banks
+__device__ inline uint32_t cpad(uint32_t b) { return b + (b >> 3); }
+constexpr int kBucketsCPadded = kBuckets + kBuckets / 8;
 constexpr int kCandMaxRows = 256;  // rows of the bucket table (k_cand workgroups) at most
 
 // Rows of the bucket table for a call: one per cand_per_row open points (a
@@ -884,79 +857,98 @@ __device__ inline uint32_t cand_rows(uint32_t open, uint32_t grid, uint32_t per_
     return (grid + lists - 1) / lists;
 }
 
-// The quadrilateral from the header (published by k_stream).
-__device__ inline void quad_from_header(const DevHeader* __restrict__ hdr, Quad& Q)
-{
-    for (int q = 0; q < 4; ++q) {
-        Q.ex[q] = hdr->ex[q];
-        Q.ey[q] = hdr->ey[q];
-        Q.ec[q] = hdr->ec[q];
-        Q.sigma[q] = hdr->sigma[q];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ hdr,
-                                                 const uint32_t* __restrict__ open_idx,
-                                                 const u64* __restrict__ open_xym, uint32_t region,
-                                                 const uint32_t* __restrict__ wgcount, uint32_t grid,
-                                                 uint32_t per_row, uint32_t* __restrict__ key_a, u64* __restrict__ val_a,
-                                                 uint32_t* __restrict__ key_b, u64* __restrict__ val_b,
-                                                 uint32_t* __restrict__ rowoff, uint32_t* __restrict__ rowmin)
+__global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr, uint32_t* __restrict__ stab,
+                                                     const ExtPartial* __restrict__ parts,
+                                                     const uint32_t* __restrict__ open_idx,
+                                                     const u64* __restrict__ open_xym, uint32_t region,
+                                                     const uint32_t* __restrict__ wgcount, uint32_t grid,
+                                                     uint32_t per_row, uint32_t* __restrict__ key_a,
+                                                     u64* __restrict__ val_a, uint32_t* __restrict__ key_b,
+                                                     u64* __restrict__ val_b, uint32_t* __restrict__ rowoff,
+                                                     uint32_t* __restrict__ rowmin, const int32_t* __restrict__ gate)
 {
     __shared__ u64 smin[4 * kSlots];
     __shared__ uint32_t sexc[4 * kSlots];
-    __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t lcnt[kBucketsPadded];  // per bucket (at bpad): counts, then next positions
-    __shared__ uint32_t lmin[kBuckets];        // smallest k2 per bucket
+    __shared__ uint32_t scratch[kCandWaves];
+    __shared__ uint32_t lcnt[kBucketsCPadded];  // per bucket (at cpad): counts, then next positions
+    __shared__ uint32_t lmin[kBuckets];         // smallest k2 per bucket
     __shared__ uint32_t s_start[kStreamGrid + 1];  // the lists' first positions in the concatenation
+    __shared__ ExtAcc s_ext[kCandWaves];
+    __shared__ Quad s_q;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    if (hdr->err) return;
+    if (gated_off(gate)) return;
+    // every workgroup: the open count and the quadrilateral, from k_stream's
+    // per-workgroup counts and extreme partials (thread t: workgroup t)
+    const uint32_t mine = tid < grid ? wgcount[tid] : 0u;
+    quad_from_partials<kCandWaves>(parts, grid, s_ext, &s_q);
+    uint32_t open;
+    (void)block_excl_sum<kCandWaves>(mine, scratch, open);
+    if (blockIdx.x == 0) {
+        // k_stream has read the sample table: cleared for the next call
+        for (int e = tid; e < 4 * kStairSlots; e += kCandBlock) stab[e] = 0;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        // the call's header: the quadrilateral and the open count for the
+        // later steps, the call's counters cleared, the call counter advanced
+        for (int q = 0; q < 4; ++q) {
+            hdr->ext_x[q] = s_q.X[q];
+            hdr->ext_y[q] = s_q.Y[q];
+            hdr->ext_idx[q] = s_q.idx[q];
+            hdr->ex[q] = s_q.ex[q];
+            hdr->ey[q] = s_q.ey[q];
+            hdr->ec[q] = s_q.ec[q];
+            hdr->sigma[q] = s_q.sigma[q];
+            hdr->s1[q] = 0;
+        }
+        hdr->err = s_q.err;
+        hdr->open = open;
+        hdr->cand = 0;
+        hdr->wide_ticket = 0;
+        hdr->fin_fail = 0;
+        hdr->epoch = hdr->epoch + 1;
+    }
+    if (s_q.err) return;
     uint32_t lists;
-    const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
+    const uint32_t rows = cand_rows(open, grid, per_row, lists);
     if (blockIdx.x >= rows) return;
     Quad Q;
-    quad_from_header(hdr, Q);
-    for (int b = tid; b < kBuckets; b += kBlock) {
-        lcnt[bpad(b)] = 0;
+    uint32_t kfirst[4];  // k1 of each region's first point: the smallest of the region
+    for (int q = 0; q < 4; ++q) {
+        Q.ex[q] = s_q.ex[q];
+        Q.ey[q] = s_q.ey[q];
+        Q.ec[q] = s_q.ec[q];
+        Q.sigma[q] = s_q.sigma[q];
+        uint32_t k2;
+        to_frame((uint32_t)q, s_q.X[q], s_q.Y[q], kfirst[q], k2);
+    }
+    for (int b = tid; b < kBuckets; b += kCandBlock) {
+        lcnt[cpad(b)] = 0;
         lmin[b] = ~0u;
     }
-    // the workgroup's lists, concatenated (thread t: lists 4t .. 4t+3)
+    // the workgroup's lists, concatenated (thread t: list t)
     const uint32_t first = blockIdx.x * lists, nl = min(lists, grid - first);
     {
-        uint32_t c[4], sum = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t l = 4 * tid + k;
-            c[k] = l < nl ? wgcount[first + l] : 0u;
-            sum += c[k];
-        }
+        const uint32_t c = tid < nl ? wgcount[first + tid] : 0u;
         uint32_t total;
-        uint32_t run = block_excl_sum(sum, scratch, total);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t l = 4 * tid + k;
-            if (l < nl) s_start[l] = run;
-            run += c[k];
-        }
+        const uint32_t run = block_excl_sum<kCandWaves>(c, scratch, total);
+        if (tid < nl) s_start[tid] = run;
         if (tid == 0) s_start[nl] = total;
     }
-    static_assert(4 * kBlock >= kStreamGrid, "four lists per thread");
     __syncthreads();
     const uint32_t count = s_start[nl];
     const size_t part = (size_t)first * region;
     uint32_t* const my_ka = key_a + part;
     u64* const my_va = val_a + part;
     uint32_t written = 0;
-    constexpr int kPer = kCandChunk / kBlock;
 
     // ---- pass 1 ----
     for (uint32_t c0 = 0; c0 < count; c0 += kCandChunk) {
-        for (int e = tid; e < 4 * kSlots; e += kBlock) smin[e] = ~0ull;
+        for (int e = tid; e < 4 * kSlots; e += kCandBlock) smin[e] = ~0ull;
         __syncthreads();
-        uint32_t k1s[kPer], k2s[kPer], idxs[kPer], addrs[kPer];
+        uint32_t k1s[kCandPer], k2s[kCandPer], idxs[kCandPer], addrs[kCandPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t e = c0 + k * kBlock + tid;
+        for (int k = 0; k < kCandPer; ++k) {
+            const uint32_t e = c0 + k * kCandBlock + tid;
             addrs[k] = ~0u;
             if (e < count) {
                 // the list holding e: the last with start <= e
@@ -974,22 +966,23 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
                     k1s[k] = k1;
                     k2s[k] = k2;
                     idxs[k] = ix;
-                    addrs[k] = (q << kSlotBits) | (k1 >> (23 - kSlotBits));
+                    const uint32_t kf = q == 0 ? kfirst[0] : q == 1 ? kfirst[1] : q == 2 ? kfirst[2] : kfirst[3];
+                    addrs[k] = q * kSlots + chunk_slot(k1 - kf);
                     atomicMin(&smin[addrs[k]], ((u64)k2 << 23) | k1);
                 }
             }
         }
         __syncthreads();
-        // Wave w scans region w's slots: sexc becomes the smallest k2 over
-        // earlier slots and the region's first point.
-        {
+        // Wave w < 4 scans region w's slots: sexc becomes the smallest k2
+        // over earlier slots and the region's first point.
+        if (wave < 4) {
             const uint32_t q = wave;
             constexpr int per = kSlots / 64;
             uint32_t v[per];
             uint32_t run = ~0u;
 #pragma unroll
             for (int k = 0; k < per; ++k) {
-                const u64 m = smin[(q << kSlotBits) + lane * per + k];
+                const u64 m = smin[q * kSlots + lane * per + k];
                 v[k] = m == ~0ull ? ~0u : (uint32_t)(m >> 23);
                 run = min(run, v[k]);
             }
@@ -1000,14 +993,14 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
             before = min(before, sigma);
 #pragma unroll
             for (int k = 0; k < per; ++k) {
-                sexc[(q << kSlotBits) + lane * per + k] = before;
+                sexc[q * kSlots + lane * per + k] = before;
                 before = min(before, v[k]);
             }
         }
         __syncthreads();
         uint32_t keep = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
+        for (int k = 0; k < kCandPer; ++k) {
             if (addrs[k] != ~0u) {
                 const u64 me = ((u64)k2s[k] << 23) | k1s[k];
                 const u64 best = smin[addrs[k]];
@@ -1017,16 +1010,16 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
             }
         }
         uint32_t total;
-        uint32_t pos = written + block_excl_sum(__popc(keep), scratch, total);
+        uint32_t pos = written + block_excl_sum<kCandWaves>(__popc(keep), scratch, total);
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
+        for (int k = 0; k < kCandPer; ++k) {
             if ((keep >> k) & 1u) {
-                const uint32_t q = addrs[k] >> kSlotBits;
+                const uint32_t q = addrs[k] / kSlots;
                 my_ka[pos] = (q << 23) | k1s[k];
                 my_va[pos] = ((u64)k2s[k] << 32) | idxs[k];
                 ++pos;
                 const uint32_t b = (q << kBucketBits) | (k1s[k] >> kLowBits);
-                atomicAdd(&lcnt[bpad(b)], 1u);
+                atomicAdd(&lcnt[cpad(b)], 1u);
                 atomicMin(&lmin[b], k2s[k]);
             }
         }
@@ -1034,28 +1027,28 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
         __syncthreads();
     }
 
-    // ---- pass 2: the row (thread t owns buckets 32t .. 32t+31) ----
+    // ---- pass 2: the row (thread t owns buckets 8t .. 8t+7) ----
     __syncthreads();  // (the counts' set-up, when there was no chunk)
     uint32_t* const my_off = rowoff + (size_t)blockIdx.x * (kBuckets + 1);
     {
-        uint32_t c[kPerThreadBuckets], sum = 0;
+        uint32_t c[kCandBucketsPer], sum = 0;
 #pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) {
-            c[k] = lcnt[bpad(tid * kPerThreadBuckets + k)];
+        for (int k = 0; k < kCandBucketsPer; ++k) {
+            c[k] = lcnt[cpad(tid * kCandBucketsPer + k)];
             sum += c[k];
         }
         uint32_t total;
-        uint32_t run = block_excl_sum(sum, scratch, total);  // (its barriers follow every read above)
+        uint32_t run = block_excl_sum<kCandWaves>(sum, scratch, total);  // (its barriers follow every read above)
 #pragma unroll
-        for (int k = 0; k < kPerThreadBuckets; ++k) {
-            lcnt[bpad(tid * kPerThreadBuckets + k)] = run;
+        for (int k = 0; k < kCandBucketsPer; ++k) {
+            lcnt[cpad(tid * kCandBucketsPer + k)] = run;
             run += c[k];
         }
         if (tid == 0) my_off[kBuckets] = total;
     }
     __syncthreads();
-    for (int b = tid; b < kBuckets; b += kBlock) {
-        my_off[b] = lcnt[bpad(b)];
+    for (int b = tid; b < kBuckets; b += kCandBlock) {
+        my_off[b] = lcnt[cpad(b)];
         rowmin[(size_t)blockIdx.x * kBuckets + b] = lmin[b];
     }
 
@@ -1063,12 +1056,12 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
     __syncthreads();  // (a workgroup-scope fence and barrier: part A's stores, before other threads read them)
     uint32_t* const my_kb = key_b + part;
     u64* const my_vb = val_b + part;
-    for (uint32_t i0 = 0; i0 < written; i0 += 4 * kBlock) {
+    for (uint32_t i0 = 0; i0 < written; i0 += 4 * kCandBlock) {
         uint32_t kk[4];
         u64 vv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + u * kBlock + tid;
+            const uint32_t i = i0 + u * kCandBlock + tid;
             kk[u] = i < written ? my_ka[i] : ~0u;
             vv[u] = i < written ? my_va[i] : 0ull;
         }
@@ -1076,7 +1069,7 @@ __global__ __launch_bounds__(kBlock) void k_cand(const DevHeader* __restrict__ h
         for (int u = 0; u < 4; ++u) {
             if (kk[u] == ~0u) continue;
             const uint32_t b = ((kk[u] >> 23) << kBucketBits) | ((kk[u] & kM) >> kLowBits);
-            const uint32_t p = atomicAdd(&lcnt[bpad(b)], 1u);
+            const uint32_t p = atomicAdd(&lcnt[cpad(b)], 1u);
             my_kb[p] = kk[u];
             my_vb[p] = vv[u];
         }
@@ -1150,26 +1143,23 @@ __global__ __launch_bounds__(kBlock) void k_count_regions(const float* __restric
 // a region has 2048 buckets); wave w sums rows w, w+4, ... of them, one
 // bucket per lane.  Per bucket: its size and smallest k2 over the rows;
 // then, inside the workgroup, the exclusive prefix sum of the sizes
-// (lstart) and exclusive prefix minimum of the smallest k2 (lthr).  The
-// workgroup that finishes last (a counter, cleared again by it) combines the
-// workgroups' totals: the first record of workgroup j's buckets (wgbase) and
-// the threshold entering them (wgthr, seeded with the region's first
-// point).  A bucket's first record is then lstart + wgbase, its threshold
-// min(lthr, wgthr).
+// (lstart) and exclusive prefix minimum of the smallest k2 (lthr), and the
+// workgroup's totals (wtot, wmin).  k_bucket_spa combines the totals of the
+// earlier workgroups itself: a bucket's first record is lstart plus the
+// records of the earlier workgroups, its threshold the minimum of lthr, the
+// earlier workgroups' of its region and the region's first point.
 constexpr int kScanBuckets = 64;                    // buckets per k_scan workgroup
 constexpr int kScanGrid = kBuckets / kScanBuckets;  // 128
 constexpr int kScanPerRegion = kScanGrid / 4;       // 32
-static_assert(kScanGrid <= 2 * 64 && kScanPerRegion == 32, "the last workgroup's combine: two waves, half a wave per region");
+static_assert(kScanGrid == 2 * 64, "k_bucket_spa's combine: two workgroup totals per lane");
 
 __global__ __launch_bounds__(kBlock) void k_scan(DevHeader* __restrict__ hdr, const uint32_t* __restrict__ rowoff,
                                                  const uint32_t* __restrict__ rowmin, uint32_t grid,
-                                                 uint32_t per_row, Buckets bk)
+                                                 uint32_t per_row, Buckets bk, const int32_t* __restrict__ gate)
 {
     __shared__ uint32_t s_c[kWaves][64], s_m[kWaves][64];
-    __shared__ uint32_t scratch[kWaves];
-    __shared__ uint32_t s_last;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    if (hdr->err) return;
+    if (gated_off(gate) || hdr->err) return;
     uint32_t lists;
     const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
     const uint32_t b = blockIdx.x * kScanBuckets + lane;
@@ -1204,6 +1194,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevHeader* __restrict__ hdr, co
             m = min(m, s_m[w][lane]);
         }
         bk.cnt[b] = c;
+        bk.bmin[b] = m;
         const uint32_t incl = wave_incl_sum(c);
         bk.lstart[b] = incl - c;
         const uint32_t mincl = wave_incl_min(m);
@@ -1212,53 +1203,26 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevHeader* __restrict__ hdr, co
         bk.lthr[b] = mexcl;
         const uint32_t tot = __shfl(incl, 63), mtot = __shfl(mincl, 63);
         if (lane == 0) {
-            // the workgroup's totals, then its arrival
-            st_dev(bk.wtot + blockIdx.x, tot);
-            st_dev(bk.wmin + blockIdx.x, mtot);
-            stores_done();
-            const uint32_t a = arrive(bk.ctr);
-            s_last = a == (uint32_t)gridDim.x - 1 ? 1u : 0u;
-            if (s_last) st_dev(bk.ctr, 0u);
+            bk.wtot[blockIdx.x] = tot;
+            bk.wmin[blockIdx.x] = mtot;
         }
     }
-    __syncthreads();
-    if (!s_last) return;
-    // the last workgroup: thread j < kScanGrid combines workgroup j
-    last_arrival_acquire();
-    const uint32_t j = tid;
-    const uint32_t t = j < (uint32_t)kScanGrid ? bk.wtot[j] : 0u;
-    const uint32_t mj = j < (uint32_t)kScanGrid ? bk.wmin[j] : ~0u;
-    uint32_t total;
-    const uint32_t base = block_excl_sum(t, scratch, total);
-    // exclusive prefix minimum over the earlier workgroups of the region
-    // (32 workgroups: half a wave), seeded with the region's first point
-    const uint32_t half = lane & 32u, q = (j / kScanPerRegion) & 3u;
-    uint32_t before = hdr->sigma[q];
-    for (uint32_t k = 0; k < 32; ++k) {  // (uniform: every lane takes part in the shuffle)
-        const uint32_t v = (uint32_t)__shfl(mj, (int)(half + k));
-        if (k < (lane & 31u)) before = min(before, v);
-    }
-    if (j < (uint32_t)kScanGrid) {
-        bk.wgbase[j] = base;
-        bk.wgthr[j] = before;
-    }
-    if (j == 0) hdr->cand = total;
 }
 
-// Workgroup g takes buckets 4g .. 4g+3.  A bucket's records are gathered
-// from the rows' parts (row w: part B of k_cand workgroup w, positions
-// [rowoff[w][b], rowoff[w][b+1]); each lane holds up to four rows).  A bucket of at most 64 records is
-// resolved by one wave without the table: lane l holds record l, which SPA
-// keeps iff its k2 is below the threshold and no record of the bucket
-// precedes it in (k1, k2, index) order with k2 <= its k2; its rank in the
-// chain is the number of kept records with a smaller k1 (kept records have
-// distinct k1).  Larger buckets use the table, the whole workgroup on one
-// bucket at a time.  Survivors go, as (index, x, y), to dev_chain at the
-// bucket's first record position (also written to bk.off); their number to
-// bk.surv.
-constexpr int kPerThreadLow = kLowSize / kBlock;  // 16
+// Workgroup g takes buckets 4g .. 4g+3, wave w bucket 4g + w.  A bucket
+// whose smallest k2 is not below the threshold entering it keeps nothing.
+// Otherwise its records are gathered from the rows' parts (row r: part B of
+// k_cand workgroup r, positions [rowoff[r][b], rowoff[r][b+1]); each lane
+// holds up to four rows).  A bucket of at most kWaveBucket records is
+// sorted and filtered by its wave alone (wave_spa); larger ones use the
+// table, the whole workgroup on one bucket at a time.  Survivors go, as
+// (index, x, y), to dev_chain at the bucket's first record position (also
+// written to bk.off); their number to bk.surv.
+constexpr int kSpaHalves = 1;                      // tables per large bucket (parts of its k1 range)
+constexpr int kSpaTab = kLowSize / kSpaHalves;     // 4096 entries
+constexpr int kPerThreadTab = kSpaTab / kBlock;    // 16
 constexpr int kBucketsPerSpa = kWaves;
-constexpr uint32_t kWaveBucket = 64;
+constexpr uint32_t kWaveBucket = 512;  // records of a bucket one wave sorts (eight per lane)
 
 __device__ inline PolyRec chain_rec(uint32_t q, uint32_t k1, uint32_t k2, uint32_t idx)
 {
@@ -1270,20 +1234,133 @@ __device__ inline PolyRec chain_rec(uint32_t q, uint32_t k1, uint32_t k2, uint32
     return PolyRec{(int32_t)idx, (int32_t)X, (int32_t)Y};
 }
 
+// Sorts the 64*PER (key, index) pairs that one wave holds, element
+// e = lane*PER + s, ascending by key, then index: a bitonic network, with
+// shuffles across lanes (partner distance j >= PER) and register swaps inside
+// a lane (j < PER).
+template <int PER>
+__device__ inline void bitonic_in_lane(u64 (&key)[PER], uint32_t (&ix)[PER], uint32_t lane, uint32_t k)
+{
+#pragma unroll
+    for (int j = PER / 2; j > 0; j >>= 1) {
+        if ((uint32_t)j >= k) continue;
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const int t = s ^ j;
+            if (t <= s) continue;
+            const uint32_t e = lane * PER + s;
+            const bool t_less = key[t] < key[s] || (key[t] == key[s] && ix[t] < ix[s]);
+            const bool s_less = key[s] < key[t] || (key[s] == key[t] && ix[s] < ix[t]);
+            if ((e & k) == 0 ? t_less : s_less) {
+                const u64 tk = key[s];
+                key[s] = key[t];
+                key[t] = tk;
+                const uint32_t ti = ix[s];
+                ix[s] = ix[t];
+                ix[t] = ti;
+            }
+        }
+    }
+}
+
+template <int PER>
+__device__ inline void wave_bitonic(u64 (&key)[PER], uint32_t (&ix)[PER])
+{
+    const uint32_t lane = lane_id();
+    for (uint32_t k = 2; k <= 64u * PER; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= (uint32_t)PER; j >>= 1) {
+            // partner e ^ j: lane ^ (j / PER), same register
+            const int d = (int)(j / PER);
+#pragma unroll
+            for (int s = 0; s < PER; ++s) {
+                const uint32_t e = lane * PER + s;
+                const u64 pk = __shfl_xor(key[s], d);
+                const uint32_t pi = __shfl_xor(ix[s], d);
+                const bool less = key[s] < pk || (key[s] == pk && ix[s] < pi);
+                // an ascending pair's lower element keeps the smaller pair,
+                // its upper one the larger; descending the reverse
+                if (less != (((e & k) == 0) == ((e & j) == 0))) {
+                    key[s] = pk;
+                    ix[s] = pi;
+                }
+            }
+        }
+        bitonic_in_lane<PER>(key, ix, lane, k);
+    }
+}
+
+// SPA of one bucket of m <= 64*PER records by one wave: the records,
+// gathered from the rows' parts (seg, pre: the bucket's first position in
+// each row's part and the records before each row), sorted by (k1, k2,
+// index); a record is kept iff its k2 is below the threshold entering the
+// bucket and below every earlier record's k2 (so of a run of equal (k1, k2)
+// at most the first, the smallest index).  Survivors go, in order, to
+// dev_chain at off; their number to surv[b].
+template <int PER>
+__device__ inline void wave_spa(uint32_t m, uint32_t b, uint32_t off, uint32_t thr,
+                                const uint32_t* __restrict__ key, const u64* __restrict__ val, size_t part,
+                                const uint32_t* seg, const uint32_t* pre, uint32_t rows,
+                                PolyRec* __restrict__ dev_chain, uint32_t* __restrict__ surv)
+{
+    const uint32_t lane = lane_id();
+    u64 kk[PER];  // k1 << 23 | k2
+    uint32_t ix[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t i = lane * PER + s;
+        kk[s] = ~0ull;
+        ix[s] = ~0u;
+        if (i < m) {
+            // the row holding record i: the last with pre <= i
+            uint32_t r = 0;
+            for (uint32_t st = kCandMaxRows / 2; st > 0; st >>= 1)
+                if (r + st < rows && pre[r + st] <= i) r += st;
+            const size_t at = (size_t)r * part + seg[r] + (i - pre[r]);
+            const u64 v = val[at];
+            kk[s] = ((u64)(key[at] & kM) << 23) | (v >> 32);
+            ix[s] = (uint32_t)v;
+        }
+    }
+    wave_bitonic<PER>(kk, ix);
+    uint32_t low = ~0u;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) low = min(low, kk[s] != ~0ull ? (uint32_t)kk[s] & kM : ~0u);
+    const uint32_t incl = wave_incl_min(low);
+    uint32_t run = __shfl_up(incl, 1);
+    if (lane == 0) run = ~0u;
+    run = min(run, thr);
+    uint32_t keep = 0;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t k2 = (uint32_t)kk[s] & kM;
+        if (kk[s] != ~0ull && k2 < run) keep |= 1u << s;
+        if (kk[s] != ~0ull) run = min(run, k2);
+    }
+    const uint32_t cnt = (uint32_t)__popc(keep);
+    const uint32_t sum = wave_incl_sum(cnt);
+    uint32_t pos = off + sum - cnt;
+    const uint32_t q = b >> kBucketBits;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        if ((keep >> s) & 1u) dev_chain[pos++] = chain_rec(q, (uint32_t)(kk[s] >> 23), (uint32_t)kk[s] & kM, ix[s]);
+    }
+    if (lane == 63) surv[b] = sum;
+}
+
 __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restrict__ key,
                                                        const u64* __restrict__ val, uint32_t region, uint32_t grid,
                                                        uint32_t per_row, const uint32_t* __restrict__ rowoff,
-                                                       const DevHeader* __restrict__ hdr, Buckets bk,
-                                                       PolyRec* __restrict__ dev_chain)
+                                                       DevHeader* __restrict__ hdr, Buckets bk,
+                                                       PolyRec* __restrict__ dev_chain, const int32_t* __restrict__ gate)
 {
     constexpr int kRowsPerLane = kCandMaxRows / 64;
-    __shared__ u64 tab[kLowSize];
+    __shared__ u64 tab[kSpaTab];
     __shared__ uint32_t scratch[kWaves];
     __shared__ uint32_t s_m[kBucketsPerSpa], s_off[kBucketsPerSpa], s_thr[kBucketsPerSpa];
     // per bucket and row: first position in the row's part, records before the row
     __shared__ uint32_t s_seg[kBucketsPerSpa][kCandMaxRows], s_pre[kBucketsPerSpa][kCandMaxRows];
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
-    if (hdr->err) return;
+    if (gated_off(gate) || hdr->err) return;
     uint32_t lists;
     const uint32_t rows = cand_rows(hdr->open, grid, per_row, lists);
     const size_t part = (size_t)lists * region;  // records in one row's part
@@ -1295,9 +1372,21 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
         return r;
     };
     {
-        // wave w: bucket 4g + w.  Its segments (rows lane, lane + 64, ...),
-        // where it starts, its threshold
+        // wave w: bucket 4g + w: where it starts, its threshold, its
+        // segments (rows lane, lane + 64, ...; loaded with the rest, before
+        // the bucket is known to be live).  A bucket whose smallest k2 is not
+        // below the threshold entering it keeps nothing (every record is
+        // dominated by an earlier bucket's record or the region's first
+        // point).
         const uint32_t b = blockIdx.x * kBucketsPerSpa + wave;
+        // k_scan workgroup g holds the bucket; lane l combines the totals of
+        // workgroups l and l + 64: the records before g, the smallest k2 over
+        // the earlier workgroups of the region (q*32 .. g-1)
+        const uint32_t g = b / kScanBuckets, q = b >> kBucketBits;
+        const uint32_t t0 = bk.wtot[lane], t1 = bk.wtot[lane + 64];
+        const uint32_t m0 = bk.wmin[lane], m1 = bk.wmin[lane + 64];
+        const uint32_t ls = bk.lstart[b], lt = bk.lthr[b], bm = bk.bmin[b];
+        const uint32_t sigma = hdr->sigma[q];
         uint32_t lo[kRowsPerLane], n[kRowsPerLane];
 #pragma unroll
         for (int k = 0; k < kRowsPerLane; ++k) {
@@ -1309,109 +1398,112 @@ __global__ __launch_bounds__(kBlock) void k_bucket_spa(const uint32_t* __restric
                 n[k] = rowoff[(size_t)r * (kBuckets + 1) + b + 1] - lo[k];
             }
         }
-        uint32_t m = 0;
-#pragma unroll
-        for (int k = 0; k < kRowsPerLane; ++k) {
-            const uint32_t incl = wave_incl_sum(n[k]);
-            s_seg[wave][lane + 64 * k] = lo[k];
-            s_pre[wave][lane + 64 * k] = m + incl - n[k];
-            m += __shfl(incl, 63);
+        const uint32_t first = q * kScanPerRegion;
+        uint32_t before = (lane < g ? t0 : 0u) + (lane + 64 < g ? t1 : 0u);
+        uint32_t mprev = min((lane >= first && lane < g) ? m0 : ~0u, (lane + 64 >= first && lane + 64 < g) ? m1 : ~0u);
+        before = wave_sum(before);
+        mprev = wave_min(mprev);
+        if (blockIdx.x == 0 && wave == 0) {
+            const uint32_t all = wave_sum(t0 + t1);
+            if (lane == 0) hdr->cand = all;
         }
-        const uint32_t off = bk.lstart[b] + bk.wgbase[b / kScanBuckets];
-        const uint32_t thr = min(bk.lthr[b], bk.wgthr[b / kScanBuckets]);
+        const uint32_t off = ls + before;
+        const uint32_t thr = min(min(lt, mprev), sigma);
+        const bool live = bm < thr;
+        uint32_t m = 0;
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < kRowsPerLane; ++k) {
+                const uint32_t incl = wave_incl_sum(n[k]);
+                s_seg[wave][lane + 64 * k] = lo[k];
+                s_pre[wave][lane + 64 * k] = m + incl - n[k];
+                m += __shfl(incl, 63);
+            }
+        }
         if (lane == 0) {
             s_m[wave] = m;
             s_off[wave] = off;
             s_thr[wave] = thr;
             bk.off[b] = off;
+            if (!live) bk.surv[b] = 0;
         }
         __builtin_amdgcn_wave_barrier();
-        if (m <= kWaveBucket) {
-            uint32_t k1 = ~0u, k2 = ~0u, idx = ~0u;
-            if (lane < m) {
-                const uint32_t r = row_of(wave, lane);
-                const size_t at = (size_t)r * part + s_seg[wave][r] + (lane - s_pre[wave][r]);
-                k1 = key[at] & kM;
-                const u64 v = val[at];
-                k2 = (uint32_t)(v >> 32);
-                idx = (uint32_t)v;
-            }
-            bool kept = lane < m && k2 < thr;
-            // j is the same in every lane: lane j's values by readlane (no LDS
-            // round trip, unlike a general shuffle)
-            for (uint32_t j = 0; j < m; ++j) {
-                const uint32_t a1 = __builtin_amdgcn_readlane(k1, j), a2 = __builtin_amdgcn_readlane(k2, j),
-                               ai = __builtin_amdgcn_readlane(idx, j);
-                const bool prec = a1 < k1 || (a1 == k1 && (a2 < k2 || (a2 == k2 && ai < idx)));
-                if (prec && a2 <= k2) kept = false;
-            }
-            const u64 kb = __ballot(kept);
-            uint32_t rank = 0;
-            for (uint32_t j = 0; j < m; ++j) {
-                const uint32_t a1 = __builtin_amdgcn_readlane(k1, j);
-                if (((kb >> j) & 1ull) && a1 < k1) ++rank;
-            }
-            if (kept) dev_chain[off + rank] = chain_rec(b >> kBucketBits, k1, k2, idx);
-            if (lane == 0) bk.surv[b] = (uint32_t)__popcll(kb);
+        if (live && m <= kWaveBucket) {
+            const uint32_t* seg = s_seg[wave];
+            const uint32_t* pre = s_pre[wave];
+            if (m <= 64) wave_spa<1>(m, b, off, thr, key, val, part, seg, pre, rows, dev_chain, bk.surv);
+            else if (m <= 128) wave_spa<2>(m, b, off, thr, key, val, part, seg, pre, rows, dev_chain, bk.surv);
+            else if (m <= 256) wave_spa<4>(m, b, off, thr, key, val, part, seg, pre, rows, dev_chain, bk.surv);
+            else wave_spa<8>(m, b, off, thr, key, val, part, seg, pre, rows, dev_chain, bk.surv);
         }
     }
     __syncthreads();
     for (int kb = 0; kb < kBucketsPerSpa; ++kb) {
         const uint32_t b = blockIdx.x * kBucketsPerSpa + kb, m = s_m[kb];
         if (m <= kWaveBucket) continue;
-        const uint32_t off = s_off[kb], thr = s_thr[kb];
-        for (int e = tid; e < kLowSize; e += kBlock) tab[e] = ~0ull;
-        __syncthreads();
-        constexpr int kBatch = 8;  // records loaded together per thread
-        for (uint32_t i0 = 0; i0 < m; i0 += kBatch * kBlock) {
-            uint32_t k1[kBatch];
-            u64 v[kBatch];  // k2 << 32 | index
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const uint32_t i = i0 + u * kBlock + tid;
-                k1[u] = 0u;
-                v[u] = ~0ull;
-                if (i < m) {
-                    const uint32_t r = row_of(kb, i);
-                    const size_t at = (size_t)r * part + s_seg[kb][r] + (i - s_pre[kb][r]);
-                    k1[u] = key[at];
-                    v[u] = val[at];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u)
-                if (v[u] != ~0ull) atomicMin(&tab[k1[u] & (kLowSize - 1)], v[u]);
-        }
-        __syncthreads();
-        // exclusive prefix minimum of k2 over the table, seeded with the
-        // threshold entering the bucket; survivors in table order
-        u64 e[kPerThreadLow];
-        uint32_t lo = ~0u;
-#pragma unroll
-        for (int k = 0; k < kPerThreadLow; ++k) {
-            e[k] = tab[tid * kPerThreadLow + k];
-            lo = min(lo, (uint32_t)(e[k] >> 32));
-        }
-        uint32_t unused;
-        uint32_t run = min(thr, block_excl_min(lo, scratch, unused));
-        uint32_t keep = 0;
-#pragma unroll
-        for (int k = 0; k < kPerThreadLow; ++k) {
-            const uint32_t k2 = (uint32_t)(e[k] >> 32);
-            if (e[k] != ~0ull && k2 < run) keep |= 1u << k;
-            run = min(run, k2);
-        }
-        uint32_t total;
-        uint32_t pos = off + block_excl_sum(__popc(keep), scratch, total);
+        const uint32_t off = s_off[kb];
+        // the bucket's k1 range in kSpaHalves parts, one table each; the
+        // running minimum and the output position carry over
+        uint32_t run_in = s_thr[kb], pos_base = off;
         const uint32_t q = b >> kBucketBits;
         const uint32_t k1base = (b & ((1u << kBucketBits) - 1)) << kLowBits;
+        for (uint32_t h = 0; h < (uint32_t)kSpaHalves; ++h) {
+            for (int e = tid; e < kSpaTab; e += kBlock) tab[e] = ~0ull;
+            __syncthreads();
+            constexpr int kBatch = 8;  // records loaded together per thread
+            for (uint32_t i0 = 0; i0 < m; i0 += kBatch * kBlock) {
+                uint32_t k1[kBatch];
+                u64 v[kBatch];  // k2 << 32 | index
 #pragma unroll
-        for (int k = 0; k < kPerThreadLow; ++k) {
-            if ((keep >> k) & 1u)
-                dev_chain[pos++] = chain_rec(q, k1base + tid * kPerThreadLow + k, (uint32_t)(e[k] >> 32), (uint32_t)e[k]);
+                for (int u = 0; u < kBatch; ++u) {
+                    const uint32_t i = i0 + u * kBlock + tid;
+                    k1[u] = 0u;
+                    v[u] = ~0ull;
+                    if (i < m) {
+                        const uint32_t r = row_of(kb, i);
+                        const size_t at = (size_t)r * part + s_seg[kb][r] + (i - s_pre[kb][r]);
+                        k1[u] = key[at];
+                        v[u] = val[at];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const uint32_t low = k1[u] & (kLowSize - 1);
+                    if (v[u] != ~0ull && low / kSpaTab == h) atomicMin(&tab[low % kSpaTab], v[u]);
+                }
+            }
+            __syncthreads();
+            // exclusive prefix minimum of k2 over the table, seeded with the
+            // running minimum entering it; survivors in table order
+            u64 e[kPerThreadTab];
+            uint32_t lo = ~0u;
+#pragma unroll
+            for (int k = 0; k < kPerThreadTab; ++k) {
+                e[k] = tab[tid * kPerThreadTab + k];
+                lo = min(lo, (uint32_t)(e[k] >> 32));
+            }
+            uint32_t tmin;
+            uint32_t run = min(run_in, block_excl_min(lo, scratch, tmin));
+            uint32_t keep = 0;
+#pragma unroll
+            for (int k = 0; k < kPerThreadTab; ++k) {
+                const uint32_t k2 = (uint32_t)(e[k] >> 32);
+                if (e[k] != ~0ull && k2 < run) keep |= 1u << k;
+                run = min(run, k2);
+            }
+            uint32_t total;
+            uint32_t pos = pos_base + block_excl_sum(__popc(keep), scratch, total);
+#pragma unroll
+            for (int k = 0; k < kPerThreadTab; ++k) {
+                if ((keep >> k) & 1u)
+                    dev_chain[pos++] = chain_rec(q, k1base + h * kSpaTab + tid * kPerThreadTab + k,
+                                                 (uint32_t)(e[k] >> 32), (uint32_t)e[k]);
+            }
+            pos_base += total;
+            run_in = min(run_in, tmin);
+            __syncthreads();
         }
-        if (tid == 0) bk.surv[b] = total;
-        __syncthreads();
+        if (tid == 0) bk.surv[b] = pos_base - off;
     }
 }
 
@@ -1450,7 +1542,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                                                   PolyRec* __restrict__ host_chain, uint32_t host_cap,
                                                   PolyRec* __restrict__ spill, uint32_t* __restrict__ segcnt,
                                                   DevHeader* __restrict__ host_hdr, int prehull,
-                                                  PolyRec* __restrict__ dev_kept, uint32_t* __restrict__ dev_segcnt)
+                                                  PolyRec* __restrict__ dev_kept, uint32_t* __restrict__ dev_segcnt,
+                                                  const int32_t* __restrict__ gate)
 {
     __shared__ uint32_t pre[kBucketsPadded];  // chain points before each bucket (at bpad)
     __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
@@ -1459,6 +1552,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
     __shared__ uint32_t scratch[kWaves];
     __shared__ uint32_t s_removed[2], s_cnt[4];
     const uint32_t tid = threadIdx.x;
+    if (gated_off(gate)) return;
     // the header, for the host, once every field is final
     auto publish_header = [&]() {
         if (blockIdx.x != 0) return;
@@ -1736,7 +1830,6 @@ static_assert(kBatchSlots == 1 << (23 - kBatchSlotShift) && kBatchList <= 1 << k
 constexpr int kBatchChunks = 64, kBatchChunk = 128;                // the first staircase sample
 constexpr int kBatchRounds = 32;                                   // pre-hull rounds at most
 constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger sets: single-hull path
-constexpr int32_t kBatchRedo = INT32_MIN;
 static_assert(kBatchList >= 2 * (int)kBatchRoundMax, "a round must fit beside a compacted list");
 static_assert(kBatchCand / kBatchBlock <= 8 && kBatchPolyMax % kBatchBlock == 0, "per-thread shares");
 // LDS: [staircase u32 x 4S][raw slot minima u32 x 4S] [list u32 x
@@ -1995,7 +2088,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                                                             const int32_t* __restrict__ order,
                                                             int32_t* __restrict__ out_idx,
                                                             int32_t* __restrict__ out_counts, uint32_t pts_odd,
-                                                            int32_t num_sets)
+                                                            int32_t num_sets, int64_t single_n)
 {
     __shared__ __align__(16) unsigned char smem[kBatchLds];
     __shared__ u64 s_ek[kBatchWaves][4];
@@ -2014,7 +2107,8 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     // stream-ordered entry point cannot read them on the host)
     const int32_t set = order ? order[blockIdx.x] : (int32_t)blockIdx.x;
     if (set < 0 || set >= num_sets) return;
-    const int64_t base = offsets[set], end = offsets[set + 1];
+    // (without offsets: one set, points [0, single_n))
+    const int64_t base = offsets ? offsets[set] : 0, end = offsets ? offsets[set + 1] : single_n;
     if (base < 0 || end < base) {
         if (threadIdx.x == 0) out_counts[set] = CH_EINVAL;
         return;
@@ -2542,11 +2636,17 @@ __device__ inline Slope line_slope(const Line& l) { return Slope{(i64)l.b2 - (i6
 // The better of two candidates: the larger slope (want_max) or the smaller.
 __device__ inline Line line_better(const Line& x, const Line& y, bool want_max)
 {
-    if (!y.ok) return x;
-    if (!x.ok) return y;
     const bool y_less = slope_less(line_slope(y), line_slope(x));
     const bool x_less = slope_less(line_slope(x), line_slope(y));
-    return (want_max ? x_less : y_less) ? y : x;
+    const bool take_y = y.ok && (!x.ok || (want_max ? x_less : y_less));
+    // (field by field: a select of whole structs goes through scratch memory)
+    Line r;
+    r.a1 = take_y ? y.a1 : x.a1;
+    r.a2 = take_y ? y.a2 : x.a2;
+    r.b1 = take_y ? y.b1 : x.b1;
+    r.b2 = take_y ? y.b2 : x.b2;
+    r.ok = take_y ? y.ok : x.ok;
+    return r;
 }
 
 // Workgroup reduction of one candidate per thread; every thread gets the
@@ -2650,10 +2750,8 @@ __device__ inline void piece_of(const uint32_t* __restrict__ segcnt, uint32_t s,
                                 uint32_t& cnt)
 {
     const v4u c = reinterpret_cast<const v4u*>(segcnt)[s];
-    const uint32_t c4[4] = {c.x, c.y, c.z, c.w};
-    off = 0;
-    for (uint32_t k = 0; k < q; ++k) off += c4[k];
-    cnt = c4[q];
+    off = (q > 0 ? c.x : 0u) + (q > 1 ? c.y : 0u) + (q > 2 ? c.z : 0u);
+    cnt = q == 0 ? c.x : q == 1 ? c.y : q == 2 ? c.z : c.w;
 }
 
 __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restrict__ hdr,
@@ -2662,7 +2760,8 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
                                                             u64* __restrict__ states,
                                                             int32_t* __restrict__ out_idx,
                                                             int32_t* __restrict__ out_count,
-                                                            DevHeader* __restrict__ host_hdr)
+                                                            DevHeader* __restrict__ host_hdr,
+                                                            const int32_t* __restrict__ gate)
 {
     __shared__ uint32_t hk1[kSeg], hk2[kSeg];
     __shared__ int32_t hidx[kSeg];
@@ -2672,6 +2771,7 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
     __shared__ uint32_t scratch[kWideWaves];
     __shared__ uint32_t s_t, s_h, s_nl, s_bad, s_base, s_fail;
     const uint32_t tid = threadIdx.x;
+    if (gated_off(gate)) return;
     if (hdr->err) {
         // a failed step: the count is the call's status
         if (blockIdx.x == 0 && tid == 0) {
@@ -2774,11 +2874,11 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
                 to_frame(q, hdr->ext_x[q], hdr->ext_y[q], e1, e2);    // E_q: left of every point
                 to_frame(q, hdr->ext_x[qn], hdr->ext_y[qn], f1, f2);  // E_{q+1}: right of every point
                 const uint32_t lo_seg = R[q].first, hi_seg = R[q].first + R[q].nseg;  // [lo_seg, hi_seg)
-                Line best[2];
+                Line best_l = Line{0, 0, 0, 0, 0u}, best_r = Line{0, 0, 0, 0, 0u};
                 // the listed segments' points (slist[0 .. nl)) as candidates,
                 // all at once: per segment its place and count, their prefix
                 // sum, then every point by one thread, four loads in flight
-                auto eval_list = [&](uint32_t nl, bool left) -> Line {
+                auto eval_list = [&](uint32_t nl, bool left) __attribute__((always_inline)) -> Line {
                     for (uint32_t e = tid; e < nl; e += kWideBlock) {
                         uint32_t o, c;
                         piece_of(segcnt, slist[e], q, o, c);
@@ -2898,12 +2998,12 @@ __global__ __launch_bounds__(kWideBlock) void k_finish_wide(DevHeader* __restric
                         if (nl) cur = line_better(cur, eval_list(nl, left), left);
                         __syncthreads();
                     }
-                    if (left) best[0] = cur;
-                    else best[1] = cur;
+                    if (left) best_l = cur;
+                    else best_r = cur;
                 }
                 // strict vertices of the piece's hull, in order
-                const Slope sl = best[0].ok ? line_slope(best[0]) : Slope{-1, 0};
-                const Slope sr = best[1].ok ? line_slope(best[1]) : Slope{1, 0};
+                const Slope sl = best_l.ok ? line_slope(best_l) : Slope{-1, 0};
+                const Slope sr = best_r.ok ? line_slope(best_r) : Slope{1, 0};
                 for (uint32_t k0 = 0; k0 < h; k0 += kWideBlock) {
                     const uint32_t k = k0 + tid;
                     bool strict = false;
@@ -3113,6 +3213,12 @@ __global__ __launch_bounds__(kBlock) void k_spa_chunked(const uint32_t* __restri
 // The finished hull, from pinned host memory into the caller's buffers.  The
 // host rewrites that memory between calls, so it is read with system-scope
 // loads, which no stale cache line can serve.
+// p[0 .. n) = v.
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_put_result(const int32_t* host_hull, int32_t h,
                                                        int32_t* __restrict__ out_idx, int32_t* __restrict__ out_count)
 {
@@ -3140,12 +3246,10 @@ struct Workspace {
     char* dbuf = nullptr;
     DevHeader* hdr = nullptr;
     ExtPartial* part = nullptr;
-    uint32_t* samp = nullptr;
-    uint32_t* stair = nullptr;
+    uint32_t* stab = nullptr;       // the sample table (zero between calls)
     uint32_t* open_idx = nullptr;   // k_stream's per-workgroup lists
     u64* open_xym = nullptr;
     uint32_t* wgcount = nullptr;
-    uint32_t* sctr = nullptr;       // k_stream's arrival counters (zero between calls)
     uint32_t* rowoff = nullptr;     // k_cand's rows of the bucket table: first position per bucket
     uint32_t* rowmin = nullptr;     // and smallest k2 per bucket
     uint32_t* key[2] = {nullptr, nullptr};  // k_cand's parts: records in chunk order, by bucket
@@ -3197,7 +3301,7 @@ struct StreamShape {
 };
 
 // ---- launch shapes (ch_tuning), per size class ----
-constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18};
+constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18, 1 << 18};
 constexpr int kTuningClasses = 16;
 std::mutex g_tune_mu;
 int g_tune_count = 0;
@@ -3210,7 +3314,8 @@ bool tuning_valid(const ch_tuning& t)
     return grid && (t.stream_unroll == 2 || t.stream_unroll == 4) && t.cand_per_row >= 1024 &&
            t.cand_per_row <= (1 << 20) && t.chain_grid >= 64 && t.chain_grid <= 4096 &&
            t.wide_grid >= 64 && t.wide_grid <= 4096 && (t.batch_unroll == 1 || t.batch_unroll == 2) &&
-           (t.batch_order == 0 || t.batch_order == 1) && t.serve_batch_max >= 0 && t.serve_batch_max <= (1 << 22);
+           (t.batch_order == 0 || t.batch_order == 1) && t.serve_batch_max >= 0 && t.serve_batch_max <= (1 << 22) &&
+           t.fused_max >= 0 && t.fused_max <= (1 << 22);
 }
 
 // The shapes of a call with n points: the class with the smallest n_max >= n.
@@ -3269,25 +3374,21 @@ size_t layout(Workspace* w, char* base, size_t cap)
     };
     Workspace tmp;
     Workspace& W = w ? *w : tmp;
-    // zeroed at allocation: the header, the look-back states, the counters
+    // zeroed at allocation: the header, the look-back states, the sample table
     W.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     W.states = reinterpret_cast<u64*>(take(sizeof(u64) * (cap / kSeg + 16)));
-    W.sctr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (2 + kStreamGrid / 32)));  // [last]: k_sample's
-    W.bk.ctr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
+    W.stab = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
     W.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
     W.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.surv = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.lstart = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.lthr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
+    W.bk.bmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.wtot = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
     W.bk.wmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
-    W.bk.wgbase = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
-    W.bk.wgthr = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kScanGrid));
     W.rowoff = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kCandMaxRows * (kBuckets + 1)));
     W.rowmin = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kCandMaxRows * kBuckets));
-    W.samp = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots * kSampleBlocks));
-    W.stair = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
     W.wgcount = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStreamGrid));
     W.open_idx = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * rc));
     W.open_xym = reinterpret_cast<u64*>(take(sizeof(u64) * rc));
@@ -3349,9 +3450,9 @@ int ensure_device(Workspace& w, size_t n)
     w.dbuf = p;
     w.cap = cap;
     layout(&w, p, cap);
-    // the header's call counter, the look-back states and the arrival
-    // counters start at zero (they sit together at the start of the layout)
-    CH_TRY(hipMemsetAsync(w.hdr, 0, reinterpret_cast<char*>(w.bk.ctr + 64) - reinterpret_cast<char*>(w.hdr), w.stream));
+    // the header's call counter, the look-back states and the sample table
+    // start at zero (they sit together at the start of the layout)
+    CH_TRY(hipMemsetAsync(w.hdr, 0, reinterpret_cast<char*>(w.part) - reinterpret_cast<char*>(w.hdr), w.stream));
     return CH_OK;
 }
 
@@ -3453,32 +3554,62 @@ int record(Workspace& w, int k)
 // polygon for the host finish.  Timing events: 0 | k_sample | 1 | k_stream |
 // 2 | k_cand (+ k_count_regions) | 3 | k_scan | 4 | k_bucket_spa, k_chain |
 // 5 | k_finish_wide | 6.
+// Set for good once a call failed after k_sample and before k_cand (which
+// clears the sample table): from then on every call clears its table first.
+std::atomic<bool> g_stab_dirty{false};
+
 int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx,
-                      int32_t* fin_count)
+                      int32_t* fin_count, bool fused = false)
 {
     hipStream_t s = w.stream;
     const ch_tuning tu = tuning_for(n);
     CH_TRY(record(w, 0));
-    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.samp, w.stair, w.hdr,
-                                 w.sctr + 1 + kStreamGrid / 32));
+    // small inputs (fused, with a device finish): every step in one
+    // workgroup of the batched kernel; the kernels below do their work only
+    // if it leaves kBatchRedo in the count (gate)
+    const int32_t* gate = nullptr;
+    if (fused && fin_idx) {
+        const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
+        auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
+        CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
+                                     pts_odd, 1, (int64_t)n));
+        gate = fin_count;
+    }
+    if (g_stab_dirty.load(std::memory_order_relaxed)) {
+        // a call failed between k_sample and k_cand somewhere: clear this
+        // workspace's sample table before it is used (a fill kernel, not a
+        // memset, so that a capture records a kernel node)
+        CH_LAUNCH(hipLaunchKernelGGL(k_fill_u32, dim3(4 * kStairSlots / kBlock), dim3(kBlock), 0, s, w.stab, 0u,
+                                     (uint32_t)(4 * kStairSlots)));
+    }
+    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.stab, gate));
+    // from here until k_cand is queued, a failure leaves the table filled
+    struct StabGuard {
+        bool armed = true;
+        ~StabGuard()
+        {
+            if (armed) g_stab_dirty.store(true, std::memory_order_relaxed);
+        }
+    } guard;
     CH_TRY(record(w, 1));
     const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
     const StreamShape sh = stream_shape(n, head, (uint32_t)tu.stream_grid, (uint32_t)tu.stream_unroll);
     if (tu.stream_unroll == 2) {
-        CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
-                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, w.hdr, w.sctr));
+        CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
+                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
     } else {
-        CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stair, w.part,
-                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, w.hdr, w.sctr));
+        CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
+                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
     }
     CH_TRY(record(w, 2));
     // the rows of the bucket table follow the open count (k_stream's, on the
     // device): up to one k_cand workgroup per cand_per_row open points
     const uint32_t gc = std::min<uint32_t>(kCandMaxRows, sh.grid);
     const uint32_t per_row = (uint32_t)tu.cand_per_row;
-    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kBlock), 0, s, w.hdr, w.open_idx, w.open_xym, sh.region,
+    CH_LAUNCH(hipLaunchKernelGGL(k_cand, dim3(gc), dim3(kCandBlock), 0, s, w.hdr, w.stab, w.part, w.open_idx, w.open_xym, sh.region,
                                  w.wgcount, sh.grid, per_row, w.key[0], w.val[0], w.key[1], w.val[1], w.rowoff,
-                                 w.rowmin));
+                                 w.rowmin, gate));
+    guard.armed = false;
     if (stats) {
         const uint32_t gr = std::max<uint32_t>(1u, std::min<uint32_t>(256u, (n + kBlock * 8 - 1) / (kBlock * 8)));
         CH_LAUNCH(hipLaunchKernelGGL(k_count_regions, dim3(gr), dim3(kBlock), 0, s, pts, n, w.hdr));
@@ -3487,25 +3618,71 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
     // the bucket table's columns -> bucket sizes, starts and thresholds;
     // then SPA per bucket, its records gathered from the rows' parts
     CH_LAUNCH(hipLaunchKernelGGL(k_scan, dim3(kScanGrid), dim3(kBlock), 0, s, w.hdr, w.rowoff, w.rowmin, sh.grid,
-                                 per_row, w.bk));
+                                 per_row, w.bk, gate));
     CH_TRY(record(w, 4));
     CH_LAUNCH(hipLaunchKernelGGL(k_bucket_spa, dim3(kBuckets / kBucketsPerSpa), dim3(kBlock), 0, s, w.key[1],
-                                 w.val[1], sh.region, sh.grid, per_row, w.rowoff, w.hdr, w.bk, w.dev_chain));
+                                 w.val[1], sh.region, sh.grid, per_row, w.rowoff, w.hdr, w.bk, w.dev_chain, gate));
     // hull2d (fin_idx) leaves the host chain buffer alone: its host finish
     // reads k_gather's polygon
     const uint32_t gch = (uint32_t)std::min<size_t>((size_t)tu.chain_grid, (n + kSeg - 1) / kSeg);
     CH_LAUNCH(hipLaunchKernelGGL(k_chain, dim3(gch), dim3(kBlock), 0, s, w.dev_chain, w.hdr, w.bk,
                                  fin_idx ? nullptr : w.h_chain_dev, (uint32_t)w.h_chain_cap, w.dev_spill,
                                  fin_idx ? nullptr : w.h_segcnt_dev, w.h_hdr_dev, stats ? 0 : 1, w.dev_kept,
-                                 w.dev_segcnt));
+                                 w.dev_segcnt, gate));
     CH_TRY(record(w, 5));
     if (fin_idx) {
-        CH_LAUNCH(hipLaunchKernelGGL(k_finish_wide, dim3((uint32_t)tu.wide_grid), dim3(kWideBlock), 0, s, w.hdr,
-                                     w.dev_segcnt,
-                                     w.dev_kept, w.states, fin_idx, fin_count, w.h_hdr_dev));
+        // items: four extreme points and at most one piece per segment and
+        // region (each region adds at most one segment boundary)
+        const size_t items = 7 + ((size_t)n + kSeg - 1) / kSeg;
+        const uint32_t gw = (uint32_t)std::min<size_t>((size_t)tu.wide_grid, items);
+        CH_LAUNCH(hipLaunchKernelGGL(k_finish_wide, dim3(gw), dim3(kWideBlock), 0, s, w.hdr, w.dev_segcnt,
+                                     w.dev_kept, w.states, fin_idx, fin_count, w.h_hdr_dev, gate));
     }
     CH_TRY(record(w, 6));
     return CH_OK;
+}
+
+// The small-input path of hull2d: the batched kernel on the one set,
+// waited for; *count receives its count (the hull size, a negative status,
+// or kBatchRedo for a set it leaves to the single-hull path).  Timing
+// events 0 and 5 bracket it (the whole hull), 6 follows at once.
+int run_fused(Workspace& w, const float* pts, uint32_t n, int32_t* out_idx, int32_t* out_count, int32_t* count)
+{
+    const ch_tuning tu = tuning_for(n);
+    CH_TRY(record(w, 0));
+    const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
+    auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
+    CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, w.stream, pts, nullptr, nullptr, out_idx,
+                                 out_count, pts_odd, 1, (int64_t)n));
+    CH_TRY(record(w, 5));
+    CH_TRY(record(w, 6));
+    CH_TRY(hipMemcpyAsync(&w.h_hdr->fin_hull, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, w.stream));
+    CH_TRY(hipStreamSynchronize(w.stream));
+    *count = w.h_hdr->fin_hull;
+    return CH_OK;
+}
+
+// Statistics of a hull the small-input path computed: the stage counts are
+// not kept (-1), the timing spans are the batched kernel's.
+void fill_fused_stats(const Workspace& w, int64_t n, int32_t hull, ch_stats* st)
+{
+    std::memset(st, 0, sizeof(*st));
+    st->n = n;
+    for (int e = 0; e < 4; ++e) {
+        st->ext_idx[e] = -1;
+        st->s1[e] = -1;
+        st->s2[e] = -1;
+    }
+    st->open = -1;
+    st->candidates = -1;
+    st->polygon = -1;
+    st->hull = hull;
+    st->device_finish = 1;
+    st->fused = 1;
+    if (g_timing && w.events) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, w.ev[0], w.ev[5]) == hipSuccess) st->ms_pre = ms;
+    }
 }
 
 int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
@@ -3667,6 +3844,20 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
     }
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0, false));
+    if (n <= (int64_t)tuning_for(n).fused_max) {
+        // small input: every step in one workgroup of the batched kernel;
+        // only a set it leaves (kBatchRedo) takes the single-hull path below
+        int32_t c = 0;
+        CH_TRY(run_fused(*w, points, (uint32_t)n, out_idx, out_count, &c));
+        if (c != kBatchRedo) {
+            if (c < 0) {
+                (void)hipMemsetAsync(out_count, 0, sizeof(int32_t), stream);
+                return c == CH_EDOMAIN ? CH_EDOMAIN : CH_EHIP;
+            }
+            fill_fused_stats(*w, n, c, &st);
+            return CH_OK;
+        }
+    }
     rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
     if (rc == CH_OK && w->h_hdr->fin_done && !w->h_hdr->fin_fail) {
         // finished on the device: the hull is in out_idx / out_count
@@ -3770,7 +3961,8 @@ int hull2d_async(const float* points, int64_t n, int32_t* out_idx, int32_t* out_
     CH_TRY(ensure_device(*w, (size_t)n));
     CH_TRY(ensure_host(*w, 0, false));
     if (cs == hipStreamCaptureStatusActive) w->captured = true;
-    return launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
+    const bool fused = n <= (int64_t)tuning_for(n).fused_max;
+    return launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count, fused);
 }
 
 int hull2d_noalloc(const float* points, int64_t n, int32_t* out_idx, int32_t* out_count, void* stream)
@@ -3800,7 +3992,8 @@ int hull2d_noalloc(const float* points, int64_t n, int32_t* out_idx, int32_t* ou
     // states among them, sits at the same place in every call)
     const size_t used = layout(&w, base, (size_t)CH_NOALLOC_MAX_POINTS);
     w.h_hdr_dev = reinterpret_cast<DevHeader*>(base + used);
-    return launch_preprocess(w, points, (uint32_t)n, false, out_idx, out_count);
+    const bool fused = n <= (int64_t)tuning_for(n).fused_max;
+    return launch_preprocess(w, points, (uint32_t)n, false, out_idx, out_count, fused);
 }
 
 int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets, int32_t* out_idx,
@@ -3874,7 +4067,8 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
             const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(points) >> 3) & 1u);
             auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
             CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
-                                         w->b_offsets, w->b_order, out_idx, out_counts, pts_odd, num_sets));
+                                         w->b_offsets, w->b_order, out_idx, out_counts, pts_odd, num_sets,
+                                         (int64_t)0));
             CH_TRY(record(*w, 1));
             CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
         }
@@ -3923,7 +4117,7 @@ int hull2d_batched_async(const float* points, const int64_t* offsets, const int3
     auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
     CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)num_sets), dim3(kBatchBlock), 0,
                                  reinterpret_cast<hipStream_t>(stream), points, offsets, order, out_idx, out_counts,
-                                 pts_odd, num_sets));
+                                 pts_odd, num_sets, (int64_t)0));
     return CH_OK;
 }
 

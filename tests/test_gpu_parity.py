@@ -5,6 +5,7 @@ points, round-1 survivor counts, SPA survivor counts and the simple polygon)
 must match the step-by-step model exactly.  Each case prints its name before
 its GPU call.
 """
+import contextlib
 import ctypes
 import sys
 
@@ -18,6 +19,7 @@ torch = pytest.importorskip("torch")
 import paper_1508_05488_amd as ch  # noqa: E402
 from oracle import hull as oracle  # noqa: E402
 from oracle import steps  # noqa: E402
+from paper_1508_05488_amd import autotune  # noqa: E402
 from paper_1508_05488_amd import workloads as wl  # noqa: E402
 from hullcheck import polygon_with_extras  # noqa: E402
 
@@ -26,9 +28,30 @@ def say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+@contextlib.contextmanager
+def single_hull_kernels_only():
+    """No call takes the small-input path (fused_max 0)."""
+    base = ch.get_tuning(-1)
+    ch.clear_tuning()
+    ch.set_tuning(2**40, autotune.shape(base, fused_max=0))
+    try:
+        yield
+    finally:
+        ch.clear_tuning()
+        ch.load_tuning()
+
+
 def gpu_hull(pts, name=""):
+    # both paths of a small input: the batched kernel's one workgroup (the
+    # default at these sizes) and the single-hull kernels
     say(f"  hull2d {name} n={pts.shape[0]}")
-    return ch.hull2d(torch.from_numpy(np.ascontiguousarray(pts)).cuda()).cpu().numpy()
+    d = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    got = ch.hull2d(d).cpu().numpy()
+    say(f"  hull2d {name}: single-hull kernels")
+    with single_hull_kernels_only():
+        alt = ch.hull2d(d).cpu().numpy()
+    assert np.array_equal(got, alt), f"{name}: the two paths differ"
+    return got
 
 
 def assert_parity(pts, name=""):
@@ -113,6 +136,10 @@ def test_domain_errors(bad):
     with pytest.raises(ch.ChainHullError) as e:
         ch.hull2d(torch.from_numpy(pts).cuda())
     assert e.value.status == ch.CH_EDOMAIN
+    say(f"  hull2d bad value {bad}: single-hull kernels")
+    with single_hull_kernels_only(), pytest.raises(ch.ChainHullError) as e:
+        ch.hull2d(torch.from_numpy(pts).cuda())
+    assert e.value.status == ch.CH_EDOMAIN
     # the stream stays usable
     assert_parity(wl.generate("square", 1000, seed=67), "after error")
 
@@ -186,8 +213,9 @@ def test_timing_stats():
     ch.set_timing(True)
     try:
         say("  hull2d timing")
-        ch.hull2d(pts)
-        st = ch.last_stats()
+        with single_hull_kernels_only():
+            ch.hull2d(pts)
+            st = ch.last_stats()
     finally:
         ch.set_timing(False)
     assert st["n"] == 200_000 and st["hull"] > 2
