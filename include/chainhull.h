@@ -332,6 +332,12 @@ typedef struct {
                                 0: never); the single-hull kernels then run only
                                 for an input it leaves (queued behind it and
                                 returning at once otherwise) */
+    int32_t list_max;        /* hull2d, hull2d_async, hull2d_noalloc: when the pass
+                                over the points leaves at most this many open
+                                points (0 .. 8192; 0: never), one workgroup of the
+                                batched kernel takes every later step from its
+                                lists; the later single-hull kernels then return at
+                                once (decided on the device) */
 } ch_tuning;
 
 /* Use *t for calls whose point count (for hull2d_batched: total points) is

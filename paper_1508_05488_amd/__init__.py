@@ -119,6 +119,7 @@ class ChTuning(ctypes.Structure):
         ("batch_order", ctypes.c_int32),
         ("serve_batch_max", ctypes.c_int32),
         ("fused_max", ctypes.c_int32),
+        ("list_max", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

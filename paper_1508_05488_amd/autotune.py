@@ -101,7 +101,7 @@ def tune_single(torch, dev, timer, quick: bool, log) -> list:
         cnt = torch.empty(1, dtype=torch.int32, device=dev)
         # the default shape's hulls: every candidate must reproduce them
         ch.clear_tuning()
-        ch.set_tuning(2**40, shape(default, fused_max=0))
+        ch.set_tuning(2**40, shape(default, fused_max=0, list_max=0))
         ref = {}
         for d, x in inputs.items():
             assert ch.hull2d_async(x, out, cnt) == ch.CH_OK
@@ -113,7 +113,7 @@ def tune_single(torch, dev, timer, quick: bool, log) -> list:
         flush = n * 8 < 512 << 20
         rows = []
         for cand in candidates(quick):
-            t = shape(default, **cand, fused_max=0)  # (the single-hull kernels themselves)
+            t = shape(default, **cand, fused_max=0, list_max=0)  # (the single-hull kernels themselves)
             ch.clear_tuning()
             ch.set_tuning(n_max, t)
             ms, ok = {}, True

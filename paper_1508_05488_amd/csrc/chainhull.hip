@@ -875,6 +875,7 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
     __shared__ uint32_t s_start[kStreamGrid + 1];  // the lists' first positions in the concatenation
     __shared__ ExtAcc s_ext[kCandWaves];
     __shared__ Quad s_q;
+    __shared__ uint32_t s_base;
     const uint32_t tid = threadIdx.x, wave = tid / 64, lane = lane_id();
     if (gated_off(gate)) return;
     // every workgroup: the open count and the quadrilateral, from k_stream's
@@ -882,7 +883,7 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
     const uint32_t mine = tid < grid ? wgcount[tid] : 0u;
     quad_from_partials<kCandWaves>(parts, grid, s_ext, &s_q);
     uint32_t open;
-    (void)block_excl_sum<kCandWaves>(mine, scratch, open);
+    const uint32_t gpre = block_excl_sum<kCandWaves>(mine, scratch, open);  // open points of lists < tid
     if (blockIdx.x == 0) {
         // k_stream has read the sample table: cleared for the next call
         for (int e = tid; e < 4 * kStairSlots; e += kCandBlock) stab[e] = 0;
@@ -925,27 +926,28 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
         lcnt[cpad(b)] = 0;
         lmin[b] = ~0u;
     }
-    // the workgroup's lists, concatenated (thread t: list t)
+    // the workgroup's lists, concatenated: their starts from the prefix over
+    // all lists (thread t: list t)
     const uint32_t first = blockIdx.x * lists, nl = min(lists, grid - first);
-    {
-        const uint32_t c = tid < nl ? wgcount[first + tid] : 0u;
-        uint32_t total;
-        const uint32_t run = block_excl_sum<kCandWaves>(c, scratch, total);
-        if (tid < nl) s_start[tid] = run;
-        if (tid == 0) s_start[nl] = total;
-    }
+    if (tid == first) s_base = gpre;
+    __syncthreads();
+    if (tid >= first && tid < first + nl) s_start[tid - first] = gpre - s_base;
+    if (tid == first + nl - 1) s_start[nl] = gpre + mine - s_base;
     __syncthreads();
     const uint32_t count = s_start[nl];
     const size_t part = (size_t)first * region;
     uint32_t* const my_ka = key_a + part;
     u64* const my_va = val_a + part;
-    uint32_t written = 0;
+    uint32_t written = 0;  // records of the chunks before the last, in part A
 
-    // ---- pass 1 ----
+    // ---- pass 1 (the last chunk's records stay in registers) ----
+    uint32_t lk[kCandPer], keep = 0;  // the last chunk's kept records: q << 23 | k1, k2 << 32 | index
+    u64 lv[kCandPer];
     for (uint32_t c0 = 0; c0 < count; c0 += kCandChunk) {
+        uint32_t k1s[kCandPer], k2s[kCandPer], idxs[kCandPer], addrs[kCandPer];
+        const bool last = c0 + kCandChunk >= count;
         for (int e = tid; e < 4 * kSlots; e += kCandBlock) smin[e] = ~0ull;
         __syncthreads();
-        uint32_t k1s[kCandPer], k2s[kCandPer], idxs[kCandPer], addrs[kCandPer];
 #pragma unroll
         for (int k = 0; k < kCandPer; ++k) {
             const uint32_t e = c0 + k * kCandBlock + tid;
@@ -998,7 +1000,7 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
             }
         }
         __syncthreads();
-        uint32_t keep = 0;
+        keep = 0;
 #pragma unroll
         for (int k = 0; k < kCandPer; ++k) {
             if (addrs[k] != ~0u) {
@@ -1009,19 +1011,23 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
                 if (ok) keep |= 1u << k;
             }
         }
-        uint32_t total;
-        uint32_t pos = written + block_excl_sum<kCandWaves>(__popc(keep), scratch, total);
+        uint32_t pos = written, total = 0;
+        if (!last) pos += block_excl_sum<kCandWaves>(__popc(keep), scratch, total);
 #pragma unroll
         for (int k = 0; k < kCandPer; ++k) {
             if ((keep >> k) & 1u) {
                 const uint32_t q = addrs[k] / kSlots;
-                my_ka[pos] = (q << 23) | k1s[k];
-                my_va[pos] = ((u64)k2s[k] << 32) | idxs[k];
-                ++pos;
+                if (!last) {
+                    my_ka[pos] = (q << 23) | k1s[k];
+                    my_va[pos] = ((u64)k2s[k] << 32) | idxs[k];
+                    ++pos;
+                }
                 const uint32_t b = (q << kBucketBits) | (k1s[k] >> kLowBits);
                 atomicAdd(&lcnt[cpad(b)], 1u);
                 atomicMin(&lmin[b], k2s[k]);
             }
+            lk[k] = ((addrs[k] / kSlots) << 23) | k1s[k];
+            lv[k] = ((u64)k2s[k] << 32) | idxs[k];
         }
         written += total;
         __syncthreads();
@@ -1052,10 +1058,20 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
         rowmin[(size_t)blockIdx.x * kBuckets + b] = lmin[b];
     }
 
-    // ---- pass 3: part A -> part B by bucket ----
+    // ---- pass 3: the last chunk's records from registers, the earlier
+    // ones from part A, each to part B at its bucket's next position ----
     __syncthreads();  // (a workgroup-scope fence and barrier: part A's stores, before other threads read them)
     uint32_t* const my_kb = key_b + part;
     u64* const my_vb = val_b + part;
+#pragma unroll
+    for (int k = 0; k < kCandPer; ++k) {
+        if ((keep >> k) & 1u) {
+            const uint32_t b = ((lk[k] >> 23) << kBucketBits) | ((lk[k] & kM) >> kLowBits);
+            const uint32_t p = atomicAdd(&lcnt[cpad(b)], 1u);
+            my_kb[p] = lk[k];
+            my_vb[p] = lv[k];
+        }
+    }
     for (uint32_t i0 = 0; i0 < written; i0 += 4 * kCandBlock) {
         uint32_t kk[4];
         u64 vv[4];
@@ -2082,13 +2098,26 @@ __device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, 
     return (int)*s_start;
 }
 
-template <int kBatchUnroll>
+// The open lists of one k_stream call, for k_batch_hull's list mode: the
+// lists (index per open point, region points apart), their counts, the
+// per-workgroup extreme partials, and the pinned header the host reads.
+struct ListSrc {
+    const uint32_t* idx;
+    const uint32_t* wgcount;
+    const ExtPartial* parts;
+    DevHeader* host_hdr;
+    uint32_t* stab;  // the sample table, cleared here (k_cand, which also clears it, may not run)
+    uint32_t region, nlists;
+    uint32_t cap;    // open points the list mode takes at most (<= kBatchList)
+};
+
+template <int kBatchUnroll, bool kFromLists = false>
 __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(const float* __restrict__ pts,
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ order,
                                                             int32_t* __restrict__ out_idx,
                                                             int32_t* __restrict__ out_counts, uint32_t pts_odd,
-                                                            int32_t num_sets, int64_t single_n)
+                                                            int32_t num_sets, int64_t single_n, ListSrc src)
 {
     __shared__ __align__(16) unsigned char smem[kBatchLds];
     __shared__ u64 s_ek[kBatchWaves][4];
@@ -2113,7 +2142,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         if (threadIdx.x == 0) out_counts[set] = CH_EINVAL;
         return;
     }
-    if (end - base > kBatchMaxSet) {
+    if (!kFromLists && end - base > kBatchMaxSet) {  // (list mode reads only the open points)
         if (threadIdx.x == 0) out_counts[set] = kBatchRedo;
         return;
     }
@@ -2125,42 +2154,6 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         return;
     }
     constexpr uint32_t S = kStairSlots;
-
-    // ---- the first staircase, from a sample of runs of consecutive points ----
-    for (uint32_t e = tid; e < 4 * S; e += kBatchBlock) raw[e] = ~0u;
-    if (tid == 0) s_n = 0;
-    __syncthreads();
-    auto lower = [&](uint32_t x, uint32_t y) {  // x, y in [0, M]
-        atomicMin(&raw[0 * S + (x >> kStairShift)], y);         // R1: (x, y)
-        atomicMin(&raw[1 * S + (y >> kStairShift)], x ^ kM);    // R2: (y, M-x)
-        atomicMin(&raw[2 * S + ((x ^ kM) >> kStairShift)], y ^ kM);  // R3: (M-x, M-y)
-        atomicMin(&raw[3 * S + ((y ^ kM) >> kStairShift)], x);  // R4: (M-y, x)
-    };
-    if (m > (2u * kBatchUnroll * kBatchBlock)) {
-        constexpr uint32_t kThreads = kBatchBlock / kBatchChunks, kPer = kBatchChunk / kThreads;
-        const uint32_t c = tid / kThreads, sub = tid % kThreads;
-        const uint32_t start = (uint32_t)(((u64)c * (m - kBatchChunk)) / (kBatchChunks - 1));
-        v2f v[kPer];
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) v[k] = p2[start + k * kThreads + sub];
-        // out-of-domain values only need to stay in range here: such a set
-        // fails with a domain error
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) lower(coord_u32(v[k].x) & kM, coord_u32(v[k].y) & kM);
-    }
-    __syncthreads();
-    batch_stair(raw, sst, scratch);
-
-    // ---- stream: domain check, staircase test, list the open points ----
-    // points before the first 16-byte boundary of the set (pts_odd: whether
-    // pts itself starts 8 bytes past one)
-    const uint32_t head = (uint32_t)(((uint64_t)base + pts_odd) & 1u);
-    const uint32_t n4 = (m - head) / 2;
-    const bool tail = ((m - head) & 1u) != 0;
-    const v4f* const p4 = reinterpret_cast<const v4f*>(ps + 2 * head);
-    const u64* const sx64 = reinterpret_cast<const u64*>(sst);
-    const u64* const sy64 = sx64 + S;
-    auto slot_of = [](uint32_t v) { return (v >> kStairShift) & (S - 1); };
     // the extreme keys of the listed points: K0 = (x, M - y), K1 = (y, x);
     // minima then maxima (coordinates only: the smallest index among a
     // point's exact duplicates is found later, in the list)
@@ -2169,154 +2162,240 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     // converts back to the same float (up to the sign of 0) and is at most
     // M; differing bits and the largest conversion accumulate
     uint32_t err = 0, hi = 0;
-    auto check = [&](float fx, float fy, uint32_t X, uint32_t Y) {
-        err |= (__float_as_uint((float)X) ^ __float_as_uint(fx)) | (__float_as_uint((float)Y) ^ __float_as_uint(fy));
-        hi = max(hi, max(X, Y));
-    };
-    uint32_t wtot = 0;  // points this wave listed since the last compaction (uniform in the wave)
-
-    // one point of every lane, the whole wave together (the append is
-    // wave-wide)
-    auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
-        const bool o1 = Y < (uint32_t)sxv;                 // R1: k2 = y
-        const bool o2 = (X ^ kM) < (uint32_t)syv;          // R2: k2 = M - x
-        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);  // R3: k2 = M - y
-        const bool o4 = X < (uint32_t)(syv >> 32);         // R4: k2 = x
-        const bool open = valid && (o1 || o2 || o3 || o4);
-        const u64 bal = __ballot(open);
-        if (bal) {
-            uint32_t first = 0;
-            if (lane == 0) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
-            first = __shfl(first, 0);
-            if (open) {
-                lidx[first + (uint32_t)__popcll(bal & lt)] = idx;
-                const uint32_t x = X & kM, y = Y & kM;
-                lower(x, y);
-                const u64 k0 = ((u64)x << 32) | (y ^ kM), k1 = ((u64)y << 32) | x;
-                ek[0] = min(ek[0], k0);
-                ek[1] = min(ek[1], k1);
-                ek[2] = max(ek[2], k0);
-                ek[3] = max(ek[3], k1);
+    if constexpr (kFromLists) {
+        // ---- list mode: k_stream's open points are the list (its
+        // staircase test already ran); the extreme keys from its partials.
+        // More open points than the list holds leave the input to the
+        // single-hull kernels. ----
+        uint32_t* const s_lst = reinterpret_cast<uint32_t*>(smem + kBatchOffRaw);  // list starts (the sample's room)
+        const uint32_t nl = src.nlists;
+        uint32_t c[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t l = u * kBatchBlock + tid;
+            c[u] = 0;
+            if (l < nl) {
+                c[u] = src.wgcount[l];
+                const ExtPartial pp = src.parts[l];
+                ek[0] = min(ek[0], pp.kmin[0]);
+                ek[1] = min(ek[1], pp.kmin[1]);
+                ek[2] = max(ek[2], pp.kmax[0]);
+                ek[3] = max(ek[3], pp.kmax[1]);
+                err |= pp.err;
             }
-            wtot += (uint32_t)__popcll(bal);
         }
-    };
-    auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
-        const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
-        check(fx, fy, X, Y);  // a lane without a point rechecks point idx
-        list_point(X, Y, idx, valid, sx64[slot_of(X)], sy64[slot_of(Y)]);
-    };
-    // the list again against the staircase rebuilt from the slot minima;
-    // every thread takes part, after a workgroup barrier with no append
-    // pending
-    auto compact = [&]() -> uint32_t {
-        batch_stair(raw, sst, scratch);
-        const uint32_t n = s_n;
-        uint32_t id[kBatchPerList];
-        v2f v[kBatchPerList];
+        // starts: list l at s_lst[l] (thread t: lists t and t + kBatchBlock)
+        uint32_t tot0, tot1;
+        const uint32_t e0 = block_excl_sum<kBatchWaves>(c[0], scratch, tot0);
+        const uint32_t e1 = block_excl_sum<kBatchWaves>(c[1], scratch, tot1);
+        if (tid < nl) s_lst[tid] = e0;
+        if (kBatchBlock + tid < nl) s_lst[kBatchBlock + tid] = tot0 + e1;
+        const uint32_t L = tot0 + tot1;
+        if (L > src.cap) {
+            if (tid == 0) out_counts[set] = kBatchRedo;
+            return;
+        }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             const uint32_t e = k * kBatchBlock + tid;
-            id[k] = e < n ? lidx[e] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) v[k] = p2[id[k]];
-        uint32_t keep = 0;
-#pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) {
-            const uint32_t X = cvt_u32_sat(v[k].x) & kM, Y = cvt_u32_sat(v[k].y) & kM;
-            const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
-            const bool open = Y < (uint32_t)sxv || (X ^ kM) < (uint32_t)syv || (Y ^ kM) < (uint32_t)(sxv >> 32) ||
-                              X < (uint32_t)(syv >> 32);
-            if (k * kBatchBlock + tid < n && open) keep |= 1u << k;
-        }
-        uint32_t kept;
-        uint32_t at = block_excl_sum<kBatchWaves>((uint32_t)__popc(keep), scratch, kept);
-#pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) {
-            if ((keep >> k) & 1u) lidx[at++] = id[k];
-        }
-        if (tid == 0) s_n = kept;
-        wtot = wave == 0 ? kept : 0u;
-        __syncthreads();
-        return kept;
-    };
-
-    if (wave == 0) {
-        if (head) visit_one(ps[0], ps[1], 0, lane == 0);
-        if (tail) visit_one(ps[2 * (m - 1)], ps[2 * (m - 1) + 1], m - 1, lane == 0);
-    }
-    constexpr uint32_t kR4 = (uint32_t)kBatchUnroll * kBatchBlock;  // float4s per round
-    const uint32_t rounds = (n4 + kR4 - 1) / kR4;
-    auto load_round = [&](uint32_t r, v4f* v) {
-#pragma unroll
-        for (int u = 0; u < kBatchUnroll; ++u)
-            v[u] = __builtin_nontemporal_load(p4 + min(r * kR4 + u * kBatchBlock + tid, n4 - 1));
-    };
-    // loads run two rounds ahead of the tests
-    v4f va[kBatchUnroll], vb[kBatchUnroll], vc[kBatchUnroll];
-    if (rounds > 0) load_round(0, va);
-    if (rounds > 1) load_round(1, vb);
-    bool full = false;  // the same in every thread
-    // (uniform) the fill at the last check, counting the two points the head
-    // and tail visits may have listed before it; rounds since; the wcnt
-    // buffer of the next check
-    uint32_t known = 2, since = 0, par = 0;
-    for (uint32_t r = 0; r < rounds; ++r) {
-        if (r + 2 < rounds) load_round(r + 2, vc);
-#pragma unroll
-        for (int u = 0; u < kBatchUnroll; ++u) {
-            const uint32_t g = r * kR4 + u * kBatchBlock + tid;
-            const bool valid = g < n4;
-            const uint32_t i0 = head + 2 * min(g, n4 - 1);
-            const uint32_t X0 = cvt_u32_sat(va[u].x), Y0 = cvt_u32_sat(va[u].y);
-            const uint32_t X1 = cvt_u32_sat(va[u].z), Y1 = cvt_u32_sat(va[u].w);
-            const u64 sx0 = sx64[slot_of(X0)], sy0 = sy64[slot_of(Y0)];
-            const u64 sx1 = sx64[slot_of(X1)], sy1 = sy64[slot_of(Y1)];
-            // (a lane past the end rechecks the last points)
-            check(va[u].x, va[u].y, X0, Y0);
-            check(va[u].z, va[u].w, X1, Y1);
-            list_point(X0, Y0, i0, valid, sx0, sy0);
-            list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
-        }
-        // The list holds at most known + since * (2u * kBatchUnroll * kBatchBlock) points now and
-        // the next round adds at most (2u * kBatchUnroll * kBatchBlock): only when that bound
-        // could pass the list's room is the fill taken (a workgroup
-        // barrier), the same in every thread: each wave posts its own count
-        // (double-buffered: a wave that runs ahead to the next check writes
-        // the other buffer).
-        ++since;
-        if (known + (since + 1) * (2u * kBatchUnroll * kBatchBlock) > (uint32_t)kBatchList) {
-            if (lane == 0) wcnt[par][wave] = wtot;
-            __syncthreads();
-            uint32_t fill = 0;
-#pragma unroll
-            for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[par][w];
-            par ^= 1u;
-            if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
-                fill = compact();
-                // a list still too full after the compaction: the set has
-                // too many open points for the workgroup
-                if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
-                    full = true;
-                    break;
-                }
+            if (e < L) {
+                uint32_t l = 0;  // the last list with start <= e
+                for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1)
+                    if (l + st < nl && s_lst[l + st] <= e) l += st;
+                lidx[e] = src.idx[(size_t)l * src.region + (e - s_lst[l])];
             }
-            known = fill;
-            since = 0;
         }
-#pragma unroll
-        for (int u = 0; u < kBatchUnroll; ++u) {
-            va[u] = vb[u];
-            vb[u] = vc[u];
+        if (tid == 0) s_n = L;
+        for (int e = tid; e < 4 * kStairSlots; e += kBatchBlock) src.stab[e] = 0;
+        __syncthreads();
+    } else {
+    constexpr uint32_t S = kStairSlots;
+    
+        // ---- the first staircase, from a sample of runs of consecutive points ----
+        for (uint32_t e = tid; e < 4 * S; e += kBatchBlock) raw[e] = ~0u;
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+        auto lower = [&](uint32_t x, uint32_t y) {  // x, y in [0, M]
+            atomicMin(&raw[0 * S + (x >> kStairShift)], y);         // R1: (x, y)
+            atomicMin(&raw[1 * S + (y >> kStairShift)], x ^ kM);    // R2: (y, M-x)
+            atomicMin(&raw[2 * S + ((x ^ kM) >> kStairShift)], y ^ kM);  // R3: (M-x, M-y)
+            atomicMin(&raw[3 * S + ((y ^ kM) >> kStairShift)], x);  // R4: (M-y, x)
+        };
+        if (m > (2u * kBatchUnroll * kBatchBlock)) {
+            constexpr uint32_t kThreads = kBatchBlock / kBatchChunks, kPer = kBatchChunk / kThreads;
+            const uint32_t c = tid / kThreads, sub = tid % kThreads;
+            const uint32_t start = (uint32_t)(((u64)c * (m - kBatchChunk)) / (kBatchChunks - 1));
+            v2f v[kPer];
+    #pragma unroll
+            for (uint32_t k = 0; k < kPer; ++k) v[k] = p2[start + k * kThreads + sub];
+            // out-of-domain values only need to stay in range here: such a set
+            // fails with a domain error
+    #pragma unroll
+            for (uint32_t k = 0; k < kPer; ++k) lower(coord_u32(v[k].x) & kM, coord_u32(v[k].y) & kM);
         }
+        __syncthreads();
+        batch_stair(raw, sst, scratch);
+    
+        // ---- stream: domain check, staircase test, list the open points ----
+        // points before the first 16-byte boundary of the set (pts_odd: whether
+        // pts itself starts 8 bytes past one)
+        const uint32_t head = (uint32_t)(((uint64_t)base + pts_odd) & 1u);
+        const uint32_t n4 = (m - head) / 2;
+        const bool tail = ((m - head) & 1u) != 0;
+        const v4f* const p4 = reinterpret_cast<const v4f*>(ps + 2 * head);
+        const u64* const sx64 = reinterpret_cast<const u64*>(sst);
+        const u64* const sy64 = sx64 + S;
+        auto slot_of = [](uint32_t v) { return (v >> kStairShift) & (S - 1); };
+        auto check = [&](float fx, float fy, uint32_t X, uint32_t Y) {
+            err |= (__float_as_uint((float)X) ^ __float_as_uint(fx)) | (__float_as_uint((float)Y) ^ __float_as_uint(fy));
+            hi = max(hi, max(X, Y));
+        };
+        uint32_t wtot = 0;  // points this wave listed since the last compaction (uniform in the wave)
+    
+        // one point of every lane, the whole wave together (the append is
+        // wave-wide)
+        auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
+            const bool o1 = Y < (uint32_t)sxv;                 // R1: k2 = y
+            const bool o2 = (X ^ kM) < (uint32_t)syv;          // R2: k2 = M - x
+            const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);  // R3: k2 = M - y
+            const bool o4 = X < (uint32_t)(syv >> 32);         // R4: k2 = x
+            const bool open = valid && (o1 || o2 || o3 || o4);
+            const u64 bal = __ballot(open);
+            if (bal) {
+                uint32_t first = 0;
+                if (lane == 0) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
+                first = __shfl(first, 0);
+                if (open) {
+                    lidx[first + (uint32_t)__popcll(bal & lt)] = idx;
+                    const uint32_t x = X & kM, y = Y & kM;
+                    lower(x, y);
+                    const u64 k0 = ((u64)x << 32) | (y ^ kM), k1 = ((u64)y << 32) | x;
+                    ek[0] = min(ek[0], k0);
+                    ek[1] = min(ek[1], k1);
+                    ek[2] = max(ek[2], k0);
+                    ek[3] = max(ek[3], k1);
+                }
+                wtot += (uint32_t)__popcll(bal);
+            }
+        };
+        auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
+            const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
+            check(fx, fy, X, Y);  // a lane without a point rechecks point idx
+            list_point(X, Y, idx, valid, sx64[slot_of(X)], sy64[slot_of(Y)]);
+        };
+        // the list again against the staircase rebuilt from the slot minima;
+        // every thread takes part, after a workgroup barrier with no append
+        // pending
+        auto compact = [&]() -> uint32_t {
+            batch_stair(raw, sst, scratch);
+            const uint32_t n = s_n;
+            uint32_t id[kBatchPerList];
+            v2f v[kBatchPerList];
+    #pragma unroll
+            for (int k = 0; k < kBatchPerList; ++k) {
+                const uint32_t e = k * kBatchBlock + tid;
+                id[k] = e < n ? lidx[e] : 0u;
+            }
+    #pragma unroll
+            for (int k = 0; k < kBatchPerList; ++k) v[k] = p2[id[k]];
+            uint32_t keep = 0;
+    #pragma unroll
+            for (int k = 0; k < kBatchPerList; ++k) {
+                const uint32_t X = cvt_u32_sat(v[k].x) & kM, Y = cvt_u32_sat(v[k].y) & kM;
+                const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
+                const bool open = Y < (uint32_t)sxv || (X ^ kM) < (uint32_t)syv || (Y ^ kM) < (uint32_t)(sxv >> 32) ||
+                                  X < (uint32_t)(syv >> 32);
+                if (k * kBatchBlock + tid < n && open) keep |= 1u << k;
+            }
+            uint32_t kept;
+            uint32_t at = block_excl_sum<kBatchWaves>((uint32_t)__popc(keep), scratch, kept);
+    #pragma unroll
+            for (int k = 0; k < kBatchPerList; ++k) {
+                if ((keep >> k) & 1u) lidx[at++] = id[k];
+            }
+            if (tid == 0) s_n = kept;
+            wtot = wave == 0 ? kept : 0u;
+            __syncthreads();
+            return kept;
+        };
+    
+        if (wave == 0) {
+            if (head) visit_one(ps[0], ps[1], 0, lane == 0);
+            if (tail) visit_one(ps[2 * (m - 1)], ps[2 * (m - 1) + 1], m - 1, lane == 0);
+        }
+        constexpr uint32_t kR4 = (uint32_t)kBatchUnroll * kBatchBlock;  // float4s per round
+        const uint32_t rounds = (n4 + kR4 - 1) / kR4;
+        auto load_round = [&](uint32_t r, v4f* v) {
+    #pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u)
+                v[u] = __builtin_nontemporal_load(p4 + min(r * kR4 + u * kBatchBlock + tid, n4 - 1));
+        };
+        // loads run two rounds ahead of the tests
+        v4f va[kBatchUnroll], vb[kBatchUnroll], vc[kBatchUnroll];
+        if (rounds > 0) load_round(0, va);
+        if (rounds > 1) load_round(1, vb);
+        bool full = false;  // the same in every thread
+        // (uniform) the fill at the last check, counting the two points the head
+        // and tail visits may have listed before it; rounds since; the wcnt
+        // buffer of the next check
+        uint32_t known = 2, since = 0, par = 0;
+        for (uint32_t r = 0; r < rounds; ++r) {
+            if (r + 2 < rounds) load_round(r + 2, vc);
+    #pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u) {
+                const uint32_t g = r * kR4 + u * kBatchBlock + tid;
+                const bool valid = g < n4;
+                const uint32_t i0 = head + 2 * min(g, n4 - 1);
+                const uint32_t X0 = cvt_u32_sat(va[u].x), Y0 = cvt_u32_sat(va[u].y);
+                const uint32_t X1 = cvt_u32_sat(va[u].z), Y1 = cvt_u32_sat(va[u].w);
+                const u64 sx0 = sx64[slot_of(X0)], sy0 = sy64[slot_of(Y0)];
+                const u64 sx1 = sx64[slot_of(X1)], sy1 = sy64[slot_of(Y1)];
+                // (a lane past the end rechecks the last points)
+                check(va[u].x, va[u].y, X0, Y0);
+                check(va[u].z, va[u].w, X1, Y1);
+                list_point(X0, Y0, i0, valid, sx0, sy0);
+                list_point(X1, Y1, i0 + 1, valid, sx1, sy1);
+            }
+            // The list holds at most known + since * (2u * kBatchUnroll * kBatchBlock) points now and
+            // the next round adds at most (2u * kBatchUnroll * kBatchBlock): only when that bound
+            // could pass the list's room is the fill taken (a workgroup
+            // barrier), the same in every thread: each wave posts its own count
+            // (double-buffered: a wave that runs ahead to the next check writes
+            // the other buffer).
+            ++since;
+            if (known + (since + 1) * (2u * kBatchUnroll * kBatchBlock) > (uint32_t)kBatchList) {
+                if (lane == 0) wcnt[par][wave] = wtot;
+                __syncthreads();
+                uint32_t fill = 0;
+    #pragma unroll
+                for (int w = 0; w < kBatchWaves; ++w) fill += wcnt[par][w];
+                par ^= 1u;
+                if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
+                    fill = compact();
+                    // a list still too full after the compaction: the set has
+                    // too many open points for the workgroup
+                    if (fill > (uint32_t)kBatchList - (2u * kBatchUnroll * kBatchBlock)) {
+                        full = true;
+                        break;
+                    }
+                }
+                known = fill;
+                since = 0;
+            }
+    #pragma unroll
+            for (int u = 0; u < kBatchUnroll; ++u) {
+                va[u] = vb[u];
+                vb[u] = vc[u];
+            }
+        }
+        __syncthreads();  // every append of the stream is in the list
+        if (full) {
+            if (tid == 0) out_counts[set] = kBatchRedo;
+            return;
+        }
+    
     }
-    __syncthreads();  // every append of the stream is in the list
-    if (full) {
-        if (tid == 0) out_counts[set] = kBatchRedo;
-        return;
-    }
-
     // ---- the extreme points and the quadrilateral ----
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -2356,7 +2435,13 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     for (int e = tid; e < 4 * kBatchSlots; e += kBatchBlock) smin[e] = ~0ull;
     __syncthreads();
     if (sq.err) {
-        if (tid == 0) out_counts[set] = CH_EDOMAIN;
+        if (tid == 0) {
+            out_counts[set] = CH_EDOMAIN;
+            if constexpr (kFromLists) {
+                src.host_hdr->err = kErrDomain;
+                src.host_hdr->fin_done = 0;
+            }
+        }
         return;
     }
     const uint32_t L = s_n;
@@ -2563,6 +2648,27 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     // ---- pre-hull rounds, the finish ----
     const int h = poly_finish(Pl, npoly, rbase[1], out_idx + base, scratch, &s_flag, &s_ext, &s_start);
     if (tid == 0) out_counts[set] = h < 0 ? kBatchRedo : h;
+    if constexpr (kFromLists) {
+        if (tid == 0 && h >= 0) {
+            // the counts for the host (the single-hull kernels, gated off,
+            // publish nothing)
+            DevHeader* const hh = src.host_hdr;
+            for (int q = 0; q < 4; ++q) {
+                hh->ext_x[q] = sq.X[q];
+                hh->ext_y[q] = sq.Y[q];
+                hh->ext_idx[q] = s_eidx[q];
+                hh->s2[q] = s_rcnt[q];
+                hh->fin_w2[q] = s_rcnt[q];
+            }
+            hh->err = 0;
+            hh->open = s_n;
+            hh->cand = nsort;
+            hh->chain = nchain;
+            hh->fin_hull = h;
+            hh->fin_fail = 0;
+            hh->fin_done = 1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -3301,7 +3407,7 @@ struct StreamShape {
 };
 
 // ---- launch shapes (ch_tuning), per size class ----
-constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18, 1 << 18};
+constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18, 1 << 15, kBatchList};
 constexpr int kTuningClasses = 16;
 std::mutex g_tune_mu;
 int g_tune_count = 0;
@@ -3315,7 +3421,7 @@ bool tuning_valid(const ch_tuning& t)
            t.cand_per_row <= (1 << 20) && t.chain_grid >= 64 && t.chain_grid <= 4096 &&
            t.wide_grid >= 64 && t.wide_grid <= 4096 && (t.batch_unroll == 1 || t.batch_unroll == 2) &&
            (t.batch_order == 0 || t.batch_order == 1) && t.serve_batch_max >= 0 && t.serve_batch_max <= (1 << 22) &&
-           t.fused_max >= 0 && t.fused_max <= (1 << 22);
+           t.fused_max >= 0 && t.fused_max <= (1 << 22) && t.list_max >= 0 && t.list_max <= kBatchList;
 }
 
 // The shapes of a call with n points: the class with the smallest n_max >= n.
@@ -3572,7 +3678,7 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
         const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
         auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
         CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
-                                     pts_odd, 1, (int64_t)n));
+                                     pts_odd, 1, (int64_t)n, ListSrc{}));
         gate = fin_count;
     }
     if (g_stab_dirty.load(std::memory_order_relaxed)) {
@@ -3602,6 +3708,18 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
                                      w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
     }
     CH_TRY(record(w, 2));
+    if (fin_idx && !gate && tu.list_max > 0) {
+        // few open points: every later step in one workgroup (the batched
+        // kernel's list mode, which also clears the sample table); the
+        // kernels below run only if it leaves the input (gate)
+        const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
+        auto kern = tu.batch_unroll == 1 ? k_batch_hull<1, true> : k_batch_hull<2, true>;
+        CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
+                                     pts_odd, 1, (int64_t)n,
+                                     ListSrc{w.open_idx, w.wgcount, w.part, w.h_hdr_dev, w.stab, sh.region, sh.grid,
+                                             (uint32_t)tu.list_max}));
+        gate = fin_count;
+    }
     // the rows of the bucket table follow the open count (k_stream's, on the
     // device): up to one k_cand workgroup per cand_per_row open points
     const uint32_t gc = std::min<uint32_t>(kCandMaxRows, sh.grid);
@@ -3653,7 +3771,7 @@ int run_fused(Workspace& w, const float* pts, uint32_t n, int32_t* out_idx, int3
     const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
     auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
     CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, w.stream, pts, nullptr, nullptr, out_idx,
-                                 out_count, pts_odd, 1, (int64_t)n));
+                                 out_count, pts_odd, 1, (int64_t)n, ListSrc{}));
     CH_TRY(record(w, 5));
     CH_TRY(record(w, 6));
     CH_TRY(hipMemcpyAsync(&w.h_hdr->fin_hull, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, w.stream));
@@ -4068,7 +4186,7 @@ int hull2d_batched(const float* points, const int64_t* offsets, int32_t num_sets
             auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
             CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)nk), dim3(kBatchBlock), 0, st, points,
                                          w->b_offsets, w->b_order, out_idx, out_counts, pts_odd, num_sets,
-                                         (int64_t)0));
+                                         (int64_t)0, ListSrc{}));
             CH_TRY(record(*w, 1));
             CH_TRY(hipMemcpyAsync(w->h_b_counts, out_counts, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
         }
@@ -4117,7 +4235,7 @@ int hull2d_batched_async(const float* points, const int64_t* offsets, const int3
     auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
     CH_LAUNCH(hipLaunchKernelGGL(kern, dim3((uint32_t)num_sets), dim3(kBatchBlock), 0,
                                  reinterpret_cast<hipStream_t>(stream), points, offsets, order, out_idx, out_counts,
-                                 pts_odd, num_sets, (int64_t)0));
+                                 pts_odd, num_sets, (int64_t)0, ListSrc{}));
     return CH_OK;
 }
 

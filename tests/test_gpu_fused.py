@@ -142,3 +142,36 @@ def test_fused_graph_replays_with_a_left_input():
             assert c == want.size and np.array_equal(out[:c].cpu().numpy(), want), rep
         del g
         ch.release_stream(s)
+
+
+@contextlib.contextmanager
+def list_max(v):
+    base = ch.get_tuning(-1)
+    ch.clear_tuning()
+    ch.set_tuning(2**40, autotune.shape(base, list_max=v))
+    try:
+        yield
+    finally:
+        ch.clear_tuning()
+        ch.load_tuning()
+
+
+@pytest.mark.parametrize("dist,n,seed", [("gaussian", 3_000_000, 941), ("square", 5_000_000, 942),
+                                         ("disk", 300_000, 943)])
+def test_list_mode_on_large_inputs(dist, n, seed):
+    # few open points after the pass over a large input: one workgroup takes
+    # every later step from k_stream's lists (or leaves the input to the
+    # single-hull kernels when they are too many)
+    pts = wl.generate(dist, n, seed)
+    want = oracle.hull(pts)
+    d = torch.from_numpy(pts).cuda()
+    say(f"  hull2d {dist} n={n} (list mode)")
+    got = ch.hull2d(d).cpu().numpy()
+    st = ch.last_stats()
+    assert np.array_equal(got, want)
+    assert st["device_finish"] and st["open"] > 0
+    got, c = run_async(ch.hull2d_async, d)
+    assert c == want.size and np.array_equal(got, want)
+    with list_max(0):
+        say(f"  hull2d {dist} n={n} (single-hull kernels)")
+        assert np.array_equal(ch.hull2d(d).cpu().numpy(), want)

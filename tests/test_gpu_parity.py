@@ -29,11 +29,10 @@ def say(msg):
 
 
 @contextlib.contextmanager
-def single_hull_kernels_only():
-    """No call takes the small-input path (fused_max 0)."""
+def tuned(**kw):
     base = ch.get_tuning(-1)
     ch.clear_tuning()
-    ch.set_tuning(2**40, autotune.shape(base, fused_max=0))
+    ch.set_tuning(2**40, autotune.shape(base, **kw))
     try:
         yield
     finally:
@@ -41,16 +40,26 @@ def single_hull_kernels_only():
         ch.load_tuning()
 
 
+def single_hull_kernels_only():
+    """Neither the small-input path nor the list mode (fused_max, list_max 0)."""
+    return tuned(fused_max=0, list_max=0)
+
+
 def gpu_hull(pts, name=""):
-    # both paths of a small input: the batched kernel's one workgroup (the
-    # default at these sizes) and the single-hull kernels
+    # every path of a small input: the default (the batched kernel's one
+    # workgroup on the points, or on k_stream's open lists), the list mode
+    # alone, and the single-hull kernels throughout
     say(f"  hull2d {name} n={pts.shape[0]}")
     d = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
     got = ch.hull2d(d).cpu().numpy()
+    say(f"  hull2d {name}: list mode")
+    with tuned(fused_max=0):
+        alt = ch.hull2d(d).cpu().numpy()
+    assert np.array_equal(got, alt), f"{name}: the list mode differs"
     say(f"  hull2d {name}: single-hull kernels")
     with single_hull_kernels_only():
         alt = ch.hull2d(d).cpu().numpy()
-    assert np.array_equal(got, alt), f"{name}: the two paths differ"
+    assert np.array_equal(got, alt), f"{name}: the single-hull kernels differ"
     return got
 
 
