@@ -137,7 +137,8 @@ struct DevHeader {
     uint32_t epoch;      // calls on this workspace so far (tags the look-back states)
     uint32_t wide_ticket;  // k_finish_wide's next item
     uint32_t fin_fail;   // 1 when k_finish_wide gave up (the host finishes)
-    uint32_t pad[4];
+    int32_t list_count;  // (host copy only) the list mode's count, for hull2d
+    uint32_t pad[3];
 };
 
 // Extreme keys: key 0 = x << 32 | (M - y), key 1 = y << 32 | x; P_minx and
@@ -1305,6 +1306,27 @@ __device__ inline void wave_bitonic(u64 (&key)[PER], uint32_t (&ix)[PER])
     }
 }
 
+// Sorts keys[0 .. n) (distinct, n <= 64*PER) ascending in one wave.
+template <int PER>
+__device__ inline void wave_sort_keys(u64* keys, uint32_t n)
+{
+    const uint32_t lane = lane_id();
+    u64 k[PER];
+    uint32_t ix[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t e = lane * PER + s;
+        k[s] = e < n ? keys[e] : ~0ull;
+        ix[s] = 0;
+    }
+    wave_bitonic<PER>(k, ix);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t e = lane * PER + s;
+        if (e < n) keys[e] = k[s];
+    }
+}
+
 // SPA of one bucket of m <= 64*PER records by one wave: the records,
 // gathered from the rows' parts (seg, pre: the bucket's first position in
 // each row's part and the records before each row), sorted by (k1, k2,
@@ -1562,7 +1584,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                                                   const int32_t* __restrict__ gate)
 {
     __shared__ uint32_t pre[kBucketsPadded];  // chain points before each bucket (at bpad)
-    __shared__ uint32_t ka[kSeg], kb[kSeg], at[kSeg];
+    __shared__ uint32_t ka[kSeg], kb[kSeg];
+    __shared__ int32_t sidx[kSeg];  // the points' indices (the output needs no second read of the chain)
     __shared__ uint16_t lst[kSeg];
     __shared__ uint8_t reg[kSeg], alive[kSeg];
     __shared__ uint32_t scratch[kWaves];
@@ -1653,7 +1676,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
                 const uint32_t q = bb[k] >> kBucketBits;
                 uint32_t k1, k2;
                 to_frame(q, (uint32_t)rr[k].x, (uint32_t)rr[k].y, k1, k2);
-                at[i] = aa[k];
+                sidx[i] = rr[k].idx;
                 reg[i] = (uint8_t)q;
                 ka[i] = k1;
                 kb[i] = k2;
@@ -1687,55 +1710,84 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         // alive flags stay in registers, the neighbours come from wave
         // scans, no workgroup barrier), then over the whole segment.
         if (prehull) {
+            // in registers: lane l holds positions 4l .. 4l+3 (k1; region << 23
+            // | k2); a lane's neighbours outside it are the last alive point
+            // of the nearest lane before with one and the first of the
+            // nearest lane after (lane scans, then one shuffle per value)
             const uint32_t p0 = tid * kPerThreadSeg;
-            const uint32_t lane = lane_id();
+            const int lane = (int)lane_id();
             bool al[kPerThreadSeg];
+            uint32_t c1[kPerThreadSeg], c2[kPerThreadSeg];
 #pragma unroll
-            for (int k = 0; k < kPerThreadSeg; ++k) al[k] = p0 + k < len;
+            for (int k = 0; k < kPerThreadSeg; ++k) {
+                const uint32_t i = p0 + k;
+                al[k] = i < len;
+                c1[k] = al[k] ? ka[i] : 0u;
+                c2[k] = al[k] ? (((uint32_t)reg[i] << 23) | kb[i]) : 0u;
+            }
             for (int round = 0; round < kPrehullRounds; ++round) {
-                // the nearest alive positions before and after this lane's
-                int last = -1, first = 1 << 30;
-#pragma unroll
-                for (int k = kPerThreadSeg - 1; k >= 0; --k)
-                    if (al[k]) first = (int)(p0 + k);
-#pragma unroll
-                for (int k = 0; k < kPerThreadSeg; ++k)
-                    if (al[k]) last = (int)(p0 + k);
-                int before = last, after = first;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const int b = __shfl_up(before, off), a = __shfl_down(after, off);
-                    if (lane >= (uint32_t)off) before = max(before, b);
-                    if (lane + off < 64) after = min(after, a);
-                }
-                int prev = __shfl_up(before, 1), next = __shfl_down(after, 1);
-                if (lane == 0) prev = -1;
-                if (lane == 63) next = 1 << 30;
-                bool gone[kPerThreadSeg];
-                // prev: the last alive before position k; then the next
-                // alive after it, scanning from the lane's end
-                int pv[kPerThreadSeg], nx[kPerThreadSeg];
-#pragma unroll
-                for (int k = 0; k < kPerThreadSeg; ++k) {
-                    pv[k] = prev;
-                    if (al[k]) prev = (int)(p0 + k);
-                }
+                uint32_t f1 = 0, f2 = 0, l1 = 0, l2 = 0;  // the lane's first and last alive point
+                bool has = false;
 #pragma unroll
                 for (int k = kPerThreadSeg - 1; k >= 0; --k) {
-                    nx[k] = next;
-                    if (al[k]) next = (int)(p0 + k);
+                    if (al[k]) {
+                        f1 = c1[k];
+                        f2 = c2[k];
+                    }
                 }
-                bool any = false;
 #pragma unroll
                 for (int k = 0; k < kPerThreadSeg; ++k) {
+                    if (al[k]) {
+                        l1 = c1[k];
+                        l2 = c2[k];
+                        has = true;
+                    }
+                }
+                int before = has ? lane : -1, after = has ? lane : 64;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int bv = __shfl_up(before, off), av = __shfl_down(after, off);
+                    if (lane >= off) before = max(before, bv);
+                    if (lane + off < 64) after = min(after, av);
+                }
+                int pl = __shfl_up(before, 1), nl = __shfl_down(after, 1);
+                if (lane == 0) pl = -1;
+                if (lane == 63) nl = 64;
+                const uint32_t q1 = (uint32_t)__shfl(l1, max(pl, 0)), q2 = (uint32_t)__shfl(l2, max(pl, 0));
+                const uint32_t n1 = (uint32_t)__shfl(f1, min(nl, 63)), n2 = (uint32_t)__shfl(f2, min(nl, 63));
+                // walk the lane: the previous alive point so far, then the
+                // next one from the lane's end
+                bool hp = pl >= 0;
+                uint32_t a1 = q1, a2 = q2;
+                bool hpv[kPerThreadSeg];
+                uint32_t pv1[kPerThreadSeg], pv2[kPerThreadSeg];
+#pragma unroll
+                for (int k = 0; k < kPerThreadSeg; ++k) {
+                    hpv[k] = hp;
+                    pv1[k] = a1;
+                    pv2[k] = a2;
+                    if (al[k]) {
+                        hp = true;
+                        a1 = c1[k];
+                        a2 = c2[k];
+                    }
+                }
+                bool hn = nl < 64;
+                uint32_t b1 = n1, b2 = n2;
+                bool any = false;
+                bool gone[kPerThreadSeg];
+#pragma unroll
+                for (int k = kPerThreadSeg - 1; k >= 0; --k) {
                     gone[k] = false;
-                    if (al[k] && pv[k] >= 0 && nx[k] < (int)len) {
-                        const uint32_t i = p0 + k, a = (uint32_t)pv[k], c = (uint32_t)nx[k];
-                        if (reg[a] == reg[i] && reg[c] == reg[i] &&
-                            frame_turn(ka[a], kb[a], ka[i], kb[i], ka[c], kb[c]) <= 0) {
-                            gone[k] = true;
-                            any = true;
-                        }
+                    if (al[k] && hpv[k] && hn && (pv2[k] >> 23) == (c2[k] >> 23) && (b2 >> 23) == (c2[k] >> 23) &&
+                        frame_turn(pv1[k], pv2[k] & kM, c1[k], c2[k] & kM, b1, b2 & kM) <= 0) {
+                        gone[k] = true;
+                        any = true;
+                    }
+                    if (al[k]) {
+                        hn = true;
+                        b1 = c1[k];
+                        b2 = c2[k];
                     }
                 }
 #pragma unroll
@@ -1768,7 +1820,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(const PolyRec* __restrict__ de
         // the kept points, in order, at base + rank
         for (uint32_t p = tid; p < n_alive; p += kBlock) {
             const uint32_t i = lst[p];
-            const PolyRec r = dev_chain[at[i]];
+            const PolyRec r = chain_rec(reg[i], ka[i], kb[i], (uint32_t)sidx[i]);
             const uint32_t o = base + p;
             if (host_chain) {  // (the host polygon of chainhull_polygon)
                 if (o < host_cap) host_chain[o] = r;
@@ -2103,6 +2155,7 @@ __device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, 
 // per-workgroup extreme partials, and the pinned header the host reads.
 struct ListSrc {
     const uint32_t* idx;
+    const u64* xym;  // x | y << 23 | mask << 46 per open point
     const uint32_t* wgcount;
     const ExtPartial* parts;
     DevHeader* host_hdr;
@@ -2126,6 +2179,9 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     __shared__ uint32_t wcnt[2][kBatchWaves];
     __shared__ Quad sq;
     __shared__ uint32_t s_n, s_flag, s_ext, s_start, s_rcnt[4];
+    // list mode: the listed points' coordinates (x | y << 23), from the
+    // open records, so that the later steps read no point twice
+    __shared__ uint32_t s_lxy[kFromLists ? 2 * kBatchList : 1];
     uint32_t* const lidx = reinterpret_cast<uint32_t*>(smem + kBatchOffList);
     uint32_t* const raw = reinterpret_cast<uint32_t*>(smem + kBatchOffRaw);
     uint32_t* const sst = reinterpret_cast<uint32_t*>(smem + kBatchOffStair);
@@ -2203,7 +2259,11 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                 uint32_t l = 0;  // the last list with start <= e
                 for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1)
                     if (l + st < nl && s_lst[l + st] <= e) l += st;
-                lidx[e] = src.idx[(size_t)l * src.region + (e - s_lst[l])];
+                const size_t at = (size_t)l * src.region + (e - s_lst[l]);
+                lidx[e] = src.idx[at];
+                const u64 r = src.xym[at];
+                s_lxy[2 * e] = (uint32_t)r & kM;
+                s_lxy[2 * e + 1] = (uint32_t)(r >> 23) & kM;
             }
         }
         if (tid == 0) s_n = L;
@@ -2458,7 +2518,14 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             id[k] = e < L ? lidx[e] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) v[k] = p2[id[k]];
+        for (int k = 0; k < kBatchPerList; ++k) {
+            if constexpr (kFromLists) {
+                const uint32_t e = min(k * kBatchBlock + tid, (uint32_t)kBatchList - 1);
+                v[k] = v2f{(float)s_lxy[2 * e], (float)s_lxy[2 * e + 1]};
+            } else {
+                v[k] = p2[id[k]];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             rec[k] = ~0ull;
@@ -2536,19 +2603,26 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     for (uint32_t e = nsort + tid; e < P2; e += kBatchBlock) skey[e] = ~0ull;
     __syncthreads();
 
-    // ---- sort (bitonic, ascending) ----
-    for (uint32_t size = 2; size <= P2; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = tid; t < P2 / 2; t += kBatchBlock) {
-                const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
-                const bool up = (i & size) == 0;
-                const u64 x = skey[i], y = skey[j];
-                if ((x > y) == up) {
-                    skey[i] = y;
-                    skey[j] = x;
+    // ---- sort (ascending): up to 64 records in one wave's registers, more
+    // by the workgroup's bitonic network in LDS (measured: a wave's network
+    // over 256 records took 11 us against 7 us for the workgroup's) ----
+    if (P2 <= 64) {
+        if (wave == 0) wave_sort_keys<1>(skey, P2);
+        __syncthreads();
+    } else {
+        for (uint32_t size = 2; size <= P2; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t t = tid; t < P2 / 2; t += kBatchBlock) {
+                    const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+                    const bool up = (i & size) == 0;
+                    const u64 x = skey[i], y = skey[j];
+                    if ((x > y) == up) {
+                        skey[i] = y;
+                        skey[j] = x;
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 
@@ -3664,61 +3738,81 @@ int record(Workspace& w, int k)
 // clears the sample table): from then on every call clears its table first.
 std::atomic<bool> g_stab_dirty{false};
 
+// Which launches of a call: all of them, the head (through k_stream and
+// the list mode, when it runs; then *listed says whether it did), or the
+// tail (from k_cand on, after a head whose list mode left the input).
+enum class Part { kAll, kHead, kTail };
+
 int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx,
-                      int32_t* fin_count, bool fused = false)
+                      int32_t* fin_count, bool fused = false, Part part = Part::kAll, bool* listed = nullptr)
 {
     hipStream_t s = w.stream;
     const ch_tuning tu = tuning_for(n);
-    CH_TRY(record(w, 0));
-    // small inputs (fused, with a device finish): every step in one
-    // workgroup of the batched kernel; the kernels below do their work only
-    // if it leaves kBatchRedo in the count (gate)
-    const int32_t* gate = nullptr;
-    if (fused && fin_idx) {
-        const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
-        auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
-        CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
-                                     pts_odd, 1, (int64_t)n, ListSrc{}));
-        gate = fin_count;
-    }
-    if (g_stab_dirty.load(std::memory_order_relaxed)) {
-        // a call failed between k_sample and k_cand somewhere: clear this
-        // workspace's sample table before it is used (a fill kernel, not a
-        // memset, so that a capture records a kernel node)
-        CH_LAUNCH(hipLaunchKernelGGL(k_fill_u32, dim3(4 * kStairSlots / kBlock), dim3(kBlock), 0, s, w.stab, 0u,
-                                     (uint32_t)(4 * kStairSlots)));
-    }
-    CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.stab, gate));
-    // from here until k_cand is queued, a failure leaves the table filled
+    const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
+    const StreamShape sh = stream_shape(n, head, (uint32_t)tu.stream_grid, (uint32_t)tu.stream_unroll);
+    // from k_sample until k_cand is queued, a failure leaves the sample
+    // table filled
     struct StabGuard {
-        bool armed = true;
+        bool armed = false;
         ~StabGuard()
         {
             if (armed) g_stab_dirty.store(true, std::memory_order_relaxed);
         }
     } guard;
-    CH_TRY(record(w, 1));
-    const uint32_t head = (reinterpret_cast<uintptr_t>(pts) & 15u) ? 1u : 0u;
-    const StreamShape sh = stream_shape(n, head, (uint32_t)tu.stream_grid, (uint32_t)tu.stream_unroll);
-    if (tu.stream_unroll == 2) {
-        CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
-                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
+    const int32_t* gate = nullptr;
+    if (part != Part::kTail) {
+        CH_TRY(record(w, 0));
+        // small inputs (fused, with a device finish): every step in one
+        // workgroup of the batched kernel; the kernels below do their work only
+        // if it leaves kBatchRedo in the count (gate)
+        if (fused && fin_idx) {
+            const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
+            auto kern = tu.batch_unroll == 1 ? k_batch_hull<1> : k_batch_hull<2>;
+            CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
+                                         pts_odd, 1, (int64_t)n, ListSrc{}));
+            gate = fin_count;
+        }
+        if (g_stab_dirty.load(std::memory_order_relaxed)) {
+            // a call failed between k_sample and k_cand somewhere: clear this
+            // workspace's sample table before it is used (a fill kernel, not a
+            // memset, so that a capture records a kernel node)
+            CH_LAUNCH(hipLaunchKernelGGL(k_fill_u32, dim3(4 * kStairSlots / kBlock), dim3(kBlock), 0, s, w.stab, 0u,
+                                         (uint32_t)(4 * kStairSlots)));
+        }
+        guard.armed = true;
+        CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.stab, gate));
+        CH_TRY(record(w, 1));
+        if (tu.stream_unroll == 2) {
+            CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
+                                         w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
+        } else {
+            CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
+                                         w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
+        }
+        CH_TRY(record(w, 2));
+        if (fin_idx && !gate && tu.list_max > 0) {
+            // few open points: every later step in one workgroup (the batched
+            // kernel's list mode, which also clears the sample table); the
+            // kernels below run only if it leaves the input (gate)
+            const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
+            auto kern = tu.batch_unroll == 1 ? k_batch_hull<1, true> : k_batch_hull<2, true>;
+            CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
+                                         pts_odd, 1, (int64_t)n,
+                                         ListSrc{w.open_idx, w.open_xym, w.wgcount, w.part, w.h_hdr_dev, w.stab, sh.region, sh.grid,
+                                                 (uint32_t)tu.list_max}));
+            gate = fin_count;
+            if (part == Part::kHead) {
+                // the caller waits for its count and queues the tail only if it
+                // left the input (the tail's k_cand then clears the table)
+                guard.armed = false;
+                if (listed) *listed = true;
+                for (int k = 3; k <= 6; ++k) CH_TRY(record(w, k));
+                return CH_OK;
+            }
+        }
+        if (listed) *listed = false;
     } else {
-        CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
-                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
-    }
-    CH_TRY(record(w, 2));
-    if (fin_idx && !gate && tu.list_max > 0) {
-        // few open points: every later step in one workgroup (the batched
-        // kernel's list mode, which also clears the sample table); the
-        // kernels below run only if it leaves the input (gate)
-        const uint32_t pts_odd = (uint32_t)((reinterpret_cast<uintptr_t>(pts) >> 3) & 1u);
-        auto kern = tu.batch_unroll == 1 ? k_batch_hull<1, true> : k_batch_hull<2, true>;
-        CH_LAUNCH(hipLaunchKernelGGL(kern, dim3(1), dim3(kBatchBlock), 0, s, pts, nullptr, nullptr, fin_idx, fin_count,
-                                     pts_odd, 1, (int64_t)n,
-                                     ListSrc{w.open_idx, w.wgcount, w.part, w.h_hdr_dev, w.stab, sh.region, sh.grid,
-                                             (uint32_t)tu.list_max}));
-        gate = fin_count;
+        guard.armed = true;  // (the head's list mode may not have cleared the table)
     }
     // the rows of the bucket table follow the open count (k_stream's, on the
     // device): up to one k_cand workgroup per cand_per_row open points
@@ -3757,6 +3851,23 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
                                      w.dev_kept, w.states, fin_idx, fin_count, w.h_hdr_dev, gate));
     }
     CH_TRY(record(w, 6));
+    return CH_OK;
+}
+
+constexpr int64_t kWaitListMax = 1 << 20;
+
+// hull2d's head: the launches through k_stream and the list mode, waited
+// for; *count receives the list mode's count (kBatchRedo: the tail must
+// run).  *listed is false when the list mode is off.
+int run_listed(Workspace& w, const float* pts, uint32_t n, int32_t* out_idx, int32_t* out_count, bool* listed,
+               int32_t* count)
+{
+    *listed = false;
+    CH_TRY(launch_preprocess(w, pts, n, false, out_idx, out_count, false, Part::kHead, listed));
+    if (!*listed) return CH_OK;  // (everything was queued: the caller waits as usual)
+    CH_TRY(hipMemcpyAsync(&w.h_hdr->list_count, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, w.stream));
+    CH_TRY(hipStreamSynchronize(w.stream));
+    *count = w.h_hdr->list_count;
     return CH_OK;
 }
 
@@ -3804,9 +3915,9 @@ void fill_fused_stats(const Workspace& w, int64_t n, int32_t hull, ch_stats* st)
 }
 
 int run_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, int32_t* fin_idx = nullptr,
-                   int32_t* fin_count = nullptr)
+                   int32_t* fin_count = nullptr, Part part = Part::kAll)
 {
-    CH_TRY(launch_preprocess(w, pts, n, stats, fin_idx, fin_count));
+    CH_TRY(launch_preprocess(w, pts, n, stats, fin_idx, fin_count, false, part));
     CH_TRY(hipStreamSynchronize(w.stream));
     if (w.h_hdr->err & kErrDomain) return CH_EDOMAIN;
     if (w.h_hdr->err) return CH_EHIP;
@@ -3976,7 +4087,39 @@ int hull_one(const float* points, int64_t n, int32_t* out_idx, int32_t* out_coun
             return CH_OK;
         }
     }
-    rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count);
+    // up to kWaitListMax points: the head, waited for, then (only if the
+    // list mode left the input) the tail, so that a call with few open
+    // points queues no tail kernels; larger inputs, which seldom leave few
+    // open points, queue everything at once (the tail gated on the device)
+    bool listed = false;
+    int32_t lc = 0;
+    if (n <= kWaitListMax) {
+        CH_TRY(run_listed(*w, points, (uint32_t)n, out_idx, out_count, &listed, &lc));
+    } else {
+        CH_TRY(launch_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count));
+    }
+    if (listed && lc != kBatchRedo) {
+        if (lc < 0) {
+            (void)hipMemsetAsync(out_count, 0, sizeof(int32_t), stream);
+            return lc == CH_EDOMAIN ? CH_EDOMAIN : CH_EHIP;
+        }
+        // the list mode published the header's counts
+        for (int q = 0; q < 4; ++q) {
+            w->w2[q] = w->h_hdr->fin_w2[q];
+            w->s2[q] = w->h_hdr->s2[q];
+        }
+        w->chain = w->h_hdr->chain;
+        fill_stats(*w, n, &st, false);
+        st.hull = lc;
+        st.device_finish = 1;
+        return CH_OK;
+    }
+    if (listed) {
+        rc = run_preprocess(*w, points, (uint32_t)n, false, out_idx, out_count, Part::kTail);
+    } else {
+        CH_TRY(hipStreamSynchronize(stream));  // (the head queued every kernel)
+        rc = w->h_hdr->err & kErrDomain ? CH_EDOMAIN : w->h_hdr->err ? CH_EHIP : CH_OK;
+    }
     if (rc == CH_OK && w->h_hdr->fin_done && !w->h_hdr->fin_fail) {
         // finished on the device: the hull is in out_idx / out_count
         for (int q = 0; q < 4; ++q) {
