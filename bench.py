@@ -88,6 +88,9 @@ def parse():
                     help="skip the plain per-set comparison of the batched measurement")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--profile-config", default="",
+                    help="only run one per-configuration input (a PER_CONFIG name) --warmup + --steps times "
+                         "through hull2d_async, for profiler traces of that input alone")
     return ap.parse_args()
 
 
@@ -460,6 +463,25 @@ def measure_serving(ch, wl, torch, dev, args):
     }
 
 
+def profile_config(ch, wl, torch, dev, args):
+    """One per-configuration input alone, for a profiler: --warmup + --steps
+    hull2d_async calls, one synchronisation at the end; prints one JSON line
+    naming it."""
+    cfg = {c[0]: c for c in PER_CONFIG}.get(args.profile_config)
+    if cfg is None:
+        raise SystemExit(f"unknown configuration {args.profile_config!r}; one of {[c[0] for c in PER_CONFIG]}")
+    name, dist, n, seed, _ = cfg
+    d = torch.from_numpy(wl.generate(dist, n, seed)).to(dev)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup + args.steps):
+        rc = ch.hull2d_async(d, out, cnt)
+        if rc != ch.CH_OK:
+            raise ch.ChainHullError(rc, f"hull2d_async {name}")
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_config": name, "n": n, "calls": args.warmup + args.steps, "hull": int(cnt.item())}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -476,6 +498,9 @@ def main():
         from paper_1508_05488_amd import build as lib_build
         lib_build.build()
     dev = torch.device("cuda:0")
+    if args.profile_config:
+        profile_config(ch, wl, torch, dev, args)
+        return
     n = args.n
     host = {d: wl.generate(d, n, seed) for d, seed in DISTS}
     inputs = {d: torch.from_numpy(host[d]).to(dev) for d, _ in DISTS}

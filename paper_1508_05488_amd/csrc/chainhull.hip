@@ -441,8 +441,9 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // the region sort and SPA unchanged, so any filter that only drops dominated
 // points may run before them.
 //
-// Sampled staircases.  k_sample takes a sample of kSamplePts points
-// (kSampleBlocks evenly spaced runs of consecutive points) and records, in
+// Sampled staircases.  k_sample takes a sample of up to kSamplePts points
+// (up to kSampleBlocks evenly spaced runs of consecutive points, about one
+// run per eight of the input) and records, in
 // each of the four region frames, the smallest k2 per slot of 2^kStairShift
 // k1 values, over all sample points (not only the region's), then turns them
 // into exclusive prefix minima over the slots.  A sample
@@ -493,22 +494,24 @@ __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
 // Table layout: frame f's slots at [f*S, (f+1)*S), S = kStairSlots; R1 by
 // x-slot, R2 by y-slot, R3 by (M-x)-slot, R4 by (M-y)-slot.  k_cand clears
 // the table again once k_stream has read it.
-__global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts, uint32_t n,
-                                                   uint32_t* __restrict__ stab, const int32_t* __restrict__ gate)
+__global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts, uint32_t n, uint32_t runs,
+                                                   uint32_t step, uint64_t mul, uint32_t* __restrict__ stab,
+                                                   const int32_t* __restrict__ gate)
 {
     __shared__ __align__(16) uint32_t st[4 * kStairSlots];
     const uint32_t tid = threadIdx.x;
     if (gated_off(gate)) return;
     for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
     __syncthreads();
-    constexpr uint32_t kRun = kBlock * kSamplePerThread;
-    const bool runs = n >= kSamplePts;
-    const uint32_t start = runs ? (uint32_t)(((u64)blockIdx.x * (n - kRun)) / (kSampleBlocks - 1)) : 0u;
+    // runs: workgroup b's run starts at b * step; otherwise (an input smaller
+    // than the gridDim.x runs) sample j reads point floor(j * mul / 2^32),
+    // mul = floor(n * 2^32 / (gridDim.x * kBlock * kSamplePerThread)) < n
+    const uint32_t start = blockIdx.x * step;
     uint32_t X[kSamplePerThread], Y[kSamplePerThread];  // every point load of a thread in flight together
 #pragma unroll
     for (int k = 0; k < kSamplePerThread; ++k) {
         const uint32_t sidx = (blockIdx.x * kBlock + tid) * kSamplePerThread + k;
-        const uint32_t i = runs ? start + k * kBlock + tid : (uint32_t)(((u64)sidx * n) / kSamplePts);
+        const uint32_t i = runs ? start + k * kBlock + tid : (uint32_t)(((u64)sidx * mul) >> 32);
         const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
         // out-of-domain values only need to stay in range here: such a call
         // fails with a domain error
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     };
     // (out-of-domain coordinates only need to index the staircase in range:
     // such a call fails with a domain error)
-    auto slot_of = [](uint32_t v) { return (v >> kStairShift) & (kStairSlots - 1); };
+    auto slot_of = [](uint32_t v) { return __builtin_amdgcn_ubfe(v, kStairShift, kStairBits); };
     auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
         const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
         ext_check(a, fx, fy, X, Y);
@@ -2609,6 +2612,14 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     if (P2 <= 64) {
         if (wave == 0) wave_sort_keys<1>(skey, P2);
         __syncthreads();
+    } else if (nsort <= (uint32_t)kBatchBlock) {
+        // by rank: each thread counts the keys below its own (distinct keys)
+        const u64 mine = tid < nsort ? skey[tid] : 0ull;
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < nsort; ++j) rank += skey[j] < mine ? 1u : 0u;
+        __syncthreads();
+        if (tid < nsort) skey[rank] = mine;
+        __syncthreads();
     } else {
         for (uint32_t size = 2; size <= P2; size <<= 1) {
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
@@ -3780,7 +3791,17 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
                                          (uint32_t)(4 * kStairSlots)));
         }
         guard.armed = true;
-        CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(kSampleBlocks), dim3(kBlock), 0, s, pts, n, w.stab, gate));
+        // one run of kBlock * kSamplePerThread points per 8 such runs of the
+        // input, from 4 to kSampleBlocks runs
+        const uint32_t sblocks = (uint32_t)std::min<uint64_t>(
+            kSampleBlocks, std::max<uint64_t>(4, (uint64_t)n / (8ull * kBlock * kSamplePerThread)));
+        const uint64_t total = (uint64_t)sblocks * kBlock * kSamplePerThread;
+        const uint32_t runs = n >= total ? 1u : 0u;
+        const uint32_t step =
+            runs && sblocks > 1 ? (uint32_t)((n - (uint64_t)kBlock * kSamplePerThread) / (sblocks - 1)) : 0u;
+        const uint64_t mul = runs ? 0ull : ((uint64_t)n << 32) / total;
+        CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(sblocks), dim3(kBlock), 0, s, pts, n, runs, step, mul, w.stab,
+                                     gate));
         CH_TRY(record(w, 1));
         if (tu.stream_unroll == 2) {
             CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
