@@ -630,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     // Workgroup b streams float4s [b*per, (b+1)*per) of the aligned part, a
     // round of kBlock*kStreamUnroll at a time.  Every lane runs the same
     // number of rounds (the list append is wave-wide); lanes past the range
-    // reread the last float4, which changes nothing and lists nothing.  The
+    // reread its last float4, which changes nothing and lists nothing.  The
     // sample table's loads go first and the first round's point loads right
     // after them, so that the wait for the table (loads complete in issue
     // order) leaves the point loads in flight while the staircases are built.
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     auto load_round = [&](uint32_t r, v4f* v) {
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u)
-            v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, n4 - 1));
+            v[u] = __builtin_nontemporal_load(p4 + min(lo + r * kRound + u * kBlock + tid, hi - 1));
     };
     // wave f holds frame f, lane l its slots l, l + 64, ..., l + 960
     // (coalesced loads; consecutive lanes write neighbouring LDS words)
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         const v4f* src = rounds ? p4 : reinterpret_cast<const v4f*>(stab);
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u)
-            va[u] = __builtin_nontemporal_load(src + (rounds ? min(lo + u * kBlock + tid, n4 - 1) : 0u));
+            va[u] = __builtin_nontemporal_load(src + (rounds ? min(lo + u * kBlock + tid, hi - 1) : 0u));
     }
     {
         // The staircases: per frame the exclusive prefix minimum of the slot
@@ -737,40 +737,37 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     };
 
     if (blockIdx.x == 0 && wave == 0 && head) visit_one(pts[0], pts[1], 0, lane == 0);
-    auto test_round = [&](uint32_t r, const v4f* v) {
-        constexpr int kP = 2 * kStreamUnroll;
-        float fxy[2 * kP];
-        uint32_t idx[kP];
-        bool valid[kP];
+    // One round: the conversions and the domain checks take the loaded
+    // values first, then the next round's loads reuse their registers, so
+    // that the staircase reads, the tests and the list appends run with the
+    // next round in flight.  The loads are unconditional (past the last
+    // round they reread the range's last float4).
+    constexpr int kP = 2 * kStreamUnroll;
+    for (uint32_t r = 0; r < rounds; ++r) {
+        uint32_t X[kP], Y[kP];
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u) {
-            const uint32_t g0 = lo + r * kRound + u * kBlock + tid, g = min(g0, n4 - 1);
-            fxy[4 * u + 0] = v[u].x;
-            fxy[4 * u + 1] = v[u].y;
-            fxy[4 * u + 2] = v[u].z;
-            fxy[4 * u + 3] = v[u].w;
-            idx[2 * u] = head + 2 * g;
-            idx[2 * u + 1] = head + 2 * g + 1;
-            valid[2 * u] = valid[2 * u + 1] = g0 < hi;
+            const float f[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                X[2 * u + h] = cvt_u32_sat(f[2 * h]);
+                Y[2 * u + h] = cvt_u32_sat(f[2 * h + 1]);
+                ext_check(a, f[2 * h], f[2 * h + 1], X[2 * u + h], Y[2 * u + h]);
+            }
         }
+        load_round(r + 1, va);
         // all staircase reads first, then the tests: one wait per round
-        uint32_t X[kP], Y[kP];
         u64 sxv[kP], syv[kP];
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
-            X[p] = cvt_u32_sat(fxy[2 * p]);
-            Y[p] = cvt_u32_sat(fxy[2 * p + 1]);
             sxv[p] = sx64[slot_of(X[p])];
             syv[p] = sy64[slot_of(Y[p])];
         }
 #pragma unroll
-        for (int p = 0; p < kP; ++p) ext_check(a, fxy[2 * p], fxy[2 * p + 1], X[p], Y[p]);
-#pragma unroll
-        for (int p = 0; p < kP; ++p) list_point(X[p], Y[p], idx[p], valid[p], sxv[p], syv[p]);
-    };
-    for (uint32_t r = 0; r < rounds; ++r) {
-        if (r) load_round(r, va);
-        test_round(r, va);
+        for (int p = 0; p < kP; ++p) {
+            const uint32_t g0 = lo + r * kRound + (p / 2) * kBlock + tid, g = min(g0, n4 - 1);
+            list_point(X[p], Y[p], head + 2 * g + (p & 1), g0 < hi, sxv[p], syv[p]);
+        }
     }
     if (blockIdx.x == 0 && wave == 0 && ((n - head) & 1u))
         visit_one(pts[2 * (n - 1)], pts[2 * (n - 1) + 1], n - 1, lane == 0);
