@@ -172,6 +172,14 @@ struct Buckets {
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
+// The lanes whose predicate holds.
+__device__ inline u64 ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+// The lanes with a > b (unsigned): the comparison's lane mask as it is (a
+// ballot of a combination of comparisons goes through a register and a
+// second comparison).
+__device__ inline u64 cmp_mask_gt(uint32_t a, uint32_t b) { return __builtin_amdgcn_uicmp(a, b, 34 /* ugt */); }
+
 // Cross-workgroup hand-offs inside one kernel.  The last workgroup to
 // arrive reads what the others wrote: they store it with device-scope
 // stores (written through to where every XCD sees it, instead of a
@@ -400,22 +408,49 @@ __device__ inline void ext_combine(ExtAcc& a, const ExtAcc& b)
     a.hi = max(a.hi, b.hi);
 }
 
+// The smallest value over the wave, in every lane: DPP row shifts inside
+// each row of 16 lanes, then the four rows' minima by readlane (no LDS
+// crossbar round trips).
+__device__ inline uint32_t wave_min_all(uint32_t v)
+{
+    v = min(v, dpp_row_shr(v, 1));
+    v = min(v, dpp_row_shr(v, 2));
+    v = min(v, dpp_row_shr(v, 4));
+    v = min(v, dpp_row_shr(v, 8));
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return min(min(r0, r1), min(r2, r3));
+}
+
+// The lexicographically smallest (hi, lo) over the wave and, among the lanes
+// holding it, the smallest index: three wave minima.
+__device__ inline void wave_lex_min(uint32_t& hi, uint32_t& lo, uint32_t& idx)
+{
+    const uint32_t mh = wave_min_all(hi);
+    const uint32_t ml = wave_min_all(hi == mh ? lo : ~0u);
+    idx = wave_min_all(hi == mh && lo == ml ? idx : ~0u);
+    hi = mh;
+    lo = ml;
+}
+
+// Every lane ends with the wave's result (ties of a key to the smaller index,
+// as take_min / take_max); maxima as minima of the complements.
 __device__ inline void ext_wave_reduce(ExtAcc& a)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        ExtAcc b;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            b.kmin[e] = __shfl_xor(a.kmin[e], off);
-            b.kmax[e] = __shfl_xor(a.kmax[e], off);
-            b.imin[e] = __shfl_xor(a.imin[e], off);
-            b.imax[e] = __shfl_xor(a.imax[e], off);
-        }
-        b.bad = __shfl_xor(a.bad, off);
-        b.hi = __shfl_xor(a.hi, off);
-        ext_combine(a, b);
+    for (int e = 0; e < 2; ++e) {
+        uint32_t h = (uint32_t)(a.kmin[e] >> 32), l = (uint32_t)a.kmin[e];
+        wave_lex_min(h, l, a.imin[e]);
+        a.kmin[e] = ((u64)h << 32) | l;
+        h = ~(uint32_t)(a.kmax[e] >> 32);
+        l = ~(uint32_t)a.kmax[e];
+        wave_lex_min(h, l, a.imax[e]);
+        a.kmax[e] = ((u64)~h << 32) | ~l;
     }
+    a.hi = ~wave_min_all(~a.hi);
+    a.bad = ballot(a.bad) != 0;
 }
 
 // Reduce over the workgroup (W waves); thread 0 gets the result.
@@ -680,6 +715,24 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             sst[at] = excl;
         }
     }
+    __syncthreads();
+    {
+        // Each slot's two frames as one interval of the other coordinate: a
+        // point is dominated in both iff y (x-slots: R1 and R3) or x (y-slots:
+        // R4 and R2) lies in [a, a + w].  R1 holds y < s1 open and R3 y >
+        // M - s3, so the interval is [s1, M - s3]; R4 and R2 give [s4, M - s2].
+        // Stored as a | w << 32; an empty interval as a = ~0u, w = 0 (every
+        // point of the slot is open).
+        u64* const s64 = reinterpret_cast<u64*>(sst);
+        for (int e = tid; e < 2 * kStairSlots; e += kBlock) {
+            const u64 v = s64[e];
+            const bool xs = e < kStairSlots;
+            const uint32_t lo = xs ? (uint32_t)v : (uint32_t)(v >> 32);   // s1 or s4
+            const uint32_t cf = xs ? (uint32_t)(v >> 32) : (uint32_t)v;   // s3 or s2
+            const bool some = cf <= kM && lo <= kM - cf;
+            s64[e] = some ? ((u64)(kM - cf - lo) << 32) | lo : (u64)~0u;
+        }
+    }
     if (tid == 0) s_fill = 0;
     __syncthreads();
     uint32_t* const my_idx = open_idx + (size_t)blockIdx.x * region;
@@ -710,14 +763,18 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     // wave calls it together (the list append is wave-wide); the branch is
     // taken when some lane of the wave has an open point.
     auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
-        const bool o1 = Y < (uint32_t)sxv;                  // R1: k2 = y
-        const bool o2 = (X ^ kM) < (uint32_t)syv;           // R2: k2 = M - x
-        const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);   // R3: k2 = M - y
-        const bool o4 = X < (uint32_t)(syv >> 32);          // R4: k2 = x
-        const bool open = (o1 | o2 | o3 | o4) & valid;
-        const u64 bal = __ballot(open);
+        const uint32_t ax = (uint32_t)sxv, wx = (uint32_t)(sxv >> 32);
+        const uint32_t ay = (uint32_t)syv, wy = (uint32_t)(syv >> 32);
+        // outside an interval (below a wraps around past w); the lane masks
+        // of the comparisons combine as they are
+        const u64 bal = (cmp_mask_gt(Y - ax, wx) | cmp_mask_gt(X - ay, wy)) & ballot(valid);
         if (bal) {
-            if (open) {
+            if ((bal >> lane) & 1u) {
+                // its frames: R1 below the y interval, R3 above it, R4 below
+                // the x interval, R2 above it; an empty interval opens both
+                const bool ex = ax == ~0u, ey = ay == ~0u;
+                const bool o1 = ex | (Y < ax), o3 = ex | (Y > ax + wx);
+                const bool o4 = ey | (X < ay), o2 = ey | (X > ay + wy);
                 const uint32_t mask = (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
                 const uint32_t slot = wcount + (uint32_t)__popcll(bal & lt);
                 lidx[wave][slot] = idx;
@@ -2321,7 +2378,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);  // R3: k2 = M - y
             const bool o4 = X < (uint32_t)(syv >> 32);         // R4: k2 = x
             const bool open = valid && (o1 || o2 || o3 || o4);
-            const u64 bal = __ballot(open);
+            const u64 bal = ballot(open);
             if (bal) {
                 uint32_t first = 0;
                 if (lane == 0) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
