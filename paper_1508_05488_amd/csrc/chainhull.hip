@@ -31,8 +31,9 @@
 //   DevHeader        extreme points, quadrilateral edges, frames, counters;
 //                    with the look-back states and the sample table it is
 //                    zeroed when the workspace is allocated
-//   stab             the sample's slot minima, complemented (4 x 1024 words;
-//                    zero again after every call)
+//   stab             the sample's slot minima, complemented (4 x 1024 words,
+//                    then 4 x 256 for the frames' first slots; zero again
+//                    after every call)
 //   ExtPartial[G]    per-workgroup extreme keys
 //   open lists       per k_stream workgroup: index; x | y << 23 | mask << 46
 //   key[2], val[2]   records: u32 q << 23 | k1, u64 k2 << 32 | index; per
@@ -512,8 +513,27 @@ constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThr
 constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
+// Each frame's first slot (k1 below 2^kStairShift) again at a finer step:
+// its test has no earlier slot, so without these every point of it would
+// pass (the four edge strips of a uniform input hold 4 / kStairSlots of it).
+constexpr int kEdgeBits = 8;
+constexpr int kEdgeSub = 1 << kEdgeBits;
+constexpr int kEdgeShift = kStairShift - kEdgeBits;
+constexpr int kStabWords = 4 * kStairSlots + 4 * kEdgeSub;  // the sample table
 constexpr int kStreamGrid = 1024;   // k_stream workgroups at most (the partials' room)
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
+
+// The frames in which a point outside its slots' intervals is open (bit
+// f - 1 for frame Rf): R1 below the y interval [ax, ax + wx], R3 above it,
+// R4 below the x interval [ay, ay + wy], R2 above it; an empty interval
+// (a = ~0u) opens both of its frames.
+__device__ inline uint32_t open_frames(uint32_t X, uint32_t Y, uint32_t ax, uint32_t wx, uint32_t ay, uint32_t wy)
+{
+    const bool ex = ax == ~0u, ey = ay == ~0u;
+    const bool o1 = ex | (Y < ax), o3 = ex | (Y > ax + wx);
+    const bool o4 = ey | (X < ay), o2 = ey | (X > ay + wy);
+    return (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
+}
 
 // Open-point record: X | Y << 23 | frame mask << 46.
 __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
@@ -533,10 +553,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
                                                    uint32_t step, uint64_t mul, uint32_t* __restrict__ stab,
                                                    const int32_t* __restrict__ gate)
 {
-    __shared__ __align__(16) uint32_t st[4 * kStairSlots];
+    __shared__ __align__(16) uint32_t st[kStabWords];
     const uint32_t tid = threadIdx.x;
     if (gated_off(gate)) return;
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock) st[e] = ~0u;
+    for (int e = tid; e < kStabWords; e += kBlock) st[e] = ~0u;
     __syncthreads();
     // runs: workgroup b's run starts at b * step; otherwise (an input smaller
     // than the gridDim.x runs) sample j reads point floor(j * mul / 2^32),
@@ -560,9 +580,20 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
         atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
         atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
         atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
+        // a frame's first slot by sub-slot as well (few points: one wave-wide
+        // test first)
+        constexpr uint32_t E = 4 * kStairSlots;
+        const bool ex0 = (X[k] >> kStairShift) == 0, ey0 = (Y[k] >> kStairShift) == 0;
+        const bool ex1 = (xm >> kStairShift) == 0, ey1 = (ym >> kStairShift) == 0;
+        if (ballot(ex0 | ey0 | ex1 | ey1)) {
+            if (ex0) atomicMin(&st[E + 0 * kEdgeSub + (X[k] >> kEdgeShift)], Y[k]);
+            if (ey0) atomicMin(&st[E + 1 * kEdgeSub + (Y[k] >> kEdgeShift)], xm);
+            if (ex1) atomicMin(&st[E + 2 * kEdgeSub + (xm >> kEdgeShift)], ym);
+            if (ey1) atomicMin(&st[E + 3 * kEdgeSub + (ym >> kEdgeShift)], X[k]);
+        }
     }
     __syncthreads();
-    for (int e = tid; e < 4 * kStairSlots; e += kBlock)
+    for (int e = tid; e < kStabWords; e += kBlock)
         if (st[e] != ~0u) atomicMax(stab + e, ~st[e]);
 }
 
@@ -655,6 +686,8 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
 {
     if (gated_off(gate)) return;
     __shared__ __align__(16) uint32_t sst[4 * kStairSlots];
+    __shared__ __align__(16) u64 ssub[4 * kEdgeSub];  // the first slots' intervals by sub-slot
+    __shared__ uint32_t s_last[4];                      // each frame's staircase at its last slot
     __shared__ uint32_t lidx[kWaves][kWaveList];
     __shared__ u64 lxym[kWaves][kWaveList];
     __shared__ ExtAcc sh[kWaves];
@@ -683,9 +716,12 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     // (coalesced loads; consecutive lanes write neighbouring LDS words)
     constexpr int kPer = kStairSlots / 64;  // 16
     static_assert(4 * 64 == kBlock, "one wave per frame");
-    uint32_t sv[kPer];
+    constexpr int kEdgePer = kEdgeSub / 64;  // 4
+    uint32_t sv[kPer], ev[kEdgePer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) sv[k] = stab[wave * kStairSlots + k * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < kEdgePer; ++k) ev[k] = stab[4 * kStairSlots + wave * kEdgeSub + k * 64 + lane];
     v4f va[kStreamUnroll];
     {
         // unconditional, so that no branch joins before the table wait (a
@@ -713,6 +749,17 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             const uint32_t sl = k * 64 + lane;
             const uint32_t at = q == 0 ? 2 * sl : q == 1 ? 2 * S + 2 * sl : q == 2 ? 2 * (S - 1 - sl) + 1 : 2 * S + 2 * (S - 1 - sl) + 1;
             sst[at] = excl;
+            if (k == kPer - 1 && lane == 63) s_last[q] = excl;
+        }
+        // the frame's first slot by sub-slot: prefix minima over its sub-slots
+        carry = ~0u;
+#pragma unroll
+        for (int k = 0; k < kEdgePer; ++k) {
+            uint32_t incl, excl, tot;
+            wave_min_scan(~ev[k], incl, excl, tot);
+            excl = min(excl, carry);
+            carry = min(carry, tot);
+            ssub[q * kEdgeSub + k * 64 + lane] = excl;
         }
     }
     __syncthreads();
@@ -723,14 +770,29 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         // M - s3, so the interval is [s1, M - s3]; R4 and R2 give [s4, M - s2].
         // Stored as a | w << 32; an empty interval as a = ~0u, w = 0 (every
         // point of the slot is open).
+        auto interval = [](uint32_t lo, uint32_t cf) -> u64 {
+            const bool some = cf <= kM && lo <= kM - cf;
+            return some ? ((u64)(kM - cf - lo) << 32) | lo : (u64)~0u;
+        };
         u64* const s64 = reinterpret_cast<u64*>(sst);
         for (int e = tid; e < 2 * kStairSlots; e += kBlock) {
             const u64 v = s64[e];
             const bool xs = e < kStairSlots;
             const uint32_t lo = xs ? (uint32_t)v : (uint32_t)(v >> 32);   // s1 or s4
             const uint32_t cf = xs ? (uint32_t)(v >> 32) : (uint32_t)v;   // s3 or s2
-            const bool some = cf <= kM && lo <= kM - cf;
-            s64[e] = some ? ((u64)(kM - cf - lo) << 32) | lo : (u64)~0u;
+            s64[e] = interval(lo, cf);
+        }
+        // The first slots by sub-slot: frame R1's first slot is x-slot 0,
+        // whose interval of y is [s1, M - s3] with s3 of that x-slot (R3's
+        // last slot); R2's is y-slot 0 ([s4, M - s2], s4 of R4's last slot);
+        // R3's x-slot S - 1 (s1 of R1's last slot); R4's y-slot S - 1 (s2 of
+        // R2's last slot).
+        for (int e = tid; e < 4 * kEdgeSub; e += kBlock) {
+            const uint32_t f = e / kEdgeSub, v = (uint32_t)ssub[e];
+            ssub[e] = f == 0 ? interval(v, s_last[2])
+                    : f == 1 ? interval(s_last[3], v)
+                    : f == 2 ? interval(s_last[0], v)
+                             : interval(v, s_last[1]);
         }
     }
     if (tid == 0) s_fill = 0;
@@ -744,12 +806,51 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     ext_init(a);
     uint32_t wcount = 0;  // the same in every lane of a wave
 
+    // Flush the wave's list: a listed point of a frame's first slot is
+    // tested again with that frame by sub-slot (the other frames as
+    // before); the points that stay open are compacted in place (an entry
+    // moves only to a position at or before its own, after every lane has
+    // read its entry) and written to the workgroup's region.
     auto flush = [&]() {
+        constexpr uint32_t S = kStairSlots;
+        uint32_t kept = 0;  // the same in every lane
+        for (uint32_t e0 = 0; e0 < wcount; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            bool keep = false;
+            uint32_t i = 0;
+            u64 r = 0;
+            if (e < wcount) {
+                i = lidx[wave][e];
+                r = lxym[wave][e];
+                keep = true;
+                const uint32_t X = (uint32_t)r & kM, Y = (uint32_t)(r >> 23) & kM;
+                const uint32_t xs = X >> kStairShift, ys = Y >> kStairShift;
+                if (xs == 0 || xs == S - 1 || ys == 0 || ys == S - 1) {
+                    const u64 sxv = xs == 0       ? ssub[0 * kEdgeSub + (X >> kEdgeShift)]
+                                    : xs == S - 1 ? ssub[2 * kEdgeSub + ((X ^ kM) >> kEdgeShift)]
+                                                  : sx64[xs];
+                    const u64 syv = ys == 0       ? ssub[1 * kEdgeSub + (Y >> kEdgeShift)]
+                                    : ys == S - 1 ? ssub[3 * kEdgeSub + ((Y ^ kM) >> kEdgeShift)]
+                                                  : sy64[ys];
+                    const uint32_t ax = (uint32_t)sxv, wx = (uint32_t)(sxv >> 32);
+                    const uint32_t ay = (uint32_t)syv, wy = (uint32_t)(syv >> 32);
+                    keep = (Y - ax > wx) || (X - ay > wy);
+                    r = open_rec(X, Y, open_frames(X, Y, ax, wx, ay, wy));
+                }
+            }
+            const u64 kb = ballot(keep);
+            const uint32_t at = kept + (uint32_t)__popcll(kb & lt);
+            if (keep) {
+                lidx[wave][at] = i;
+                lxym[wave][at] = r;
+            }
+            kept += (uint32_t)__popcll(kb);
+        }
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&s_fill, wcount);
+        if (lane == 0) base = atomicAdd(&s_fill, kept);
         base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);  // (every lane is active here)
         __builtin_amdgcn_wave_barrier();
-        for (uint32_t e = lane; e < wcount; e += 64) {
+        for (uint32_t e = lane; e < kept; e += 64) {
             const uint32_t i = lidx[wave][e];
             const u64 r = lxym[wave][e];
             ext_take(a, (uint32_t)r & kM, (uint32_t)(r >> 23) & kM, i);
@@ -759,6 +860,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         __builtin_amdgcn_wave_barrier();
         wcount = 0;
     };
+    // (out-of-domain coordinates only need to index the staircase in range:
+    // such a call fails with a domain error)
+    auto slot_of = [](uint32_t v) { return __builtin_amdgcn_ubfe(v, kStairShift, kStairBits); };
     // One point of every lane: list it if it is open.  Every lane of the
     // wave calls it together (the list append is wave-wide); the branch is
     // taken when some lane of the wave has an open point.
@@ -770,12 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         const u64 bal = (cmp_mask_gt(Y - ax, wx) | cmp_mask_gt(X - ay, wy)) & ballot(valid);
         if (bal) {
             if ((bal >> lane) & 1u) {
-                // its frames: R1 below the y interval, R3 above it, R4 below
-                // the x interval, R2 above it; an empty interval opens both
-                const bool ex = ax == ~0u, ey = ay == ~0u;
-                const bool o1 = ex | (Y < ax), o3 = ex | (Y > ax + wx);
-                const bool o4 = ey | (X < ay), o2 = ey | (X > ay + wy);
-                const uint32_t mask = (o1 ? 1u : 0u) | (o2 ? 2u : 0u) | (o3 ? 4u : 0u) | (o4 ? 8u : 0u);
+                const uint32_t mask = open_frames(X, Y, ax, wx, ay, wy);
                 const uint32_t slot = wcount + (uint32_t)__popcll(bal & lt);
                 lidx[wave][slot] = idx;
                 lxym[wave][slot] = open_rec(X & kM, Y & kM, mask);
@@ -784,9 +883,6 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
             if (wcount > (uint32_t)(kWaveList - 64)) flush();
         }
     };
-    // (out-of-domain coordinates only need to index the staircase in range:
-    // such a call fails with a domain error)
-    auto slot_of = [](uint32_t v) { return __builtin_amdgcn_ubfe(v, kStairShift, kStairBits); };
     auto visit_one = [&](float fx, float fy, uint32_t idx, bool valid) {
         const uint32_t X = cvt_u32_sat(fx), Y = cvt_u32_sat(fy);
         ext_check(a, fx, fy, X, Y);
@@ -944,7 +1040,7 @@ __global__ __launch_bounds__(kCandBlock) void k_cand(DevHeader* __restrict__ hdr
     const uint32_t gpre = block_excl_sum<kCandWaves>(mine, scratch, open);  // open points of lists < tid
     if (blockIdx.x == 0) {
         // k_stream has read the sample table: cleared for the next call
-        for (int e = tid; e < 4 * kStairSlots; e += kCandBlock) stab[e] = 0;
+        for (int e = tid; e < kStabWords; e += kCandBlock) stab[e] = 0;
     }
     if (blockIdx.x == 0 && tid == 0) {
         // the call's header: the quadrilateral and the open count for the
@@ -1952,6 +2048,24 @@ constexpr int kBatchSlots = 512;                                   // k1 slots p
 constexpr int kBatchSlotShift = 23 - 9;                            // log2(kBatchSlots) = 9
 constexpr int kBatchPosBits = 14;                                  // list position in a sort key
 static_assert(kBatchSlots == 1 << (23 - kBatchSlotShift) && kBatchList <= 1 << kBatchPosBits, "slots");
+
+// The list mode's filter slot of a record: d = k1 minus the k1 of its
+// region's first point (the region's smallest); exact below 16, then 16
+// slots per power of two up to 2^19 (a relative step of 1/16, from the
+// float exponent and the top mantissa bits), then steps of 2^15.  Fine where
+// a region's chain starts steep (k_stream's open points of a uniform input
+// crowd there: its edge strips), no coarser than 2^15 further on;
+// non-decreasing in d, so an earlier slot still means a smaller k1.  (The
+// batched path keeps even steps of 2^kBatchSlotShift.)
+__device__ inline uint32_t list_slot(uint32_t d)
+{
+    if (d < 16u) return d;
+    if (d < (1u << 19)) return (__float_as_uint((float)d) >> 19) - (131u << 4) + 16u;  // exact float
+    return 256u + (min(d, (1u << 23) - 1u) >> 15) - 16u;
+}
+// (2^19 - 1 maps to slot 255, 2^19 to 256; any d, an out-of-domain set's
+// too, below 256 + 2^8 - 16)
+static_assert(((145u - 131u) << 4) + 15u + 16u == 255u && 256u + 256u - 16u <= (uint32_t)kBatchSlots, "list_slot range");
 constexpr int kBatchChunks = 64, kBatchChunk = 128;                // the first staircase sample
 constexpr int kBatchRounds = 32;                                   // pre-hull rounds at most
 constexpr int64_t kBatchMaxSet = 1 << 22;                          // larger sets: single-hull path
@@ -2309,22 +2423,43 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             return;
         }
         __syncthreads();
+        // Entry e of the list: the last list with start <= e (binary
+        // searches of a thread's entries side by side), then every load of
+        // the thread in flight together (past L: the first list's first
+        // slot, read and dropped), then the LDS writes.
+        size_t at[kBatchPerList];
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) at[k] = 0;
+        for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kBatchPerList; ++k) {
+                const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
+                if (l + st < nl && s_lst[l + st] <= e) at[k] = l + st;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
+            at[k] = e < L ? (size_t)l * src.region + (e - s_lst[l]) : 0;
+        }
+        uint32_t gi[kBatchPerList];
+        u64 gr[kBatchPerList];
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            gi[k] = src.idx[at[k]];
+            gr[k] = src.xym[at[k]];
+        }
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             const uint32_t e = k * kBatchBlock + tid;
             if (e < L) {
-                uint32_t l = 0;  // the last list with start <= e
-                for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1)
-                    if (l + st < nl && s_lst[l + st] <= e) l += st;
-                const size_t at = (size_t)l * src.region + (e - s_lst[l]);
-                lidx[e] = src.idx[at];
-                const u64 r = src.xym[at];
-                s_lxy[2 * e] = (uint32_t)r & kM;
-                s_lxy[2 * e + 1] = (uint32_t)(r >> 23) & kM;
+                lidx[e] = gi[k];
+                s_lxy[2 * e] = (uint32_t)gr[k] & kM;
+                s_lxy[2 * e + 1] = (uint32_t)(gr[k] >> 23) & kM;
             }
         }
         if (tid == 0) s_n = L;
-        for (int e = tid; e < 4 * kStairSlots; e += kBatchBlock) src.stab[e] = 0;
+        for (int e = tid; e < kStabWords; e += kBatchBlock) src.stab[e] = 0;
         __syncthreads();
     } else {
     constexpr uint32_t S = kStairSlots;
@@ -2566,6 +2701,12 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
 
     // ---- exact regions and region slot minima of the listed points ----
     u64 rec[kBatchPerList];
+    uint32_t kf[4];  // k1 of each region's first point
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t k2;
+        to_frame((uint32_t)q, Q.X[q], Q.Y[q], kf[q], k2);
+    }
     {
         uint32_t id[kBatchPerList];
         v2f v[kBatchPerList];
@@ -2597,7 +2738,9 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                 if (q < 4) {
                     uint32_t k1, k2;
                     to_frame(q, X, Y, k1, k2);
-                    atomicMin(&smin[q * kBatchSlots + (k1 >> kBatchSlotShift)], ((u64)k2 << 23) | k1);
+                    const uint32_t f = q == 0 ? kf[0] : q == 1 ? kf[1] : q == 2 ? kf[2] : kf[3];
+                    const uint32_t sl = kFromLists ? list_slot(k1 - f) : (k1 >> kBatchSlotShift);
+                    atomicMin(&smin[q * kBatchSlots + sl], ((u64)k2 << 23) | k1);
                     rec[k] = ((u64)q << 46) | ((u64)k1 << 23) | k2;
                 }
             }
@@ -2639,7 +2782,8 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     for (int k = 0; k < kBatchPerList; ++k) {
         if (rec[k] != ~0ull) {
             const uint32_t q = (uint32_t)(rec[k] >> 46), k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
-            const uint32_t sl = q * kBatchSlots + (k1 >> kBatchSlotShift);
+            const uint32_t f = q == 0 ? kf[0] : q == 1 ? kf[1] : q == 2 ? kf[2] : kf[3];
+            const uint32_t sl = q * kBatchSlots + (kFromLists ? list_slot(k1 - f) : (k1 >> kBatchSlotShift));
             const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
             if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) keep |= 1u << k;
         }
@@ -3546,7 +3690,7 @@ struct StreamShape {
 };
 
 // ---- launch shapes (ch_tuning), per size class ----
-constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18, 1 << 15, kBatchList};
+constexpr ch_tuning kDefaultTuning = {1024, 4, 2048, 1024, 1024, 2, 0, 1 << 18, 1 << 15, kBatchList / 2};
 constexpr int kTuningClasses = 16;
 std::mutex g_tune_mu;
 int g_tune_count = 0;
@@ -3622,7 +3766,7 @@ size_t layout(Workspace* w, char* base, size_t cap)
     // zeroed at allocation: the header, the look-back states, the sample table
     W.hdr = reinterpret_cast<DevHeader*>(take(sizeof(DevHeader)));
     W.states = reinterpret_cast<u64*>(take(sizeof(u64) * (cap / kSeg + 16)));
-    W.stab = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4 * kStairSlots));
+    W.stab = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kStabWords));
     W.part = reinterpret_cast<ExtPartial*>(take(sizeof(ExtPartial) * kStreamGrid));
     W.bk.cnt = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
     W.bk.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kBuckets));
@@ -3841,8 +3985,8 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
             // a call failed between k_sample and k_cand somewhere: clear this
             // workspace's sample table before it is used (a fill kernel, not a
             // memset, so that a capture records a kernel node)
-            CH_LAUNCH(hipLaunchKernelGGL(k_fill_u32, dim3(4 * kStairSlots / kBlock), dim3(kBlock), 0, s, w.stab, 0u,
-                                         (uint32_t)(4 * kStairSlots)));
+            CH_LAUNCH(hipLaunchKernelGGL(k_fill_u32, dim3(kStabWords / kBlock), dim3(kBlock), 0, s, w.stab, 0u,
+                                         (uint32_t)kStabWords));
         }
         guard.armed = true;
         // one run of kBlock * kSamplePerThread points per 8 such runs of the

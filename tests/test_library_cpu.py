@@ -113,7 +113,7 @@ def test_tuning_table_on_the_host():
     base = ch.get_tuning(-1)
     assert base == {"stream_grid": 1024, "stream_unroll": 4, "cand_per_row": 2048, "chain_grid": 1024,
                     "wide_grid": 1024, "batch_unroll": 2, "batch_order": 0, "serve_batch_max": 1 << 18,
-                    "fused_max": 1 << 15, "list_max": 8192}
+                    "fused_max": 1 << 15, "list_max": 4096}
     try:
         ch.set_tuning(1000, dict(base, stream_grid=256, cand_per_row=2048))
         ch.set_tuning(10**6, dict(base, stream_unroll=2))
