@@ -436,6 +436,16 @@ __device__ inline void wave_lex_min(uint32_t& hi, uint32_t& lo, uint32_t& idx)
     lo = ml;
 }
 
+// The smallest 64-bit value over the wave, in every lane (high words, then
+// the low words of the lanes holding the smallest high word).
+__device__ inline u64 wave_min_u64(u64 v)
+{
+    const uint32_t h = (uint32_t)(v >> 32), l = (uint32_t)v;
+    const uint32_t mh = wave_min_all(h);
+    const uint32_t ml = wave_min_all(h == mh ? l : ~0u);
+    return ((u64)mh << 32) | ml;
+}
+
 // Every lane ends with the wave's result (ties of a key to the smaller index,
 // as take_min / take_max); maxima as minima of the complements.
 __device__ inline void ext_wave_reduce(ExtAcc& a)
@@ -2399,7 +2409,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         uint32_t c[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const uint32_t l = u * kBatchBlock + tid;
+            const uint32_t l = 2 * tid + u;
             c[u] = 0;
             if (l < nl) {
                 c[u] = src.wgcount[l];
@@ -2411,30 +2421,32 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                 err |= pp.err;
             }
         }
-        // starts: list l at s_lst[l] (thread t: lists t and t + kBatchBlock)
-        uint32_t tot0, tot1;
-        const uint32_t e0 = block_excl_sum<kBatchWaves>(c[0], scratch, tot0);
-        const uint32_t e1 = block_excl_sum<kBatchWaves>(c[1], scratch, tot1);
-        if (tid < nl) s_lst[tid] = e0;
-        if (kBatchBlock + tid < nl) s_lst[kBatchBlock + tid] = tot0 + e1;
-        const uint32_t L = tot0 + tot1;
+        // starts: list l at s_lst[l] (thread t: lists 2t and 2t + 1)
+        uint32_t L;
+        const uint32_t e0 = block_excl_sum<kBatchWaves>(c[0] + c[1], scratch, L);
+        if (2 * tid < nl) s_lst[2 * tid] = e0;
+        if (2 * tid + 1 < nl) s_lst[2 * tid + 1] = e0 + c[0];
         if (L > src.cap) {
             if (tid == 0) out_counts[set] = kBatchRedo;
             return;
         }
         __syncthreads();
         // Entry e of the list: the last list with start <= e (binary
-        // searches of a thread's entries side by side), then every load of
-        // the thread in flight together (past L: the first list's first
-        // slot, read and dropped), then the LDS writes.
+        // searches of a thread's entries side by side, rows of entries that
+        // exist only), then every load of the thread in flight together
+        // (past L: the first list's first slot, read and dropped), then the
+        // LDS writes.
+        const uint32_t rows_used = (L + kBatchBlock - 1) / kBatchBlock;
         size_t at[kBatchPerList];
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) at[k] = 0;
         for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1) {
 #pragma unroll
             for (int k = 0; k < kBatchPerList; ++k) {
-                const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
-                if (l + st < nl && s_lst[l + st] <= e) at[k] = l + st;
+                if ((uint32_t)k < rows_used) {
+                    const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
+                    if (l + st < nl && s_lst[l + st] <= e) at[k] = l + st;
+                }
             }
         }
 #pragma unroll
@@ -2446,20 +2458,21 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         u64 gr[kBatchPerList];
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
-            gi[k] = src.idx[at[k]];
-            gr[k] = src.xym[at[k]];
+            if ((uint32_t)k < rows_used) {
+                gi[k] = src.idx[at[k]];
+                gr[k] = src.xym[at[k]];
+            }
         }
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             const uint32_t e = k * kBatchBlock + tid;
-            if (e < L) {
+            if ((uint32_t)k < rows_used && e < L) {
                 lidx[e] = gi[k];
                 s_lxy[2 * e] = (uint32_t)gr[k] & kM;
                 s_lxy[2 * e + 1] = (uint32_t)(gr[k] >> 23) & kM;
             }
         }
         if (tid == 0) s_n = L;
-        for (int e = tid; e < kStabWords; e += kBatchBlock) src.stab[e] = 0;
         __syncthreads();
     } else {
     constexpr uint32_t S = kStairSlots;
@@ -2649,14 +2662,11 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     
     }
     // ---- the extreme points and the quadrilateral ----
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        ek[0] = min(ek[0], (u64)__shfl_xor(ek[0], off));
-        ek[1] = min(ek[1], (u64)__shfl_xor(ek[1], off));
-        ek[2] = max(ek[2], (u64)__shfl_xor(ek[2], off));
-        ek[3] = max(ek[3], (u64)__shfl_xor(ek[3], off));
-    }
-    const bool wave_bad = __ballot((err & 0x7fffffffu) != 0 || hi > kM) != 0;
+    ek[0] = wave_min_u64(ek[0]);
+    ek[1] = wave_min_u64(ek[1]);
+    ek[2] = ~wave_min_u64(~ek[2]);
+    ek[3] = ~wave_min_u64(~ek[3]);
+    const bool wave_bad = ballot((err & 0x7fffffffu) != 0 || hi > kM) != 0;
     if (lane == 0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) s_ek[wave][e] = ek[e];
@@ -2694,6 +2704,8 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                 src.host_hdr->fin_done = 0;
             }
         }
+        if constexpr (kFromLists)  // (the tail does not run after a domain error)
+            for (int e = tid; e < kStabWords; e += kBatchBlock) src.stab[e] = 0;
         return;
     }
     const uint32_t L = s_n;
@@ -2932,6 +2944,10 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     const int h = poly_finish(Pl, npoly, rbase[1], out_idx + base, scratch, &s_flag, &s_ext, &s_start);
     if (tid == 0) out_counts[set] = h < 0 ? kBatchRedo : h;
     if constexpr (kFromLists) {
+        // the sample table, clear for the next call (after a hand-back the
+        // tail's k_cand clears it)
+        if (h >= 0)
+            for (int e = tid; e < kStabWords; e += kBatchBlock) src.stab[e] = 0;
         if (tid == 0 && h >= 0) {
             // the counts for the host (the single-hull kernels, gated off,
             // publish nothing)

@@ -153,6 +153,25 @@ def test_domain_errors(bad):
     assert_parity(wl.generate("square", 1000, seed=67), "after error")
 
 
+@pytest.mark.parametrize("bad", [np.nan, 0.5, 2.0 ** 23])
+def test_domain_error_in_the_list_mode_leaves_a_clean_sample_table(bad):
+    # above the small-input path: the pass over the points, then the list
+    # mode finds the error; the sample table must be clear for the calls
+    # after it (a stale table would drop hull points)
+    pts = wl.generate("square", 200_000, seed=69)
+    pts[54321, 1] = bad
+    say(f"  hull2d 200K bad value {bad}")
+    with pytest.raises(ch.ChainHullError) as e:
+        ch.hull2d(torch.from_numpy(pts).cuda())
+    assert e.value.status == ch.CH_EDOMAIN
+    out, cnt = torch.empty(200_000, dtype=torch.int32, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert ch.hull2d_async(torch.from_numpy(pts).cuda(), out, cnt) == 0
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == ch.CH_EDOMAIN
+    for dist, seed in (("disk", 70), ("square", 71), ("gaussian", 72)):
+        assert_parity(wl.generate(dist, 300_000, seed=seed), f"{dist} 300K after the error")
+
+
 def test_negative_zero_is_zero():
     pts = wl.generate("square", 5000, seed=68)
     pts[:100] = -0.0
