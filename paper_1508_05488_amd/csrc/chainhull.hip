@@ -119,6 +119,16 @@ constexpr int32_t kBatchRedo = INT32_MIN;  // a count: the batched kernel left t
 // only if it left kBatchRedo, and return at once otherwise.
 __device__ inline bool gated_off(const int32_t* gate) { return gate && *gate != kBatchRedo; }
 
+#ifdef CH_PHASE_TIMING
+// Instrumented builds only: the batched kernel's time per phase, summed over
+// the sets that finish ([0, 8): batched path, [8, 16): list mode; 100 MHz
+// ticks of the workgroup's thread 0), and the sets counted ([16], [17]).
+__device__ unsigned long long g_phase_ticks[18];
+#define CH_PHASE_MARK(k) (ph[k] = __builtin_amdgcn_s_memrealtime())
+#else
+#define CH_PHASE_MARK(k) ((void)0)
+#endif
+
 struct DevHeader {
     double ec[4];        // ex*E_q.y - ey*E_q.x for the edge E_q -> E_{q+1}
     int32_t ex[4], ey[4];
@@ -2384,6 +2394,10 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         return;
     }
     const uint32_t m = (uint32_t)(end - base);
+#ifdef CH_PHASE_TIMING
+    u64 ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#endif
+    CH_PHASE_MARK(0);
     const float* const ps = pts + 2 * base;
     const v2f* const p2 = reinterpret_cast<const v2f*>(ps);
     if (m == 0) {
@@ -2661,6 +2675,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         }
     
     }
+    CH_PHASE_MARK(1);
     // ---- the extreme points and the quadrilateral ----
     ek[0] = wave_min_u64(ek[0]);
     ek[1] = wave_min_u64(ek[1]);
@@ -2711,6 +2726,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     const uint32_t L = s_n;
     const Quad Q = sq;
 
+    CH_PHASE_MARK(2);
     // ---- exact regions and region slot minima of the listed points ----
     u64 rec[kBatchPerList];
     uint32_t kf[4];  // k1 of each region's first point
@@ -2816,6 +2832,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     for (uint32_t e = nsort + tid; e < P2; e += kBatchBlock) skey[e] = ~0ull;
     __syncthreads();
 
+    CH_PHASE_MARK(3);
     // ---- sort (ascending): up to 64 records in one wave's registers, more
     // by the workgroup's bitonic network in LDS (measured: a wave's network
     // over 256 records took 11 us against 7 us for the workgroup's) ----
@@ -2847,6 +2864,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         }
     }
 
+    CH_PHASE_MARK(4);
     // ---- SPA over the sorted records; chain positions ----
     // thread t holds sorted records [t*per, t*per + per), per <= 8
     const uint32_t per = (P2 + kBatchBlock - 1) / kBatchBlock;
@@ -2898,6 +2916,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     }
     __syncthreads();
 
+    CH_PHASE_MARK(5);
     // ---- the polygon in LDS (everything above is dead now) ----
     const BatchPoly Pl = poly_view(smem);
     const uint32_t npoly = nchain + 4;
@@ -2940,9 +2959,18 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     }
     __syncthreads();
 
+    CH_PHASE_MARK(6);
     // ---- pre-hull rounds, the finish ----
     const int h = poly_finish(Pl, npoly, rbase[1], out_idx + base, scratch, &s_flag, &s_ext, &s_start);
     if (tid == 0) out_counts[set] = h < 0 ? kBatchRedo : h;
+#ifdef CH_PHASE_TIMING
+    CH_PHASE_MARK(7);
+    if (tid == 0 && h >= 0) {
+        const int b = kFromLists ? 8 : 0;
+        for (int k = 0; k < 7; ++k) atomicAdd(&g_phase_ticks[b + k], ph[k + 1] - ph[k]);
+        atomicAdd(&g_phase_ticks[16 + (kFromLists ? 1 : 0)], 1ull);
+    }
+#endif
     if constexpr (kFromLists) {
         // the sample table, clear for the next call (after a hand-back the
         // tail's k_cand clears it)
@@ -4746,6 +4774,20 @@ int chainhull_get_tuning(int64_t n, ch_tuning* out)
     *out = n < 0 ? kDefaultTuning : tuning_for(n);
     return CH_OK;
 }
+
+#ifdef CH_PHASE_TIMING
+// Instrumented builds only (not declared in the public header): the batched
+// kernel's phase sums (18 values), read and cleared.
+int chainhull_phase_ticks(unsigned long long* out)
+{
+    if (!out) return CH_EINVAL;
+    CH_TRY(hipDeviceSynchronize());
+    CH_TRY(hipMemcpyFromSymbol(out, HIP_SYMBOL(chainhull::g_phase_ticks), sizeof(unsigned long long) * 18));
+    static const unsigned long long zero[18] = {};
+    CH_TRY(hipMemcpyToSymbol(HIP_SYMBOL(chainhull::g_phase_ticks), zero, sizeof(zero)));
+    return CH_OK;
+}
+#endif
 
 size_t chainhull_workspace_bytes(int64_t n)
 {
