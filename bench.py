@@ -688,7 +688,12 @@ def main():
     # the autotuner's launch shapes (a file under tuning/ for this GPU, applied
     # when the library loaded) against the built-in defaults, on the queued
     # path: the same steps again with the defaults
+    try:
+        key = ch.device_key()
+    except Exception as e:  # (reported, not fatal)
+        key = repr(e)
     tuning = {"source": os.path.relpath(ch.tuning_source(), ROOT) if ch.tuning_source() else None,
+              "device_key": key, "note": ch.tuning_note(),
               "shapes_20m": ch.get_tuning(n), "default_shapes": ch.get_tuning(-1)}
     if ch.tuning_source():
         ch.clear_tuning()

@@ -131,6 +131,7 @@ TUNING_DIR = os.path.join(_PKG, "tuning")
 
 _lib = None
 _tuning_loaded = None
+_tuning_note = None
 
 
 def lib():
@@ -224,19 +225,31 @@ def tuning_path(key: str | None = None) -> str:
 
 def load_tuning(path: str | None = None):
     """Apply the autotuner's saved shapes for the current GPU (a JSON file
-    under tuning/, written by autotune.py), when one exists.  Returns the
-    path applied, or None (defaults).  Without a GPU nothing is read."""
-    global _tuning_loaded
+    under tuning/, written by autotune.py), when one exists: the file of the
+    device's key, else the one file of its architecture (the device's
+    reported name can differ between processes, under a profiler for
+    instance).  Returns the path applied, or None (defaults; the reason in
+    tuning_note()).  Without a GPU nothing is read."""
+    global _tuning_loaded, _tuning_note
+    import glob
     import json
     if path is None:
         try:
             import torch
             if not torch.cuda.is_available():
+                _tuning_note = "no GPU"
                 return None
-            path = tuning_path()
-        except Exception:
+            key = device_key()
+            path = tuning_path(key)
+            if not os.path.exists(path):
+                same_arch = sorted(glob.glob(os.path.join(TUNING_DIR, key.split("_")[0] + "_*.json")))
+                if len(same_arch) == 1:
+                    path = same_arch[0]
+        except Exception as e:  # (no usable device: the defaults)
+            _tuning_note = f"no device key: {e!r}"
             return None
     if not os.path.exists(path):
+        _tuning_note = f"no tuning file {os.path.basename(path)}"
         return None
     with open(path) as f:
         doc = json.load(f)
@@ -248,7 +261,14 @@ def load_tuning(path: str | None = None):
         if rc != CH_OK:
             raise ChainHullError(rc, f"tuning file {path}")
     _tuning_loaded = path
+    _tuning_note = None
     return path
+
+
+def tuning_note():
+    """Why no tuning file was applied (None when one was)."""
+    lib()
+    return _tuning_note
 
 
 def tuning_source():

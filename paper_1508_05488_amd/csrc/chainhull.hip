@@ -527,8 +527,8 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 // record precedes it with k1 <= its k1.  The rest become sort records.
 // ---------------------------------------------------------------------------
 
-constexpr int kSampleBlocks = 64;
-constexpr int kSamplePerThread = 32;
+constexpr int kSampleBlocks = 128;
+constexpr int kSamplePerThread = 16;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
 constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
@@ -4034,9 +4034,9 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
         }
         guard.armed = true;
         // one run of kBlock * kSamplePerThread points per 8 such runs of the
-        // input, from 4 to kSampleBlocks runs
+        // input, from 8 to kSampleBlocks runs
         const uint32_t sblocks = (uint32_t)std::min<uint64_t>(
-            kSampleBlocks, std::max<uint64_t>(4, (uint64_t)n / (8ull * kBlock * kSamplePerThread)));
+            kSampleBlocks, std::max<uint64_t>(8, (uint64_t)n / (8ull * kBlock * kSamplePerThread)));
         const uint64_t total = (uint64_t)sblocks * kBlock * kSamplePerThread;
         const uint32_t runs = n >= total ? 1u : 0u;
         const uint32_t step =
