@@ -250,6 +250,7 @@ def load_tuning(path: str | None = None):
             return None
     if not os.path.exists(path):
         _tuning_note = f"no tuning file {os.path.basename(path)}"
+        _tuning_loaded = None
         return None
     with open(path) as f:
         doc = json.load(f)

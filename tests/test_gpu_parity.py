@@ -306,3 +306,37 @@ def test_device_finish_one_and_many_workgroups():
         st = ch.last_stats()
         assert st["device_finish"] and st["polygon"] > 3584
         assert np.array_equal(got, oracle.hull(adv))
+
+
+def _edge_inputs():
+    # the sampled staircases' first slots (k1 below 2^13 in each frame) and
+    # their sub-slots (2^5 wide), and the list mode's filter slots
+    rng = wl.rng_for(81)
+    M = (1 << 23) - 1
+    n = 200_000
+    out = {}
+    # a thin vertical strip: every point in x-slot 0
+    out["strip x<8192"] = np.stack([rng.integers(0, 8192, n), rng.integers(0, M + 1, n)], 1)
+    # a square frame: only the four edge strips
+    side = rng.integers(0, 4, n)
+    a = rng.integers(0, M + 1, n)
+    b = rng.integers(0, 8192, n)
+    x = np.where(side == 0, b, np.where(side == 1, M - b, a))
+    y = np.where(side == 2, b, np.where(side == 3, M - b, a))
+    out["frame"] = np.stack([x, y], 1)
+    # coordinates on sub-slot and slot boundaries near every edge
+    cand = np.array([0, 1, 31, 32, 33, 63, 64, 8159, 8160, 8191, 8192, 8193, 16383, 16384])
+    vals = np.concatenate([cand, M - cand, rng.integers(0, M + 1, 64)])
+    out["slot boundaries"] = np.stack([rng.choice(vals, n), rng.choice(vals, n)], 1)
+    # a uniform square with its edge strips crowded (a quarter of the points)
+    sq = rng.integers(0, M + 1, (n, 2))
+    k = n // 4
+    sq[:k, 0] = rng.integers(0, 64, k)
+    out["crowded left edge"] = sq
+    return {k: v.astype(np.float32) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("name", ["strip x<8192", "frame", "slot boundaries", "crowded left edge"])
+def test_first_slot_and_sub_slot_edges(name):
+    pts = _edge_inputs()[name]
+    assert_parity(pts, name)

@@ -133,3 +133,23 @@ def test_tuning_table_on_the_host():
     finally:
         ch.clear_tuning()
     assert ch.get_tuning(10) == base
+
+
+def test_tuning_file_found_by_architecture(monkeypatch):
+    # a process may see the device without its name (under rocprofv3 the
+    # key reads "gfx950_"): the one tuning file of the architecture applies
+    import torch
+    files = [f for f in os.listdir(ch.TUNING_DIR) if f.startswith("gfx950_") and f.endswith(".json")]
+    if len(files) != 1:
+        pytest.skip("no single gfx950 tuning file")
+    ch.lib()
+    monkeypatch.setattr(torch.cuda, "is_available", lambda: True)
+    monkeypatch.setattr(ch, "device_key", lambda: "gfx950_")
+    try:
+        path = ch.load_tuning()
+        assert path is not None and os.path.basename(path) == files[0]
+        assert ch.tuning_note() is None
+        monkeypatch.setattr(ch, "device_key", lambda: "gfx000_Other")
+        assert ch.load_tuning() is None and "no tuning file" in ch.tuning_note()
+    finally:
+        ch.clear_tuning()
