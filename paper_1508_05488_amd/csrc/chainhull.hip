@@ -69,6 +69,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <type_traits>
 #include <vector>
 
 #include "chainhull.h"
@@ -2445,42 +2446,49 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             return;
         }
         __syncthreads();
-        // Entry e of the list: the last list with start <= e (binary
-        // searches of a thread's entries side by side, rows of entries that
-        // exist only), then every load of the thread in flight together
-        // (past L: the first list's first slot, read and dropped), then the
-        // LDS writes.
-        const uint32_t rows_used = (L + kBatchBlock - 1) / kBatchBlock;
-        size_t at[kBatchPerList];
+        // Entry e of the list: the last list with start <= e, by binary
+        // searches of all a thread's entries side by side without branches
+        // (each step's LDS reads issued together, one wait), then every load
+        // of the thread in flight together (past L: the first list's first
+        // slot, read and dropped), then the LDS writes.
+        uint32_t lst[kBatchPerList];
 #pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) at[k] = 0;
-        for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1) {
+        for (int k = 0; k < kBatchPerList; ++k) lst[k] = 0;
+        // (the first rows only when the list is short: a uniform choice)
+        auto search = [&](auto rows) {
+            constexpr int R = decltype(rows)::value;
+            for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1) {
+                uint32_t nxt[R];
 #pragma unroll
-            for (int k = 0; k < kBatchPerList; ++k) {
-                if ((uint32_t)k < rows_used) {
-                    const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
-                    if (l + st < nl && s_lst[l + st] <= e) at[k] = l + st;
+                for (int k = 0; k < R; ++k) nxt[k] = s_lst[min(lst[k] + st, nl - 1)];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const uint32_t e = k * kBatchBlock + tid;
+                    lst[k] = (lst[k] + st < nl && nxt[k] <= e) ? lst[k] + st : lst[k];
                 }
             }
-        }
+        };
+        if (L <= 4u * kBatchBlock)
+            search(std::integral_constant<int, 4>{});
+        else
+            search(std::integral_constant<int, kBatchPerList>{});
+        size_t at[kBatchPerList];
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
-            const uint32_t e = k * kBatchBlock + tid, l = (uint32_t)at[k];
+            const uint32_t e = k * kBatchBlock + tid, l = lst[k];
             at[k] = e < L ? (size_t)l * src.region + (e - s_lst[l]) : 0;
         }
         uint32_t gi[kBatchPerList];
         u64 gr[kBatchPerList];
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
-            if ((uint32_t)k < rows_used) {
-                gi[k] = src.idx[at[k]];
-                gr[k] = src.xym[at[k]];
-            }
+            gi[k] = src.idx[at[k]];
+            gr[k] = src.xym[at[k]];
         }
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             const uint32_t e = k * kBatchBlock + tid;
-            if ((uint32_t)k < rows_used && e < L) {
+            if (e < L) {
                 lidx[e] = gi[k];
                 s_lxy[2 * e] = (uint32_t)gr[k] & kM;
                 s_lxy[2 * e + 1] = (uint32_t)(gr[k] >> 23) & kM;
