@@ -230,41 +230,6 @@ __device__ inline void take_max(u64& k, uint32_t& i, u64 ok, uint32_t oi)
     }
 }
 
-__device__ inline uint32_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-__device__ inline uint32_t wave_min(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off));
-    return v;
-}
-
-__device__ inline uint32_t wave_incl_sum(uint32_t v)
-{
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(v, off);
-        if (lane >= (uint32_t)off) v += o;
-    }
-    return v;
-}
-
-__device__ inline uint32_t wave_incl_min(uint32_t v)
-{
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(v, off);
-        if (lane >= (uint32_t)off) v = min(v, o);
-    }
-    return v;
-}
 
 // Inclusive and exclusive minimum scans over the wave without the LDS
 // crossbar: DPP row shifts inside each row of 16 lanes, then the rows'
@@ -299,6 +264,42 @@ __device__ inline void wave_min_scan(uint32_t v, uint32_t& incl, uint32_t& excl,
     const uint32_t sh = dpp_row_shr(v, 1);
     excl = (lane & 15u) == 0 ? before : min(sh, before);
 }
+
+// DPP row shift by n with 0 for the lanes whose source lies outside the row.
+__device__ inline uint32_t dpp_row_shr0(uint32_t v, int ctrl_n)
+{
+    switch (ctrl_n) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    case 4: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    }
+}
+
+// Inclusive sum and minimum scans over the wave (every lane active), by DPP
+// row shifts and the rows' totals through readlane.
+__device__ inline uint32_t wave_incl_sum(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+    v += dpp_row_shr0(v, 1);
+    v += dpp_row_shr0(v, 2);
+    v += dpp_row_shr0(v, 4);
+    v += dpp_row_shr0(v, 8);
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = r0 + (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = r1 + (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    return v + (lane < 16 ? 0u : lane < 32 ? r0 : lane < 48 ? r1 : r2);
+}
+
+__device__ inline uint32_t wave_incl_min(uint32_t v)
+{
+    uint32_t incl, excl, total;
+    wave_min_scan(v, incl, excl, total);
+    return incl;
+}
+
+// The sum over the wave, in every lane (every lane active).
+__device__ inline uint32_t wave_sum(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(v), 63); }
 
 // Exclusive workgroup sum of one value per thread (W waves); `total` gets
 // the sum.
@@ -435,6 +436,8 @@ __device__ inline uint32_t wave_min_all(uint32_t v)
     const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
     return min(min(r0, r1), min(r2, r3));
 }
+
+__device__ inline uint32_t wave_min(uint32_t v) { return wave_min_all(v); }
 
 // The lexicographically smallest (hi, lo) over the wave and, among the lanes
 // holding it, the smallest index: three wave minima.
