@@ -309,7 +309,8 @@ int chainhull_release_stream(void* stream);
  * 2.2.2, 4.3); here every shape that no LDS layout fixes is a run-time
  * choice, picked per size class by the project's autotuner
  * (paper_1508_05488_amd/autotune.py), which times the candidates on the
- * device, checks that each gives the same hulls, and stores the fastest.
+ * device, checks that each gives the same hulls, and stores the fastest
+ * (the defaults unless a candidate is at least 2 % faster).
  * Every field must hold one of the values listed; results never depend on
  * the shape.
  */
