@@ -69,7 +69,6 @@
 #include <map>
 #include <mutex>
 #include <utility>
-#include <type_traits>
 #include <vector>
 
 #include "chainhull.h"
@@ -2449,32 +2448,26 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             return;
         }
         __syncthreads();
-        // Entry e of the list: the last list with start <= e, by binary
-        // searches of all a thread's entries side by side without branches
-        // (each step's LDS reads issued together, one wait), then every load
-        // of the thread in flight together (past L: the first list's first
-        // slot, read and dropped), then the LDS writes.
+        // Entry e of the list: its list from an owner array (the
+        // staircase's room, free in the list mode), which each thread fills
+        // for its two lists; then every load of the thread in flight
+        // together (past L: the first list's first slot, read and dropped),
+        // then the LDS writes.  (A list longer than the others only makes
+        // its thread's loop longer: at most L <= kBatchList entries.)
+        uint16_t* const s_own = reinterpret_cast<uint16_t*>(smem + kBatchOffStair);
+        static_assert(2 * (size_t)kBatchList <= 4 * 4 * (size_t)kStairSlots && kStreamGrid <= 65536, "owner array");
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t l = 2 * tid + u, first = u == 0 ? e0 : e0 + c[0];
+            for (uint32_t q = 0; q < c[u]; ++q) s_own[first + q] = (uint16_t)l;
+        }
+        __syncthreads();
         uint32_t lst[kBatchPerList];
 #pragma unroll
-        for (int k = 0; k < kBatchPerList; ++k) lst[k] = 0;
-        // (the first rows only when the list is short: a uniform choice)
-        auto search = [&](auto rows) {
-            constexpr int R = decltype(rows)::value;
-            for (uint32_t st = kStreamGrid / 2; st > 0; st >>= 1) {
-                uint32_t nxt[R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) nxt[k] = s_lst[min(lst[k] + st, nl - 1)];
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const uint32_t e = k * kBatchBlock + tid;
-                    lst[k] = (lst[k] + st < nl && nxt[k] <= e) ? lst[k] + st : lst[k];
-                }
-            }
-        };
-        if (L <= 4u * kBatchBlock)
-            search(std::integral_constant<int, 4>{});
-        else
-            search(std::integral_constant<int, kBatchPerList>{});
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t e = k * kBatchBlock + tid;
+            lst[k] = e < L ? s_own[e] : 0u;
+        }
         size_t at[kBatchPerList];
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
