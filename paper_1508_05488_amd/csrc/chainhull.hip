@@ -2733,6 +2733,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     CH_PHASE_MARK(2);
     // ---- exact regions and region slot minima of the listed points ----
     u64 rec[kBatchPerList];
+    uint32_t rslot[kBatchPerList];  // a record's filter slot (0 without a record)
     uint32_t kf[4];  // k1 of each region's first point
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -2759,6 +2760,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
 #pragma unroll
         for (int k = 0; k < kBatchPerList; ++k) {
             rec[k] = ~0ull;
+            if constexpr (kFromLists) rslot[k] = 0;
             if (k * kBatchBlock + tid < L) {
                 const uint32_t X = (uint32_t)v[k].x, Y = (uint32_t)v[k].y;
                 // the extreme points' smallest indices among their duplicates
@@ -2774,6 +2776,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
                     const uint32_t sl = kFromLists ? list_slot(k1 - f) : (k1 >> kBatchSlotShift);
                     atomicMin(&smin[q * kBatchSlots + sl], ((u64)k2 << 23) | k1);
                     rec[k] = ((u64)q << 46) | ((u64)k1 << 23) | k2;
+                    if constexpr (kFromLists) rslot[k] = q * kBatchSlots + sl;
                 }
             }
         }
@@ -2810,14 +2813,32 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
     }
     // survivors become sort keys: record << kBatchPosBits | list position
     uint32_t keep = 0;
+    if constexpr (kFromLists) {
+        // (one workgroup: every row's two LDS reads issued together, then
+        // the tests)
+        u64 best[kBatchPerList];
+        uint32_t exc[kBatchPerList];
 #pragma unroll
-    for (int k = 0; k < kBatchPerList; ++k) {
-        if (rec[k] != ~0ull) {
-            const uint32_t q = (uint32_t)(rec[k] >> 46), k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
-            const uint32_t f = q == 0 ? kf[0] : q == 1 ? kf[1] : q == 2 ? kf[2] : kf[3];
-            const uint32_t sl = q * kBatchSlots + (kFromLists ? list_slot(k1 - f) : (k1 >> kBatchSlotShift));
-            const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
-            if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) keep |= 1u << k;
+        for (int k = 0; k < kBatchPerList; ++k) {
+            best[k] = smin[rslot[k]];
+            exc[k] = sexc[rslot[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            const uint32_t k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
+            const u64 me = ((u64)k2 << 23) | k1;
+            if (rec[k] != ~0ull && k2 < exc[k] && !(best[k] < me && (uint32_t)(best[k] & kM) <= k1)) keep |= 1u << k;
+        }
+    } else {
+        // (two workgroups per CU: registers are short, one row at a time)
+#pragma unroll
+        for (int k = 0; k < kBatchPerList; ++k) {
+            if (rec[k] != ~0ull) {
+                const uint32_t k1 = (uint32_t)(rec[k] >> 23) & kM, k2 = (uint32_t)rec[k] & kM;
+                const uint32_t sl = ((uint32_t)(rec[k] >> 46)) * kBatchSlots + (k1 >> kBatchSlotShift);
+                const u64 me = ((u64)k2 << 23) | k1, best = smin[sl];
+                if (k2 < sexc[sl] && !(best < me && (uint32_t)(best & kM) <= k1)) keep |= 1u << k;
+            }
         }
     }
     uint32_t nsort;
