@@ -546,6 +546,16 @@ constexpr int kStabWords = 4 * kStairSlots + 4 * kEdgeSub;  // the sample table
 constexpr int kStreamGrid = 1024;   // k_stream workgroups at most (the partials' room)
 constexpr int kWaveList = 256;      // open points listed per wave before a flush
 
+// A slot pair's two frames as one interval of the other coordinate: the
+// point is dominated in both iff that coordinate lies in [lo, M - cf]
+// (lo: the lower frame's staircase, cf: the upper frame's), stored as
+// a | w << 32 with w = M - cf - a; an empty interval as a = ~0u, w = 0.
+__device__ inline u64 stair_interval(uint32_t lo, uint32_t cf)
+{
+    const bool some = cf <= kM && lo <= kM - cf;
+    return some ? ((u64)(kM - cf - lo) << 32) | lo : (u64)~0u;
+}
+
 // The frames in which a point outside its slots' intervals is open (bit
 // f - 1 for frame Rf): R1 below the y interval [ax, ax + wx], R3 above it,
 // R4 below the x interval [ay, ay + wy], R2 above it; an empty interval
@@ -793,10 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
         // M - s3, so the interval is [s1, M - s3]; R4 and R2 give [s4, M - s2].
         // Stored as a | w << 32; an empty interval as a = ~0u, w = 0 (every
         // point of the slot is open).
-        auto interval = [](uint32_t lo, uint32_t cf) -> u64 {
-            const bool some = cf <= kM && lo <= kM - cf;
-            return some ? ((u64)(kM - cf - lo) << 32) | lo : (u64)~0u;
-        };
+        const auto interval = stair_interval;
         u64* const s64 = reinterpret_cast<u64*>(sst);
         for (int e = tid; e < 2 * kStairSlots; e += kBlock) {
             const u64 v = s64[e];
@@ -2262,6 +2269,14 @@ __device__ inline void batch_stair(const uint32_t* raw, uint32_t* sst, uint32_t*
         excl = min(excl, v[k]);
     }
     __syncthreads();
+    // each slot pair as one interval (the test of k_stream)
+    u64* const s64 = reinterpret_cast<u64*>(sst);
+    for (uint32_t e = tid; e < 2 * S; e += kBatchBlock) {
+        const u64 pv = s64[e];
+        const bool xs = e < S;
+        s64[e] = stair_interval(xs ? (uint32_t)pv : (uint32_t)(pv >> 32), xs ? (uint32_t)(pv >> 32) : (uint32_t)pv);
+    }
+    __syncthreads();
 }
 
 // The polygon phase: pre-hull rounds on the polygon Pl[0 .. npoly) (x, y,
@@ -2539,13 +2554,13 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
         // one point of every lane, the whole wave together (the append is
         // wave-wide)
         auto list_point = [&](uint32_t X, uint32_t Y, uint32_t idx, bool valid, u64 sxv, u64 syv) {
-            const bool o1 = Y < (uint32_t)sxv;                 // R1: k2 = y
-            const bool o2 = (X ^ kM) < (uint32_t)syv;          // R2: k2 = M - x
-            const bool o3 = (Y ^ kM) < (uint32_t)(sxv >> 32);  // R3: k2 = M - y
-            const bool o4 = X < (uint32_t)(syv >> 32);         // R4: k2 = x
-            const bool open = valid && (o1 || o2 || o3 || o4);
-            const u64 bal = ballot(open);
+            // outside the slots' intervals (the comparisons' lane masks as
+            // they are)
+            const u64 bal = (cmp_mask_gt(Y - (uint32_t)sxv, (uint32_t)(sxv >> 32)) |
+                             cmp_mask_gt(X - (uint32_t)syv, (uint32_t)(syv >> 32))) &
+                            ballot(valid);
             if (bal) {
+                const bool open = (bal >> lane) & 1u;
                 uint32_t first = 0;
                 if (lane == 0) first = atomicAdd(&s_n, (uint32_t)__popcll(bal));
                 first = __shfl(first, 0);
@@ -2587,8 +2602,7 @@ __global__ __launch_bounds__(kBatchBlock, kBatchWavesPerSimd) void k_batch_hull(
             for (int k = 0; k < kBatchPerList; ++k) {
                 const uint32_t X = cvt_u32_sat(v[k].x) & kM, Y = cvt_u32_sat(v[k].y) & kM;
                 const u64 sxv = sx64[X >> kStairShift], syv = sy64[Y >> kStairShift];
-                const bool open = Y < (uint32_t)sxv || (X ^ kM) < (uint32_t)syv || (Y ^ kM) < (uint32_t)(sxv >> 32) ||
-                                  X < (uint32_t)(syv >> 32);
+                const bool open = Y - (uint32_t)sxv > (uint32_t)(sxv >> 32) || X - (uint32_t)syv > (uint32_t)(syv >> 32);
                 if (k * kBatchBlock + tid < n && open) keep |= 1u << k;
             }
             uint32_t kept;
