@@ -2279,6 +2279,60 @@ __device__ inline void batch_stair(const uint32_t* raw, uint32_t* sst, uint32_t*
     __syncthreads();
 }
 
+// poly_finish's rounds on a polygon of at most 64 vertices by one wave
+// (the first; every lane calls it), vertex k of the current polygon in lane
+// k: neighbours by lane exchange, removal by compaction of the kept lanes (a
+// forward permute), no workgroup barrier.  A convex result is written to out
+// (*s_flag = 1), else the polygon left is in Pl.lst (*s_flag = 0); *s_ext
+// receives its size.  Kept out of line: it runs once per set.
+__device__ __attribute__((noinline)) void wave_poly_rounds(BatchPoly Pl, uint32_t npoly, uint32_t first,
+                                                           int32_t* __restrict__ out, uint32_t* s_flag,
+                                                           uint32_t* s_ext)
+{
+    const uint32_t lane = lane_id();
+    bool keep = lane < npoly && Pl.alive[lane] != 0;
+    uint32_t vid = lane, rg = keep ? Pl.reg[lane] : 0u;
+    int32_t x = keep ? Pl.x[lane] : 0, y = keep ? Pl.y[lane] : 0;
+    uint32_t cnt = 0;
+    bool convex = false;
+    for (int round = 0;; ++round) {
+        // kept lanes to lanes 0 .. cnt-1 in order, the others above
+        const u64 km = ballot(keep);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        cnt = (uint32_t)__popcll(km);
+        const uint32_t to = keep ? below : cnt + (lane - below);
+        vid = (uint32_t)__builtin_amdgcn_ds_permute((int)(to * 4), (int)vid);
+        rg = (uint32_t)__builtin_amdgcn_ds_permute((int)(to * 4), (int)rg);
+        x = __builtin_amdgcn_ds_permute((int)(to * 4), x);
+        y = __builtin_amdgcn_ds_permute((int)(to * 4), y);
+        if (round == kBatchRounds) break;  // (a removal in every round: Melkman)
+        const bool act = lane < cnt;
+        const uint32_t pl = lane == 0 ? (cnt ? cnt - 1 : 0u) : lane - 1, nl = lane + 1 >= cnt ? 0u : lane + 1;
+        const int32_t px = __shfl(x, (int)pl), py = __shfl(y, (int)pl);
+        const int32_t nx = __shfl(x, (int)nl), ny = __shfl(y, (int)nl);
+        const i64 t = (i64)(x - px) * (i64)(ny - py) - (i64)(y - py) * (i64)(nx - px);
+        const bool bad = act && t <= 0;
+        const bool gone = bad && rg < 4;
+        if (ballot(gone) == 0) {
+            convex = ballot(bad) == 0 && cnt >= 3;
+            break;
+        }
+        keep = act && !gone;
+    }
+    const bool act = lane < cnt;
+    if (convex) {
+        const u64 fm = ballot(act && vid == first);
+        const uint32_t start = fm ? (uint32_t)__builtin_ctzll(fm) : 0u;
+        if (act) out[lane >= start ? lane - start : lane + cnt - start] = Pl.idx[vid];
+    } else if (act) {
+        Pl.lst[lane] = (uint16_t)vid;
+    }
+    if (lane == 0) {
+        *s_flag = convex ? 1u : 0u;
+        *s_ext = cnt;
+    }
+}
+
 // The polygon phase: pre-hull rounds on the polygon Pl[0 .. npoly) (x, y,
 // idx, region 0..3 or 4 for an extreme point, all alive), then the hull into
 // out.  A chain vertex whose turn with its current neighbours (points of its
@@ -2289,13 +2343,26 @@ __device__ inline void batch_stair(const uint32_t* raw, uint32_t* sst, uint32_t*
 // included, is a strict left turn, the simple polygon is convex and is the
 // hull: it is written out in parallel from polygon position `first`
 // (P_miny, the lowest then leftmost point).  Otherwise one thread runs
-// Melkman.  Every thread of the workgroup (kBatchBlock) calls it; returns the
-// hull size, the same in every thread, or -1 when Melkman's deque would
-// leave its room.  s_flag, s_ext, s_start: LDS words.
+// Melkman.  A polygon of at most 64 vertices takes the rounds in one wave
+// (a vertex per lane), a larger one in the workgroup.  Every thread of the
+// workgroup (kBatchBlock) calls it; returns the hull size, the same in every
+// thread, or -1 when Melkman's deque would leave its room.  s_flag, s_ext,
+// s_start: LDS words.
 __device__ int poly_finish(const BatchPoly& Pl, uint32_t npoly, uint32_t first, int32_t* __restrict__ out,
                            uint32_t* scratch, uint32_t* s_flag, uint32_t* s_ext, uint32_t* s_start)
 {
     const uint32_t tid = threadIdx.x;
+    if (npoly <= 64) {
+        // the rounds by the first wave
+        if (tid < 64) wave_poly_rounds(Pl, npoly, first, out, s_flag, s_ext);
+        __syncthreads();
+        const bool convex = *s_flag != 0;
+        const uint32_t cnt = *s_ext;
+        if (convex) return (int)cnt;
+        if (tid == 0) *s_start = (uint32_t)batch_melkman(Pl, cnt, out);
+        __syncthreads();
+        return (int)*s_start;
+    }
     auto compact_poly = [&]() -> uint32_t {
         constexpr int kPer = kBatchPolyMax / kBatchBlock;
         uint32_t mine = 0;
