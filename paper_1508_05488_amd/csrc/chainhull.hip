@@ -533,6 +533,11 @@ __device__ inline void ext_block_reduce(ExtAcc& a, ExtAcc* sh)
 constexpr int kSampleBlocks = 128;
 constexpr int kSamplePerThread = 16;
 constexpr uint32_t kSamplePts = (uint32_t)kSampleBlocks * kBlock * kSamplePerThread;
+// An input of at most kSelfSampleMax points skips k_sample: every k_stream
+// workgroup takes its own sample, kBlock * kSamplePerThread evenly spaced
+// points, into LDS (one launch less; such an input leaves few open points
+// with that sample too).
+constexpr uint32_t kSelfSampleMax = 1u << 18;
 constexpr int kStairBits = 10;
 constexpr int kStairSlots = 1 << kStairBits;
 constexpr int kStairShift = 23 - kStairBits;
@@ -574,6 +579,28 @@ __device__ inline u64 open_rec(uint32_t X, uint32_t Y, uint32_t mask)
     return (u64)X | ((u64)Y << 23) | ((u64)mask << 46);
 }
 
+// One sample point (X, Y) into the slot minima st (LDS, the table layout
+// below, ~0u: no point yet).  Every lane of the wave calls it together.
+__device__ inline void sample_point(uint32_t* st, uint32_t X, uint32_t Y)
+{
+    const uint32_t xm = X ^ kM, ym = Y ^ kM;
+    atomicMin(&st[0 * kStairSlots + (X >> kStairShift)], Y);   // R1: (x, y)
+    atomicMin(&st[1 * kStairSlots + (Y >> kStairShift)], xm);  // R2: (y, M-x)
+    atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym); // R3: (M-x, M-y)
+    atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X);  // R4: (M-y, x)
+    // a frame's first slot by sub-slot as well (few points: one wave-wide
+    // test first)
+    constexpr uint32_t E = 4 * kStairSlots;
+    const bool ex0 = (X >> kStairShift) == 0, ey0 = (Y >> kStairShift) == 0;
+    const bool ex1 = (xm >> kStairShift) == 0, ey1 = (ym >> kStairShift) == 0;
+    if (ballot(ex0 | ey0 | ex1 | ey1)) {
+        if (ex0) atomicMin(&st[E + 0 * kEdgeSub + (X >> kEdgeShift)], Y);
+        if (ey0) atomicMin(&st[E + 1 * kEdgeSub + (Y >> kEdgeShift)], xm);
+        if (ex1) atomicMin(&st[E + 2 * kEdgeSub + (xm >> kEdgeShift)], ym);
+        if (ey1) atomicMin(&st[E + 3 * kEdgeSub + (ym >> kEdgeShift)], X);
+    }
+}
+
 // k_sample: workgroup b reads a run of kBlock * kSamplePerThread consecutive
 // points (coalesced), the runs evenly spaced (a smaller input is sampled with
 // repeats at evenly spaced indices), takes its per-frame slot minima in LDS
@@ -607,24 +634,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ pts
         Y[k] = coord_u32(p.y) & kM;
     }
 #pragma unroll
-    for (int k = 0; k < kSamplePerThread; ++k) {
-        const uint32_t xm = X[k] ^ kM, ym = Y[k] ^ kM;
-        atomicMin(&st[0 * kStairSlots + (X[k] >> kStairShift)], Y[k]);  // R1: (x, y)
-        atomicMin(&st[1 * kStairSlots + (Y[k] >> kStairShift)], xm);    // R2: (y, M-x)
-        atomicMin(&st[2 * kStairSlots + (xm >> kStairShift)], ym);      // R3: (M-x, M-y)
-        atomicMin(&st[3 * kStairSlots + (ym >> kStairShift)], X[k]);    // R4: (M-y, x)
-        // a frame's first slot by sub-slot as well (few points: one wave-wide
-        // test first)
-        constexpr uint32_t E = 4 * kStairSlots;
-        const bool ex0 = (X[k] >> kStairShift) == 0, ey0 = (Y[k] >> kStairShift) == 0;
-        const bool ex1 = (xm >> kStairShift) == 0, ey1 = (ym >> kStairShift) == 0;
-        if (ballot(ex0 | ey0 | ex1 | ey1)) {
-            if (ex0) atomicMin(&st[E + 0 * kEdgeSub + (X[k] >> kEdgeShift)], Y[k]);
-            if (ey0) atomicMin(&st[E + 1 * kEdgeSub + (Y[k] >> kEdgeShift)], xm);
-            if (ex1) atomicMin(&st[E + 2 * kEdgeSub + (xm >> kEdgeShift)], ym);
-            if (ey1) atomicMin(&st[E + 3 * kEdgeSub + (ym >> kEdgeShift)], X[k]);
-        }
-    }
+    for (int k = 0; k < kSamplePerThread; ++k) sample_point(st, X[k], Y[k]);
     __syncthreads();
     for (int e = tid; e < kStabWords; e += kBlock)
         if (st[e] != ~0u) atomicMax(stab + e, ~st[e]);
@@ -709,16 +719,20 @@ __device__ inline void quad_from_partials(const ExtPartial* __restrict__ part, u
 // the open arrays and their number to wgcount[b]: no two workgroups share a
 // counter (same-address atomics from many workgroups serialise).  `per`
 // float4s per workgroup, a multiple of kBlock*kStreamUnroll (the float4
-// loads in flight per thread).
-template <int kStreamUnroll>
+// loads in flight per thread).  kSelfSample: the workgroup takes its own
+// sample instead of reading stab: kSamplePerThread runs of kBlock
+// consecutive points (coalesced), run k from floor(k * smul / 2^32), smul =
+// floor(max(n - kBlock, 0) * 2^32 / (kSamplePerThread - 1)).
+template <int kStreamUnroll, bool kSelfSample = false>
 __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts, uint32_t n, uint32_t head,
                                                    const uint32_t* __restrict__ stab, ExtPartial* __restrict__ part,
                                                    uint32_t* __restrict__ open_idx, u64* __restrict__ open_xym,
                                                    uint32_t per, uint32_t region, uint32_t* __restrict__ wgcount,
-                                                   const int32_t* __restrict__ gate)
+                                                   uint64_t smul, const int32_t* __restrict__ gate)
 {
     if (gated_off(gate)) return;
     __shared__ __align__(16) uint32_t sst[4 * kStairSlots];
+    __shared__ uint32_t own_tab[kSelfSample ? kStabWords : 1];  // the own sample's slot minima
     __shared__ __align__(16) u64 ssub[4 * kEdgeSub];  // the first slots' intervals by sub-slot
     __shared__ uint32_t s_last[4];                      // each frame's staircase at its last slot
     __shared__ uint32_t lidx[kWaves][kWaveList];
@@ -751,10 +765,12 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
     static_assert(4 * 64 == kBlock, "one wave per frame");
     constexpr int kEdgePer = kEdgeSub / 64;  // 4
     uint32_t sv[kPer], ev[kEdgePer];
+    if constexpr (!kSelfSample) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) sv[k] = stab[wave * kStairSlots + k * 64 + lane];
+        for (int k = 0; k < kPer; ++k) sv[k] = stab[wave * kStairSlots + k * 64 + lane];
 #pragma unroll
-    for (int k = 0; k < kEdgePer; ++k) ev[k] = stab[4 * kStairSlots + wave * kEdgeSub + k * 64 + lane];
+        for (int k = 0; k < kEdgePer; ++k) ev[k] = stab[4 * kStairSlots + wave * kEdgeSub + k * 64 + lane];
+    }
     v4f va[kStreamUnroll];
     {
         // unconditional, so that no branch joins before the table wait (a
@@ -763,6 +779,28 @@ __global__ __launch_bounds__(kBlock) void k_stream(const float* __restrict__ pts
 #pragma unroll
         for (int u = 0; u < kStreamUnroll; ++u)
             va[u] = __builtin_nontemporal_load(src + (rounds ? min(lo + u * kBlock + tid, hi - 1) : 0u));
+    }
+    if constexpr (kSelfSample) {
+        // k_sample's slot minima of the workgroup's own sample, in LDS (the
+        // first round's loads above stay in flight meanwhile); the table as
+        // k_sample leaves it holds their complements
+        for (int e = tid; e < kStabWords; e += kBlock) own_tab[e] = ~0u;
+        uint32_t X[kSamplePerThread], Y[kSamplePerThread];
+#pragma unroll
+        for (int k = 0; k < kSamplePerThread; ++k) {
+            const uint32_t i = min((uint32_t)(((u64)k * smul) >> 32) + tid, n - 1);
+            const v2f p = *reinterpret_cast<const v2f*>(pts + 2 * (size_t)i);
+            X[k] = coord_u32(p.x) & kM;  // (out of domain: in range here, the call fails)
+            Y[k] = coord_u32(p.y) & kM;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSamplePerThread; ++k) sample_point(own_tab, X[k], Y[k]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) sv[k] = ~own_tab[wave * kStairSlots + k * 64 + lane];
+#pragma unroll
+        for (int k = 0; k < kEdgePer; ++k) ev[k] = ~own_tab[4 * kStairSlots + wave * kEdgeSub + k * 64 + lane];
     }
     {
         // The staircases: per frame the exclusive prefix minimum of the slot
@@ -4139,25 +4177,27 @@ int launch_preprocess(Workspace& w, const float* pts, uint32_t n, bool stats, in
                                          (uint32_t)kStabWords));
         }
         guard.armed = true;
-        // one run of kBlock * kSamplePerThread points per 8 such runs of the
-        // input, from 8 to kSampleBlocks runs
-        const uint32_t sblocks = (uint32_t)std::min<uint64_t>(
-            kSampleBlocks, std::max<uint64_t>(8, (uint64_t)n / (8ull * kBlock * kSamplePerThread)));
-        const uint64_t total = (uint64_t)sblocks * kBlock * kSamplePerThread;
-        const uint32_t runs = n >= total ? 1u : 0u;
-        const uint32_t step =
-            runs && sblocks > 1 ? (uint32_t)((n - (uint64_t)kBlock * kSamplePerThread) / (sblocks - 1)) : 0u;
-        const uint64_t mul = runs ? 0ull : ((uint64_t)n << 32) / total;
-        CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(sblocks), dim3(kBlock), 0, s, pts, n, runs, step, mul, w.stab,
-                                     gate));
-        CH_TRY(record(w, 1));
-        if (tu.stream_unroll == 2) {
-            CH_LAUNCH(hipLaunchKernelGGL(k_stream<2>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
-                                         w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
-        } else {
-            CH_LAUNCH(hipLaunchKernelGGL(k_stream<4>, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
-                                         w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, gate));
+        // a small input: each k_stream workgroup samples it itself
+        const bool own = n > 0 && n <= kSelfSampleMax;
+        if (!own) {
+            // one run of kBlock * kSamplePerThread points per 8 such runs of
+            // the input, from 8 to kSampleBlocks runs
+            const uint32_t sblocks = (uint32_t)std::min<uint64_t>(
+                kSampleBlocks, std::max<uint64_t>(8, (uint64_t)n / (8ull * kBlock * kSamplePerThread)));
+            const uint64_t total = (uint64_t)sblocks * kBlock * kSamplePerThread;
+            const uint32_t runs = n >= total ? 1u : 0u;
+            const uint32_t step =
+                runs && sblocks > 1 ? (uint32_t)((n - (uint64_t)kBlock * kSamplePerThread) / (sblocks - 1)) : 0u;
+            const uint64_t mul = runs ? 0ull : ((uint64_t)n << 32) / total;
+            CH_LAUNCH(hipLaunchKernelGGL(k_sample, dim3(sblocks), dim3(kBlock), 0, s, pts, n, runs, step, mul, w.stab,
+                                         gate));
         }
+        CH_TRY(record(w, 1));
+        const uint64_t smul = own && n > (uint32_t)kBlock ? ((uint64_t)(n - kBlock) << 32) / (kSamplePerThread - 1) : 0ull;
+        auto kstream = tu.stream_unroll == 2 ? (own ? k_stream<2, true> : k_stream<2, false>)
+                                             : (own ? k_stream<4, true> : k_stream<4, false>);
+        CH_LAUNCH(hipLaunchKernelGGL(kstream, dim3(sh.grid), dim3(kBlock), 0, s, pts, n, head, w.stab, w.part,
+                                     w.open_idx, w.open_xym, sh.per, sh.region, w.wgcount, smul, gate));
         CH_TRY(record(w, 2));
         if (fin_idx && !gate && tu.list_max > 0) {
             // few open points: every later step in one workgroup (the batched

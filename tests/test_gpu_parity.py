@@ -340,3 +340,13 @@ def _edge_inputs():
 def test_first_slot_and_sub_slot_edges(name):
     pts = _edge_inputs()[name]
     assert_parity(pts, name)
+
+
+@pytest.mark.parametrize("n", [20_000, 262_144, 262_145])
+def test_own_sample_and_sampling_kernel_bound(n):
+    # up to 2^18 points every k_stream workgroup samples the input itself;
+    # above, k_sample's table: both sides of the bound, shuffled and sorted
+    for dist, seed in (("square", 90), ("disk", 91), ("gaussian", 92)):
+        pts = wl.generate(dist, n, seed=seed)
+        assert_parity(pts, f"{dist} {n}")
+        assert_parity(np.ascontiguousarray(pts[np.argsort(pts[:, 0], kind="stable")]), f"{dist} {n} sorted by x")
